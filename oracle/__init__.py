@@ -1,0 +1,209 @@
+"""CPU oracle of the pixel-track reconstruction path.
+
+TEST INFRASTRUCTURE ONLY: this package is the independent reference the HIP
+library is checked against.  Only tests/, the smoke check and the benchmark's
+CPU-baseline leg may import it; the product package never does.
+
+Two tiers, sharing no code with the HIP library:
+
+* ``pxt_oracle.c`` (built with gcc, FP64, ``-ffp-contract=off``): the whole
+  path on one event by the plain definitions -- all hit pairs for doublets,
+  all doublet pairs sharing a hit for links, recursive depth-first search
+  for n-tuplets, per-doublet best-tuple cleaning, and the broken-line fit
+  solved by Householder QR.  Wrapped here through ctypes.
+* ``brute.py`` (numpy): O(n^2) doublets and O(n^3) triplets enumerated
+  directly over hits, path growth by repeated extension, and the fit by a
+  generic least-squares solve.  Used on tiny events to cross-check the C tier.
+"""
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pxt_oracle.c")
+_LIB = os.path.join(_HERE, "libpxt_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+PAD = 0xFFFFFFFF
+ITEMS = dict(doublets=0, links=1, raw=2, raw_score=3, keep=4, tracks=5,
+             params=6, cov=7, chi2=8, kref=9)
+_SHAPES = dict(doublets=(np.uint32, 2), links=(np.uint32, 3), raw=(np.uint32, 8),
+               raw_score=(np.float64, 1), keep=(np.uint8, 1), tracks=(np.uint32, 8),
+               params=(np.float64, 5), cov=(np.float64, 15), chi2=(np.float64, 2),
+               kref=(np.float64, 1))
+
+MAX_LAYERS = 16
+MAX_PAIRS = 64
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("c_kappa", ctypes.c_double),
+        ("n_layers", ctypes.c_int),
+        ("layer_kind", ctypes.c_int * MAX_LAYERS),
+        ("n_pairs", ctypes.c_int),
+        ("pair_inner", ctypes.c_int * MAX_PAIRS),
+        ("pair_outer", ctypes.c_int * MAX_PAIRS),
+        ("kmax", ctypes.c_double), ("z0max", ctypes.c_double),
+        ("arz", ctypes.c_double), ("d0max", ctypes.c_double),
+        ("sigma_u", ctypes.c_double), ("sigma_z", ctypes.c_double),
+        ("sigma_r", ctypes.c_double), ("x_over_x0", ctypes.c_double),
+        ("pt_max", ctypes.c_double),
+    ]
+
+
+def build(force=False):
+    """Compile the C oracle with gcc (FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = ctypes.CDLL(_LIB)
+            L.orc_run.restype = ctypes.c_void_p
+            L.orc_run.argtypes = [ctypes.POINTER(Config), ctypes.c_uint32,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]
+            L.orc_status.argtypes = [ctypes.c_void_p]
+            L.orc_count.restype = ctypes.c_uint64
+            L.orc_count.argtypes = [ctypes.c_void_p, ctypes.c_int]
+            L.orc_data.restype = ctypes.c_void_p
+            L.orc_data.argtypes = [ctypes.c_void_p, ctypes.c_int]
+            L.orc_free.argtypes = [ctypes.c_void_p]
+            d = ctypes.c_double
+            L.orc_doublet_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 6
+            L.orc_link_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 9
+            L.orc_link_terms.argtypes = [ctypes.POINTER(Config)] + [d] * 9 + [ctypes.c_void_p]
+            L.orc_fit.argtypes = [ctypes.POINTER(Config), ctypes.c_int] + [ctypes.c_void_p] * 8
+            _lib = L
+    return _lib
+
+
+def make_config(det):
+    """ctypes config from the detector dictionary (eventgen.DETECTOR layout)."""
+    c = Config()
+    c.c_kappa = det["c_kappa"]
+    layers = sorted(det["layers"], key=lambda l: l["id"])
+    c.n_layers = len(layers)
+    for l in layers:
+        c.layer_kind[l["id"]] = int(l["kind"])
+    c.n_pairs = len(det["pairs"])
+    for i, (a, b) in enumerate(det["pairs"]):
+        c.pair_inner[i] = a
+        c.pair_outer[i] = b
+    cu, f = det["cuts"], det["fit"]
+    c.kmax, c.z0max, c.arz, c.d0max = cu["kmax"], cu["z0max"], cu["arz"], cu["d0max"]
+    c.sigma_u, c.sigma_z, c.sigma_r = f["sigma_u"], f["sigma_z"], f["sigma_r"]
+    c.x_over_x0, c.pt_max = f["x_over_x0"], f["pt_max"]
+    return c
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def reconstruct(x, y, z, layer, det):
+    """Run the whole path on one event.  Returns a dict of numpy arrays:
+
+    doublets [Nd,2], links [Nl,3], raw [Nt,8], raw_score [Nt], keep [Nt],
+    tracks [Nk,8], params [Nk,5], cov [Nk,15], chi2 [Nk,2], kref [Nk],
+    status (0 ok, 1 path longer than 8 hits).  Hit indices are event-local
+    input-order indices; tuples are padded with 0xFFFFFFFF.
+    """
+    L = lib()
+    cfg = make_config(det)
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    layer = np.ascontiguousarray(layer, np.int16)
+    r = L.orc_run(ctypes.byref(cfg), x.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(layer))
+    if not r:
+        raise MemoryError("oracle allocation failed")
+    try:
+        out = {"status": L.orc_status(r)}
+        for name, idx in ITEMS.items():
+            dt, w = _SHAPES[name]
+            n = L.orc_count(r, idx)
+            p = L.orc_data(r, idx)
+            if n == 0 or not p:
+                a = np.zeros((0, w) if w > 1 else (0,), dtype=dt)
+            else:
+                nbytes = int(n) * w * np.dtype(dt).itemsize
+                buf = (ctypes.c_char * nbytes).from_address(p)
+                a = np.frombuffer(buf, dtype=dt).copy()
+                a = a.reshape(int(n), w) if w > 1 else a
+            out[name] = a
+        return out
+    finally:
+        L.orc_free(r)
+
+
+def fit(X, Y, Z, kind, det):
+    """Broken-line fit of one hit tuple given in path order (float64 arrays).
+
+    kind[i] = 0 barrel, 1 disk.  Returns (params[5], cov[15], chi2[2], kref).
+    """
+    L = lib()
+    cfg = make_config(det)
+    X = np.ascontiguousarray(X, np.float64)
+    Y = np.ascontiguousarray(Y, np.float64)
+    Z = np.ascontiguousarray(Z, np.float64)
+    K = np.ascontiguousarray(kind, np.int32)
+    p = np.zeros(5); cv = np.zeros(15); ch = np.zeros(2); kr = np.zeros(1)
+    rc = L.orc_fit(ctypes.byref(cfg), int(X.shape[0]), _ptr(X), _ptr(Y), _ptr(Z),
+                   _ptr(K), _ptr(p), _ptr(cv), _ptr(ch), _ptr(kr))
+    if rc != 0:
+        raise ValueError("oracle fit failed (%d)" % rc)
+    return p, cv, ch, float(kr[0])
+
+
+def doublet_ok(det, pi, po):
+    cfg = make_config(det)
+    return bool(lib().orc_doublet_ok(ctypes.byref(cfg), *map(float, pi), *map(float, po)))
+
+
+def link_ok(det, pa, pb, pc):
+    cfg = make_config(det)
+    return bool(lib().orc_link_ok(ctypes.byref(cfg), *map(float, pa), *map(float, pb),
+                                  *map(float, pc)))
+
+
+def link_terms(det, pa, pb, pc):
+    cfg = make_config(det)
+    out = np.zeros(5)
+    lib().orc_link_terms(ctypes.byref(cfg), *map(float, pa), *map(float, pb),
+                         *map(float, pc), _ptr(out))
+    return out
+
+
+def unpack_cov(c15):
+    """5x5 symmetric matrix from the packed lower triangle."""
+    m = np.zeros((5, 5))
+    k = 0
+    for a in range(5):
+        for b in range(a + 1):
+            m[a, b] = m[b, a] = c15[k]
+            k += 1
+    return m
+
+
+def canonical(tuples):
+    """Sort rows lexicographically (canonical order of a set of tuples)."""
+    t = np.asarray(tuples)
+    if t.shape[0] == 0:
+        return t
+    keys = tuple(t[:, i] for i in range(t.shape[1] - 1, -1, -1))
+    return t[np.lexsort(keys)]
