@@ -1,0 +1,204 @@
+/*
+ * pxt -- pixel-track reconstruction core on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libpxt.so.  The library implements the Tracks module of the
+ * heterogeneous pixel reconstruction described in "Porting CMS Heterogeneous
+ * Pixel Reconstruction to Kokkos" (arXiv:2104.06573), Sec. 2: from the 3-D
+ * pixel hits of an event it forms hit n-tuplets and fits each one to obtain
+ * track parameters.  The steps run on the GPU in hand-written HIP kernels:
+ *
+ *   per-layer phi binning of the hits (counting sort),
+ *   doublets: hit pairs on allowed layer pairs passing geometric cuts,
+ *   cellular-automaton links between doublets that share a hit,
+ *   n-tuplets: every root-to-leaf path of the link graph with 3..8 hits,
+ *   duplicate cleaning: each doublet keeps only its best n-tuplet,
+ *   broken-line helix fit of every surviving n-tuplet.
+ *
+ * The paper states only what the module produces (n-tuplets from hits, and
+ * their fitted track parameters); the cut definitions, cleaning rule and fit
+ * formulation implemented here are the readings documented with the
+ * library.  The paper's performance lessons are built in: all device memory
+ * is allocated once per context (its memory-pool result, Sec. 5), arenas are
+ * never default-initialised (its View-initialisation result, Sec. 4.2), and
+ * many events of uneven size go through one launch sequence (its
+ * concurrent-events result, Sec. 5).
+ *
+ * Conventions
+ *  - Every function returns a pxt_status (0 = PXT_OK).  No exception or
+ *    abort crosses the ABI.  pxt_last_error() gives a message.
+ *  - Calls that take a stream are asynchronous on that HIP stream
+ *    (hipStream_t passed as void*; NULL = the null stream).  Their return
+ *    code covers argument validation and launch only.  Conditions found on
+ *    the device (capacity overflow, a path longer than 8 hits) are written
+ *    to pxt_counts.status together with the required sizes; read it after
+ *    synchronising the stream.  On such a status every output of that call
+ *    is invalid (never silently truncated): grow the capacities and retry.
+ *  - Units: cm, GeV.  The field is along +z.
+ *  - A context is used by one host thread at a time.  Calls on one context
+ *    must be ordered on one stream.
+ */
+#ifndef PXT_H
+#define PXT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PXT_ABI_VERSION 1
+
+#define PXT_MAX_LAYERS 16
+#define PXT_MAX_PAIRS 32
+#define PXT_MAX_TUPLE_HITS 8
+#define PXT_PAD 0xffffffffu
+
+typedef enum pxt_status {
+  PXT_OK = 0,
+  PXT_ERR_INVALID_ARG = 1, /* null pointer, size or config out of range   */
+  PXT_ERR_CAPACITY = 2,    /* a capacity was exceeded; see required[]     */
+  PXT_ERR_HIP = 3,         /* a HIP runtime call failed                   */
+  PXT_ERR_OOM = 4,         /* device allocation failed at create          */
+  PXT_ERR_BUSY = 5,        /* server queue full / no free slot            */
+  PXT_ERR_PATH = 6,        /* a link-graph path longer than 8 hits        */
+  PXT_ERR_NOT_READY = 7    /* pxt_poll: result not complete yet           */
+} pxt_status;
+
+enum { PXT_LAYER_BARREL = 0, PXT_LAYER_DISK = 1 };
+
+/* Geometry, cuts, fit constants, capacities and tuning.
+ * Physics fields define the result; tuning fields never change it. */
+typedef struct pxt_config {
+  /* --- physics -------------------------------------------------------- */
+  double c_kappa;                    /* curvature [1/cm] = c_kappa / pT [GeV] */
+  int32_t n_layers;                  /* layer ids are 0..n_layers-1          */
+  int32_t layer_kind[PXT_MAX_LAYERS];/* PXT_LAYER_BARREL / PXT_LAYER_DISK    */
+  int32_t n_pairs;                   /* allowed (inner, outer) layer pairs   */
+  int32_t pair_inner[PXT_MAX_PAIRS];
+  int32_t pair_outer[PXT_MAX_PAIRS];
+  double kmax;      /* doublet/link curvature cut [1/cm]                      */
+  double z0max;     /* doublet longitudinal impact cut [cm]                   */
+  double arz;       /* link r-z alignment cut (sine of the turning angle)     */
+  double d0max;     /* link transverse impact cut [cm]                        */
+  double sigma_u;   /* r-phi resolution [cm]                                  */
+  double sigma_z;   /* barrel z resolution [cm]                               */
+  double sigma_r;   /* disk r resolution [cm]                                 */
+  double x_over_x0; /* material per layer at normal incidence [X0]           */
+  double pt_max;    /* momentum cap of the scattering estimate [GeV]          */
+  /* --- capacities (summed over one call's batch) ---------------------- */
+  uint32_t max_events;
+  uint32_t max_hits;
+  uint32_t max_doublets;
+  uint32_t max_link_words;  /* 64-bit link-mask words, about one per doublet */
+  uint32_t max_tuples;      /* raw n-tuplets before cleaning               */
+  /* --- tuning ------------------------------------------------------------ */
+  int32_t phi_bins;         /* phi bins per layer, 16..4096                */
+  int32_t block_size;       /* threads per block of the per-item kernels   */
+  double pt_fp64;           /* fit tuples with pT_ref above this in FP64   */
+} pxt_config;
+
+/* One call's input: a ragged batch of events in structure-of-arrays form.
+ * x, y, z, layer are DEVICE pointers with event_offsets[n_events] entries;
+ * event e owns [event_offsets[e], event_offsets[e+1]).  event_offsets is a
+ * HOST pointer (non-decreasing, starting at 0).  Hits whose layer id is
+ * outside 0..n_layers-1 take part in nothing. */
+typedef struct pxt_hits {
+  uint32_t n_events;
+  const uint32_t* event_offsets; /* host, [n_events + 1]            */
+  const float* x;                /* device, [n_hits]                */
+  const float* y;
+  const float* z;
+  const int16_t* layer;          /* device, [n_hits]                */
+  const int16_t* module;         /* device or NULL; not used        */
+} pxt_hits;
+
+/* Device-written summary of one call.  required[] holds the sizes a retry
+ * needs when status == PXT_ERR_CAPACITY:
+ *   required[0] doublets, [1] link-mask words, [2] raw n-tuplets,
+ *   [3] output tracks. */
+typedef struct pxt_counts {
+  int32_t status;
+  uint32_t n_tracks;
+  uint32_t n_doublets;
+  uint32_t n_links;
+  uint32_t n_raw_tuples;
+  uint32_t n_fp64;          /* tracks fitted on the FP64 path              */
+  uint32_t n_hits_binned;   /* hits with a valid layer id                  */
+  uint32_t reserved;
+  uint64_t required[4];
+} pxt_counts;
+
+/* Caller-owned DEVICE output buffers, each with room for `capacity` tracks.
+ * Tracks come out in unspecified order.  hit_idx holds event-local
+ * input-order hit indices in path order (increasing radius), padded with
+ * PXT_PAD.  params = (phi0, d0, q/pT, cot theta, z0) at the point of closest
+ * approach to the transverse origin; d0 > 0 when the origin is left of the
+ * direction of motion.  cov = packed lower triangle of the 5x5 covariance
+ * (row-major: (0,0),(1,0),(1,1),(2,0),...).  chi2 = (transverse, long.).
+ * flags bit 0: fitted on the FP64 path.  per_event_tracks[e] receives the
+ * number of tracks of event e.  counts receives the summary. */
+typedef struct pxt_tracks {
+  uint32_t capacity;
+  uint32_t* hit_idx;          /* [capacity][8]  */
+  uint8_t* n_hits;            /* [capacity]     */
+  uint32_t* event_id;         /* [capacity]     */
+  float* params;              /* [capacity][5]  */
+  float* cov;                 /* [capacity][15] */
+  float* chi2;                /* [capacity][2]  */
+  uint8_t* flags;             /* [capacity]     */
+  uint32_t* per_event_tracks; /* [n_events]     */
+  pxt_counts* counts;         /* [1]            */
+} pxt_tracks;
+
+typedef struct pxt_ctx pxt_ctx;
+
+/* Version of this ABI (PXT_ABI_VERSION). */
+int pxt_abi_version(void);
+
+/* Static message for a status code. */
+const char* pxt_status_str(int status);
+
+/* Message of the last failing call on ctx (or of the last failing create
+ * on this thread when ctx is NULL).  Valid until the next call. */
+const char* pxt_last_error(const pxt_ctx* ctx);
+
+/* Fill *cfg with the defaults of the tuning and capacity fields (physics
+ * fields zeroed).  Returns PXT_ERR_INVALID_ARG if cfg is NULL. */
+int pxt_config_defaults(pxt_config* cfg);
+
+/* Create a context on HIP device `hip_device`: validates cfg and allocates
+ * every device arena once from its capacities (no allocation happens per
+ * call afterwards).  *out receives the context.  Errors:
+ * PXT_ERR_INVALID_ARG (bad config), PXT_ERR_OOM, PXT_ERR_HIP. */
+int pxt_create(const pxt_config* cfg, int hip_device, pxt_ctx** out);
+
+/* Free the context and its arenas (synchronises its device first). */
+void pxt_destroy(pxt_ctx* ctx);
+
+/* Run the whole path on a batch of events (n_events == 1 is the plain
+ * one-event path).  Asynchronous on `hip_stream`; the host reads only
+ * in->event_offsets, which may be reused as soon as the call returns.
+ * Errors returned directly: PXT_ERR_INVALID_ARG (null pointers, n_events
+ * above max_events, more hits than max_hits, decreasing offsets),
+ * PXT_ERR_HIP.  Device-side conditions go to out->counts->status. */
+int pxt_reconstruct(pxt_ctx* ctx, const pxt_hits* in, pxt_tracks* out,
+                    void* hip_stream);
+
+/* Debug dumps of the last pxt_reconstruct on ctx, in a form the tests can
+ * put in canonical order.  Synchronises `hip_stream`.  Rows of uint32:
+ *   PXT_DUMP_DOUBLETS:  (event, inner hit, outer hit)        3 words
+ *   PXT_DUMP_LINKS:     (event, hit a, hit b, hit c)         4 words
+ *   PXT_DUMP_RAW:       (event, 8 padded hits)               9 words
+ * with event-local input-order hit indices.  dst is HOST memory of `cap`
+ * rows; *count receives the number of rows that exist (rows beyond cap are
+ * not written; call again with a larger buffer).
+ * Errors: PXT_ERR_INVALID_ARG, PXT_ERR_HIP. */
+enum { PXT_DUMP_DOUBLETS = 0, PXT_DUMP_LINKS = 1, PXT_DUMP_RAW = 2 };
+int pxt_debug_dump(pxt_ctx* ctx, int what, uint32_t* dst, uint64_t cap,
+                   uint64_t* count, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PXT_H */

@@ -1,0 +1,290 @@
+"""Python binding of libpxt, the MI355X pixel-track reconstruction core.
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of libpxt.so (built from csrc/ by ``build.py``).  PyTorch provides
+device memory and the HIP stream; nothing is computed with it.  If the
+library is missing or no GPU is present the calls raise -- there is no CPU
+fallback.
+
+    import eventgen, paper_2104_06573_amd as pxt
+    rec = pxt.Reconstructor(eventgen.DETECTOR, max_events=1, max_hits=40000)
+    ev = eventgen.generate("pu50", 1)
+    out = rec.run_numpy([ev])          # uploads, runs, syncs
+    out.hit_idx, out.params, out.cov, out.chi2, out.counts
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpxt.so")
+
+MAX_LAYERS = 16
+MAX_PAIRS = 32
+PAD = 0xFFFFFFFF
+
+OK, ERR_INVALID_ARG, ERR_CAPACITY, ERR_HIP, ERR_OOM, ERR_BUSY, ERR_PATH, ERR_NOT_READY = range(8)
+DUMP_DOUBLETS, DUMP_LINKS, DUMP_RAW = 0, 1, 2
+
+# every symbol include/pxt.h declares
+EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_defaults",
+           "pxt_create", "pxt_destroy", "pxt_reconstruct", "pxt_debug_dump")
+
+
+class PxtConfig(ctypes.Structure):
+    _fields_ = [
+        ("c_kappa", ctypes.c_double),
+        ("n_layers", ctypes.c_int32),
+        ("layer_kind", ctypes.c_int32 * MAX_LAYERS),
+        ("n_pairs", ctypes.c_int32),
+        ("pair_inner", ctypes.c_int32 * MAX_PAIRS),
+        ("pair_outer", ctypes.c_int32 * MAX_PAIRS),
+        ("kmax", ctypes.c_double), ("z0max", ctypes.c_double),
+        ("arz", ctypes.c_double), ("d0max", ctypes.c_double),
+        ("sigma_u", ctypes.c_double), ("sigma_z", ctypes.c_double),
+        ("sigma_r", ctypes.c_double), ("x_over_x0", ctypes.c_double),
+        ("pt_max", ctypes.c_double),
+        ("max_events", ctypes.c_uint32), ("max_hits", ctypes.c_uint32),
+        ("max_doublets", ctypes.c_uint32), ("max_link_words", ctypes.c_uint32),
+        ("max_tuples", ctypes.c_uint32),
+        ("phi_bins", ctypes.c_int32), ("block_size", ctypes.c_int32),
+        ("pt_fp64", ctypes.c_double),
+    ]
+
+
+class PxtHits(ctypes.Structure):
+    _fields_ = [
+        ("n_events", ctypes.c_uint32),
+        ("event_offsets", ctypes.c_void_p),
+        ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+        ("layer", ctypes.c_void_p), ("module", ctypes.c_void_p),
+    ]
+
+
+class PxtCounts(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("n_tracks", ctypes.c_uint32),
+        ("n_doublets", ctypes.c_uint32), ("n_links", ctypes.c_uint32),
+        ("n_raw_tuples", ctypes.c_uint32), ("n_fp64", ctypes.c_uint32),
+        ("n_hits_binned", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("required", ctypes.c_uint64 * 4),
+    ]
+
+
+class PxtTracks(ctypes.Structure):
+    _fields_ = [
+        ("capacity", ctypes.c_uint32),
+        ("hit_idx", ctypes.c_void_p), ("n_hits", ctypes.c_void_p),
+        ("event_id", ctypes.c_void_p), ("params", ctypes.c_void_p),
+        ("cov", ctypes.c_void_p), ("chi2", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p), ("per_event_tracks", ctypes.c_void_p),
+        ("counts", ctypes.c_void_p),
+    ]
+
+
+COUNTS_WORDS = ctypes.sizeof(PxtCounts) // 4
+
+_lib = None
+
+
+class PxtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("pxt status %d: %s" % (status, msg))
+        self.status = status
+
+
+def lib():
+    """Load libpxt.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpxt.so not built: run python -m paper_2104_06573_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pxt_abi_version.restype = ctypes.c_int
+        L.pxt_status_str.restype = ctypes.c_char_p
+        L.pxt_status_str.argtypes = [ctypes.c_int]
+        L.pxt_last_error.restype = ctypes.c_char_p
+        L.pxt_last_error.argtypes = [ctypes.c_void_p]
+        L.pxt_config_defaults.argtypes = [ctypes.POINTER(PxtConfig)]
+        L.pxt_create.argtypes = [ctypes.POINTER(PxtConfig), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_void_p)]
+        L.pxt_destroy.argtypes = [ctypes.c_void_p]
+        L.pxt_destroy.restype = None
+        L.pxt_reconstruct.argtypes = [ctypes.c_void_p, ctypes.POINTER(PxtHits),
+                                      ctypes.POINTER(PxtTracks), ctypes.c_void_p]
+        L.pxt_debug_dump.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
+                max_link_words=None, max_tuples=1 << 19, phi_bins=256, block_size=256,
+                pt_fp64=20.0):
+    """pxt_config from a detector dictionary (eventgen.DETECTOR layout)."""
+    c = PxtConfig()
+    if lib().pxt_config_defaults(ctypes.byref(c)) != OK:
+        raise PxtError(ERR_INVALID_ARG, "pxt_config_defaults")
+    c.c_kappa = det["c_kappa"]
+    layers = sorted(det["layers"], key=lambda l: l["id"])
+    c.n_layers = len(layers)
+    for l in layers:
+        c.layer_kind[l["id"]] = int(l["kind"])
+    c.n_pairs = len(det["pairs"])
+    for i, (a, b) in enumerate(det["pairs"]):
+        c.pair_inner[i] = a
+        c.pair_outer[i] = b
+    cu, f = det["cuts"], det["fit"]
+    c.kmax, c.z0max, c.arz, c.d0max = cu["kmax"], cu["z0max"], cu["arz"], cu["d0max"]
+    c.sigma_u, c.sigma_z, c.sigma_r = f["sigma_u"], f["sigma_z"], f["sigma_r"]
+    c.x_over_x0, c.pt_max = f["x_over_x0"], f["pt_max"]
+    c.max_events = max_events
+    c.max_hits = max_hits
+    c.max_doublets = max_doublets
+    c.max_link_words = max_link_words if max_link_words is not None else max_doublets
+    c.max_tuples = max_tuples
+    c.phi_bins = phi_bins
+    c.block_size = block_size
+    c.pt_fp64 = pt_fp64
+    return c
+
+
+class Result:
+    """Outputs of one call (torch device tensors, sliced to n_tracks)."""
+
+    def __init__(self, counts, per_event, hit_idx, n_hits, event_id, params, cov, chi2, flags):
+        self.counts = counts
+        self.per_event_tracks = per_event
+        self.hit_idx = hit_idx
+        self.n_hits = n_hits
+        self.event_id = event_id
+        self.params = params
+        self.cov = cov
+        self.chi2 = chi2
+        self.flags = flags
+
+    def numpy(self):
+        import torch  # noqa: F401
+        return {k: getattr(self, k).cpu().numpy() for k in
+                ("hit_idx", "n_hits", "event_id", "params", "cov", "chi2", "flags",
+                 "per_event_tracks")}
+
+
+def counts_dict(words):
+    c = PxtCounts.from_buffer_copy(np.ascontiguousarray(words, np.uint32).tobytes())
+    return dict(status=c.status, n_tracks=c.n_tracks, n_doublets=c.n_doublets,
+                n_links=c.n_links, n_raw_tuples=c.n_raw_tuples, n_fp64=c.n_fp64,
+                n_hits_binned=c.n_hits_binned, required=list(c.required))
+
+
+class Reconstructor:
+    """One libpxt context on one GPU with its output buffers.
+
+    max_tracks is the capacity of the output buffers (caller-owned in the C
+    ABI; owned by this object here).
+    """
+
+    def __init__(self, det, device=0, max_tracks=1 << 18, **caps):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.cfg = make_config(det, **caps)
+        h = ctypes.c_void_p()
+        st = lib().pxt_create(ctypes.byref(self.cfg), device, ctypes.byref(h))
+        if st != OK:
+            raise PxtError(st, lib().pxt_last_error(None).decode())
+        self.h = h
+        self.max_tracks = int(max_tracks)
+        E = int(self.cfg.max_events)
+        T = self.max_tracks
+        dev = self.device
+        self.o_hit_idx = torch.empty((T, 8), dtype=torch.int32, device=dev)
+        self.o_n_hits = torch.empty(T, dtype=torch.uint8, device=dev)
+        self.o_event_id = torch.empty(T, dtype=torch.int32, device=dev)
+        self.o_params = torch.empty((T, 5), dtype=torch.float32, device=dev)
+        self.o_cov = torch.empty((T, 15), dtype=torch.float32, device=dev)
+        self.o_chi2 = torch.empty((T, 2), dtype=torch.float32, device=dev)
+        self.o_flags = torch.empty(T, dtype=torch.uint8, device=dev)
+        self.o_per_event = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+        self.o_counts = torch.empty(COUNTS_WORDS, dtype=torch.int32, device=dev)
+        self._tracks = PxtTracks(
+            T, self.o_hit_idx.data_ptr(), self.o_n_hits.data_ptr(), self.o_event_id.data_ptr(),
+            self.o_params.data_ptr(), self.o_cov.data_ptr(), self.o_chi2.data_ptr(),
+            self.o_flags.data_ptr(), self.o_per_event.data_ptr(), self.o_counts.data_ptr())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pxt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self, stream):
+        if stream is None:
+            stream = self.torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def launch(self, x, y, z, layer, offsets, stream=None):
+        """Enqueue one call; x, y, z (float32), layer (int16) are device
+        tensors, offsets a host uint32 array of n_events + 1 entries."""
+        offs = np.ascontiguousarray(offsets, dtype=np.uint32)
+        self._offs = offs
+        hits = PxtHits(offs.shape[0] - 1, offs.ctypes.data, x.data_ptr(), y.data_ptr(),
+                       z.data_ptr(), layer.data_ptr(), None)
+        st = lib().pxt_reconstruct(self.h, ctypes.byref(hits), ctypes.byref(self._tracks),
+                                   self._stream(stream))
+        if st != OK:
+            raise PxtError(st, lib().pxt_last_error(self.h).decode())
+        return offs.shape[0] - 1
+
+    def read_counts(self):
+        return counts_dict(self.o_counts.cpu().numpy().view(np.uint32))
+
+    def result(self, n_events, counts=None):
+        counts = counts or self.read_counts()
+        n = counts["n_tracks"] if counts["status"] == OK else 0
+        return Result(counts, self.o_per_event[:n_events], self.o_hit_idx[:n], self.o_n_hits[:n],
+                      self.o_event_id[:n], self.o_params[:n], self.o_cov[:n], self.o_chi2[:n],
+                      self.o_flags[:n])
+
+    def run(self, x, y, z, layer, offsets, stream=None):
+        n_events = self.launch(x, y, z, layer, offsets, stream)
+        self.torch.cuda.synchronize(self.device)
+        return self.result(n_events)
+
+    def upload(self, events):
+        """Concatenate host events (objects with x, y, z, layer arrays) into
+        one ragged batch on the device; returns (x, y, z, layer, offsets)."""
+        t = self.torch
+        dev = self.device
+        offs = np.zeros(len(events) + 1, dtype=np.uint32)
+        offs[1:] = np.cumsum([len(e.x) for e in events])
+        cat = lambda f, dt: t.from_numpy(np.ascontiguousarray(
+            np.concatenate([getattr(e, f) for e in events]) if events else np.zeros(0), dt)).to(dev)
+        return (cat("x", np.float32), cat("y", np.float32), cat("z", np.float32),
+                cat("layer", np.int16), offs)
+
+    def run_numpy(self, events):
+        x, y, z, layer, offs = self.upload(events)
+        return self.run(x, y, z, layer, offs)
+
+    def dump(self, what, stream=None):
+        """Debug dump of the last call (rows of uint32, see pxt.h)."""
+        width = {DUMP_DOUBLETS: 3, DUMP_LINKS: 4, DUMP_RAW: 9}[what]
+        cnt = ctypes.c_uint64(0)
+        st = lib().pxt_debug_dump(self.h, what, None, 0, ctypes.byref(cnt), self._stream(stream))
+        if st != OK:
+            raise PxtError(st, lib().pxt_last_error(self.h).decode())
+        buf = np.zeros((int(cnt.value), width), dtype=np.uint32)
+        st = lib().pxt_debug_dump(self.h, what, buf.ctypes.data, buf.shape[0], ctypes.byref(cnt),
+                                  self._stream(stream))
+        if st != OK:
+            raise PxtError(st, lib().pxt_last_error(self.h).decode())
+        return buf

@@ -1,0 +1,175 @@
+// Device-side types and wavefront primitives shared by the pxt kernels.
+//
+// Everything here targets gfx950 (CDNA4): 64-lane wavefronts, 64-bit ballot
+// masks, LDS for cross-wave exchange.  The whole library is compiled with
+// -ffp-contract=off so that every double-precision cut is evaluated with the
+// rounding of the written expression (no fused multiply-adds), which is what
+// makes the cut decisions reproducible bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pxt.h"
+
+namespace pxt {
+
+constexpr int kMaxLayers = PXT_MAX_LAYERS;
+constexpr int kMaxOuterPerLayer = 8;
+constexpr int kMaxHits = PXT_MAX_TUPLE_HITS;   // hits per n-tuplet
+constexpr int kMaxCells = kMaxHits - 1;        // doublets per n-tuplet
+constexpr uint32_t kPad = PXT_PAD;
+constexpr int kWave = 64;
+constexpr float kPiF = 3.14159265358979f;
+
+// Counters kept in device memory for one call (zeroed by k_clear).
+enum Ctr : int {
+  C_STATUS = 0,      // int32 pxt_status found on the device
+  C_NBINS,           // number of phi bins of the batch (host-known)
+  C_NBINNED,         // hits with a valid layer id
+  C_ND,              // doublets
+  C_NWORDS,          // link-mask words
+  C_NLINKS,          // links
+  C_NTUP,            // raw n-tuplets (append counter; may exceed capacity)
+  C_NSURV,           // n-tuplets surviving the cleaning
+  C_NFP64,           // tuples refitted in FP64
+  C_REQ_D,           // required sizes on overflow
+  C_REQ_W,
+  C_REQ_T,
+  C_REQ_K,
+  C_NCTR
+};
+
+// Physics and tuning constants, passed by value to the kernels.
+struct DevCfg {
+  int n_layers;
+  int nphi;
+  float phi_scale;                          // nphi / (2 pi)
+  float kmax_f;
+  int layer_kind[kMaxLayers];
+  int n_outer[kMaxLayers];                  // pairs leaving each layer
+  int outer[kMaxLayers][kMaxOuterPerLayer]; // their outer layers, table order
+  double kmax, z0max, arz, d0max;
+  double c_kappa, sigma_u, sigma_z, sigma_r, x_over_x0, pt_max, pt_fp64;
+  uint32_t cap_doublets, cap_words, cap_tuples;
+};
+
+// Device arenas of one context.
+struct Ws {
+  uint32_t* ctr;          // [C_NCTR]
+  uint32_t* evt_off;      // [E + 1]
+  uint32_t* keys;         // [H]   bin key of each input hit
+  uint32_t* bin_cnt;      // [nbins + 1]
+  uint32_t* bin_off;      // [nbins + 1]
+  uint32_t* rmax;         // [E * L] largest hit radius per layer (float bits)
+  // binned hits
+  float* bx;
+  float* by;
+  float* bz;
+  double* br;             // transverse radius in FP64
+  float* bphi;
+  uint32_t* bidx;         // event-local input index
+  uint32_t* bevt;         // event id
+  uint8_t* blay;          // layer id
+  // doublets
+  uint32_t* dcnt;         // [H + 1] doublets per inner hit
+  uint32_t* cell_off;     // [H + 1] first doublet of each inner hit
+  uint32_t* cin;          // [D] inner binned hit
+  uint32_t* cout;         // [D] outer binned hit
+  uint32_t* mw;           // [D + 1] link-mask words per doublet
+  uint32_t* moff;         // [D + 1]
+  uint64_t* masks;        // [W]
+  uint8_t* has_inner;     // [D]
+  uint32_t* nout;         // [D] outer links per doublet
+  // n-tuplets
+  uint32_t* thit;         // [8][T] binned hits (slot-major)
+  uint32_t* tcell;        // [7][T] doublets
+  uint8_t* tn;            // [T] hits
+  double* tscore;         // [T]
+  // cleaning
+  uint32_t* ccnt;         // [D + 1] tuples through each doublet
+  uint32_t* coff;         // [D + 1]
+  uint32_t* clist;        // [7 T]
+  uint32_t* best;         // [D]
+  uint32_t* surv;         // [T]
+  uint32_t* fp64_list;    // [T]
+  // scan scratch
+  uint32_t* block_sums;   // [kScanBlocks + 1]
+};
+
+constexpr int kScanBlocks = 512;
+constexpr int kScanThreads = 256;
+
+// ------------------------------------------------------------------------
+// wavefront primitives
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive prefix sum across the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t o = __shfl_up(v, d, kWave);
+    if (lane >= (uint32_t)d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Exclusive block-wide prefix sum; `tot` receives the block total.
+// lds must hold blockDim.x / 64 + 1 words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds,
+                                                    uint32_t& tot) {
+  const uint32_t lane = lane_id();
+  const uint32_t wid = threadIdx.x / kWave;
+  const uint32_t nw = blockDim.x / kWave;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == kWave - 1) lds[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t w = lane < nw ? lds[lane] : 0u;
+    uint32_t wi = wave_incl_scan(w);
+    if (lane < nw) lds[lane] = wi - w;
+    if (lane == nw - 1) lds[nw] = wi;
+  }
+  __syncthreads();
+  uint32_t res = lds[wid] + inc - v;
+  tot = lds[nw];
+  __syncthreads();
+  return res;
+}
+
+// Append `want` (0 or 1) items per lane to a global counter with one atomic
+// per wavefront; returns this lane's slot (valid when want != 0).
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
+  const uint64_t m = __ballot(want);
+  if (m == 0) return 0;
+  const uint32_t leader = __ffsll((unsigned long long)m) - 1;
+  const uint32_t below = __popcll(m & ((1ull << lane_id()) - 1ull));
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = __shfl(base, leader, kWave);
+  return base + below;
+}
+
+__device__ __forceinline__ void set_status(uint32_t* ctr, int st) {
+  atomicCAS(&ctr[C_STATUS], 0u, (uint32_t)st);
+}
+
+__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t n,
+                                                    uint32_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace pxt

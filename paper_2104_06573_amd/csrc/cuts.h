@@ -1,0 +1,142 @@
+// Geometric cuts of the doublet and link steps, in FP64 on FP32 hits.
+//
+// The paper names the steps (hit doublets, cellular-automaton linking into
+// n-tuplets, Sec. 2) but no cut; the cuts below are this library's reading:
+//
+//  doublet (inner i, outer o):
+//   D1  r_o > r_i
+//   D2  the r-z line through both hits meets r = 0 within |z| <= z0max:
+//       |z_i (r_o - r_i) - r_i (z_o - z_i)| <= z0max (r_o - r_i)
+//   D3  the circle through the origin and both hits has curvature <= kmax:
+//       2 |x_i y_o - y_i x_o| <= kmax r_i r_o |p_o - p_i|
+//   D4  x_i x_o + y_i y_o > 0
+//  link (hits a, b, c of doublets (a,b), (b,c)):
+//   L1  r-z alignment: |dr_ab dz_bc - dz_ab dr_bc| <= arz l_ab l_bc
+//   L2  Menger curvature: 2 |(b-a) x (c-a)| <= kmax |ab| |bc| |ac|
+//   L3  distance of the origin from the circle through a, b, c <= d0max,
+//       evaluated as | |a|^2 + 2 a.o | / (|C| + R) with o = C - a (the same
+//       quantity as ||C| - R|, free of the cancellation of two large radii);
+//       for exactly collinear points, the distance from their line.
+//
+// Every operation is written in the order the decision is defined in, and
+// the library is built without FP contraction, so each comparison sees the
+// correctly rounded IEEE double of the written expression.
+#pragma once
+
+#include "common.h"
+
+namespace pxt {
+
+struct HitD {
+  double x, y, z, r;
+};
+
+__device__ __forceinline__ HitD load_hit(const Ws& w, uint32_t i) {
+  HitD h;
+  h.x = (double)w.bx[i];
+  h.y = (double)w.by[i];
+  h.z = (double)w.bz[i];
+  h.r = w.br[i];
+  return h;
+}
+
+__device__ __forceinline__ bool doublet_ok(const DevCfg& c, const HitD& i,
+                                           const HitD& o) {
+  if (!(o.r > i.r)) return false;
+  const double dr = o.r - i.r;
+  const double l2 = fabs(i.z * dr - i.r * (o.z - i.z));
+  if (!(l2 <= c.z0max * dr)) return false;
+  const double cr = i.x * o.y - i.y * o.x;
+  const double dx = o.x - i.x, dy = o.y - i.y;
+  const double chord = sqrt(dx * dx + dy * dy);
+  if (!(2.0 * fabs(cr) <= c.kmax * i.r * o.r * chord)) return false;
+  return i.x * o.x + i.y * o.y > 0.0;
+}
+
+// Terms of the link cuts: t0 = |r-z cross|, t1 = arz l_ab l_bc,
+// t2 = 2 |cross|, t3 = kmax |ab||bc||ac|, d0 = transverse impact.
+struct LinkTerms {
+  double t0, t1, t2, t3, d0;
+};
+
+__device__ __forceinline__ LinkTerms link_terms(const DevCfg& c, const HitD& a,
+                                                const HitD& b, const HitD& h) {
+  LinkTerms t;
+  const double dra = b.r - a.r, dza = b.z - a.z;
+  const double drb = h.r - b.r, dzb = h.z - b.z;
+  t.t0 = fabs(dra * dzb - dza * drb);
+  const double lab = sqrt(dra * dra + dza * dza);
+  const double lbc = sqrt(drb * drb + dzb * dzb);
+  t.t1 = c.arz * lab * lbc;
+  const double ux = b.x - a.x, uy = b.y - a.y;
+  const double vx = h.x - a.x, vy = h.y - a.y;
+  const double wx = h.x - b.x, wy = h.y - b.y;
+  const double cr = ux * vy - uy * vx;
+  const double nab = sqrt(ux * ux + uy * uy);
+  const double nac = sqrt(vx * vx + vy * vy);
+  const double nbc = sqrt(wx * wx + wy * wy);
+  t.t2 = 2.0 * fabs(cr);
+  t.t3 = c.kmax * nab * nbc * nac;
+  const double D = 2.0 * cr;
+  if (D == 0.0) {
+    t.d0 = fabs(a.x * vy - a.y * vx) / nac;
+  } else {
+    const double uu = ux * ux + uy * uy, vv = vx * vx + vy * vy;
+    const double ox = (vy * uu - uy * vv) / D;
+    const double oy = (ux * vv - vx * uu) / D;
+    const double R = sqrt(ox * ox + oy * oy);
+    const double cx = a.x + ox, cy = a.y + oy;
+    const double dc = sqrt(cx * cx + cy * cy);
+    const double aa = a.x * a.x + a.y * a.y;
+    const double ao = a.x * ox + a.y * oy;
+    t.d0 = fabs(aa + 2.0 * ao) / (dc + R);
+  }
+  return t;
+}
+
+__device__ __forceinline__ bool link_ok(const DevCfg& c, const HitD& a,
+                                        const HitD& b, const HitD& h) {
+  // L1 first: the terms are the same expressions as in link_terms, only
+  // evaluated lazily, so every decision is unchanged
+  const double dra = b.r - a.r, dza = b.z - a.z;
+  const double drb = h.r - b.r, dzb = h.z - b.z;
+  const double t0 = fabs(dra * dzb - dza * drb);
+  const double lab = sqrt(dra * dra + dza * dza);
+  const double lbc = sqrt(drb * drb + dzb * dzb);
+  if (!(t0 <= c.arz * lab * lbc)) return false;
+  const double ux = b.x - a.x, uy = b.y - a.y;
+  const double vx = h.x - a.x, vy = h.y - a.y;
+  const double wx = h.x - b.x, wy = h.y - b.y;
+  const double cr = ux * vy - uy * vx;
+  const double nab = sqrt(ux * ux + uy * uy);
+  const double nac = sqrt(vx * vx + vy * vy);
+  const double nbc = sqrt(wx * wx + wy * wy);
+  if (!(2.0 * fabs(cr) <= c.kmax * nab * nbc * nac)) return false;
+  const double D = 2.0 * cr;
+  double d0;
+  if (D == 0.0) {
+    d0 = fabs(a.x * vy - a.y * vx) / nac;
+  } else {
+    const double uu = ux * ux + uy * uy, vv = vx * vx + vy * vy;
+    const double ox = (vy * uu - uy * vv) / D;
+    const double oy = (ux * vv - vx * uu) / D;
+    const double R = sqrt(ox * ox + oy * oy);
+    const double cx = a.x + ox, cy = a.y + oy;
+    const double dc = sqrt(cx * cx + cy * cy);
+    const double aa = a.x * a.x + a.y * a.y;
+    const double ao = a.x * ox + a.y * oy;
+    d0 = fabs(aa + 2.0 * ao) / (dc + R);
+  }
+  return d0 <= c.d0max;
+}
+
+// Cleaning score of one consecutive hit triple.
+__device__ __forceinline__ double triple_score(const DevCfg& c, const HitD& a,
+                                               const HitD& b, const HitD& h) {
+  const LinkTerms t = link_terms(c, a, b, h);
+  const double q1 = t.t0 / t.t1;
+  const double q2 = t.d0 / c.d0max;
+  return q1 * q1 + q2 * q2;
+}
+
+}  // namespace pxt

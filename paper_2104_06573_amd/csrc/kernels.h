@@ -1,0 +1,565 @@
+// Pipeline kernels: binning, doublets, links, n-tuplets, cleaning, fit.
+//
+// Every kernel works on a ragged batch of events at once: hits of all
+// events are flattened, and each per-item kernel recovers its event from
+// the item (binary search of the event offsets for input hits, a stored id
+// for binned hits).  One event is simply a batch of one.  Kernels whose work
+// size is only known on the device (doublets, cells, tuples) take it from
+// device memory and loop grid-stride, so a launch sequence never waits for
+// the host and can be captured in a HIP graph.
+#pragma once
+
+#include "common.h"
+#include "cuts.h"
+#include "fit.h"
+
+namespace pxt {
+
+struct OutPtrs {
+  uint32_t capacity;
+  uint32_t* hit_idx;
+  uint8_t* n_hits;
+  uint32_t* event_id;
+  float* params;
+  float* cov;
+  float* chi2;
+  uint8_t* flags;
+  uint32_t* per_event_tracks;
+  pxt_counts* counts;
+};
+
+// ------------------------------------------------------------------ clear
+
+__global__ void k_clear(Ws w, uint32_t n_events, uint32_t n_layers, uint32_t nbins,
+                        uint32_t* per_event_tracks) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = tid; i < nbins + 1; i += stride) w.bin_cnt[i] = 0;
+  for (uint32_t i = tid; i < n_events * n_layers; i += stride) w.rmax[i] = 0;
+  for (uint32_t i = tid; i < n_events; i += stride) per_event_tracks[i] = 0;
+  if (tid < C_NCTR) w.ctr[tid] = tid == C_NBINS ? nbins : 0u;
+}
+
+// ------------------------------------------------------- binning (prep) --
+
+__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ x,
+                                              const float* __restrict__ y,
+                                              const int16_t* __restrict__ layer,
+                                              uint32_t n_hits, uint32_t n_events,
+                                              Ws w, DevCfg c) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_hits) return;
+  const uint32_t e = upper_bound_u32(w.evt_off, n_events + 1, g) - 1;
+  const int l = layer[g];
+  if (l < 0 || l >= c.n_layers) {
+    w.keys[g] = kPad;
+    return;
+  }
+  const float xf = x[g], yf = y[g];
+  const float phi = atan2f(yf, xf);
+  int b = (int)((phi + kPiF) * c.phi_scale);
+  b = b < 0 ? 0 : (b >= c.nphi ? c.nphi - 1 : b);
+  const uint32_t key = (e * (uint32_t)c.n_layers + (uint32_t)l) * (uint32_t)c.nphi + (uint32_t)b;
+  w.keys[g] = key;
+  atomicAdd(&w.bin_cnt[key], 1u);
+  const float r = sqrtf(xf * xf + yf * yf);
+  atomicMax(&w.rmax[e * c.n_layers + l], __float_as_uint(r));
+}
+
+__global__ __launch_bounds__(256) void k_fill(const float* __restrict__ x,
+                                              const float* __restrict__ y,
+                                              const float* __restrict__ z,
+                                              const int16_t* __restrict__ layer,
+                                              uint32_t n_hits, uint32_t n_events,
+                                              Ws w) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_hits) return;
+  const uint32_t key = w.keys[g];
+  if (key == kPad) return;
+  const uint32_t e = upper_bound_u32(w.evt_off, n_events + 1, g) - 1;
+  const uint32_t pos = w.bin_off[key] + atomicSub(&w.bin_cnt[key], 1u) - 1u;
+  const float xf = x[g], yf = y[g];
+  w.bx[pos] = xf;
+  w.by[pos] = yf;
+  w.bz[pos] = z[g];
+  const double X = (double)xf, Y = (double)yf;
+  w.br[pos] = sqrt(X * X + Y * Y);
+  w.bphi[pos] = atan2f(yf, xf);
+  w.bidx[pos] = g - w.evt_off[e];
+  w.bevt[pos] = e;
+  w.blay[pos] = (uint8_t)layer[g];
+}
+
+// -------------------------------------------------- device-wide scan ---
+// Exclusive scan of n = *n_dev entries of `in` into `out[0..n]` (out[n] is
+// the total, also stored in *total_dst when non-null).  Three launches:
+// per-chunk sums, a one-block scan of the chunk sums, per-chunk scans.
+
+__device__ __forceinline__ void scan_chunk(uint32_t n, uint32_t& beg, uint32_t& end) {
+  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t per_r = (per + blockDim.x - 1) / blockDim.x * blockDim.x;
+  beg = min(n, blockIdx.x * per_r);
+  end = min(n, beg + per_r);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                               const uint32_t* n_dev,
+                                                               uint32_t* block_sums,
+                                                               const uint32_t* ctr) {
+  if (ctr[C_STATUS]) return;
+  const uint32_t n = *n_dev;
+  uint32_t beg, end;
+  scan_chunk(n, beg, end);
+  uint32_t s = 0;
+  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) s += in[i];
+  s = wave_sum(s);
+  __shared__ uint32_t part[kScanThreads / kWave];
+  if (lane_id() == 0) part[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (uint32_t k = 0; k < blockDim.x / kWave; ++k) t += part[k];
+    block_sums[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* block_sums, uint32_t nblk,
+                                                   const uint32_t* ctr) {
+  if (ctr[C_STATUS]) return;
+  __shared__ uint32_t lds[1024 / kWave + 1];
+  const uint32_t v = threadIdx.x < nblk ? block_sums[threadIdx.x] : 0u;
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan(v, lds, tot);
+  if (threadIdx.x < nblk) block_sums[threadIdx.x] = ex;
+  if (threadIdx.x == 0) block_sums[nblk] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
+                                                             uint32_t* __restrict__ out,
+                                                             const uint32_t* n_dev,
+                                                             const uint32_t* block_sums,
+                                                             uint32_t nblk, uint32_t* total_dst,
+                                                             const uint32_t* ctr) {
+  if (ctr[C_STATUS]) return;
+  const uint32_t n = *n_dev;
+  uint32_t beg, end;
+  scan_chunk(n, beg, end);
+  __shared__ uint32_t lds[kScanThreads / kWave + 1];
+  uint32_t carry = block_sums[blockIdx.x];
+  for (uint32_t base = beg; base < end; base += blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t v = i < end ? in[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, lds, tot);
+    if (i < end) out[i] = carry + ex;
+    carry += tot;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t total = block_sums[nblk];
+    out[n] = total;
+    if (total_dst) *total_dst = total;
+  }
+}
+
+// ------------------------------------------------------------- doublets --
+// One thread per binned inner hit.  For every layer pair leaving its layer,
+// the outer layer's hits are visited only inside a phi window that is a
+// superset of every pair passing D3/D4: a circle through the origin with
+// curvature <= kmax turns by asin(kmax r_o / 2) - asin(kmax r_i / 2) between
+// radii r_i and r_o, which grows with r_o, so the window uses the largest
+// outer radius of the event's layer, plus one guard bin per side.  The cut
+// itself decides, so the window never changes the result.
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c, uint32_t hit_bound) {
+  const uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t nb = ctr[C_NBINNED];
+  if (FILL && w.cell_off[nb] > c.cap_doublets) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      set_status(w.ctr, PXT_ERR_CAPACITY);
+      w.ctr[C_REQ_D] = w.cell_off[nb];
+    }
+    return;
+  }
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nb; g += gridDim.x * blockDim.x) {
+    const int li = w.blay[g];
+    const uint32_t e = w.bevt[g];
+    const HitD hi = load_hit(w, g);
+    const float ri = (float)hi.r;
+    const float phi = w.bphi[g];
+    uint32_t cnt = 0;
+    uint32_t pos = FILL ? w.cell_off[g] : 0u;
+    for (int p = 0; p < c.n_outer[li]; ++p) {
+      const int lo = c.outer[li][p];
+      const float rmo = __uint_as_float(w.rmax[e * c.n_layers + lo]) * 1.000001f;
+      if (!(rmo > ri * 0.999999f)) continue;
+      const uint32_t base = (e * (uint32_t)c.n_layers + (uint32_t)lo) * (uint32_t)c.nphi;
+      const float ao = 0.5f * c.kmax_f * rmo;
+      int blo = 0, bhi = c.nphi - 1;
+      bool full = ao >= 0.70710678f;
+      if (!full) {
+        const float W = asinf(ao) - asinf(0.5f * c.kmax_f * ri);
+        if (!(W >= 0.0f && W < 4.0f && phi >= -4.0f && phi <= 4.0f)) {
+          full = true;  // non-finite input: fall back to the whole layer
+        } else {
+          blo = (int)floorf((phi - W + kPiF) * c.phi_scale) - 1;
+          bhi = (int)floorf((phi + W + kPiF) * c.phi_scale) + 1;
+          full = bhi - blo + 1 >= c.nphi;
+        }
+      }
+      uint32_t seg_b[2], seg_e[2];
+      int nseg;
+      if (full) {
+        seg_b[0] = w.bin_off[base];
+        seg_e[0] = w.bin_off[base + c.nphi];
+        nseg = 1;
+      } else if (blo < 0) {
+        seg_b[0] = w.bin_off[base + blo + c.nphi];
+        seg_e[0] = w.bin_off[base + c.nphi];
+        seg_b[1] = w.bin_off[base];
+        seg_e[1] = w.bin_off[base + bhi + 1];
+        nseg = 2;
+      } else if (bhi >= c.nphi) {
+        seg_b[0] = w.bin_off[base + blo];
+        seg_e[0] = w.bin_off[base + c.nphi];
+        seg_b[1] = w.bin_off[base];
+        seg_e[1] = w.bin_off[base + bhi - c.nphi + 1];
+        nseg = 2;
+      } else {
+        seg_b[0] = w.bin_off[base + blo];
+        seg_e[0] = w.bin_off[base + bhi + 1];
+        nseg = 1;
+      }
+      for (int s = 0; s < nseg; ++s) {
+        for (uint32_t j = seg_b[s]; j < seg_e[s]; ++j) {
+          const HitD ho = load_hit(w, j);
+          if (doublet_ok(c, hi, ho)) {
+            if (FILL) {
+              w.cin[pos] = g;
+              w.cout[pos] = j;
+              const uint32_t deg = w.cell_off[j + 1] - w.cell_off[j];
+              w.mw[pos] = (deg + 63u) >> 6;
+              w.has_inner[pos] = 0;
+              w.ccnt[pos] = 0;
+              ++pos;
+            } else {
+              ++cnt;
+            }
+          }
+        }
+      }
+    }
+    if (!FILL) w.dcnt[g] = cnt;
+  }
+}
+
+// ---------------------------------------------------------------- links --
+// One thread per doublet (a,b).  Its candidate outer neighbours are the
+// doublets leaving hit b: the contiguous range cell_off[b] .. cell_off[b+1]
+// (doublets are stored grouped by inner hit).  The accepted ones are kept as
+// a bit mask over that range, one 64-bit word per 64 candidates, so a single
+// evaluation pass needs no second pass and no atomics.
+
+__global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
+  uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t nd = ctr[C_ND];
+  const uint32_t nwords = w.moff[nd];
+  if (nwords > c.cap_words) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      set_status(ctr, PXT_ERR_CAPACITY);
+      ctr[C_REQ_W] = nwords;
+    }
+    return;
+  }
+  uint32_t links = 0;
+  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
+    const uint32_t a = w.cin[d], b = w.cout[d];
+    const HitD ha = load_hit(w, a), hb = load_hit(w, b);
+    const uint32_t k0 = w.cell_off[b], deg = w.cell_off[b + 1] - k0;
+    const uint32_t mo = w.moff[d];
+    uint32_t nout = 0;
+    for (uint32_t wd = 0; wd * 64u < deg; ++wd) {
+      uint64_t mask = 0;
+      const uint32_t lim = min(64u, deg - wd * 64u);
+      for (uint32_t bit = 0; bit < lim; ++bit) {
+        const uint32_t d2 = k0 + wd * 64u + bit;
+        const HitD hc = load_hit(w, w.cout[d2]);
+        if (link_ok(c, ha, hb, hc)) {
+          mask |= 1ull << bit;
+          w.has_inner[d2] = 1;
+        }
+      }
+      w.masks[mo + wd] = mask;
+      nout += (uint32_t)__popcll(mask);
+    }
+    w.nout[d] = nout;
+    links += nout;
+  }
+  links = wave_sum(links);
+  if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
+}
+
+// ------------------------------------------------------------ n-tuplets --
+// One thread per root doublet (no inner neighbour, at least one outer):
+// iterative depth-first search over the outer-neighbour masks; every path
+// ending at a doublet without outer neighbours is appended as an n-tuplet.
+
+__device__ __forceinline__ void emit_tuple(Ws& w, const DevCfg& c, const uint32_t* path,
+                                           int depth) {
+  const uint32_t t = atomicAdd(&w.ctr[C_NTUP], 1u);
+  if (t >= c.cap_tuples) return;
+  const uint32_t T = c.cap_tuples;
+  const int nh = depth + 2;
+  w.thit[t] = w.cin[path[0]];
+#pragma unroll
+  for (int j = 0; j < kMaxCells; ++j) {
+    w.thit[(size_t)(j + 1) * T + t] = j <= depth ? w.cout[path[j]] : kPad;
+    w.tcell[(size_t)j * T + t] = j <= depth ? path[j] : kPad;
+  }
+  w.tn[t] = (uint8_t)nh;
+}
+
+__global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t nd = w.ctr[C_ND];
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nd; r += gridDim.x * blockDim.x) {
+    if (w.has_inner[r] || w.nout[r] == 0) continue;
+    uint32_t path[kMaxCells];
+    uint32_t word[kMaxCells];   // current mask word index per depth
+    uint64_t bits[kMaxCells];   // remaining bits of that word
+    uint32_t nwd[kMaxCells];    // words per depth
+    uint32_t kbase[kMaxCells];  // first candidate doublet per depth
+    int depth = 0;
+    path[0] = r;
+    {
+      const uint32_t b = w.cout[r];
+      kbase[0] = w.cell_off[b];
+      nwd[0] = w.mw[r];
+      word[0] = 0;
+      bits[0] = nwd[0] ? w.masks[w.moff[r]] : 0ull;
+    }
+    bool overflow = false;
+    while (depth >= 0) {
+      if (bits[depth] == 0) {
+        if (++word[depth] < nwd[depth]) {
+          bits[depth] = w.masks[w.moff[path[depth]] + word[depth]];
+          continue;
+        }
+        --depth;
+        continue;
+      }
+      const int k = __ffsll((unsigned long long)bits[depth]) - 1;
+      bits[depth] &= bits[depth] - 1;
+      const uint32_t child = kbase[depth] + word[depth] * 64u + (uint32_t)k;
+      if (depth + 1 >= kMaxCells) {
+        overflow = true;
+        break;
+      }
+      path[depth + 1] = child;
+      if (w.nout[child] == 0) {
+        emit_tuple(w, c, path, depth + 1);
+        continue;
+      }
+      ++depth;
+      kbase[depth] = w.cell_off[w.cout[child]];
+      nwd[depth] = w.mw[child];
+      word[depth] = 0;
+      bits[depth] = nwd[depth] ? w.masks[w.moff[child]] : 0ull;
+    }
+    if (overflow) set_status(w.ctr, PXT_ERR_PATH);
+  }
+}
+
+// ------------------------------------------------------------- cleaning --
+// Each doublet keeps only its best n-tuplet under the total order
+// (more hits, lower score, lexicographically smaller event-local hit tuple);
+// a tuple survives iff it is the best at every one of its doublets.
+
+__global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
+  uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t ntup = ctr[C_NTUP];
+  if (ntup > c.cap_tuples) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      set_status(ctr, PXT_ERR_CAPACITY);
+      ctr[C_REQ_T] = ntup;
+    }
+    return;
+  }
+  const uint32_t T = c.cap_tuples;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
+    const int n = w.tn[t];
+    HitD h0 = load_hit(w, w.thit[t]);
+    HitD h1 = load_hit(w, w.thit[(size_t)T + t]);
+    double s = 0.0;
+    for (int j = 1; j + 1 < n; ++j) {
+      const HitD h2 = load_hit(w, w.thit[(size_t)(j + 1) * T + t]);
+      s += triple_score(c, h0, h1, h2);
+      h0 = h1;
+      h1 = h2;
+    }
+    w.tscore[t] = s;
+    for (int j = 0; j + 1 < n; ++j) atomicAdd(&w.ccnt[w.tcell[(size_t)j * T + t]], 1u);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cfill(Ws w, DevCfg c) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t ntup = w.ctr[C_NTUP];
+  const uint32_t T = c.cap_tuples;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
+    const int n = w.tn[t];
+    for (int j = 0; j + 1 < n; ++j) {
+      const uint32_t d = w.tcell[(size_t)j * T + t];
+      const uint32_t pos = w.coff[d] + atomicSub(&w.ccnt[d], 1u) - 1u;
+      w.clist[pos] = t;
+    }
+  }
+}
+
+// true if tuple a ranks before tuple b
+__device__ __forceinline__ bool ranks_before(const Ws& w, uint32_t T, uint32_t a, uint32_t b) {
+  const int na = w.tn[a], nbh = w.tn[b];
+  if (na != nbh) return na > nbh;
+  const double sa = w.tscore[a], sb = w.tscore[b];
+  if (sa != sb) return sa < sb;
+  for (int j = 0; j < kMaxHits; ++j) {
+    const uint32_t ha = w.thit[(size_t)j * T + a], hb = w.thit[(size_t)j * T + b];
+    const uint32_t ia = ha == kPad ? kPad : w.bidx[ha];
+    const uint32_t ib = hb == kPad ? kPad : w.bidx[hb];
+    if (ia != ib) return ia < ib;
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t nd = w.ctr[C_ND];
+  const uint32_t T = c.cap_tuples;
+  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
+    const uint32_t b0 = w.coff[d], b1 = w.coff[d + 1];
+    if (b0 == b1) continue;
+    uint32_t best = w.clist[b0];
+    for (uint32_t k = b0 + 1; k < b1; ++k) {
+      const uint32_t t = w.clist[k];
+      if (ranks_before(w, T, t, best)) best = t;
+    }
+    w.best[d] = best;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_survive(Ws w, DevCfg c, uint32_t* per_event_tracks) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t ntup = w.ctr[C_NTUP];
+  const uint32_t T = c.cap_tuples;
+  const uint32_t lim = (ntup + blockDim.x - 1) / blockDim.x * blockDim.x;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < lim; t += gridDim.x * blockDim.x) {
+    bool alive = false;
+    if (t < ntup) {
+      alive = true;
+      const int n = w.tn[t];
+      for (int j = 0; j + 1 < n; ++j)
+        if (w.best[w.tcell[(size_t)j * T + t]] != t) alive = false;
+    }
+    const uint32_t slot = wave_append(&w.ctr[C_NSURV], alive);
+    if (alive) {
+      w.surv[slot] = t;
+      atomicAdd(&per_event_tracks[w.bevt[w.thit[t]]], 1u);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ fit --
+
+template <typename T>
+__device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_t s,
+                               bool fp64) {
+  const uint32_t TT = c.cap_tuples;
+  const uint32_t t = w.surv[s];
+  const int n = w.tn[t];
+  double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
+  int kind[kMaxHits];
+  uint32_t hid[kMaxHits];
+#pragma unroll
+  for (int j = 0; j < kMaxHits; ++j) {
+    const uint32_t h = w.thit[(size_t)j * TT + t];
+    hid[j] = h;
+    if (j < n) {
+      X[j] = (double)w.bx[h];
+      Y[j] = (double)w.by[h];
+      Z[j] = (double)w.bz[h];
+      kind[j] = c.layer_kind[w.blay[h]];
+    } else {
+      X[j] = Y[j] = Z[j] = 0.0;
+      kind[j] = 0;
+    }
+  }
+  FitGeo g;
+  fit_geometry(c, n, X, Y, Z, kind, g);
+  FitOut f;
+  fit_dispatch<T>(c, g, f);
+  if (!fp64 && f.need64) {
+    const uint32_t k = atomicAdd(&w.ctr[C_NFP64], 1u);
+    w.fp64_list[k] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) o.params[(size_t)s * 5 + i] = f.params[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) o.cov[(size_t)s * 15 + i] = f.cov[i];
+  o.chi2[(size_t)s * 2 + 0] = f.chi2[0];
+  o.chi2[(size_t)s * 2 + 1] = f.chi2[1];
+  o.flags[s] = fp64 ? 1 : 0;
+  if (!fp64) {
+#pragma unroll
+    for (int j = 0; j < kMaxHits; ++j)
+      o.hit_idx[(size_t)s * 8 + j] = hid[j] == kPad ? kPad : w.bidx[hid[j]];
+    o.n_hits[s] = (uint8_t)n;
+    o.event_id[s] = w.bevt[hid[0]];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c, OutPtrs o) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t ns = w.ctr[C_NSURV];
+  if (ns > o.capacity) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      set_status(w.ctr, PXT_ERR_CAPACITY);
+      w.ctr[C_REQ_K] = ns;
+    }
+    return;
+  }
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x)
+    fit_one<float>(w, c, o, s, false);
+}
+
+__global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c, OutPtrs o) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t n64 = w.ctr[C_NFP64];
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n64; k += gridDim.x * blockDim.x)
+    fit_one<double>(w, c, o, w.fp64_list[k], true);
+}
+
+// --------------------------------------------------------------- finish --
+
+__global__ void k_finish(Ws w, OutPtrs o) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t* ctr = w.ctr;
+  pxt_counts* k = o.counts;
+  const int st = (int)ctr[C_STATUS];
+  k->status = st;
+  k->n_tracks = st ? 0u : ctr[C_NSURV];
+  k->n_doublets = ctr[C_ND];
+  k->n_links = ctr[C_NLINKS];
+  k->n_raw_tuples = ctr[C_NTUP];
+  k->n_fp64 = ctr[C_NFP64];
+  k->n_hits_binned = ctr[C_NBINNED];
+  k->reserved = 0;
+  k->required[0] = ctr[C_REQ_D];
+  k->required[1] = ctr[C_REQ_W];
+  k->required[2] = ctr[C_REQ_T];
+  k->required[3] = ctr[C_REQ_K];
+}
+
+}  // namespace pxt

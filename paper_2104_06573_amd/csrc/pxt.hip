@@ -1,0 +1,430 @@
+// libpxt: C ABI of the pixel-track reconstruction core (see include/pxt.h).
+//
+// Host side: context creation (one device allocation carved into arenas,
+// sized from the configured capacities), argument validation, the launch
+// sequence of one call on the caller's stream, and debug dumps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace pxt;
+
+struct pxt_ctx {
+  int device = 0;
+  pxt_config cfg{};
+  DevCfg dc{};
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  Ws ws{};
+  uint32_t* h_staging = nullptr;   // pinned copy of the event offsets
+  hipEvent_t staging_free = nullptr;
+  bool staging_pending = false;
+  int n_cu = 256;
+  std::string err;
+  // last call, for the debug dumps
+  bool have_last = false;
+  uint32_t last_events = 0;
+  std::vector<uint32_t> last_offsets;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(pxt_ctx* c, int st, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return st;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                 \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return fail((ctx), PXT_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t n) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * std::max<size_t>(n, 1);
+    return p;
+  }
+};
+
+void carve(Carver& cv, const pxt_config& c, Ws& w) {
+  const size_t H = c.max_hits, D = c.max_doublets, Wd = c.max_link_words, T = c.max_tuples;
+  const size_t E = c.max_events;
+  const size_t nbins = E * (size_t)c.n_layers * (size_t)c.phi_bins;
+  w.ctr = cv.take<uint32_t>(C_NCTR);
+  w.evt_off = cv.take<uint32_t>(E + 1);
+  w.keys = cv.take<uint32_t>(H);
+  w.bin_cnt = cv.take<uint32_t>(nbins + 1);
+  w.bin_off = cv.take<uint32_t>(nbins + 1);
+  w.rmax = cv.take<uint32_t>(E * c.n_layers);
+  w.bx = cv.take<float>(H);
+  w.by = cv.take<float>(H);
+  w.bz = cv.take<float>(H);
+  w.br = cv.take<double>(H);
+  w.bphi = cv.take<float>(H);
+  w.bidx = cv.take<uint32_t>(H);
+  w.bevt = cv.take<uint32_t>(H);
+  w.blay = cv.take<uint8_t>(H);
+  w.dcnt = cv.take<uint32_t>(H + 1);
+  w.cell_off = cv.take<uint32_t>(H + 1);
+  w.cin = cv.take<uint32_t>(D);
+  w.cout = cv.take<uint32_t>(D);
+  w.mw = cv.take<uint32_t>(D + 1);
+  w.moff = cv.take<uint32_t>(D + 1);
+  w.masks = cv.take<uint64_t>(Wd);
+  w.has_inner = cv.take<uint8_t>(D);
+  w.nout = cv.take<uint32_t>(D);
+  w.thit = cv.take<uint32_t>(8 * T);
+  w.tcell = cv.take<uint32_t>(7 * T);
+  w.tn = cv.take<uint8_t>(T);
+  w.tscore = cv.take<double>(T);
+  w.ccnt = cv.take<uint32_t>(D + 1);
+  w.coff = cv.take<uint32_t>(D + 1);
+  w.clist = cv.take<uint32_t>(7 * T);
+  w.best = cv.take<uint32_t>(D);
+  w.surv = cv.take<uint32_t>(T);
+  w.fp64_list = cv.take<uint32_t>(T);
+  w.block_sums = cv.take<uint32_t>(kScanBlocks + 1);
+}
+
+int validate_config(const pxt_config* c, std::string& why) {
+  if (!(c->c_kappa > 0)) return why = "c_kappa must be > 0", 1;
+  if (c->n_layers < 1 || c->n_layers > PXT_MAX_LAYERS) return why = "n_layers out of range", 1;
+  if (c->n_pairs < 0 || c->n_pairs > PXT_MAX_PAIRS) return why = "n_pairs out of range", 1;
+  int per_layer[PXT_MAX_LAYERS] = {0};
+  for (int i = 0; i < c->n_pairs; ++i) {
+    const int a = c->pair_inner[i], b = c->pair_outer[i];
+    if (a < 0 || a >= c->n_layers || b < 0 || b >= c->n_layers || a == b)
+      return why = "layer pair out of range", 1;
+    if (++per_layer[a] > kMaxOuterPerLayer) return why = "more than 8 pairs leave one layer", 1;
+  }
+  for (int l = 0; l < c->n_layers; ++l)
+    if (c->layer_kind[l] != PXT_LAYER_BARREL && c->layer_kind[l] != PXT_LAYER_DISK)
+      return why = "layer_kind must be 0 or 1", 1;
+  if (!(c->kmax > 0 && c->z0max > 0 && c->arz > 0 && c->d0max > 0))
+    return why = "cuts must be > 0", 1;
+  if (!(c->sigma_u > 0 && c->sigma_z > 0 && c->sigma_r > 0 && c->x_over_x0 > 0 && c->pt_max > 0))
+    return why = "fit constants must be > 0", 1;
+  if (c->max_events < 1 || c->max_hits < 1 || c->max_doublets < 1 || c->max_link_words < 1 ||
+      c->max_tuples < 1)
+    return why = "capacities must be >= 1", 1;
+  if ((uint64_t)c->max_hits >= 0xffffffffull || (uint64_t)c->max_doublets >= 0xfffffff0ull ||
+      (uint64_t)c->max_tuples * 8ull >= 0xfffffff0ull)
+    return why = "capacity too large for 32-bit indices", 1;
+  if (c->phi_bins < 16 || c->phi_bins > 4096) return why = "phi_bins out of 16..4096", 1;
+  if ((uint64_t)c->max_events * c->n_layers * c->phi_bins >= 0x7fffffffull)
+    return why = "max_events * n_layers * phi_bins too large", 1;
+  if (c->block_size < 64 || c->block_size > 256 || c->block_size % 64)
+    return why = "block_size must be 64, 128, 192 or 256", 1;
+  if (!(c->pt_fp64 > 0)) return why = "pt_fp64 must be > 0", 1;
+  return 0;
+}
+
+void make_devcfg(const pxt_config& c, DevCfg& d) {
+  std::memset(&d, 0, sizeof(d));
+  d.n_layers = c.n_layers;
+  d.nphi = c.phi_bins;
+  d.phi_scale = (float)(c.phi_bins / (2.0 * M_PI));
+  d.kmax_f = (float)c.kmax;
+  for (int l = 0; l < c.n_layers; ++l) d.layer_kind[l] = c.layer_kind[l];
+  for (int i = 0; i < c.n_pairs; ++i) {
+    const int a = c.pair_inner[i];
+    d.outer[a][d.n_outer[a]++] = c.pair_outer[i];
+  }
+  d.kmax = c.kmax;
+  d.z0max = c.z0max;
+  d.arz = c.arz;
+  d.d0max = c.d0max;
+  d.c_kappa = c.c_kappa;
+  d.sigma_u = c.sigma_u;
+  d.sigma_z = c.sigma_z;
+  d.sigma_r = c.sigma_r;
+  d.x_over_x0 = c.x_over_x0;
+  d.pt_max = c.pt_max;
+  d.pt_fp64 = c.pt_fp64;
+  d.cap_doublets = c.max_doublets;
+  d.cap_words = c.max_link_words;
+  d.cap_tuples = c.max_tuples;
+}
+
+// Launch the three-kernel exclusive scan of n = *n_dev entries.
+void launch_scan(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t* n_dev,
+                 uint32_t* total_dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, n_dev,
+                     w.block_sums, w.ctr);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, w.block_sums, (uint32_t)kScanBlocks,
+                     w.ctr);
+  hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, out, n_dev,
+                     w.block_sums, (uint32_t)kScanBlocks, total_dst, w.ctr);
+}
+
+uint32_t grid_for(uint64_t items, int bs, uint32_t cap_blocks) {
+  uint64_t g = (items + bs - 1) / bs;
+  if (g < 1) g = 1;
+  return (uint32_t)std::min<uint64_t>(g, cap_blocks);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pxt_abi_version(void) { return PXT_ABI_VERSION; }
+
+const char* pxt_status_str(int s) {
+  switch (s) {
+    case PXT_OK: return "ok";
+    case PXT_ERR_INVALID_ARG: return "invalid argument";
+    case PXT_ERR_CAPACITY: return "capacity exceeded";
+    case PXT_ERR_HIP: return "HIP runtime error";
+    case PXT_ERR_OOM: return "out of device memory";
+    case PXT_ERR_BUSY: return "busy";
+    case PXT_ERR_PATH: return "link-graph path longer than 8 hits";
+    case PXT_ERR_NOT_READY: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+const char* pxt_last_error(const pxt_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int pxt_config_defaults(pxt_config* cfg) {
+  if (!cfg) return PXT_ERR_INVALID_ARG;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->max_events = 64;
+  cfg->max_hits = 1u << 20;
+  cfg->max_doublets = 1u << 24;
+  cfg->max_link_words = 1u << 24;
+  cfg->max_tuples = 1u << 22;
+  cfg->phi_bins = 256;
+  cfg->block_size = 256;
+  cfg->pt_fp64 = 20.0;
+  return PXT_OK;
+}
+
+int pxt_create(const pxt_config* cfg, int hip_device, pxt_ctx** out) {
+  if (!cfg || !out) return fail(nullptr, PXT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::string why;
+  if (validate_config(cfg, why)) return fail(nullptr, PXT_ERR_INVALID_ARG, why);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "no such HIP device");
+  pxt_ctx* c = new (std::nothrow) pxt_ctx();
+  if (!c) return fail(nullptr, PXT_ERR_OOM, "host allocation failed");
+  c->device = hip_device;
+  c->cfg = *cfg;
+  make_devcfg(*cfg, c->dc);
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, PXT_ERR_HIP, "hipSetDevice failed");
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  Carver size_pass;
+  carve(size_pass, *cfg, c->ws);
+  c->arena_bytes = size_pass.off + 256;
+  if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
+    delete c;
+    return fail(nullptr, PXT_ERR_OOM, "hipMalloc of " + std::to_string(c->arena_bytes) + " bytes failed");
+  }
+  Carver real;
+  real.base = static_cast<char*>(c->arena);
+  carve(real, *cfg, c->ws);
+  if (hipHostMalloc((void**)&c->h_staging, sizeof(uint32_t) * (cfg->max_events + 1),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming) != hipSuccess) {
+    pxt_destroy(c);
+    return fail(nullptr, PXT_ERR_HIP, "pinned staging allocation failed");
+  }
+  *out = c;
+  return PXT_OK;
+}
+
+void pxt_destroy(pxt_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->staging_free) (void)hipEventDestroy(c->staging_free);
+  if (c->h_staging) (void)hipHostFree(c->h_staging);
+  if (c->arena) (void)hipFree(c->arena);
+  delete c;
+}
+
+int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* stream) {
+  if (!c) return PXT_ERR_INVALID_ARG;
+  if (!in || !out) return fail(c, PXT_ERR_INVALID_ARG, "null argument");
+  const pxt_config& cfg = c->cfg;
+  const uint32_t E = in->n_events;
+  if (E > cfg.max_events) return fail(c, PXT_ERR_INVALID_ARG, "n_events above max_events");
+  if (!in->event_offsets) return fail(c, PXT_ERR_INVALID_ARG, "null event_offsets");
+  if (in->event_offsets[0] != 0) return fail(c, PXT_ERR_INVALID_ARG, "event_offsets[0] != 0");
+  for (uint32_t e = 0; e < E; ++e)
+    if (in->event_offsets[e + 1] < in->event_offsets[e])
+      return fail(c, PXT_ERR_INVALID_ARG, "decreasing event_offsets");
+  const uint32_t H = in->event_offsets[E];
+  if (H > cfg.max_hits) return fail(c, PXT_ERR_INVALID_ARG, "more hits than max_hits");
+  if (H > 0 && (!in->x || !in->y || !in->z || !in->layer))
+    return fail(c, PXT_ERR_INVALID_ARG, "null hit array");
+  if (!out->counts || (E > 0 && !out->per_event_tracks))
+    return fail(c, PXT_ERR_INVALID_ARG, "null counts / per_event_tracks");
+  if (out->capacity > 0 && (!out->hit_idx || !out->n_hits || !out->event_id || !out->params ||
+                            !out->cov || !out->chi2 || !out->flags))
+    return fail(c, PXT_ERR_INVALID_ARG, "null track buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+
+  // offsets -> pinned staging -> device (wait until the previous copy read it)
+  if (c->staging_pending) HIP_OR_FAIL(c, hipEventSynchronize(c->staging_free));
+  std::memcpy(c->h_staging, in->event_offsets, sizeof(uint32_t) * (E + 1));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->ws.evt_off, c->h_staging, sizeof(uint32_t) * (E + 1),
+                                hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(c, hipEventRecord(c->staging_free, s));
+  c->staging_pending = true;
+
+  const Ws& w = c->ws;
+  const DevCfg& d = c->dc;
+  const int bs = cfg.block_size;
+  const uint32_t nbins = E * (uint32_t)cfg.n_layers * (uint32_t)cfg.phi_bins;
+  const uint32_t persist = (uint32_t)c->n_cu * 8u;
+  OutPtrs o{out->capacity, out->hit_idx, out->n_hits, out->event_id, out->params, out->cov,
+            out->chi2, out->flags, out->per_event_tracks, out->counts};
+
+  hipLaunchKernelGGL(k_clear, dim3(grid_for(std::max<uint64_t>(nbins + 1, C_NCTR), 256, persist)),
+                     dim3(256), 0, s, w, E, (uint32_t)cfg.n_layers, nbins,
+                     E ? out->per_event_tracks : w.ctr + C_NCTR - 1);
+  if (H > 0) {
+    hipLaunchKernelGGL(k_prep, dim3(grid_for(H, 256, 1u << 30)), dim3(256), 0, s, in->x, in->y,
+                       in->layer, H, E, w, d);
+    launch_scan(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, s);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(H, 256, 1u << 30)), dim3(256), 0, s, in->x, in->y,
+                       in->z, in->layer, H, E, w);
+    const uint32_t gh = grid_for(H, bs, persist);
+    hipLaunchKernelGGL(k_doublets<false>, dim3(gh), dim3(bs), 0, s, w, d, H);
+    launch_scan(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, s);
+    hipLaunchKernelGGL(k_doublets<true>, dim3(gh), dim3(bs), 0, s, w, d, H);
+    launch_scan(w, w.mw, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, s);
+    const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
+    hipLaunchKernelGGL(k_links, dim3(gd), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_tuples, dim3(gd), dim3(bs), 0, s, w, d);
+    const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
+    hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
+    launch_scan(w, w.ccnt, w.coff, w.ctr + C_ND, nullptr, s);
+    hipLaunchKernelGGL(k_cfill, dim3(gt), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_best, dim3(gd), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_survive, dim3(gt), dim3(bs), 0, s, w, d, out->per_event_tracks);
+    hipLaunchKernelGGL(k_fit32, dim3(grid_for(cfg.max_tuples, 256, persist)), dim3(256), 0, s, w,
+                       d, o);
+    hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)c->n_cu)), dim3(64),
+                       0, s, w, d, o);
+  }
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, w, o);
+  HIP_OR_FAIL(c, hipGetLastError());
+  c->have_last = true;
+  c->last_events = E;
+  c->last_offsets.assign(in->event_offsets, in->event_offsets + E + 1);
+  return PXT_OK;
+}
+
+int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* count,
+                   void* stream) {
+  if (!c) return PXT_ERR_INVALID_ARG;
+  if (!count || (cap > 0 && !dst)) return fail(c, PXT_ERR_INVALID_ARG, "null argument");
+  if (!c->have_last) return fail(c, PXT_ERR_INVALID_ARG, "no previous reconstruct call");
+  if (what < PXT_DUMP_DOUBLETS || what > PXT_DUMP_RAW)
+    return fail(c, PXT_ERR_INVALID_ARG, "unknown dump");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipStreamSynchronize(s));
+  const Ws& w = c->ws;
+  uint32_t ctr[C_NCTR];
+  HIP_OR_FAIL(c, hipMemcpy(ctr, w.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+  if (ctr[C_STATUS]) return fail(c, PXT_ERR_INVALID_ARG, "last call ended with a device status");
+  const uint32_t nb = ctr[C_NBINNED], nd = ctr[C_ND], nt = ctr[C_NTUP];
+  std::vector<uint32_t> bidx(nb), bevt(nb);
+  if (nb) {
+    HIP_OR_FAIL(c, hipMemcpy(bidx.data(), w.bidx, 4ull * nb, hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(c, hipMemcpy(bevt.data(), w.bevt, 4ull * nb, hipMemcpyDeviceToHost));
+  }
+  std::vector<uint32_t> rows;
+  if (what == PXT_DUMP_DOUBLETS || what == PXT_DUMP_LINKS) {
+    std::vector<uint32_t> cin(nd), cout(nd);
+    if (nd) {
+      HIP_OR_FAIL(c, hipMemcpy(cin.data(), w.cin, 4ull * nd, hipMemcpyDeviceToHost));
+      HIP_OR_FAIL(c, hipMemcpy(cout.data(), w.cout, 4ull * nd, hipMemcpyDeviceToHost));
+    }
+    if (what == PXT_DUMP_DOUBLETS) {
+      rows.reserve(3ull * nd);
+      for (uint32_t k = 0; k < nd; ++k) {
+        rows.push_back(bevt[cin[k]]);
+        rows.push_back(bidx[cin[k]]);
+        rows.push_back(bidx[cout[k]]);
+      }
+    } else {
+      std::vector<uint32_t> cell_off(nb + 1), mw(nd), moff(nd + 1);
+      HIP_OR_FAIL(c, hipMemcpy(cell_off.data(), w.cell_off, 4ull * (nb + 1), hipMemcpyDeviceToHost));
+      if (nd) HIP_OR_FAIL(c, hipMemcpy(mw.data(), w.mw, 4ull * nd, hipMemcpyDeviceToHost));
+      HIP_OR_FAIL(c, hipMemcpy(moff.data(), w.moff, 4ull * (nd + 1), hipMemcpyDeviceToHost));
+      const uint32_t nwords = moff[nd];
+      std::vector<uint64_t> masks(nwords);
+      if (nwords)
+        HIP_OR_FAIL(c, hipMemcpy(masks.data(), w.masks, 8ull * nwords, hipMemcpyDeviceToHost));
+      for (uint32_t k = 0; k < nd; ++k) {
+        const uint32_t b = cout[k], k0 = cell_off[b];
+        for (uint32_t wd = 0; wd < mw[k]; ++wd) {
+          uint64_t m = masks[moff[k] + wd];
+          while (m) {
+            const int bit = __builtin_ctzll(m);
+            m &= m - 1;
+            const uint32_t d2 = k0 + wd * 64u + (uint32_t)bit;
+            rows.push_back(bevt[cin[k]]);
+            rows.push_back(bidx[cin[k]]);
+            rows.push_back(bidx[b]);
+            rows.push_back(bidx[cout[d2]]);
+          }
+        }
+      }
+    }
+  } else {
+    const uint32_t T = c->cfg.max_tuples;
+    const uint32_t n = std::min(nt, T);
+    std::vector<uint32_t> th(8ull * T);
+    if (n) HIP_OR_FAIL(c, hipMemcpy(th.data(), w.thit, 4ull * 8 * T, hipMemcpyDeviceToHost));
+    rows.reserve(9ull * n);
+    for (uint32_t t = 0; t < n; ++t) {
+      rows.push_back(bevt[th[t]]);
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t h = th[(size_t)j * T + t];
+        rows.push_back(h == kPad ? kPad : bidx[h]);
+      }
+    }
+  }
+  const uint64_t width = what == PXT_DUMP_DOUBLETS ? 3 : (what == PXT_DUMP_LINKS ? 4 : 9);
+  const uint64_t nrows = rows.size() / width;
+  *count = nrows;
+  const uint64_t ncopy = std::min(nrows, cap);
+  if (ncopy) std::memcpy(dst, rows.data(), sizeof(uint32_t) * width * ncopy);
+  return PXT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Doublets, links, raw n-tuplets and surviving tracks must be identical sets
+per event (bit-exact after canonical sorting); fitted parameters must agree
+with the FP64 oracle within 1e-4 relative to max(|value|, floor) with floors
+phi0 1 rad, d0 0.01 cm, q/pT 0.001 /GeV, cot(theta) 0.1, z0 1 cm; the
+covariance diagonal within 1e-3 relative (its square roots).
+"""
+
+import numpy as np
+import pytest
+
+import eventgen
+import oracle
+from tests.compare import FIT_RTOL, canon_rows, fit_errors, match_tracks, per_event_rows
+
+pytestmark = pytest.mark.gpu
+
+DET = eventgen.DETECTOR
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return t
+
+
+def make_rec(**kw):
+    import paper_2104_06573_amd as pxt
+    caps = dict(max_events=64, max_hits=1 << 20, max_doublets=1 << 22, max_link_words=1 << 22,
+                max_tuples=1 << 20, max_tracks=1 << 19)
+    caps.update(kw)
+    return pxt.Reconstructor(DET, **caps)
+
+
+def run_and_dump(rec, events):
+    import paper_2104_06573_amd as pxt
+    res = rec.run_numpy(events)
+    assert res.counts["status"] == 0, res.counts
+    out = res.numpy()
+    dumps = {k: rec.dump(v) for k, v in (("d", pxt.DUMP_DOUBLETS), ("l", pxt.DUMP_LINKS),
+                                          ("r", pxt.DUMP_RAW))}
+    return res, out, dumps
+
+
+def check_events(events, res, out, dumps, check_cov=True, fit_stats=None):
+    n = len(events)
+    D = per_event_rows(dumps["d"], n)
+    L = per_event_rows(dumps["l"], n)
+    R = per_event_rows(dumps["r"], n)
+    tot_tracks = 0
+    for e, ev in enumerate(events):
+        o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, DET)
+        assert o["status"] == 0
+        np.testing.assert_array_equal(D[e], canon_rows(o["doublets"]), err_msg="doublets ev%d" % e)
+        np.testing.assert_array_equal(L[e], canon_rows(o["links"]), err_msg="links ev%d" % e)
+        np.testing.assert_array_equal(R[e], canon_rows(o["raw"]), err_msg="raw tuples ev%d" % e)
+        gh, gp, gc, gx, gf, oh, op, oc, ox = match_tracks(out, o, e)
+        np.testing.assert_array_equal(gh, oh, err_msg="tracks ev%d" % e)
+        assert int(out["per_event_tracks"][e]) == oh.shape[0]
+        tot_tracks += oh.shape[0]
+        if oh.shape[0] == 0:
+            continue
+        err = fit_errors(gp, op)
+        if fit_stats is not None:
+            fit_stats.append(err)
+        bad = np.nonzero(err.max(axis=1) > FIT_RTOL)[0]
+        assert bad.size == 0, ("fit ev%d" % e, err[bad[:5]], gp[bad[:5]], op[bad[:5]], gf[bad[:5]])
+        if check_cov:
+            diag = [0, 2, 5, 9, 14]
+            sg = np.sqrt(gc[:, diag].astype(np.float64))
+            so = np.sqrt(oc[:, diag])
+            np.testing.assert_allclose(sg, so, rtol=1e-3, err_msg="cov diag ev%d" % e)
+            np.testing.assert_allclose(gx, ox, rtol=2e-3, atol=2e-3, err_msg="chi2 ev%d" % e)
+    assert res.counts["n_tracks"] == tot_tracks
+
+
+def test_tiny_batch(torch):
+    events = [eventgen.generate("tiny", s) for s in range(24)]
+    rec = make_rec()
+    res, out, dumps = run_and_dump(rec, events)
+    check_events(events, res, out, dumps)
+
+
+def test_separated_tracks_recover_truth(torch):
+    events = [eventgen.generate("tiny", s, phi_spacing=True) for s in range(8)]
+    rec = make_rec()
+    res = rec.run_numpy(events).numpy()
+    for e, ev in enumerate(events):
+        m = res["event_id"] == e
+        got = canon_rows(res["hit_idx"][m].view(np.uint32))
+        truth = np.full((len(ev.track_hits), 8), 0xFFFFFFFF, np.uint32)
+        for i, h in enumerate(ev.track_hits):
+            truth[i, :len(h)] = h
+        np.testing.assert_array_equal(got, canon_rows(truth))
+
+
+def test_pu50_batch(torch):
+    events = [eventgen.generate("pu50", 100 + s) for s in range(3)]
+    rec = make_rec()
+    res, out, dumps = run_and_dump(rec, events)
+    stats = []
+    check_events(events, res, out, dumps, fit_stats=stats)
+    err = np.concatenate(stats)
+    print("pu50 fit rel. error max", err.max(axis=0), "p99.9", np.percentile(err, 99.9, axis=0),
+          "fp64 fraction %.4f" % (res.counts["n_fp64"] / max(res.counts["n_tracks"], 1)))
+
+
+def test_pu200_event(torch):
+    events = [eventgen.generate("pu200", 7)]
+    rec = make_rec(max_doublets=3 << 20, max_link_words=3 << 20)
+    res, out, dumps = run_and_dump(rec, events)
+    stats = []
+    check_events(events, res, out, dumps, fit_stats=stats)
+    err = np.concatenate(stats)
+    print("pu200 fit rel. error max", err.max(axis=0), "p99.9", np.percentile(err, 99.9, axis=0),
+          "fp64 fraction %.4f" % (res.counts["n_fp64"] / max(res.counts["n_tracks"], 1)))
+
+
+def _tracks_by_event(out, n):
+    rows = []
+    for e in range(n):
+        m = out["event_id"] == e
+        h = out["hit_idx"][m].view(np.uint32)
+        o = np.lexsort(h.T[::-1]) if h.shape[0] else np.zeros(0, int)
+        rows.append((h[o], out["params"][m][o], out["cov"][m][o]))
+    return rows
+
+
+def test_batch_equivalence(torch):
+    # each event's result is the same alone, in a ragged batch, and in any
+    # order of the batch (tracks bit-exact; fits bit-exact: same code)
+    events = eventgen.make_batch("batch", 6, seed=3)
+    rec = make_rec()
+    batch = _tracks_by_event(rec.run_numpy(events).numpy(), len(events))
+    perm = [4, 0, 5, 2, 1, 3]
+    permuted = _tracks_by_event(rec.run_numpy([events[i] for i in perm]).numpy(), len(events))
+    for e, ev in enumerate(events):
+        alone = _tracks_by_event(rec.run_numpy([ev]).numpy(), 1)[0]
+        for other in (batch[e], permuted[perm.index(e)]):
+            np.testing.assert_array_equal(alone[0], other[0])
+            np.testing.assert_array_equal(alone[1], other[1])
+            np.testing.assert_array_equal(alone[2], other[2])
+
+
+@pytest.mark.parametrize("phi_bins,block", [(16, 256), (64, 64), (1024, 128), (4096, 256)])
+def test_tuning_invariance(torch, phi_bins, block):
+    events = [eventgen.generate("pu50", 55), eventgen.generate("tiny", 3)]
+    ref = _tracks_by_event(make_rec().run_numpy(events).numpy(), 2)
+    got = _tracks_by_event(make_rec(phi_bins=phi_bins, block_size=block).run_numpy(events).numpy(), 2)
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+
+
+class _Ev:
+    def __init__(self, x, y, z, layer):
+        self.x = np.asarray(x, np.float32)
+        self.y = np.asarray(y, np.float32)
+        self.z = np.asarray(z, np.float32)
+        self.layer = np.asarray(layer, np.int16)
+
+
+def test_edge_cases(torch):
+    tiny = eventgen.generate("tiny", 1)
+    empty = _Ev([], [], [], [])
+    one_layer = _Ev(tiny.x[tiny.layer == 0], tiny.y[tiny.layer == 0], tiny.z[tiny.layer == 0],
+                    tiny.layer[tiny.layer == 0])
+    bad_layers = _Ev(tiny.x, tiny.y, tiny.z, np.where(np.arange(tiny.n_hits) % 3 == 0, -1,
+                                                      np.where(np.arange(tiny.n_hits) % 3 == 1,
+                                                               99, tiny.layer)))
+    dup = _Ev(np.concatenate([tiny.x, tiny.x[:10]]), np.concatenate([tiny.y, tiny.y[:10]]),
+              np.concatenate([tiny.z, tiny.z[:10]]), np.concatenate([tiny.layer, tiny.layer[:10]]))
+    events = [empty, tiny, one_layer, empty, bad_layers, dup, empty]
+    rec = make_rec()
+    res, out, dumps = run_and_dump(rec, events)
+    check_events(events, res, out, dumps)
+    # an empty batch
+    import paper_2104_06573_amd as pxt
+    x = torch.zeros(1, device="cuda")
+    lay = torch.zeros(1, dtype=torch.int16, device="cuda")
+    r = rec.run(x, x, x, lay, np.zeros(1, np.uint32))
+    assert r.counts["status"] == 0 and r.counts["n_tracks"] == 0
+    r = rec.run(x, x, x, lay, np.zeros(4, np.uint32))
+    assert r.counts["status"] == 0 and r.counts["n_tracks"] == 0
+
+
+def test_capacity_overflow_and_retry(torch):
+    import paper_2104_06573_amd as pxt
+    events = [eventgen.generate("pu50", 9)]
+    o = oracle.reconstruct(events[0].x, events[0].y, events[0].z, events[0].layer, DET)
+    nd, nt, nk = len(o["doublets"]), len(o["raw"]), len(o["tracks"])
+    for caps, idx, need in ((dict(max_doublets=nd - 1), 0, nd),
+                            (dict(max_tuples=nt - 1), 2, nt),
+                            (dict(max_tracks=nk - 1), 3, nk)):
+        rec = make_rec(**caps)
+        r = rec.run_numpy(events)
+        assert r.counts["status"] == pxt.ERR_CAPACITY, (caps, r.counts)
+        assert r.counts["required"][idx] == need, (caps, r.counts)
+        assert r.counts["n_tracks"] == 0
+    rec = make_rec(max_doublets=nd, max_tuples=nt, max_tracks=nk)
+    r = rec.run_numpy(events)
+    assert r.counts["status"] == 0 and r.counts["n_tracks"] == nk
+    # the context recovers after an overflow on the next call
+    rec2 = make_rec(max_doublets=nd - 1)
+    assert rec2.run_numpy(events).counts["status"] == pxt.ERR_CAPACITY
+    assert rec2.run_numpy([eventgen.generate("tiny", 2)]).counts["status"] == 0
+
+
+def test_invalid_arguments(torch):
+    import paper_2104_06573_amd as pxt
+    rec = make_rec(max_events=2, max_hits=1000)
+    ev = eventgen.generate("tiny", 0)
+    x, y, z, lay, offs = rec.upload([ev, ev, ev])
+    with pytest.raises(pxt.PxtError) as e:
+        rec.launch(x, y, z, lay, offs)
+    assert e.value.status == pxt.ERR_INVALID_ARG
+    with pytest.raises(pxt.PxtError):
+        rec.launch(x, y, z, lay, np.array([0, 50, 40], np.uint32))
+    big = eventgen.generate("pu50", 0)
+    x, y, z, lay, offs = rec.upload([big])
+    with pytest.raises(pxt.PxtError):
+        rec.launch(x, y, z, lay, offs)
