@@ -1,0 +1,222 @@
+"""Throughput benchmark of the pixel-track reconstruction path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pu50|pu200]
+
+A step is one pxt_reconstruct call over one batch of synthetic events already
+resident in HBM (the whole path: binning, doublets, links, n-tuplets,
+cleaning, fit, output).  The timed region is K steps bracketed by device
+synchronisation; value = events/s of the batched path.  The same run also
+times the plain path (one event per call, synchronised per event, as the
+paper's one-concurrent-event mode), a per-stage breakdown from HIP events on
+the library's stream, and the CPU oracle on the host cores (one event per
+thread) on a bounded sample.  Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name: (generator recipe, events per batch, description)
+    "pu50": ("pu50", 64, "PU~50 events: 1500 tracks, 10 vertices, 4 barrel layers + 3 disks "
+                         "per side, 5% noise hits"),
+    "pu200": ("pu200", 32, "PU~200 events: 6000 tracks, 40 vertices, 4 barrel layers + 3 disks "
+                           "per side, 15% noise hits"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pu50", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=0, help="events per batch (default per workload)")
+    ap.add_argument("--pool", type=int, default=2, help="distinct batches cycled through")
+    ap.add_argument("--plain-events", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=48, help="events for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--phi-bins", type=int, default=256)
+    return ap.parse_args()
+
+
+def gen_events(kind, n, seed0):
+    import eventgen
+    return [eventgen.generate(kind, seed0 + i) for i in range(n)]
+
+
+# Algorithmic HBM bytes of one launch of each single-kernel stage: every
+# array the kernel must read or write, touched once (re-reads of candidates
+# from cache are not counted).  Nh binned hits, Nd doublets, Nw link-mask
+# words, Nt raw n-tuplets, Nk tracks, nbar mean hits per n-tuplet.
+def algorithmic_bytes(stage, n):
+    Nh, Nd, Nw, Nt, Nk = n["Nh"], n["Nd"], n["Nw"], n["Nt"], n["Nk"]
+    nbar = n["nbar"]
+    table = {
+        # x, y (8) + layer (2) read, bin key (4) written
+        "prep": 14 * Nh,
+        # x, y, z, layer, key read (18); binned SoA written (33)
+        "fill": 51 * Nh,
+        # binned hit read (29), doublet count written (4)
+        "doublet_count": 33 * Nh,
+        # binned hit + offset read (33); doublet in/out, mask-word count,
+        # flags, tuple counter written (17 per doublet)
+        "doublet_fill": 33 * Nh + 17 * Nd,
+        # hit coordinates (20 per hit); per doublet: in/out, offsets of its
+        # outer hit, mask offset, neighbour count, root flag, candidate
+        # outer-hit id (29); mask words (8)
+        "links": 20 * Nh + 29 * Nd + 8 * Nw,
+        # root test, graph walk (21 per doublet), masks, n-tuplets written
+        "tuples": 21 * Nd + 8 * Nw + 61 * Nt,
+        # n-tuplet hits/doublets read (61), hit coordinates, score written (8)
+        "score": (69 + 20 * nbar) * Nt,
+        # n-tuplet read (61 + 13 per hit) and the track record written (126)
+        "fit32": (61 + 13 * nbar + 126) * Nk,
+    }
+    return table.get(stage)
+
+
+def roofline(stages, counts, n_hits, peak_gbs):
+    """Roofline entry of the dominant single-kernel stage."""
+    n = {"Nh": n_hits, "Nd": counts["n_doublets"], "Nw": counts["n_words"],
+         "Nt": counts["n_raw_tuples"], "Nk": counts["n_tracks"], "nbar": 3.5}
+    cand = {k: v for k, v in stages.items() if algorithmic_bytes(k, n) is not None}
+    dom = max(cand, key=cand.get)
+    byts = algorithmic_bytes(dom, n)
+    gbs = byts / (cand[dom] * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 2), "peak": peak_gbs,
+            "unit": "GB/s", "frac": round(gbs / peak_gbs, 5), "traffic": None,
+            "bytes_per_launch": int(byts), "avg_launch_ms": round(cand[dom], 5)}
+
+
+def cpu_baseline(events, det):
+    """The oracle as it stands, one event per thread over the host cores."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    oracle.lib()
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda e: oracle.reconstruct(e.x, e.y, e.z, e.layer, det)["status"], events))
+    dt = time.perf_counter() - t0
+    return len(events) / dt, cores, dt
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (events are independent; a multi-GPU "
+              "deployment is one process per GPU). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import eventgen
+    import paper_2104_06573_amd as pxt
+
+    det = eventgen.DETECTOR
+    kind, batch_default, desc = WORKLOADS[args.workload]
+    B = args.batch or batch_default
+    pool = [gen_events(kind, B, 1000 + 97 * p) for p in range(args.pool)]
+    hits_per_event = float(np.mean([e.n_hits for b in pool for e in b]))
+    max_hits = max(sum(e.n_hits for e in b) for b in pool)
+    per_ev_d = 100_000 if kind == "pu50" else 1_700_000
+    per_ev_t = 8_000 if kind == "pu50" else 200_000
+    rec = pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
+                            max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
+                            max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
+                            phi_bins=args.phi_bins)
+    dev_batches = [rec.upload(b) for b in pool]
+    torch.cuda.synchronize()
+
+    def step(i):
+        x, y, z, l, offs = dev_batches[i % len(dev_batches)]
+        rec.launch(x, y, z, l, offs)
+
+    # correctness guard on the first batch (status only; parity is tested)
+    step(0)
+    torch.cuda.synchronize()
+    c0 = rec.read_counts()
+    assert c0["status"] == 0, c0
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    ev_per_s = B * args.steps / dt
+
+    # stage breakdown with HIP events on the library's stream
+    stages = rec.stage_times(dev_batches[0], repeats=5)
+
+    # plain path: one event per call, synchronised per event
+    plain_events = [e for b in pool for e in b][: args.plain_events]
+    prec = pxt.Reconstructor(det, max_events=1, max_hits=max(e.n_hits for e in plain_events) + 16,
+                             max_doublets=per_ev_d * 2, max_link_words=per_ev_d * 2,
+                             max_tuples=per_ev_t * 2, max_tracks=per_ev_t * 2,
+                             phi_bins=args.phi_bins)
+    plain_dev = [prec.upload([e]) for e in plain_events]
+    for i in range(min(4, len(plain_dev))):
+        prec.launch(*plain_dev[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d in plain_dev:
+        prec.launch(*d)
+        torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t0
+    plain_ev_s = len(plain_dev) / plain_dt
+
+    counts = c0
+    out = {
+        "metric": "events/s at PU50/PU200 on 1 MI355X (batched/served vs plain)",
+        "value": round(ev_per_s, 2),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": desc + ", %d events per batch" % B,
+            "events_per_batch": B,
+            "hits_per_event": round(hits_per_event, 1),
+            "phi_bins": args.phi_bins,
+            "path": "batched (one launch sequence per batch)",
+        },
+        "plain_events_per_s": round(plain_ev_s, 2),
+        "batched_over_plain": round(ev_per_s / plain_ev_s, 2),
+        "hits_per_s": round(ev_per_s * hits_per_event, 1),
+        "per_batch_counts": {k: counts[k] for k in ("n_doublets", "n_links", "n_raw_tuples",
+                                                    "n_tracks", "n_fp64")},
+        "stage_ms": stages,
+    }
+    roof = roofline(stages, counts, int(dev_batches[0][4][-1]), HBM_PEAK_GBS)
+    out["roofline"] = roof
+    if not args.no_cpu:
+        sample = [e for b in pool for e in b][: args.cpu_sample]
+        v, cores, cdt = cpu_baseline(sample, det)
+        out["cpu_baseline"] = {"value": round(v, 2), "unit": "events/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "%d %s events, one per thread, %.1f s wall" %
+                                         (len(sample), args.workload, cdt)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -124,7 +124,7 @@ typedef struct pxt_counts {
   uint32_t n_raw_tuples;
   uint32_t n_fp64;          /* tracks fitted on the FP64 path              */
   uint32_t n_hits_binned;   /* hits with a valid layer id                  */
-  uint32_t reserved;
+  uint32_t n_link_words;    /* 64-bit link-mask words used                 */
   uint64_t required[4];
 } pxt_counts;
 
@@ -196,6 +196,24 @@ int pxt_reconstruct(pxt_ctx* ctx, const pxt_hits* in, pxt_tracks* out,
 enum { PXT_DUMP_DOUBLETS = 0, PXT_DUMP_LINKS = 1, PXT_DUMP_RAW = 2 };
 int pxt_debug_dump(pxt_ctx* ctx, int what, uint32_t* dst, uint64_t cap,
                    uint64_t* count, void* hip_stream);
+
+/* Per-stage timing.  With timing enabled, pxt_reconstruct records a HIP
+ * event on the call's stream before each stage and after the last one, so
+ * a stage's duration is that of its kernels on the device.  Meant for
+ * profiling runs; adds one event record per stage.  Returns
+ * PXT_ERR_INVALID_ARG for a NULL ctx. */
+int pxt_set_timing(pxt_ctx* ctx, int enable);
+
+/* Durations in milliseconds of the stages of the last call made with timing
+ * enabled (synchronises on its last event).  ms is HOST memory of cap
+ * floats; *n_stages receives the number of stages (PXT_N_STAGES).  Stages
+ * skipped by that call (an empty batch) read 0.  Errors:
+ * PXT_ERR_INVALID_ARG (no timed call yet, null pointers), PXT_ERR_HIP. */
+#define PXT_N_STAGES 18
+int pxt_stage_times(pxt_ctx* ctx, float* ms, int cap, int* n_stages);
+
+/* Static name of stage i (0 <= i < PXT_N_STAGES), or NULL. */
+const char* pxt_stage_name(int stage);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,9 @@ DUMP_DOUBLETS, DUMP_LINKS, DUMP_RAW = 0, 1, 2
 
 # every symbol include/pxt.h declares
 EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_defaults",
-           "pxt_create", "pxt_destroy", "pxt_reconstruct", "pxt_debug_dump")
+           "pxt_create", "pxt_destroy", "pxt_reconstruct", "pxt_debug_dump",
+           "pxt_set_timing", "pxt_stage_times", "pxt_stage_name")
+N_STAGES = 18
 
 
 class PxtConfig(ctypes.Structure):
@@ -68,7 +70,7 @@ class PxtCounts(ctypes.Structure):
         ("status", ctypes.c_int32), ("n_tracks", ctypes.c_uint32),
         ("n_doublets", ctypes.c_uint32), ("n_links", ctypes.c_uint32),
         ("n_raw_tuples", ctypes.c_uint32), ("n_fp64", ctypes.c_uint32),
-        ("n_hits_binned", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("n_hits_binned", ctypes.c_uint32), ("n_link_words", ctypes.c_uint32),
         ("required", ctypes.c_uint64 * 4),
     ]
 
@@ -117,8 +119,17 @@ def lib():
         L.pxt_debug_dump.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                      ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64),
                                      ctypes.c_void_p]
+        L.pxt_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.pxt_stage_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
+        L.pxt_stage_name.restype = ctypes.c_char_p
+        L.pxt_stage_name.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
+
+
+def stage_names():
+    return [lib().pxt_stage_name(i).decode() for i in range(N_STAGES)]
 
 
 def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
@@ -177,7 +188,8 @@ def counts_dict(words):
     c = PxtCounts.from_buffer_copy(np.ascontiguousarray(words, np.uint32).tobytes())
     return dict(status=c.status, n_tracks=c.n_tracks, n_doublets=c.n_doublets,
                 n_links=c.n_links, n_raw_tuples=c.n_raw_tuples, n_fp64=c.n_fp64,
-                n_hits_binned=c.n_hits_binned, required=list(c.required))
+                n_hits_binned=c.n_hits_binned, n_words=c.n_link_words,
+                required=list(c.required))
 
 
 class Reconstructor:
@@ -288,3 +300,31 @@ class Reconstructor:
         if st != OK:
             raise PxtError(st, lib().pxt_last_error(self.h).decode())
         return buf
+
+    def set_timing(self, on):
+        st = lib().pxt_set_timing(self.h, 1 if on else 0)
+        if st != OK:
+            raise PxtError(st, lib().pxt_last_error(self.h).decode())
+
+    def last_stage_times(self):
+        """Per-stage device durations (ms) of the last timed call."""
+        buf = (ctypes.c_float * N_STAGES)()
+        n = ctypes.c_int(0)
+        st = lib().pxt_stage_times(self.h, buf, N_STAGES, ctypes.byref(n))
+        if st != OK:
+            raise PxtError(st, lib().pxt_last_error(self.h).decode())
+        return dict(zip(stage_names(), [float(v) for v in buf[:n.value]]))
+
+    def stage_times(self, batch, repeats=5):
+        """Mean per-stage durations (ms) over `repeats` timed calls on the
+        uploaded batch (x, y, z, layer, offsets)."""
+        self.set_timing(True)
+        acc = None
+        try:
+            for _ in range(repeats):
+                self.launch(*batch)
+                t = self.last_stage_times()
+                acc = t if acc is None else {k: acc[k] + t[k] for k in acc}
+        finally:
+            self.set_timing(False)
+        return {k: v / repeats for k, v in acc.items()}

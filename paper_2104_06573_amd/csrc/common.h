@@ -30,7 +30,7 @@ enum Ctr : int {
   C_ND,              // doublets
   C_NWORDS,          // link-mask words
   C_NLINKS,          // links
-  C_NTUP,            // raw n-tuplets (append counter; may exceed capacity)
+  C_NTUP,            // raw n-tuplets
   C_NSURV,           // n-tuplets surviving the cleaning
   C_NFP64,           // tuples refitted in FP64
   C_REQ_D,           // required sizes on overflow
@@ -81,6 +81,8 @@ struct Ws {
   uint64_t* masks;        // [W]
   uint8_t* has_inner;     // [D]
   uint32_t* nout;         // [D] outer links per doublet
+  uint32_t* rcnt;         // [D + 1] n-tuplets per root doublet
+  uint32_t* roff;         // [D + 1]
   // n-tuplets
   uint32_t* thit;         // [8][T] binned hits (slot-major)
   uint32_t* tcell;        // [7][T] doublets
@@ -91,6 +93,8 @@ struct Ws {
   uint32_t* coff;         // [D + 1]
   uint32_t* clist;        // [7 T]
   uint32_t* best;         // [D]
+  uint32_t* talive;       // [T + 1] survives the cleaning
+  uint32_t* toff;         // [T + 1]
   uint32_t* surv;         // [T]
   uint32_t* fp64_list;    // [T]
   // scan scratch

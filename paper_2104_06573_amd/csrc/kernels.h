@@ -35,7 +35,6 @@ __global__ void k_clear(Ws w, uint32_t n_events, uint32_t n_layers, uint32_t nbi
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = tid; i < nbins + 1; i += stride) w.bin_cnt[i] = 0;
-  for (uint32_t i = tid; i < n_events * n_layers; i += stride) w.rmax[i] = 0;
   for (uint32_t i = tid; i < n_events; i += stride) per_event_tracks[i] = 0;
   if (tid < C_NCTR) w.ctr[tid] = tid == C_NBINS ? nbins : 0u;
 }
@@ -62,8 +61,6 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ x,
   const uint32_t key = (e * (uint32_t)c.n_layers + (uint32_t)l) * (uint32_t)c.nphi + (uint32_t)b;
   w.keys[g] = key;
   atomicAdd(&w.bin_cnt[key], 1u);
-  const float r = sqrtf(xf * xf + yf * yf);
-  atomicMax(&w.rmax[e * c.n_layers + l], __float_as_uint(r));
 }
 
 __global__ __launch_bounds__(256) void k_fill(const float* __restrict__ x,
@@ -88,6 +85,24 @@ __global__ __launch_bounds__(256) void k_fill(const float* __restrict__ x,
   w.bidx[pos] = g - w.evt_off[e];
   w.bevt[pos] = e;
   w.blay[pos] = (uint8_t)layer[g];
+}
+
+// Largest transverse radius of each (event, layer): one wavefront per
+// segment of the binned array (hits of one layer of one event are
+// contiguous), a max-reduction across lanes.
+__global__ __launch_bounds__(256) void k_rmax(Ws w, uint32_t n_events, uint32_t n_layers,
+                                              uint32_t nphi) {
+  const uint32_t nseg = n_events * n_layers;
+  const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+  for (uint32_t sg = wid; sg < nseg; sg += nwaves) {
+    const uint32_t b0 = w.bin_off[sg * nphi], b1 = w.bin_off[(sg + 1) * nphi];
+    float m = 0.0f;
+    for (uint32_t i = b0 + lane_id(); i < b1; i += kWave) m = fmaxf(m, (float)w.br[i]);
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, kWave));
+    if (lane_id() == 0) w.rmax[sg] = __float_as_uint(m);
+  }
 }
 
 // -------------------------------------------------- device-wide scan ---
@@ -304,33 +319,37 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
 // ------------------------------------------------------------ n-tuplets --
 // One thread per root doublet (no inner neighbour, at least one outer):
 // iterative depth-first search over the outer-neighbour masks; every path
-// ending at a doublet without outer neighbours is appended as an n-tuplet.
+// that ends at a doublet without outer neighbours is an n-tuplet.  Two
+// passes: the first counts each root's paths, an exclusive scan turns the
+// counts into offsets, the second writes the paths there.  No atomics, and
+// the n-tuplets come out ordered by root doublet (hence by event).
 
-__device__ __forceinline__ void emit_tuple(Ws& w, const DevCfg& c, const uint32_t* path,
-                                           int depth) {
-  const uint32_t t = atomicAdd(&w.ctr[C_NTUP], 1u);
-  if (t >= c.cap_tuples) return;
-  const uint32_t T = c.cap_tuples;
-  const int nh = depth + 2;
-  w.thit[t] = w.cin[path[0]];
-#pragma unroll
-  for (int j = 0; j < kMaxCells; ++j) {
-    w.thit[(size_t)(j + 1) * T + t] = j <= depth ? w.cout[path[j]] : kPad;
-    w.tcell[(size_t)j * T + t] = j <= depth ? path[j] : kPad;
-  }
-  w.tn[t] = (uint8_t)nh;
-}
-
+template <bool FILL>
 __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
-  if (w.ctr[C_STATUS]) return;
-  const uint32_t nd = w.ctr[C_ND];
+  uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t nd = ctr[C_ND];
+  const uint32_t T = c.cap_tuples;
+  if (FILL && w.roff[nd] > T) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      set_status(ctr, PXT_ERR_CAPACITY);
+      ctr[C_REQ_T] = w.roff[nd];
+    }
+    return;
+  }
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nd; r += gridDim.x * blockDim.x) {
-    if (w.has_inner[r] || w.nout[r] == 0) continue;
+    if (w.has_inner[r] || w.nout[r] == 0) {
+      if (!FILL) w.rcnt[r] = 0;
+      continue;
+    }
     uint32_t path[kMaxCells];
-    uint32_t word[kMaxCells];   // current mask word index per depth
-    uint64_t bits[kMaxCells];   // remaining bits of that word
-    uint32_t nwd[kMaxCells];    // words per depth
+    uint32_t word[kMaxCells];   // current mask word per depth
+    uint64_t bits[kMaxCells];   // its remaining bits
+    uint32_t nwd[kMaxCells];    // mask words per depth
     uint32_t kbase[kMaxCells];  // first candidate doublet per depth
+    uint32_t cnt = 0;
+    const uint32_t base = FILL ? w.roff[r] : 0u;
+    const uint32_t h0 = w.cin[r];
     int depth = 0;
     path[0] = r;
     {
@@ -359,7 +378,18 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       }
       path[depth + 1] = child;
       if (w.nout[child] == 0) {
-        emit_tuple(w, c, path, depth + 1);
+        if (FILL) {
+          const uint32_t t = base + cnt;
+          const int last = depth + 1;
+          w.thit[t] = h0;
+#pragma unroll
+          for (int j = 0; j < kMaxCells; ++j) {
+            w.thit[(size_t)(j + 1) * T + t] = j <= last ? w.cout[path[j]] : kPad;
+            w.tcell[(size_t)j * T + t] = j <= last ? path[j] : kPad;
+          }
+          w.tn[t] = (uint8_t)(last + 2);
+        }
+        ++cnt;
         continue;
       }
       ++depth;
@@ -368,7 +398,8 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       word[depth] = 0;
       bits[depth] = nwd[depth] ? w.masks[w.moff[child]] : 0ull;
     }
-    if (overflow) set_status(w.ctr, PXT_ERR_PATH);
+    if (overflow) set_status(ctr, PXT_ERR_PATH);
+    if (!FILL) w.rcnt[r] = cnt;
   }
 }
 
@@ -381,13 +412,6 @@ __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t ntup = ctr[C_NTUP];
-  if (ntup > c.cap_tuples) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      set_status(ctr, PXT_ERR_CAPACITY);
-      ctr[C_REQ_T] = ntup;
-    }
-    return;
-  }
   const uint32_t T = c.cap_tuples;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     const int n = w.tn[t];
@@ -450,24 +474,34 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_survive(Ws w, DevCfg c, uint32_t* per_event_tracks) {
+__global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const uint32_t ntup = w.ctr[C_NTUP];
   const uint32_t T = c.cap_tuples;
-  const uint32_t lim = (ntup + blockDim.x - 1) / blockDim.x * blockDim.x;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < lim; t += gridDim.x * blockDim.x) {
-    bool alive = false;
-    if (t < ntup) {
-      alive = true;
-      const int n = w.tn[t];
-      for (int j = 0; j + 1 < n; ++j)
-        if (w.best[w.tcell[(size_t)j * T + t]] != t) alive = false;
-    }
-    const uint32_t slot = wave_append(&w.ctr[C_NSURV], alive);
-    if (alive) {
-      w.surv[slot] = t;
-      atomicAdd(&per_event_tracks[w.bevt[w.thit[t]]], 1u);
-    }
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
+    uint32_t alive = 1;
+    const int n = w.tn[t];
+    for (int j = 0; j + 1 < n; ++j)
+      if (w.best[w.tcell[(size_t)j * T + t]] != t) alive = 0;
+    w.talive[t] = alive;
+  }
+}
+
+// Survivors in n-tuplet order (offsets from the scan of the alive flags);
+// per-event track counts from the event boundaries, which the binned hits,
+// doublets, n-tuplets and survivors all respect in that order.
+__global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c, uint32_t n_events,
+                                                 uint32_t* per_event_tracks) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t ntup = w.ctr[C_NTUP];
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t t = tid; t < ntup; t += gridDim.x * blockDim.x)
+    if (w.talive[t]) w.surv[w.toff[t]] = t;
+  const uint32_t per_ev = (uint32_t)c.n_layers * (uint32_t)c.nphi;
+  for (uint32_t e = tid; e < n_events; e += gridDim.x * blockDim.x) {
+    const uint32_t a = w.toff[w.roff[w.cell_off[w.bin_off[e * per_ev]]]];
+    const uint32_t b = w.toff[w.roff[w.cell_off[w.bin_off[(e + 1) * per_ev]]]];
+    per_event_tracks[e] = b - a;
   }
 }
 
@@ -555,7 +589,7 @@ __global__ void k_finish(Ws w, OutPtrs o) {
   k->n_raw_tuples = ctr[C_NTUP];
   k->n_fp64 = ctr[C_NFP64];
   k->n_hits_binned = ctr[C_NBINNED];
-  k->reserved = 0;
+  k->n_link_words = ctr[C_NWORDS];
   k->required[0] = ctr[C_REQ_D];
   k->required[1] = ctr[C_REQ_W];
   k->required[2] = ctr[C_REQ_T];

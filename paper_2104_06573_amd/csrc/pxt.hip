@@ -29,6 +29,11 @@ struct pxt_ctx {
   bool staging_pending = false;
   int n_cu = 256;
   std::string err;
+  // per-stage timing
+  bool timing = false;
+  bool timed_valid = false;
+  hipEvent_t ev[PXT_N_STAGES + 1] = {};
+  bool stage_run[PXT_N_STAGES] = {};
   // last call, for the debug dumps
   bool have_last = false;
   uint32_t last_events = 0;
@@ -93,6 +98,8 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
+  w.rcnt = cv.take<uint32_t>(D + 1);
+  w.roff = cv.take<uint32_t>(D + 1);
   w.thit = cv.take<uint32_t>(8 * T);
   w.tcell = cv.take<uint32_t>(7 * T);
   w.tn = cv.take<uint8_t>(T);
@@ -101,6 +108,8 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.coff = cv.take<uint32_t>(D + 1);
   w.clist = cv.take<uint32_t>(7 * T);
   w.best = cv.take<uint32_t>(D);
+  w.talive = cv.take<uint32_t>(T + 1);
+  w.toff = cv.take<uint32_t>(T + 1);
   w.surv = cv.take<uint32_t>(T);
   w.fp64_list = cv.take<uint32_t>(T);
   w.block_sums = cv.take<uint32_t>(kScanBlocks + 1);
@@ -176,6 +185,22 @@ void launch_scan(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t*
   hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, out, n_dev,
                      w.block_sums, (uint32_t)kScanBlocks, total_dst, w.ctr);
 }
+
+const char* const kStageNames[PXT_N_STAGES] = {
+    "clear",       "prep",         "bin_scan",      "fill",  "doublet_count", "doublet_scan",
+    "doublet_fill", "word_scan",   "links",         "tuples", "score",        "cell_scan",
+    "cell_fill",   "best",         "survive",       "fit32", "fit64",        "finish"};
+
+// Marks the start of stage i when timing is on.
+struct StageMarks {
+  pxt_ctx* c;
+  hipStream_t s;
+  void mark(int i) {
+    if (!c->timing) return;
+    (void)hipEventRecord(c->ev[i], s);
+    c->stage_run[i] = true;
+  }
+};
 
 uint32_t grid_for(uint64_t items, int bs, uint32_t cap_blocks) {
   uint64_t g = (items + bs - 1) / bs;
@@ -266,6 +291,8 @@ void pxt_destroy(pxt_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->staging_free) (void)hipEventDestroy(c->staging_free);
+  for (int i = 0; i <= PXT_N_STAGES; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->h_staging) (void)hipHostFree(c->h_staging);
   if (c->arena) (void)hipFree(c->arena);
   delete c;
@@ -310,35 +337,66 @@ int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* strea
   OutPtrs o{out->capacity, out->hit_idx, out->n_hits, out->event_id, out->params, out->cov,
             out->chi2, out->flags, out->per_event_tracks, out->counts};
 
+  StageMarks sm{c, s};
+  if (c->timing)
+    for (int i = 0; i < PXT_N_STAGES; ++i) c->stage_run[i] = false;
+  sm.mark(0);
   hipLaunchKernelGGL(k_clear, dim3(grid_for(std::max<uint64_t>(nbins + 1, C_NCTR), 256, persist)),
                      dim3(256), 0, s, w, E, (uint32_t)cfg.n_layers, nbins,
                      E ? out->per_event_tracks : w.ctr + C_NCTR - 1);
   if (H > 0) {
+    sm.mark(1);
     hipLaunchKernelGGL(k_prep, dim3(grid_for(H, 256, 1u << 30)), dim3(256), 0, s, in->x, in->y,
                        in->layer, H, E, w, d);
+    sm.mark(2);
     launch_scan(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, s);
+    sm.mark(3);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(H, 256, 1u << 30)), dim3(256), 0, s, in->x, in->y,
                        in->z, in->layer, H, E, w);
     const uint32_t gh = grid_for(H, bs, persist);
+    hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
+                       dim3(256), 0, s, w, E, (uint32_t)cfg.n_layers, (uint32_t)cfg.phi_bins);
+    sm.mark(4);
     hipLaunchKernelGGL(k_doublets<false>, dim3(gh), dim3(bs), 0, s, w, d, H);
+    sm.mark(5);
     launch_scan(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, s);
+    sm.mark(6);
     hipLaunchKernelGGL(k_doublets<true>, dim3(gh), dim3(bs), 0, s, w, d, H);
+    sm.mark(7);
     launch_scan(w, w.mw, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, s);
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
+    sm.mark(8);
     hipLaunchKernelGGL(k_links, dim3(gd), dim3(bs), 0, s, w, d);
-    hipLaunchKernelGGL(k_tuples, dim3(gd), dim3(bs), 0, s, w, d);
+    sm.mark(9);
+    hipLaunchKernelGGL(k_tuples<false>, dim3(gd), dim3(bs), 0, s, w, d);
+    launch_scan(w, w.rcnt, w.roff, w.ctr + C_ND, w.ctr + C_NTUP, s);
+    hipLaunchKernelGGL(k_tuples<true>, dim3(gd), dim3(bs), 0, s, w, d);
     const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
+    sm.mark(10);
     hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
+    sm.mark(11);
     launch_scan(w, w.ccnt, w.coff, w.ctr + C_ND, nullptr, s);
+    sm.mark(12);
     hipLaunchKernelGGL(k_cfill, dim3(gt), dim3(bs), 0, s, w, d);
+    sm.mark(13);
     hipLaunchKernelGGL(k_best, dim3(gd), dim3(bs), 0, s, w, d);
-    hipLaunchKernelGGL(k_survive, dim3(gt), dim3(bs), 0, s, w, d, out->per_event_tracks);
+    sm.mark(14);
+    hipLaunchKernelGGL(k_alive, dim3(gt), dim3(bs), 0, s, w, d);
+    launch_scan(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, s);
+    hipLaunchKernelGGL(k_compact, dim3(gt), dim3(bs), 0, s, w, d, E, out->per_event_tracks);
+    sm.mark(15);
     hipLaunchKernelGGL(k_fit32, dim3(grid_for(cfg.max_tuples, 256, persist)), dim3(256), 0, s, w,
                        d, o);
+    sm.mark(16);
     hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)c->n_cu)), dim3(64),
                        0, s, w, d, o);
   }
+  sm.mark(17);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, w, o);
+  if (c->timing) {
+    (void)hipEventRecord(c->ev[PXT_N_STAGES], s);
+    c->timed_valid = true;
+  }
   HIP_OR_FAIL(c, hipGetLastError());
   c->have_last = true;
   c->last_events = E;
@@ -425,6 +483,39 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
   const uint64_t ncopy = std::min(nrows, cap);
   if (ncopy) std::memcpy(dst, rows.data(), sizeof(uint32_t) * width * ncopy);
   return PXT_OK;
+}
+
+int pxt_set_timing(pxt_ctx* c, int enable) {
+  if (!c) return PXT_ERR_INVALID_ARG;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  if (enable && !c->ev[0])
+    for (int i = 0; i <= PXT_N_STAGES; ++i) HIP_OR_FAIL(c, hipEventCreate(&c->ev[i]));
+  c->timing = enable != 0;
+  c->timed_valid = false;
+  return PXT_OK;
+}
+
+int pxt_stage_times(pxt_ctx* c, float* ms, int cap, int* n_stages) {
+  if (!c) return PXT_ERR_INVALID_ARG;
+  if (!n_stages || (cap > 0 && !ms)) return fail(c, PXT_ERR_INVALID_ARG, "null argument");
+  if (!c->timed_valid) return fail(c, PXT_ERR_INVALID_ARG, "no timed call");
+  *n_stages = PXT_N_STAGES;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipEventSynchronize(c->ev[PXT_N_STAGES]));
+  for (int i = 0; i < PXT_N_STAGES && i < cap; ++i) {
+    ms[i] = 0.0f;
+    if (!c->stage_run[i]) continue;
+    int j = i + 1;
+    while (j < PXT_N_STAGES && !c->stage_run[j]) ++j;
+    float t = 0.0f;
+    HIP_OR_FAIL(c, hipEventElapsedTime(&t, c->ev[i], c->ev[j]));
+    ms[i] = t;
+  }
+  return PXT_OK;
+}
+
+const char* pxt_stage_name(int i) {
+  return (i >= 0 && i < PXT_N_STAGES) ? kStageNames[i] : nullptr;
 }
 
 }  // extern "C"
