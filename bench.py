@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=48, help="events for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
+    ap.add_argument("--group-lanes", type=int, default=32)
+    ap.add_argument("--link-kernel", type=int, default=0)
     return ap.parse_args()
 
 
@@ -134,7 +136,8 @@ def main():
     rec = pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
                             max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
                             max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
-                            phi_bins=args.phi_bins)
+                            phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                            link_kernel=args.link_kernel)
     dev_batches = [rec.upload(b) for b in pool]
     torch.cuda.synchronize()
 
@@ -166,7 +169,8 @@ def main():
     prec = pxt.Reconstructor(det, max_events=1, max_hits=max(e.n_hits for e in plain_events) + 16,
                              max_doublets=per_ev_d * 2, max_link_words=per_ev_d * 2,
                              max_tuples=per_ev_t * 2, max_tracks=per_ev_t * 2,
-                             phi_bins=args.phi_bins)
+                             phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                            link_kernel=args.link_kernel)
     plain_dev = [prec.upload([e]) for e in plain_events]
     for i in range(min(4, len(plain_dev))):
         prec.launch(*plain_dev[i])
@@ -197,6 +201,8 @@ def main():
             "events_per_batch": B,
             "hits_per_event": round(hits_per_event, 1),
             "phi_bins": args.phi_bins,
+            "group_lanes": args.group_lanes,
+            "link_kernel": args.link_kernel,
             "path": "batched (one launch sequence per batch)",
         },
         "plain_events_per_s": round(plain_ev_s, 2),

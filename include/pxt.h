@@ -94,6 +94,10 @@ typedef struct pxt_config {
   /* --- tuning ------------------------------------------------------------ */
   int32_t phi_bins;         /* phi bins per layer, 16..4096                */
   int32_t block_size;       /* threads per block of the per-item kernels   */
+  int32_t group_lanes;      /* lanes per item in doublet/link kernels:
+                               16, 32 or 64                                */
+  int32_t link_kernel;      /* link step: 0 one thread per doublet,
+                               1 one lane group per doublet               */
   double pt_fp64;           /* fit tuples with pT_ref above this in FP64   */
 } pxt_config;
 

@@ -52,6 +52,7 @@ class PxtConfig(ctypes.Structure):
         ("max_doublets", ctypes.c_uint32), ("max_link_words", ctypes.c_uint32),
         ("max_tuples", ctypes.c_uint32),
         ("phi_bins", ctypes.c_int32), ("block_size", ctypes.c_int32),
+        ("group_lanes", ctypes.c_int32), ("link_kernel", ctypes.c_int32),
         ("pt_fp64", ctypes.c_double),
     ]
 
@@ -134,7 +135,7 @@ def stage_names():
 
 def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
                 max_link_words=None, max_tuples=1 << 19, phi_bins=256, block_size=256,
-                pt_fp64=20.0):
+                group_lanes=32, link_kernel=0, pt_fp64=20.0):
     """pxt_config from a detector dictionary (eventgen.DETECTOR layout)."""
     c = PxtConfig()
     if lib().pxt_config_defaults(ctypes.byref(c)) != OK:
@@ -159,6 +160,8 @@ def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
     c.max_tuples = max_tuples
     c.phi_bins = phi_bins
     c.block_size = block_size
+    c.group_lanes = group_lanes
+    c.link_kernel = link_kernel
     c.pt_fp64 = pt_fp64
     return c
 

@@ -50,8 +50,10 @@ struct DevCfg {
   int n_outer[kMaxLayers];                  // pairs leaving each layer
   int outer[kMaxLayers][kMaxOuterPerLayer]; // their outer layers, table order
   double kmax, z0max, arz, d0max;
+  double kmax2, arz2;                       // squares, for the fast forms
   double c_kappa, sigma_u, sigma_z, sigma_r, x_over_x0, pt_max, pt_fp64;
   uint32_t cap_doublets, cap_words, cap_tuples;
+  int link_thread;                          // one thread per doublet in links
 };
 
 // Device arenas of one context.
@@ -81,6 +83,12 @@ struct Ws {
   uint64_t* masks;        // [W]
   uint8_t* has_inner;     // [D]
   uint32_t* nout;         // [D] outer links per doublet
+  float* ox;              // [D] outer hit of each doublet: x, y, z, r
+  float* oy;
+  float* oz;
+  double* orr;
+  uint32_t* cb;           // [D] first doublet leaving the outer hit
+  uint32_t* cdeg;         // [D] number of doublets leaving the outer hit
   uint32_t* rcnt;         // [D + 1] n-tuplets per root doublet
   uint32_t* roff;         // [D + 1]
   // n-tuplets
@@ -160,6 +168,23 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool want) {
   if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
   base = __shfl(base, leader, kWave);
   return base + below;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor(v, d, kWave));
+  return v;
+}
+
+// XCD-aware logical block index.  Consecutive workgroups of a dispatch go
+// round-robin to the 8 XCDs of the chip; with this remap each XCD receives
+// a contiguous range of logical blocks, so the contiguous item chunks it
+// processes (doublets of the same events) share that XCD's L2.  Identity
+// unless the grid is a multiple of 8.
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t b = blockIdx.x, n = gridDim.x;
+  if (n % 8u) return b;
+  return (b % 8u) * (n / 8u) + b / 8u;
 }
 
 __device__ __forceinline__ void set_status(uint32_t* ctr, int st) {

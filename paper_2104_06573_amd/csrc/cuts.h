@@ -130,6 +130,84 @@ __device__ __forceinline__ bool link_ok(const DevCfg& c, const HitD& a,
   return d0 <= c.d0max;
 }
 
+// ---------------------------------------------------------------------
+// Decision-identical fast forms.  A comparison lhs <= k * sqrt(p) * ...
+// between non-negative doubles is first made on squares, lhs^2 against
+// k^2 * p * ..., which needs no square root.  Both sides of the squared
+// comparison are within a few ulps (relative 1e-15) of the exact squares of
+// the rounded quantities the defining expression compares, so outside a
+// relative band of 1e-9 around equality the squared comparison returns the
+// same answer; inside the band the defining expression itself is evaluated.
+
+constexpr double kBandHi = 1.0 + 1e-9;
+constexpr double kBandLo = 1.0 - 1e-9;
+
+__device__ __forceinline__ bool doublet_ok_fast(const DevCfg& c, const HitD& i,
+                                                const HitD& o) {
+  if (!(o.r > i.r)) return false;
+  const double dr = o.r - i.r;
+  const double l2 = fabs(i.z * dr - i.r * (o.z - i.z));
+  if (!(l2 <= c.z0max * dr)) return false;
+  if (!(i.x * o.x + i.y * o.y > 0.0)) return false;
+  const double cr = i.x * o.y - i.y * o.x;
+  const double dx = o.x - i.x, dy = o.y - i.y;
+  const double ch2 = dx * dx + dy * dy;
+  const double lhs = 2.0 * fabs(cr);
+  const double L = lhs * lhs;
+  const double R = c.kmax2 * (i.r * i.r) * (o.r * o.r) * ch2;
+  if (L > R * kBandHi) return false;
+  if (L < R * kBandLo) return true;
+  return lhs <= c.kmax * i.r * o.r * sqrt(ch2);
+}
+
+// Link cut split in two: the r-z cut L1 needs only (r, z) of the third hit;
+// the transverse cuts L2, L3 need its (x, y).
+__device__ __forceinline__ bool link_rz_pass(const DevCfg& c, const HitD& a, const HitD& b,
+                                             double rc, double zc) {
+  const double dra = b.r - a.r, dza = b.z - a.z;
+  const double drb = rc - b.r, dzb = zc - b.z;
+  const double t0 = fabs(dra * dzb - dza * drb);
+  const double lab2 = dra * dra + dza * dza;
+  const double lbc2 = drb * drb + dzb * dzb;
+  const double L = t0 * t0, R = c.arz2 * lab2 * lbc2;
+  if (L > R * kBandHi) return false;
+  if (L < R * kBandLo) return true;
+  return t0 <= c.arz * sqrt(lab2) * sqrt(lbc2);
+}
+
+__device__ __forceinline__ bool link_xy_pass(const DevCfg& c, const HitD& a, const HitD& b,
+                                             const HitD& h) {
+  const double ux = b.x - a.x, uy = b.y - a.y;
+  const double vx = h.x - a.x, vy = h.y - a.y;
+  const double wx = h.x - b.x, wy = h.y - b.y;
+  const double cr = ux * vy - uy * vx;
+  const double ab2 = ux * ux + uy * uy;
+  const double ac2 = vx * vx + vy * vy;
+  const double bc2 = wx * wx + wy * wy;
+  const double t2 = 2.0 * fabs(cr);
+  {
+    const double L = t2 * t2, R = c.kmax2 * ab2 * bc2 * ac2;
+    if (L > R * kBandHi) return false;
+    if (!(L < R * kBandLo) && !(t2 <= c.kmax * sqrt(ab2) * sqrt(bc2) * sqrt(ac2)))
+      return false;
+  }
+  const double D = 2.0 * cr;
+  double d0;
+  if (D == 0.0) {
+    d0 = fabs(a.x * vy - a.y * vx) / sqrt(ac2);
+  } else {
+    const double ox = (vy * ab2 - uy * ac2) / D;
+    const double oy = (ux * ac2 - vx * ab2) / D;
+    const double R = sqrt(ox * ox + oy * oy);
+    const double cx = a.x + ox, cy = a.y + oy;
+    const double dc = sqrt(cx * cx + cy * cy);
+    const double aa = a.x * a.x + a.y * a.y;
+    const double ao = a.x * ox + a.y * oy;
+    d0 = fabs(aa + 2.0 * ao) / (dc + R);
+  }
+  return d0 <= c.d0max;
+}
+
 // Cleaning score of one consecutive hit triple.
 __device__ __forceinline__ double triple_score(const DevCfg& c, const HitD& a,
                                                const HitD& b, const HitD& h) {

@@ -177,16 +177,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 }
 
 // ------------------------------------------------------------- doublets --
-// One thread per binned inner hit.  For every layer pair leaving its layer,
-// the outer layer's hits are visited only inside a phi window that is a
+// For every binned inner hit and every layer pair leaving its layer, the
+// outer layer's hits are visited only inside a phi window that is a
 // superset of every pair passing D3/D4: a circle through the origin with
 // curvature <= kmax turns by asin(kmax r_o / 2) - asin(kmax r_i / 2) between
 // radii r_i and r_o, which grows with r_o, so the window uses the largest
 // outer radius of the event's layer, plus one guard bin per side.  The cut
 // itself decides, so the window never changes the result.
+//
+// Work split: a group of G lanes (G = 16, 32 or 64) handles one inner hit;
+// its lanes take consecutive candidates of the window, so the candidate
+// loads are coalesced, and a ballot over the group gives each accepted
+// doublet its position (count pass: the popcount; fill pass: the prefix),
+// so the fill writes are coalesced too and keep the candidate order.  Each
+// block processes one contiguous chunk of inner hits (XCD-aware remap).
 
-template <bool FILL>
-__global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c, uint32_t hit_bound) {
+template <int G, bool FILL>
+__global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
   const uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nb = ctr[C_NBINNED];
@@ -197,113 +204,163 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c, uint32_t hit_b
     }
     return;
   }
-  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nb; g += gridDim.x * blockDim.x) {
-    const int li = w.blay[g];
-    const uint32_t e = w.bevt[g];
-    const HitD hi = load_hit(w, g);
-    const float ri = (float)hi.r;
-    const float phi = w.bphi[g];
+  const uint32_t lane = lane_id(), sub = lane % G, grp = lane / G;
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull) << (grp * G);
+  const uint64_t below = gmask & ((1ull << lane) - 1ull);
+  const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
+  const uint32_t chunk = (nb + gridDim.x - 1) / gridDim.x;
+  const uint32_t beg = min(nb, xcd_block() * chunk), end = min(nb, beg + chunk);
+  for (uint32_t base = beg; base < end; base += gpb) {
+    const uint32_t g = base + gib;
+    const bool active = g < end;
+    int li = 0, npairs = 0;
+    uint32_t e = 0;
+    HitD hi{0.0, 0.0, 0.0, 0.0};
+    float ri = 0.0f, phi = 0.0f;
+    if (active) {
+      li = w.blay[g];
+      e = w.bevt[g];
+      hi = load_hit(w, g);
+      ri = (float)hi.r;
+      phi = w.bphi[g];
+      npairs = c.n_outer[li];
+    }
     uint32_t cnt = 0;
-    uint32_t pos = FILL ? w.cell_off[g] : 0u;
-    for (int p = 0; p < c.n_outer[li]; ++p) {
-      const int lo = c.outer[li][p];
-      const float rmo = __uint_as_float(w.rmax[e * c.n_layers + lo]) * 1.000001f;
-      if (!(rmo > ri * 0.999999f)) continue;
-      const uint32_t base = (e * (uint32_t)c.n_layers + (uint32_t)lo) * (uint32_t)c.nphi;
-      const float ao = 0.5f * c.kmax_f * rmo;
-      int blo = 0, bhi = c.nphi - 1;
-      bool full = ao >= 0.70710678f;
-      if (!full) {
-        const float W = asinf(ao) - asinf(0.5f * c.kmax_f * ri);
-        if (!(W >= 0.0f && W < 4.0f && phi >= -4.0f && phi <= 4.0f)) {
-          full = true;  // non-finite input: fall back to the whole layer
-        } else {
-          blo = (int)floorf((phi - W + kPiF) * c.phi_scale) - 1;
-          bhi = (int)floorf((phi + W + kPiF) * c.phi_scale) + 1;
-          full = bhi - blo + 1 >= c.nphi;
-        }
-      }
-      uint32_t seg_b[2], seg_e[2];
-      int nseg;
-      if (full) {
-        seg_b[0] = w.bin_off[base];
-        seg_e[0] = w.bin_off[base + c.nphi];
-        nseg = 1;
-      } else if (blo < 0) {
-        seg_b[0] = w.bin_off[base + blo + c.nphi];
-        seg_e[0] = w.bin_off[base + c.nphi];
-        seg_b[1] = w.bin_off[base];
-        seg_e[1] = w.bin_off[base + bhi + 1];
-        nseg = 2;
-      } else if (bhi >= c.nphi) {
-        seg_b[0] = w.bin_off[base + blo];
-        seg_e[0] = w.bin_off[base + c.nphi];
-        seg_b[1] = w.bin_off[base];
-        seg_e[1] = w.bin_off[base + bhi - c.nphi + 1];
-        nseg = 2;
-      } else {
-        seg_b[0] = w.bin_off[base + blo];
-        seg_e[0] = w.bin_off[base + bhi + 1];
-        nseg = 1;
-      }
-      for (int s = 0; s < nseg; ++s) {
-        for (uint32_t j = seg_b[s]; j < seg_e[s]; ++j) {
-          const HitD ho = load_hit(w, j);
-          if (doublet_ok(c, hi, ho)) {
-            if (FILL) {
-              w.cin[pos] = g;
-              w.cout[pos] = j;
-              const uint32_t deg = w.cell_off[j + 1] - w.cell_off[j];
-              w.mw[pos] = (deg + 63u) >> 6;
-              w.has_inner[pos] = 0;
-              w.ccnt[pos] = 0;
-              ++pos;
+    uint32_t pos = (FILL && active) ? w.cell_off[g] : 0u;
+    const uint32_t maxp = wave_max((uint32_t)npairs);
+    for (uint32_t p = 0; p < maxp; ++p) {
+      uint32_t s0b = 0, s0n = 0, s1b = 0, s1n = 0;
+      if (active && (int)p < npairs) {
+        const int lo = c.outer[li][p];
+        const float rmo = __uint_as_float(w.rmax[e * c.n_layers + lo]) * 1.000001f;
+        if (rmo > ri * 0.999999f) {
+          const uint32_t bb = (e * (uint32_t)c.n_layers + (uint32_t)lo) * (uint32_t)c.nphi;
+          const float ao = 0.5f * c.kmax_f * rmo;
+          int blo = 0, bhi = c.nphi - 1;
+          bool full = ao >= 0.70710678f;
+          if (!full) {
+            const float W = asinf(ao) - asinf(0.5f * c.kmax_f * ri);
+            if (!(W >= 0.0f && W < 4.0f && phi >= -4.0f && phi <= 4.0f)) {
+              full = true;  // non-finite input: fall back to the whole layer
             } else {
-              ++cnt;
+              blo = (int)floorf((phi - W + kPiF) * c.phi_scale) - 1;
+              bhi = (int)floorf((phi + W + kPiF) * c.phi_scale) + 1;
+              full = bhi - blo + 1 >= c.nphi;
             }
+          }
+          if (full) {
+            s0b = w.bin_off[bb];
+            s0n = w.bin_off[bb + c.nphi] - s0b;
+          } else if (blo < 0) {
+            s0b = w.bin_off[bb + blo + c.nphi];
+            s0n = w.bin_off[bb + c.nphi] - s0b;
+            s1b = w.bin_off[bb];
+            s1n = w.bin_off[bb + bhi + 1] - s1b;
+          } else if (bhi >= c.nphi) {
+            s0b = w.bin_off[bb + blo];
+            s0n = w.bin_off[bb + c.nphi] - s0b;
+            s1b = w.bin_off[bb];
+            s1n = w.bin_off[bb + bhi - c.nphi + 1] - s1b;
+          } else {
+            s0b = w.bin_off[bb + blo];
+            s0n = w.bin_off[bb + bhi + 1] - s0b;
           }
         }
       }
+      const uint32_t tot = s0n + s1n;
+      const uint32_t maxit = wave_max((tot + G - 1) / G);
+      for (uint32_t it = 0; it < maxit; ++it) {
+        const uint32_t k = it * G + sub;
+        bool ok = false;
+        uint32_t j = 0;
+        if (k < tot) {
+          j = k < s0n ? s0b + k : s1b + (k - s0n);
+          ok = doublet_ok_fast(c, hi, load_hit(w, j));
+        }
+        const uint64_t bal = __ballot(ok);
+        if (FILL && ok) {
+          const uint32_t q = pos + (uint32_t)__popcll(bal & below);
+          w.cin[q] = g;
+          w.cout[q] = j;
+          const uint32_t jb = w.cell_off[j], deg = w.cell_off[j + 1] - jb;
+          w.mw[q] = (deg + 63u) >> 6;
+          w.cb[q] = jb;
+          w.cdeg[q] = deg;
+          w.has_inner[q] = 0;
+          w.ccnt[q] = 0;
+          w.nout[q] = 0;
+          const HitD ho = load_hit(w, j);
+          w.ox[q] = (float)ho.x;
+          w.oy[q] = (float)ho.y;
+          w.oz[q] = (float)ho.z;
+          w.orr[q] = ho.r;
+        }
+        const uint32_t ng = (uint32_t)__popcll(bal & gmask);
+        pos += ng;
+        cnt += ng;
+      }
     }
-    if (!FILL) w.dcnt[g] = cnt;
+    if (!FILL && active && sub == 0) w.dcnt[g] = cnt;
   }
 }
 
 // ---------------------------------------------------------------- links --
-// One thread per doublet (a,b).  Its candidate outer neighbours are the
-// doublets leaving hit b: the contiguous range cell_off[b] .. cell_off[b+1]
-// (doublets are stored grouped by inner hit).  The accepted ones are kept as
-// a bit mask over that range, one 64-bit word per 64 candidates, so a single
-// evaluation pass needs no second pass and no atomics.
+// The candidate outer neighbours of doublet (a,b) are the doublets leaving
+// hit b: the contiguous range cell_off[b] .. cell_off[b+1] (doublets are
+// stored grouped by inner hit).  Each doublet carries a copy of its outer
+// hit's coordinates, so the candidates' (r, z) -- all that the r-z cut,
+// which rejects the great majority, needs -- are read sequentially; x, y
+// follow only for candidates that pass it.  The accepted candidates form a
+// bit mask over the range, one 64-bit word per 64 candidates.
 
-__global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
+__device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c, uint32_t nd) {
+  const uint32_t nwords = w.moff[nd];
+  if (nwords <= c.cap_words) return true;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    set_status(w.ctr, PXT_ERR_CAPACITY);
+    w.ctr[C_REQ_W] = nwords;
+  }
+  return false;
+}
+
+// One thread per doublet (a,b), looping over its candidates.
+__global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
-  const uint32_t nwords = w.moff[nd];
-  if (nwords > c.cap_words) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      set_status(ctr, PXT_ERR_CAPACITY);
-      ctr[C_REQ_W] = nwords;
-    }
-    return;
-  }
+  if (!links_capacity(w, c, nd)) return;
   uint32_t links = 0;
-  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
-    const uint32_t a = w.cin[d], b = w.cout[d];
-    const HitD ha = load_hit(w, a), hb = load_hit(w, b);
-    const uint32_t k0 = w.cell_off[b], deg = w.cell_off[b + 1] - k0;
+  for (uint32_t d = xcd_block() * blockDim.x + threadIdx.x; d < nd;
+       d += gridDim.x * blockDim.x) {
+    const HitD ha = load_hit(w, w.cin[d]);
+    const HitD hb{(double)w.ox[d], (double)w.oy[d], (double)w.oz[d], w.orr[d]};
+    const uint32_t k0 = w.cb[d], deg = w.cdeg[d];
     const uint32_t mo = w.moff[d];
     uint32_t nout = 0;
     for (uint32_t wd = 0; wd * 64u < deg; ++wd) {
       uint64_t mask = 0;
       const uint32_t lim = min(64u, deg - wd * 64u);
-      for (uint32_t bit = 0; bit < lim; ++bit) {
-        const uint32_t d2 = k0 + wd * 64u + bit;
-        const HitD hc = load_hit(w, w.cout[d2]);
-        if (link_ok(c, ha, hb, hc)) {
-          mask |= 1ull << bit;
-          w.has_inner[d2] = 1;
+      for (uint32_t b8 = 0; b8 < lim; b8 += 8) {
+        // issue eight candidates' (r, z) loads before testing them
+        double rc[8];
+        float zc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t d2 = k0 + wd * 64u + b8 + u;
+          const bool in = b8 + u < lim;
+          rc[u] = in ? w.orr[d2] : 0.0;
+          zc[u] = in ? w.oz[d2] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (b8 + u >= lim) break;
+          const uint32_t d2 = k0 + wd * 64u + b8 + u;
+          if (!link_rz_pass(c, ha, hb, rc[u], (double)zc[u])) continue;
+          const HitD hc{(double)w.ox[d2], (double)w.oy[d2], (double)zc[u], rc[u]};
+          if (link_xy_pass(c, ha, hb, hc)) {
+            mask |= 1ull << (b8 + u);
+            w.has_inner[d2] = 1;
+          }
         }
       }
       w.masks[mo + wd] = mask;
@@ -314,6 +371,112 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
   }
   links = wave_sum(links);
   if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
+}
+
+// A group of G lanes per doublet (a,b).  Each step covers 64 consecutive
+// candidates: lane l of the group takes candidates l, l + G, ..., issuing
+// the U = 64 / G loads of their (r, z) back to back before the r-z tests.
+// The few candidates that pass the r-z cut are not tested further in place
+// -- the transverse tests (divisions, square roots) would run with almost
+// all lanes idle -- but pushed to a per-wavefront queue in LDS; whenever 64
+// are queued they are tested with all lanes busy.  Accepted links set their
+// bit in the (pre-cleared) mask word with atomicOr and count into nout.
+
+constexpr int kQueue = 128;  // queue entries per wavefront
+
+__device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint2* q, uint32_t n,
+                                            uint32_t& links) {
+  const uint32_t lane = lane_id();
+  if (lane < n) {
+    const uint2 it = q[lane];
+    const uint32_t d = it.x, k = it.y;
+    const uint32_t a = w.cin[d];
+    const HitD ha = load_hit(w, a);
+    const HitD hb{(double)w.ox[d], (double)w.oy[d], (double)w.oz[d], w.orr[d]};
+    const uint32_t d2 = w.cb[d] + k;
+    const HitD hc{(double)w.ox[d2], (double)w.oy[d2], (double)w.oz[d2], w.orr[d2]};
+    if (link_xy_pass(c, ha, hb, hc)) {
+      atomicOr((unsigned long long*)&w.masks[w.moff[d] + (k >> 6)], 1ull << (k & 63u));
+      atomicAdd(&w.nout[d], 1u);
+      w.has_inner[d2] = 1;
+      ++links;
+    }
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
+  constexpr int U = kWave / G;
+  __shared__ uint2 queue[256 / kWave][kQueue];
+  uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t nd = ctr[C_ND];
+  if (!links_capacity(w, c, nd)) return;
+  const uint32_t lane = lane_id(), sub = lane % G;
+  uint2* q = queue[threadIdx.x / kWave];
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
+  const uint32_t chunk = (nd + gridDim.x - 1) / gridDim.x;
+  const uint32_t beg = min(nd, xcd_block() * chunk), end = min(nd, beg + chunk);
+  uint32_t links = 0, qn = 0;
+  for (uint32_t base = beg; base < end; base += gpb) {
+    const uint32_t d = base + gib;
+    uint32_t kb = 0, deg = 0;
+    HitD ha{0.0, 0.0, 0.0, 0.0}, hb{0.0, 0.0, 0.0, 0.0};
+    if (d < end) {
+      ha = load_hit(w, w.cin[d]);
+      hb = HitD{(double)w.ox[d], (double)w.oy[d], (double)w.oz[d], w.orr[d]};
+      kb = w.cb[d];
+      deg = w.cdeg[d];
+    }
+    const uint32_t maxw = wave_max((deg + 63u) / 64u);
+    for (uint32_t wd = 0; wd < maxw; ++wd) {
+      double rc[U];
+      float zc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t k = wd * 64u + (uint32_t)(u * G) + sub;
+        rc[u] = 0.0;
+        zc[u] = 0.0f;
+        if (k < deg) {
+          rc[u] = w.orr[kb + k];
+          zc[u] = w.oz[kb + k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t k = wd * 64u + (uint32_t)(u * G) + sub;
+        const bool ok = k < deg && link_rz_pass(c, ha, hb, rc[u], (double)zc[u]);
+        const uint64_t bal = __ballot(ok);
+        if (ok) q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(d, k);
+        qn += (uint32_t)__popcll(bal);
+        if (qn >= (uint32_t)kWave) {
+          __threadfence_block();
+          links_flush(w, c, q, kWave, links);
+          __threadfence_block();
+          const uint32_t rest = qn - kWave;
+          const uint2 mv = lane < rest ? q[kWave + lane] : make_uint2(0, 0);
+          __threadfence_block();
+          if (lane < rest) q[lane] = mv;
+          __threadfence_block();
+          qn = rest;
+        }
+      }
+    }
+  }
+  __threadfence_block();
+  links_flush(w, c, q, qn, links);
+  links = wave_sum(links);
+  if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
+}
+
+// Clears the link-mask words ahead of the queued link kernel.
+__global__ __launch_bounds__(256) void k_zero_words(Ws w, DevCfg c) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t n = w.moff[w.ctr[C_ND]];
+  if (n > c.cap_words) return;  // reported by the link kernel
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    w.masks[i] = 0;
 }
 
 // ------------------------------------------------------------ n-tuplets --

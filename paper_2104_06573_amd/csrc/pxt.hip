@@ -98,6 +98,12 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
+  w.ox = cv.take<float>(D);
+  w.oy = cv.take<float>(D);
+  w.oz = cv.take<float>(D);
+  w.orr = cv.take<double>(D);
+  w.cb = cv.take<uint32_t>(D);
+  w.cdeg = cv.take<uint32_t>(D);
   w.rcnt = cv.take<uint32_t>(D + 1);
   w.roff = cv.take<uint32_t>(D + 1);
   w.thit = cv.take<uint32_t>(8 * T);
@@ -145,6 +151,9 @@ int validate_config(const pxt_config* c, std::string& why) {
   if (c->block_size < 64 || c->block_size > 256 || c->block_size % 64)
     return why = "block_size must be 64, 128, 192 or 256", 1;
   if (!(c->pt_fp64 > 0)) return why = "pt_fp64 must be > 0", 1;
+  if (c->group_lanes != 16 && c->group_lanes != 32 && c->group_lanes != 64)
+    return why = "group_lanes must be 16, 32 or 64", 1;
+  if (c->link_kernel != 0 && c->link_kernel != 1) return why = "link_kernel must be 0 or 1", 1;
   return 0;
 }
 
@@ -160,6 +169,8 @@ void make_devcfg(const pxt_config& c, DevCfg& d) {
     d.outer[a][d.n_outer[a]++] = c.pair_outer[i];
   }
   d.kmax = c.kmax;
+  d.kmax2 = c.kmax * c.kmax;
+  d.arz2 = c.arz * c.arz;
   d.z0max = c.z0max;
   d.arz = c.arz;
   d.d0max = c.d0max;
@@ -173,6 +184,7 @@ void make_devcfg(const pxt_config& c, DevCfg& d) {
   d.cap_doublets = c.max_doublets;
   d.cap_words = c.max_link_words;
   d.cap_tuples = c.max_tuples;
+  d.link_thread = c.link_kernel == 0;
 }
 
 // Launch the three-kernel exclusive scan of n = *n_dev entries.
@@ -206,6 +218,36 @@ uint32_t grid_for(uint64_t items, int bs, uint32_t cap_blocks) {
   uint64_t g = (items + bs - 1) / bs;
   if (g < 1) g = 1;
   return (uint32_t)std::min<uint64_t>(g, cap_blocks);
+}
+
+// Grid of the chunked group kernels: a multiple of 8 blocks (an equal share
+// per XCD), about four items per lane group, at most cap_blocks.
+uint32_t grid_chunked(uint64_t items, int bs, int G, uint32_t cap_blocks) {
+  const uint64_t groups = (items + 3) / 4;
+  uint64_t g = (groups * G + bs - 1) / bs;
+  g = std::max<uint64_t>(8, (g + 7) / 8 * 8);
+  return (uint32_t)std::min<uint64_t>(g, cap_blocks / 8 * 8);
+}
+
+template <bool FILL>
+void launch_doublets(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, const DevCfg& d) {
+  switch (G) {
+    case 16: hipLaunchKernelGGL((k_doublets<16, FILL>), grid, block, 0, s, w, d); break;
+    case 64: hipLaunchKernelGGL((k_doublets<64, FILL>), grid, block, 0, s, w, d); break;
+    default: hipLaunchKernelGGL((k_doublets<32, FILL>), grid, block, 0, s, w, d); break;
+  }
+}
+
+void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, const DevCfg& d) {
+  if (d.link_thread) {
+    hipLaunchKernelGGL(k_links_thread, grid, block, 0, s, w, d);
+    return;
+  }
+  switch (G) {
+    case 16: hipLaunchKernelGGL((k_links<16>), grid, block, 0, s, w, d); break;
+    case 64: hipLaunchKernelGGL((k_links<64>), grid, block, 0, s, w, d); break;
+    default: hipLaunchKernelGGL((k_links<32>), grid, block, 0, s, w, d); break;
+  }
 }
 
 }  // namespace
@@ -242,6 +284,8 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->max_tuples = 1u << 22;
   cfg->phi_bins = 256;
   cfg->block_size = 256;
+  cfg->group_lanes = 32;
+  cfg->link_kernel = 0;
   cfg->pt_fp64 = 20.0;
   return PXT_OK;
 }
@@ -353,20 +397,25 @@ int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* strea
     sm.mark(3);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(H, 256, 1u << 30)), dim3(256), 0, s, in->x, in->y,
                        in->z, in->layer, H, E, w);
-    const uint32_t gh = grid_for(H, bs, persist);
     hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
                        dim3(256), 0, s, w, E, (uint32_t)cfg.n_layers, (uint32_t)cfg.phi_bins);
+    const int G = cfg.group_lanes;
+    const uint32_t gh = grid_chunked(H, bs, G, persist);
     sm.mark(4);
-    hipLaunchKernelGGL(k_doublets<false>, dim3(gh), dim3(bs), 0, s, w, d, H);
+    launch_doublets<false>(G, dim3(gh), dim3(bs), s, w, d);
     sm.mark(5);
     launch_scan(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, s);
     sm.mark(6);
-    hipLaunchKernelGGL(k_doublets<true>, dim3(gh), dim3(bs), 0, s, w, d, H);
+    launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
     sm.mark(7);
     launch_scan(w, w.mw, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, s);
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
+    if (cfg.link_kernel)
+      hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
     sm.mark(8);
-    hipLaunchKernelGGL(k_links, dim3(gd), dim3(bs), 0, s, w, d);
+    launch_links(G, dim3(cfg.link_kernel ? grid_chunked((uint64_t)H * 16, bs, G, persist)
+                                          : std::max<uint32_t>(8, gd / 8 * 8)),
+                 dim3(bs), s, w, d);
     sm.mark(9);
     hipLaunchKernelGGL(k_tuples<false>, dim3(gd), dim3(bs), 0, s, w, d);
     launch_scan(w, w.rcnt, w.roff, w.ctr + C_ND, w.ctr + C_NTUP, s);

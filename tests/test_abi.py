@@ -63,3 +63,30 @@ def test_null_arguments_rejected():
     cnt = ctypes.c_uint64()
     assert L.pxt_debug_dump(None, 0, None, 0, ctypes.byref(cnt), None) == pxt.ERR_INVALID_ARG
     L.pxt_destroy(None)
+
+
+def test_struct_sizes_match_header():
+    # compile a probe of sizeof/offsetof with the host compiler and compare
+    import subprocess
+    import tempfile
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "pxt.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pxt_config), offsetof(pxt_config, pt_fp64),
+         offsetof(pxt_config, group_lanes), sizeof(pxt_hits), sizeof(pxt_tracks),
+         sizeof(pxt_counts));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "p.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "p")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
+        got = list(map(int, subprocess.check_output([exe]).split()))
+    want = [ctypes.sizeof(pxt.PxtConfig), pxt.PxtConfig.pt_fp64.offset,
+            pxt.PxtConfig.group_lanes.offset, ctypes.sizeof(pxt.PxtHits),
+            ctypes.sizeof(pxt.PxtTracks), ctypes.sizeof(pxt.PxtCounts)]
+    assert got == want

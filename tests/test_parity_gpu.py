@@ -145,11 +145,14 @@ def test_batch_equivalence(torch):
             np.testing.assert_array_equal(alone[2], other[2])
 
 
-@pytest.mark.parametrize("phi_bins,block", [(16, 256), (64, 64), (1024, 128), (4096, 256)])
-def test_tuning_invariance(torch, phi_bins, block):
+@pytest.mark.parametrize("phi_bins,block,group,lk", [(16, 256, 16, 0), (64, 64, 64, 1),
+                                                     (1024, 128, 32, 1), (4096, 256, 16, 1),
+                                                     (256, 192, 64, 0), (256, 64, 16, 0)])
+def test_tuning_invariance(torch, phi_bins, block, group, lk):
     events = [eventgen.generate("pu50", 55), eventgen.generate("tiny", 3)]
     ref = _tracks_by_event(make_rec().run_numpy(events).numpy(), 2)
-    got = _tracks_by_event(make_rec(phi_bins=phi_bins, block_size=block).run_numpy(events).numpy(), 2)
+    got = _tracks_by_event(make_rec(phi_bins=phi_bins, block_size=block, group_lanes=group,
+                                    link_kernel=lk).run_numpy(events).numpy(), 2)
     for a, b in zip(ref, got):
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
