@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--phi-bins", type=int, default=256)
     ap.add_argument("--group-lanes", type=int, default=32)
     ap.add_argument("--link-kernel", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
     return ap.parse_args()
 
 
@@ -137,7 +138,7 @@ def main():
                             max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
                             max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
                             phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                            link_kernel=args.link_kernel)
+                            link_kernel=args.link_kernel, use_graph=args.graph)
     dev_batches = [rec.upload(b) for b in pool]
     torch.cuda.synchronize()
 
@@ -161,8 +162,15 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     ev_per_s = B * args.steps / dt
 
-    # stage breakdown with HIP events on the library's stream
-    stages = rec.stage_times(dev_batches[0], repeats=5)
+    # stage breakdown with HIP events on the library's stream (direct mode:
+    # events cannot sit inside the replayed graph)
+    trec = pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
+                             max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
+                             max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
+                             phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                             link_kernel=args.link_kernel, use_graph=0)
+    stages = trec.stage_times(trec.upload(pool[0]), repeats=5)
+    trec.close()
 
     # plain path: one event per call, synchronised per event
     plain_events = [e for b in pool for e in b][: args.plain_events]
@@ -170,7 +178,7 @@ def main():
                              max_doublets=per_ev_d * 2, max_link_words=per_ev_d * 2,
                              max_tuples=per_ev_t * 2, max_tracks=per_ev_t * 2,
                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                            link_kernel=args.link_kernel)
+                            link_kernel=args.link_kernel, use_graph=args.graph)
     plain_dev = [prec.upload([e]) for e in plain_events]
     for i in range(min(4, len(plain_dev))):
         prec.launch(*plain_dev[i])
@@ -203,6 +211,7 @@ def main():
             "phi_bins": args.phi_bins,
             "group_lanes": args.group_lanes,
             "link_kernel": args.link_kernel,
+            "hip_graph": bool(args.graph),
             "path": "batched (one launch sequence per batch)",
         },
         "plain_events_per_s": round(plain_ev_s, 2),

@@ -98,6 +98,9 @@ typedef struct pxt_config {
                                16, 32 or 64                                */
   int32_t link_kernel;      /* link step: 0 one thread per doublet,
                                1 one lane group per doublet               */
+  int32_t use_graph;        /* 1: replay the launch sequence as a HIP
+                               graph captured at the first call (stage
+                               timing is then unavailable)                */
   double pt_fp64;           /* fit tuples with pT_ref above this in FP64   */
 } pxt_config;
 

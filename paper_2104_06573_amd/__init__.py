@@ -53,6 +53,7 @@ class PxtConfig(ctypes.Structure):
         ("max_tuples", ctypes.c_uint32),
         ("phi_bins", ctypes.c_int32), ("block_size", ctypes.c_int32),
         ("group_lanes", ctypes.c_int32), ("link_kernel", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
         ("pt_fp64", ctypes.c_double),
     ]
 
@@ -135,7 +136,7 @@ def stage_names():
 
 def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
                 max_link_words=None, max_tuples=1 << 19, phi_bins=256, block_size=256,
-                group_lanes=32, link_kernel=0, pt_fp64=20.0):
+                group_lanes=32, link_kernel=0, use_graph=0, pt_fp64=20.0):
     """pxt_config from a detector dictionary (eventgen.DETECTOR layout)."""
     c = PxtConfig()
     if lib().pxt_config_defaults(ctypes.byref(c)) != OK:
@@ -162,6 +163,7 @@ def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
     c.block_size = block_size
     c.group_lanes = group_lanes
     c.link_kernel = link_kernel
+    c.use_graph = use_graph
     c.pt_fp64 = pt_fp64
     return c
 

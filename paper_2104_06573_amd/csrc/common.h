@@ -56,10 +56,13 @@ struct DevCfg {
   int link_thread;                          // one thread per doublet in links
 };
 
+struct CallDesc;
+
 // Device arenas of one context.
 struct Ws {
+  const CallDesc* call;   // descriptor of the current call
   uint32_t* ctr;          // [C_NCTR]
-  uint32_t* evt_off;      // [E + 1]
+  uint32_t* evt_off;      // [E + 1] (follows the descriptor)
   uint32_t* keys;         // [H]   bin key of each input hit
   uint32_t* bin_cnt;      // [nbins + 1]
   uint32_t* bin_off;      // [nbins + 1]

@@ -28,71 +28,90 @@ struct OutPtrs {
   pxt_counts* counts;
 };
 
+// Per-call values live in device memory (CallDesc, copied from a pinned
+// host slot at the start of each call), so a launch sequence captured once
+// in a HIP graph serves every later call: only the descriptor changes.
+struct CallDesc {
+  uint32_t n_events;
+  uint32_t n_hits;
+  uint32_t pad[2];
+  const float* x;
+  const float* y;
+  const float* z;
+  const int16_t* layer;
+  OutPtrs out;
+};
+
 // ------------------------------------------------------------------ clear
 
-__global__ void k_clear(Ws w, uint32_t n_events, uint32_t n_layers, uint32_t nbins,
-                        uint32_t* per_event_tracks) {
+__global__ void k_clear(Ws w, DevCfg c) {
+  const CallDesc* cd = w.call;
+  const uint32_t E = cd->n_events;
+  const uint32_t nbins = E * (uint32_t)c.n_layers * (uint32_t)c.nphi;
+  uint32_t* per_event_tracks = cd->out.per_event_tracks;
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = tid; i < nbins + 1; i += stride) w.bin_cnt[i] = 0;
-  for (uint32_t i = tid; i < n_events; i += stride) per_event_tracks[i] = 0;
+  for (uint32_t i = tid; i < E; i += stride) per_event_tracks[i] = 0;
   if (tid < C_NCTR) w.ctr[tid] = tid == C_NBINS ? nbins : 0u;
 }
 
 // ------------------------------------------------------- binning (prep) --
 
-__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ x,
-                                              const float* __restrict__ y,
-                                              const int16_t* __restrict__ layer,
-                                              uint32_t n_hits, uint32_t n_events,
-                                              Ws w, DevCfg c) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_hits) return;
-  const uint32_t e = upper_bound_u32(w.evt_off, n_events + 1, g) - 1;
-  const int l = layer[g];
-  if (l < 0 || l >= c.n_layers) {
-    w.keys[g] = kPad;
-    return;
+__global__ __launch_bounds__(256) void k_prep(Ws w, DevCfg c) {
+  const CallDesc* cd = w.call;
+  const uint32_t H = cd->n_hits, E = cd->n_events;
+  const float* __restrict__ x = cd->x;
+  const float* __restrict__ y = cd->y;
+  const int16_t* __restrict__ layer = cd->layer;
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < H; g += gridDim.x * blockDim.x) {
+    const uint32_t e = upper_bound_u32(w.evt_off, E + 1, g) - 1;
+    const int l = layer[g];
+    if (l < 0 || l >= c.n_layers) {
+      w.keys[g] = kPad;
+      continue;
+    }
+    const float xf = x[g], yf = y[g];
+    const float phi = atan2f(yf, xf);
+    int b = (int)((phi + kPiF) * c.phi_scale);
+    b = b < 0 ? 0 : (b >= c.nphi ? c.nphi - 1 : b);
+    const uint32_t key = (e * (uint32_t)c.n_layers + (uint32_t)l) * (uint32_t)c.nphi + (uint32_t)b;
+    w.keys[g] = key;
+    atomicAdd(&w.bin_cnt[key], 1u);
   }
-  const float xf = x[g], yf = y[g];
-  const float phi = atan2f(yf, xf);
-  int b = (int)((phi + kPiF) * c.phi_scale);
-  b = b < 0 ? 0 : (b >= c.nphi ? c.nphi - 1 : b);
-  const uint32_t key = (e * (uint32_t)c.n_layers + (uint32_t)l) * (uint32_t)c.nphi + (uint32_t)b;
-  w.keys[g] = key;
-  atomicAdd(&w.bin_cnt[key], 1u);
 }
 
-__global__ __launch_bounds__(256) void k_fill(const float* __restrict__ x,
-                                              const float* __restrict__ y,
-                                              const float* __restrict__ z,
-                                              const int16_t* __restrict__ layer,
-                                              uint32_t n_hits, uint32_t n_events,
-                                              Ws w) {
-  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_hits) return;
-  const uint32_t key = w.keys[g];
-  if (key == kPad) return;
-  const uint32_t e = upper_bound_u32(w.evt_off, n_events + 1, g) - 1;
-  const uint32_t pos = w.bin_off[key] + atomicSub(&w.bin_cnt[key], 1u) - 1u;
-  const float xf = x[g], yf = y[g];
-  w.bx[pos] = xf;
-  w.by[pos] = yf;
-  w.bz[pos] = z[g];
-  const double X = (double)xf, Y = (double)yf;
-  w.br[pos] = sqrt(X * X + Y * Y);
-  w.bphi[pos] = atan2f(yf, xf);
-  w.bidx[pos] = g - w.evt_off[e];
-  w.bevt[pos] = e;
-  w.blay[pos] = (uint8_t)layer[g];
+__global__ __launch_bounds__(256) void k_fill(Ws w) {
+  const CallDesc* cd = w.call;
+  const uint32_t H = cd->n_hits, E = cd->n_events;
+  const float* __restrict__ x = cd->x;
+  const float* __restrict__ y = cd->y;
+  const float* __restrict__ z = cd->z;
+  const int16_t* __restrict__ layer = cd->layer;
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < H; g += gridDim.x * blockDim.x) {
+    const uint32_t key = w.keys[g];
+    if (key == kPad) continue;
+    const uint32_t e = upper_bound_u32(w.evt_off, E + 1, g) - 1;
+    const uint32_t pos = w.bin_off[key] + atomicSub(&w.bin_cnt[key], 1u) - 1u;
+    const float xf = x[g], yf = y[g];
+    w.bx[pos] = xf;
+    w.by[pos] = yf;
+    w.bz[pos] = z[g];
+    const double X = (double)xf, Y = (double)yf;
+    w.br[pos] = sqrt(X * X + Y * Y);
+    w.bphi[pos] = atan2f(yf, xf);
+    w.bidx[pos] = g - w.evt_off[e];
+    w.bevt[pos] = e;
+    w.blay[pos] = (uint8_t)layer[g];
+  }
 }
 
 // Largest transverse radius of each (event, layer): one wavefront per
 // segment of the binned array (hits of one layer of one event are
 // contiguous), a max-reduction across lanes.
-__global__ __launch_bounds__(256) void k_rmax(Ws w, uint32_t n_events, uint32_t n_layers,
-                                              uint32_t nphi) {
-  const uint32_t nseg = n_events * n_layers;
+__global__ __launch_bounds__(256) void k_rmax(Ws w, DevCfg c) {
+  const uint32_t n_layers = (uint32_t)c.n_layers, nphi = (uint32_t)c.nphi;
+  const uint32_t nseg = w.call->n_events * n_layers;
   const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
   for (uint32_t sg = wid; sg < nseg; sg += nwaves) {
@@ -653,9 +672,10 @@ __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
 // Survivors in n-tuplet order (offsets from the scan of the alive flags);
 // per-event track counts from the event boundaries, which the binned hits,
 // doublets, n-tuplets and survivors all respect in that order.
-__global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c, uint32_t n_events,
-                                                 uint32_t* per_event_tracks) {
+__global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
+  const uint32_t n_events = w.call->n_events;
+  uint32_t* per_event_tracks = w.call->out.per_event_tracks;
   const uint32_t ntup = w.ctr[C_NTUP];
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t t = tid; t < ntup; t += gridDim.x * blockDim.x)
@@ -717,8 +737,9 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   }
 }
 
-__global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c, OutPtrs o) {
+__global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
+  const OutPtrs o = w.call->out;
   const uint32_t ns = w.ctr[C_NSURV];
   if (ns > o.capacity) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -731,8 +752,9 @@ __global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c, OutPtrs o) {
     fit_one<float>(w, c, o, s, false);
 }
 
-__global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c, OutPtrs o) {
+__global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
+  const OutPtrs o = w.call->out;
   const uint32_t n64 = w.ctr[C_NFP64];
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n64; k += gridDim.x * blockDim.x)
     fit_one<double>(w, c, o, w.fp64_list[k], true);
@@ -740,10 +762,10 @@ __global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c, OutPtrs o) {
 
 // --------------------------------------------------------------- finish --
 
-__global__ void k_finish(Ws w, OutPtrs o) {
+__global__ void k_finish(Ws w) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const uint32_t* ctr = w.ctr;
-  pxt_counts* k = o.counts;
+  pxt_counts* k = w.call->out.counts;
   const int st = (int)ctr[C_STATUS];
   k->status = st;
   k->n_tracks = st ? 0u : ctr[C_NSURV];

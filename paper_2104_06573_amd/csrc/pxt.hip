@@ -24,9 +24,19 @@ struct pxt_ctx {
   void* arena = nullptr;
   size_t arena_bytes = 0;
   Ws ws{};
-  uint32_t* h_staging = nullptr;   // pinned copy of the event offsets
-  hipEvent_t staging_free = nullptr;
-  bool staging_pending = false;
+  // ring of pinned host slots holding each call's descriptor and event
+  // offsets; a slot is rewritten only after the call that used it has
+  // consumed it, so the host may run up to kSlots calls ahead
+  static constexpr int kSlots = 4;
+  char* h_slots = nullptr;
+  size_t slot_bytes = 0;
+  hipEvent_t slot_free[kSlots] = {};
+  bool slot_pending[kSlots] = {};
+  int next_slot = 0;
+  // HIP graphs of the launch sequence, one per slot (graph mode)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[kSlots] = {};
+  hipGraphExec_t gexec[kSlots] = {};
   int n_cu = 256;
   std::string err;
   // per-stage timing
@@ -71,12 +81,19 @@ struct Carver {
   }
 };
 
+size_t desc_bytes() { return align_up(sizeof(CallDesc), 64); }
+size_t slot_bytes_for(const pxt_config& c) {
+  return desc_bytes() + sizeof(uint32_t) * ((size_t)c.max_events + 1);
+}
+
 void carve(Carver& cv, const pxt_config& c, Ws& w) {
   const size_t H = c.max_hits, D = c.max_doublets, Wd = c.max_link_words, T = c.max_tuples;
+  const size_t nbins = (size_t)c.max_events * (size_t)c.n_layers * (size_t)c.phi_bins;
   const size_t E = c.max_events;
-  const size_t nbins = E * (size_t)c.n_layers * (size_t)c.phi_bins;
+  char* call = cv.take<char>(slot_bytes_for(c));
+  w.call = reinterpret_cast<const CallDesc*>(call);
+  w.evt_off = call ? reinterpret_cast<uint32_t*>(call + desc_bytes()) : nullptr;
   w.ctr = cv.take<uint32_t>(C_NCTR);
-  w.evt_off = cv.take<uint32_t>(E + 1);
   w.keys = cv.take<uint32_t>(H);
   w.bin_cnt = cv.take<uint32_t>(nbins + 1);
   w.bin_off = cv.take<uint32_t>(nbins + 1);
@@ -154,6 +171,7 @@ int validate_config(const pxt_config* c, std::string& why) {
   if (c->group_lanes != 16 && c->group_lanes != 32 && c->group_lanes != 64)
     return why = "group_lanes must be 16, 32 or 64", 1;
   if (c->link_kernel != 0 && c->link_kernel != 1) return why = "link_kernel must be 0 or 1", 1;
+  if (c->use_graph != 0 && c->use_graph != 1) return why = "use_graph must be 0 or 1", 1;
   return 0;
 }
 
@@ -250,6 +268,89 @@ void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, cons
   }
 }
 
+// The launch sequence of one call on stream s.  In graph mode it is
+// captured once per slot: work sizes come from the capacities and every
+// kernel reads the call's actual sizes from the descriptor; in direct mode
+// the grids are sized from this call's hits (H) and events (E).
+void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, uint32_t E) {
+  const pxt_config& cfg = c->cfg;
+  const Ws& w = c->ws;
+  const DevCfg& d = c->dc;
+  const int bs = cfg.block_size;
+  const uint32_t persist = (uint32_t)c->n_cu * 8u;
+  const size_t copy = graph_mode ? c->slot_bytes : desc_bytes() + sizeof(uint32_t) * (E + 1);
+  (void)hipMemcpyAsync(const_cast<CallDesc*>(w.call), c->h_slots + (size_t)slot * c->slot_bytes,
+                       copy, hipMemcpyHostToDevice, s);
+  if (graph_mode) {
+    H = cfg.max_hits;
+    E = cfg.max_events;
+  }
+  const uint32_t nbins = E * (uint32_t)cfg.n_layers * (uint32_t)cfg.phi_bins;
+  StageMarks sm{c, s};
+  const bool timed = c->timing && !graph_mode;
+  if (timed)
+    for (int i = 0; i < PXT_N_STAGES; ++i) c->stage_run[i] = false;
+  if (timed) sm.mark(0);
+  hipLaunchKernelGGL(k_clear, dim3(grid_for(std::max<uint64_t>(nbins + 1, C_NCTR), 256, persist)),
+                     dim3(256), 0, s, w, d);
+  if (H > 0) {
+    const uint32_t gh1 = grid_for(H, 256, persist);
+    if (timed) sm.mark(1);
+    hipLaunchKernelGGL(k_prep, dim3(gh1), dim3(256), 0, s, w, d);
+    if (timed) sm.mark(2);
+    launch_scan(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, s);
+    if (timed) sm.mark(3);
+    hipLaunchKernelGGL(k_fill, dim3(gh1), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
+                       dim3(256), 0, s, w, d);
+    const int G = cfg.group_lanes;
+    const uint32_t gh = grid_chunked(H, bs, G, persist);
+    if (timed) sm.mark(4);
+    launch_doublets<false>(G, dim3(gh), dim3(bs), s, w, d);
+    if (timed) sm.mark(5);
+    launch_scan(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, s);
+    if (timed) sm.mark(6);
+    launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
+    if (timed) sm.mark(7);
+    launch_scan(w, w.mw, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, s);
+    const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
+    if (cfg.link_kernel) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
+    if (timed) sm.mark(8);
+    launch_links(G, dim3(cfg.link_kernel ? grid_chunked((uint64_t)H * 16, bs, G, persist)
+                                          : std::max<uint32_t>(8, gd / 8 * 8)),
+                 dim3(bs), s, w, d);
+    if (timed) sm.mark(9);
+    hipLaunchKernelGGL(k_tuples<false>, dim3(gd), dim3(bs), 0, s, w, d);
+    launch_scan(w, w.rcnt, w.roff, w.ctr + C_ND, w.ctr + C_NTUP, s);
+    hipLaunchKernelGGL(k_tuples<true>, dim3(gd), dim3(bs), 0, s, w, d);
+    const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
+    if (timed) sm.mark(10);
+    hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
+    if (timed) sm.mark(11);
+    launch_scan(w, w.ccnt, w.coff, w.ctr + C_ND, nullptr, s);
+    if (timed) sm.mark(12);
+    hipLaunchKernelGGL(k_cfill, dim3(gt), dim3(bs), 0, s, w, d);
+    if (timed) sm.mark(13);
+    hipLaunchKernelGGL(k_best, dim3(gd), dim3(bs), 0, s, w, d);
+    if (timed) sm.mark(14);
+    hipLaunchKernelGGL(k_alive, dim3(gt), dim3(bs), 0, s, w, d);
+    launch_scan(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, s);
+    hipLaunchKernelGGL(k_compact, dim3(gt), dim3(bs), 0, s, w, d);
+    if (timed) sm.mark(15);
+    hipLaunchKernelGGL(k_fit32, dim3(grid_for(cfg.max_tuples, 256, persist)), dim3(256), 0, s, w,
+                       d);
+    if (timed) sm.mark(16);
+    hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)c->n_cu)), dim3(64),
+                       0, s, w, d);
+  }
+  if (timed) sm.mark(17);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, w);
+  if (timed) {
+    (void)hipEventRecord(c->ev[PXT_N_STAGES], s);
+    c->timed_valid = true;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -286,6 +387,7 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->block_size = 256;
   cfg->group_lanes = 32;
   cfg->link_kernel = 0;
+  cfg->use_graph = 0;
   cfg->pt_fp64 = 20.0;
   return PXT_OK;
 }
@@ -320,11 +422,15 @@ int pxt_create(const pxt_config* cfg, int hip_device, pxt_ctx** out) {
   Carver real;
   real.base = static_cast<char*>(c->arena);
   carve(real, *cfg, c->ws);
-  if (hipHostMalloc((void**)&c->h_staging, sizeof(uint32_t) * (cfg->max_events + 1),
-                    hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming) != hipSuccess) {
+  c->slot_bytes = slot_bytes_for(*cfg);
+  bool ok = hipHostMalloc((void**)&c->h_slots, c->slot_bytes * pxt_ctx::kSlots,
+                          hipHostMallocDefault) == hipSuccess;
+  for (int i = 0; ok && i < pxt_ctx::kSlots; ++i)
+    ok = hipEventCreateWithFlags(&c->slot_free[i], hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
     pxt_destroy(c);
-    return fail(nullptr, PXT_ERR_HIP, "pinned staging allocation failed");
+    return fail(nullptr, PXT_ERR_HIP, "pinned staging / stream creation failed");
   }
   *out = c;
   return PXT_OK;
@@ -334,10 +440,15 @@ void pxt_destroy(pxt_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  if (c->staging_free) (void)hipEventDestroy(c->staging_free);
+  for (int i = 0; i < pxt_ctx::kSlots; ++i) {
+    if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+    if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+    if (c->slot_free[i]) (void)hipEventDestroy(c->slot_free[i]);
+  }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (int i = 0; i <= PXT_N_STAGES; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-  if (c->h_staging) (void)hipHostFree(c->h_staging);
+  if (c->h_slots) (void)hipHostFree(c->h_slots);
   if (c->arena) (void)hipFree(c->arena);
   delete c;
 }
@@ -365,88 +476,42 @@ int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* strea
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_OR_FAIL(c, hipSetDevice(c->device));
 
-  // offsets -> pinned staging -> device (wait until the previous copy read it)
-  if (c->staging_pending) HIP_OR_FAIL(c, hipEventSynchronize(c->staging_free));
-  std::memcpy(c->h_staging, in->event_offsets, sizeof(uint32_t) * (E + 1));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->ws.evt_off, c->h_staging, sizeof(uint32_t) * (E + 1),
-                                hipMemcpyHostToDevice, s));
-  HIP_OR_FAIL(c, hipEventRecord(c->staging_free, s));
-  c->staging_pending = true;
+  // descriptor + offsets -> pinned slot (after its previous user read it)
+  const int slot = c->next_slot;
+  c->next_slot = (slot + 1) % pxt_ctx::kSlots;
+  if (c->slot_pending[slot]) HIP_OR_FAIL(c, hipEventSynchronize(c->slot_free[slot]));
+  char* hs = c->h_slots + (size_t)slot * c->slot_bytes;
+  CallDesc desc{};
+  desc.n_events = E;
+  desc.n_hits = H;
+  desc.x = in->x;
+  desc.y = in->y;
+  desc.z = in->z;
+  desc.layer = in->layer;
+  desc.out = OutPtrs{out->capacity, out->hit_idx, out->n_hits, out->event_id, out->params,
+                     out->cov, out->chi2, out->flags, out->per_event_tracks, out->counts};
+  std::memcpy(hs, &desc, sizeof(desc));
+  std::memcpy(hs + desc_bytes(), in->event_offsets, sizeof(uint32_t) * (E + 1));
 
-  const Ws& w = c->ws;
-  const DevCfg& d = c->dc;
-  const int bs = cfg.block_size;
-  const uint32_t nbins = E * (uint32_t)cfg.n_layers * (uint32_t)cfg.phi_bins;
-  const uint32_t persist = (uint32_t)c->n_cu * 8u;
-  OutPtrs o{out->capacity, out->hit_idx, out->n_hits, out->event_id, out->params, out->cov,
-            out->chi2, out->flags, out->per_event_tracks, out->counts};
-
-  StageMarks sm{c, s};
-  if (c->timing)
-    for (int i = 0; i < PXT_N_STAGES; ++i) c->stage_run[i] = false;
-  sm.mark(0);
-  hipLaunchKernelGGL(k_clear, dim3(grid_for(std::max<uint64_t>(nbins + 1, C_NCTR), 256, persist)),
-                     dim3(256), 0, s, w, E, (uint32_t)cfg.n_layers, nbins,
-                     E ? out->per_event_tracks : w.ctr + C_NCTR - 1);
-  if (H > 0) {
-    sm.mark(1);
-    hipLaunchKernelGGL(k_prep, dim3(grid_for(H, 256, 1u << 30)), dim3(256), 0, s, in->x, in->y,
-                       in->layer, H, E, w, d);
-    sm.mark(2);
-    launch_scan(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, s);
-    sm.mark(3);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(H, 256, 1u << 30)), dim3(256), 0, s, in->x, in->y,
-                       in->z, in->layer, H, E, w);
-    hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
-                       dim3(256), 0, s, w, E, (uint32_t)cfg.n_layers, (uint32_t)cfg.phi_bins);
-    const int G = cfg.group_lanes;
-    const uint32_t gh = grid_chunked(H, bs, G, persist);
-    sm.mark(4);
-    launch_doublets<false>(G, dim3(gh), dim3(bs), s, w, d);
-    sm.mark(5);
-    launch_scan(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, s);
-    sm.mark(6);
-    launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
-    sm.mark(7);
-    launch_scan(w, w.mw, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, s);
-    const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
-    if (cfg.link_kernel)
-      hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
-    sm.mark(8);
-    launch_links(G, dim3(cfg.link_kernel ? grid_chunked((uint64_t)H * 16, bs, G, persist)
-                                          : std::max<uint32_t>(8, gd / 8 * 8)),
-                 dim3(bs), s, w, d);
-    sm.mark(9);
-    hipLaunchKernelGGL(k_tuples<false>, dim3(gd), dim3(bs), 0, s, w, d);
-    launch_scan(w, w.rcnt, w.roff, w.ctr + C_ND, w.ctr + C_NTUP, s);
-    hipLaunchKernelGGL(k_tuples<true>, dim3(gd), dim3(bs), 0, s, w, d);
-    const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
-    sm.mark(10);
-    hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
-    sm.mark(11);
-    launch_scan(w, w.ccnt, w.coff, w.ctr + C_ND, nullptr, s);
-    sm.mark(12);
-    hipLaunchKernelGGL(k_cfill, dim3(gt), dim3(bs), 0, s, w, d);
-    sm.mark(13);
-    hipLaunchKernelGGL(k_best, dim3(gd), dim3(bs), 0, s, w, d);
-    sm.mark(14);
-    hipLaunchKernelGGL(k_alive, dim3(gt), dim3(bs), 0, s, w, d);
-    launch_scan(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, s);
-    hipLaunchKernelGGL(k_compact, dim3(gt), dim3(bs), 0, s, w, d, E, out->per_event_tracks);
-    sm.mark(15);
-    hipLaunchKernelGGL(k_fit32, dim3(grid_for(cfg.max_tuples, 256, persist)), dim3(256), 0, s, w,
-                       d, o);
-    sm.mark(16);
-    hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)c->n_cu)), dim3(64),
-                       0, s, w, d, o);
-  }
-  sm.mark(17);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, w, o);
-  if (c->timing) {
-    (void)hipEventRecord(c->ev[PXT_N_STAGES], s);
-    c->timed_valid = true;
+  if (cfg.use_graph) {
+    if (!c->gexec[slot]) {
+      HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      enqueue(c, c->cap_stream, slot, true, 0, 0);
+      hipGraph_t g = nullptr;
+      const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &g);
+      if (e1 != hipSuccess || !g)
+        return fail(c, PXT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e1));
+      c->graph[slot] = g;
+      HIP_OR_FAIL(c, hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0));
+    }
+    HIP_OR_FAIL(c, hipGraphLaunch(c->gexec[slot], s));
+    c->timed_valid = false;
+  } else {
+    enqueue(c, s, slot, false, H, E);
   }
   HIP_OR_FAIL(c, hipGetLastError());
+  HIP_OR_FAIL(c, hipEventRecord(c->slot_free[slot], s));
+  c->slot_pending[slot] = true;
   c->have_last = true;
   c->last_events = E;
   c->last_offsets.assign(in->event_offsets, in->event_offsets + E + 1);
