@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--group-lanes", type=int, default=32)
     ap.add_argument("--link-kernel", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (Hz)")
+    ap.add_argument("--serve-events", type=int, default=10000)
+    ap.add_argument("--serve-pool", type=int, default=96, help="distinct events cycled through")
+    ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--no-serve", action="store_true")
     return ap.parse_args()
 
 
@@ -113,6 +118,34 @@ def cpu_baseline(events, det):
         list(ex.map(lambda e: oracle.reconstruct(e.x, e.y, e.z, e.layer, det)["status"], events))
     dt = time.perf_counter() - t0
     return len(events) / dt, cores, dt
+
+
+def serving_leg(det, args):
+    """Continuous batching under Poisson arrivals (PU 30..140 mix), then a
+    saturating burst for the sustained rate."""
+    import eventgen
+    from paper_2104_06573_amd.serve import Server, poisson_run
+    pool = eventgen.make_batch("serve", args.serve_pool, seed=11)
+    events = [pool[i % len(pool)] for i in range(args.serve_events)]
+    srv = Server(det, n_lanes=args.serve_lanes, max_batch_events=64, doublets_per_hit=40,
+                 max_events=64, max_hits=1_400_000, max_doublets=36 << 20,
+                 max_link_words=36 << 20, max_tuples=6 << 20, phi_bins=args.phi_bins,
+                 group_lanes=args.group_lanes, link_kernel=args.link_kernel, use_graph=1)
+    poisson_run(srv, events[:300], rate_hz=args.serve_rate)          # warm-up
+    rep = poisson_run(srv, events, rate_hz=args.serve_rate)
+    sat = poisson_run(srv, events, rate_hz=1e7)
+    st = srv.stats()
+    srv.close()
+    keep = ("events", "events_per_s", "p50_us", "p99_us", "mean_us", "mean_batch", "failed")
+    return {
+        "workload": "Poisson arrivals, PU uniform 30..140 (30 tracks per PU unit), pool of %d "
+                    "distinct events cycled" % len(pool),
+        "lanes": args.serve_lanes,
+        "offered_rate_hz": args.serve_rate,
+        "at_rate": {k: round(rep[k], 2) if isinstance(rep[k], float) else rep[k] for k in keep},
+        "saturated": {k: round(sat[k], 2) if isinstance(sat[k], float) else sat[k] for k in keep},
+        "solo_retries": st["solo_retries"],
+    }
 
 
 def main():
@@ -223,6 +256,8 @@ def main():
     }
     roof = roofline(stages, counts, int(dev_batches[0][4][-1]), HBM_PEAK_GBS)
     out["roofline"] = roof
+    if not args.no_serve and args.workload == "pu50":
+        out["served"] = serving_leg(det, args)
     if not args.no_cpu:
         sample = [e for b in pool for e in b][: args.cpu_sample]
         v, cores, cdt = cpu_baseline(sample, det)

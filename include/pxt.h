@@ -222,6 +222,83 @@ int pxt_stage_times(pxt_ctx* ctx, float* ms, int cap, int* n_stages);
 /* Static name of stage i (0 <= i < PXT_N_STAGES), or NULL. */
 const char* pxt_stage_name(int stage);
 
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching over several concurrent lanes.          */
+/*                                                                      */
+/* A server owns n_lanes contexts, each with its own HIP stream, device   */
+/* input/output buffers and pinned staging.  pxt_submit (any thread)     */
+/* copies one event's hits from HOST memory into the server and returns a */
+/* ticket at once; a dispatcher thread forms a batch from the pending     */
+/* events whenever a lane is free, admitting events while the batch fits */
+/* the lane's arena capacities (events, hits, and doublets estimated from */
+/* hits), and runs copy-in, reconstruction and copy-out on that lane's    */
+/* stream while the other lanes' batches are on the device.  A batch that */
+/* overflows a capacity on the device is re-run one event at a time, so  */
+/* an oversize event fails alone (status PXT_ERR_CAPACITY) without        */
+/* affecting the others.  Results are the same as for the event alone.   */
+
+typedef struct pxt_server pxt_server;
+
+typedef struct pxt_server_config {
+  int32_t n_lanes;          /* concurrent batches (1..16)                 */
+  uint32_t queue_depth;     /* pending events accepted; beyond: BUSY      */
+  uint32_t max_batch_events;/* events per batch (<= cfg max_events)       */
+  uint32_t doublets_per_hit;/* admission estimate of doublets per hit     */
+} pxt_server_config;
+
+/* Caller-owned HOST buffers receiving one event's tracks (same layouts as
+ * pxt_tracks, for this event only; event_id is implicit).  On return
+ * status, n_tracks (tracks of the event, also when above capacity: then
+ * nothing is copied and status is PXT_ERR_CAPACITY) and the timing fields
+ * are set. */
+typedef struct pxt_event_tracks {
+  uint32_t capacity;
+  uint32_t* hit_idx;   /* [capacity][8]  */
+  uint8_t* n_hits;     /* [capacity]     */
+  float* params;       /* [capacity][5]  */
+  float* cov;          /* [capacity][15] */
+  float* chi2;         /* [capacity][2]  */
+  uint8_t* flags;      /* [capacity]     */
+  uint32_t n_tracks;
+  int32_t status;
+  double latency_us;   /* submit to results on the host                 */
+  double queue_us;     /* submit to the start of its batch              */
+  uint32_t batch_events;/* events in the batch it ran in                */
+} pxt_event_tracks;
+
+typedef struct pxt_server_stats {
+  uint64_t submitted, completed, failed, rejected, batches;
+  uint64_t events_in_batches;   /* sum of batch sizes                    */
+  uint64_t solo_retries;        /* events re-run alone after an overflow */
+} pxt_server_stats;
+
+/* Create a server on HIP device `hip_device`.  cfg gives physics and the
+ * capacities of ONE lane (max_events, max_hits, ...); every lane allocates
+ * its arenas at creation (n_lanes times cfg's footprint).  Errors:
+ * PXT_ERR_INVALID_ARG, PXT_ERR_OOM, PXT_ERR_HIP. */
+int pxt_server_create(const pxt_config* cfg, const pxt_server_config* scfg,
+                      int hip_device, pxt_server** out);
+
+/* Submit one event; x, y, z, layer are HOST arrays of n_hits entries and
+ * are copied before return.  *ticket identifies the event for pxt_poll.
+ * Errors: PXT_ERR_INVALID_ARG (null pointers, n_hits above the lane's
+ * max_hits), PXT_ERR_BUSY (queue full). */
+int pxt_submit(pxt_server* s, const float* x, const float* y, const float* z,
+               const int16_t* layer, uint32_t n_hits, uint64_t* ticket);
+
+/* Wait up to timeout_ms (negative: forever) for the event's result and copy
+ * it into *out; the ticket is released on success.  Returns PXT_OK,
+ * PXT_ERR_NOT_READY (timeout; the ticket stays valid) or
+ * PXT_ERR_INVALID_ARG (unknown ticket).  The event's own status (e.g.
+ * PXT_ERR_CAPACITY) is in out->status. */
+int pxt_poll(pxt_server* s, uint64_t ticket, pxt_event_tracks* out, int timeout_ms);
+
+/* Counters since creation. */
+int pxt_server_get_stats(pxt_server* s, pxt_server_stats* out);
+
+/* Finish the work in flight, stop the dispatcher and free everything. */
+void pxt_server_destroy(pxt_server* s);
+
 #ifdef __cplusplus
 }
 #endif

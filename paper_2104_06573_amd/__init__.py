@@ -31,7 +31,9 @@ DUMP_DOUBLETS, DUMP_LINKS, DUMP_RAW = 0, 1, 2
 # every symbol include/pxt.h declares
 EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_defaults",
            "pxt_create", "pxt_destroy", "pxt_reconstruct", "pxt_debug_dump",
-           "pxt_set_timing", "pxt_stage_times", "pxt_stage_name")
+           "pxt_set_timing", "pxt_stage_times", "pxt_stage_name",
+           "pxt_server_create", "pxt_submit", "pxt_poll", "pxt_server_get_stats",
+           "pxt_server_destroy")
 N_STAGES = 18
 
 

@@ -2,7 +2,8 @@
 
     python -m paper_2104_06573_amd.build
 
-The library is one translation unit (csrc/pxt.hip with its headers) built
+The library is csrc/pxt.hip (kernels and the C ABI) and csrc/server.cpp
+(the continuous-batching server over that ABI), built
 for gfx950 only, without floating-point contraction (the double-precision
 cuts must round exactly as written) and with packed FP32 instructions
 disabled.
@@ -14,7 +15,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "pxt.hip")
+SRCS = [os.path.join(HERE, "csrc", "pxt.hip"), os.path.join(HERE, "csrc", "server.cpp")]
 LIB = os.path.join(HERE, "libpxt.so")
 ARCH = "gfx950"
 
@@ -40,8 +41,8 @@ def build(verbose=False, extra=()):
     cmd = [hipcc()] + FLAGS + list(extra) + [
         "-I", os.path.join(ROOT, "include"),
         "-I", os.path.join(HERE, "csrc"),
-        "-o", tmp, SRC,
-    ]
+        "-o", tmp,
+    ] + SRCS + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -90,3 +90,20 @@ int main(void) {
             pxt.PxtConfig.group_lanes.offset, ctypes.sizeof(pxt.PxtHits),
             ctypes.sizeof(pxt.PxtTracks), ctypes.sizeof(pxt.PxtCounts)]
     assert got == want
+
+
+def test_server_argument_validation():
+    from paper_2104_06573_amd import serve
+    L = serve._bind()
+    cfg = pxt.make_config(eventgen.DETECTOR)
+    h = ctypes.c_void_p()
+    bad = serve.ServerConfig(0, 16, 8, 40)
+    assert L.pxt_server_create(ctypes.byref(cfg), ctypes.byref(bad), 0,
+                               ctypes.byref(h)) == pxt.ERR_INVALID_ARG
+    bad = serve.ServerConfig(2, 0, 8, 40)
+    assert L.pxt_server_create(ctypes.byref(cfg), ctypes.byref(bad), 0,
+                               ctypes.byref(h)) == pxt.ERR_INVALID_ARG
+    t = ctypes.c_uint64()
+    assert L.pxt_submit(None, None, None, None, None, 0, ctypes.byref(t)) == pxt.ERR_INVALID_ARG
+    assert L.pxt_poll(None, 1, None, 0) == pxt.ERR_INVALID_ARG
+    L.pxt_server_destroy(None)
