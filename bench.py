@@ -45,14 +45,17 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=48, help="events for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
-    ap.add_argument("--group-lanes", type=int, default=32)
-    ap.add_argument("--link-kernel", type=int, default=0)
+    ap.add_argument("--group-lanes", type=int, default=16)
+    ap.add_argument("--link-kernel", type=int, default=-1,
+                    help="0 thread per doublet, 1 lane group + queue (default: per workload)")
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (Hz)")
     ap.add_argument("--serve-events", type=int, default=10000)
     ap.add_argument("--serve-pool", type=int, default=96, help="distinct events cycled through")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 512 MiB device copy first (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -64,45 +67,83 @@ def gen_events(kind, n, seed0):
 # Algorithmic HBM bytes of one launch of each single-kernel stage: every
 # array the kernel must read or write, touched once (re-reads of candidates
 # from cache are not counted).  Nh binned hits, Nd doublets, Nw link-mask
-# words, Nt raw n-tuplets, Nk tracks, nbar mean hits per n-tuplet.
+# words, Nt raw n-tuplets, Nk tracks, nbar mean hits per track.
 def algorithmic_bytes(stage, n):
     Nh, Nd, Nw, Nt, Nk = n["Nh"], n["Nd"], n["Nw"], n["Nt"], n["Nk"]
     nbar = n["nbar"]
     table = {
         # x, y (8) + layer (2) read, bin key (4) written
         "prep": 14 * Nh,
-        # x, y, z, layer, key read (18); binned SoA written (33)
+        # key, x, y, z, layer read (18); binned SoA written (33)
         "fill": 51 * Nh,
         # binned hit read (29), doublet count written (4)
         "doublet_count": 33 * Nh,
-        # binned hit + offset read (33); doublet in/out, mask-word count,
-        # flags, tuple counter written (17 per doublet)
-        "doublet_fill": 33 * Nh + 17 * Nd,
-        # hit coordinates (20 per hit); per doublet: in/out, offsets of its
-        # outer hit, mask offset, neighbour count, root flag, candidate
-        # outer-hit id (29); mask words (8)
-        "links": 20 * Nh + 29 * Nd + 8 * Nw,
-        # root test, graph walk (21 per doublet), masks, n-tuplets written
-        "tuples": 21 * Nd + 8 * Nw + 61 * Nt,
+        # binned hit + offset read (33); per doublet written: in/out hits,
+        # mask words, candidate range, flags, counters, outer-hit copy (49)
+        "doublet_fill": 33 * Nh + 49 * Nd,
+        # inner-hit coordinates (20 per hit); per doublet: inner hit, outer-hit
+        # copy, candidate range, mask offset, neighbour count (40) and its
+        # (r, z) as a candidate (12); mask words written (8)
+        "links": 20 * Nh + 52 * Nd + 8 * Nw,
+        # root test and graph walk (25 per doublet), masks, n-tuplets written
+        "tuples": 25 * Nd + 8 * Nw + 61 * Nt,
         # n-tuplet hits/doublets read (61), hit coordinates, score written (8)
         "score": (69 + 20 * nbar) * Nt,
-        # n-tuplet read (61 + 13 per hit) and the track record written (126)
-        "fit32": (61 + 13 * nbar + 126) * Nk,
+        # survivor, n-tuplet, hits and ids read (41 + 17 per hit), record written (126)
+        "fit32": (41 + 17 * nbar + 126) * Nk,
     }
     return table.get(stage)
 
 
-def roofline(stages, counts, n_hits, peak_gbs):
+# kernel that implements each single-kernel stage (for the counter lookup)
+STAGE_KERNEL = {"prep": "pxt::k_prep", "fill": "pxt::k_fill",
+                "doublet_count": "pxt::k_doublets<16, false>",
+                "doublet_fill": "pxt::k_doublets<16, true>", "links": "pxt::k_links_thread",
+                "score": "pxt::k_score", "fit32": "pxt::k_fit32"}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2104_06573_amd", "csrc")
+    for f in ("common.h", "cuts.h", "fit.h", "kernels.h", "pxt.hip"):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if it is absent or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_pu50_batch64.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    try:
+        blob = json.loads(txt.split("```json")[1].split("```")[0])
+    except (IndexError, ValueError):
+        return None
+    if blob.get("source_hash") != kernel_source_hash():
+        return None
+    return blob["bytes_per_launch"].get(kernel)
+
+
+def roofline(stages, counts, n_hits, peak_gbs, workload, args):
     """Roofline entry of the dominant single-kernel stage."""
     n = {"Nh": n_hits, "Nd": counts["n_doublets"], "Nw": counts["n_words"],
-         "Nt": counts["n_raw_tuples"], "Nk": counts["n_tracks"], "nbar": 3.5}
+         "Nt": counts["n_raw_tuples"], "Nk": counts["n_tracks"], "nbar": 3.4}
     cand = {k: v for k, v in stages.items() if algorithmic_bytes(k, n) is not None}
     dom = max(cand, key=cand.get)
     byts = algorithmic_bytes(dom, n)
     gbs = byts / (cand[dom] * 1e-3) / 1e9
-    return {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 2), "peak": peak_gbs,
-            "unit": "GB/s", "frac": round(gbs / peak_gbs, 5), "traffic": None,
-            "bytes_per_launch": int(byts), "avg_launch_ms": round(cand[dom], 5)}
+    traffic = None
+    kname = STAGE_KERNEL.get(dom)
+    if (workload == "pu50" and kname and args.link_kernel == 0 and args.group_lanes == 16
+            and args.batch in (0, 64)):
+        traffic = measured_traffic(kname)
+    return {"kernel": kname or dom, "bound": "hbm", "achieved": round(gbs, 2), "peak": peak_gbs,
+            "unit": "GB/s", "frac": round(gbs / peak_gbs, 5), "traffic": traffic,
+            "algorithmic_bytes_per_launch": int(byts), "avg_launch_ms": round(cand[dom], 5)}
 
 
 def cpu_baseline(events, det):
@@ -160,6 +201,14 @@ def main():
     import paper_2104_06573_amd as pxt
 
     det = eventgen.DETECTOR
+    if args.link_kernel < 0:
+        args.link_kernel = 0 if args.workload == "pu50" else 1
+    if args.calib_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     kind, batch_default, desc = WORKLOADS[args.workload]
     B = args.batch or batch_default
     pool = [gen_events(kind, B, 1000 + 97 * p) for p in range(args.pool)]
@@ -254,7 +303,7 @@ def main():
                                                     "n_tracks", "n_fp64")},
         "stage_ms": stages,
     }
-    roof = roofline(stages, counts, int(dev_batches[0][4][-1]), HBM_PEAK_GBS)
+    roof = roofline(stages, counts, int(dev_batches[0][4][-1]), HBM_PEAK_GBS, args.workload, args)
     out["roofline"] = roof
     if not args.no_serve and args.workload == "pu50":
         out["served"] = serving_leg(det, args)
