@@ -46,8 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
     ap.add_argument("--group-lanes", type=int, default=16)
-    ap.add_argument("--link-kernel", type=int, default=-1,
-                    help="0 thread per doublet, 1 lane group + queue (default: per workload)")
+    ap.add_argument("--link-kernel", type=int, default=0,
+                    help="0 thread per doublet, 1 lane group + queue")
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (Hz)")
     ap.add_argument("--serve-events", type=int, default=10000)
@@ -138,6 +138,10 @@ def roofline(stages, counts, n_hits, peak_gbs, workload, args):
     gbs = byts / (cand[dom] * 1e-3) / 1e9
     traffic = None
     kname = STAGE_KERNEL.get(dom)
+    if dom == "links" and args.link_kernel == 1:
+        kname = "pxt::k_links<%d>" % args.group_lanes
+    if dom in ("doublet_count", "doublet_fill"):
+        kname = kname.replace("<16,", "<%d," % args.group_lanes)
     if (workload == "pu50" and kname and args.link_kernel == 0 and args.group_lanes == 16
             and args.batch in (0, 64)):
         traffic = measured_traffic(kname)
@@ -201,8 +205,6 @@ def main():
     import paper_2104_06573_amd as pxt
 
     det = eventgen.DETECTOR
-    if args.link_kernel < 0:
-        args.link_kernel = 0 if args.workload == "pu50" else 1
     if args.calib_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

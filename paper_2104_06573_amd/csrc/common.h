@@ -33,11 +33,14 @@ enum Ctr : int {
   C_NTUP,            // raw n-tuplets
   C_NSURV,           // n-tuplets surviving the cleaning
   C_NFP64,           // tuples refitted in FP64
+  C_NROOT,           // root doublets of the n-tuplet search
   C_REQ_D,           // required sizes on overflow
   C_REQ_W,
   C_REQ_T,
   C_REQ_K,
-  C_NCTR
+  C_TICKET0,         // tile tickets of the single-pass scans of one call
+  C_TICKET_END = C_TICKET0 + 8,
+  C_NCTR = C_TICKET_END
 };
 
 // Physics and tuning constants, passed by value to the kernels.
@@ -54,6 +57,7 @@ struct DevCfg {
   double c_kappa, sigma_u, sigma_z, sigma_r, x_over_x0, pt_max, pt_fp64;
   uint32_t cap_doublets, cap_words, cap_tuples;
   int link_thread;                          // one thread per doublet in links
+  float th_win, th_far;                     // r-z angle prefilter of the links
 };
 
 struct CallDesc;
@@ -81,17 +85,14 @@ struct Ws {
   uint32_t* cell_off;     // [H + 1] first doublet of each inner hit
   uint32_t* cin;          // [D] inner binned hit
   uint32_t* cout;         // [D] outer binned hit
-  uint32_t* mw;           // [D + 1] link-mask words per doublet
   uint32_t* moff;         // [D + 1]
   uint64_t* masks;        // [W]
   uint8_t* has_inner;     // [D]
   uint32_t* nout;         // [D] outer links per doublet
-  float* ox;              // [D] outer hit of each doublet: x, y, z, r
-  float* oy;
-  float* oz;
-  double* orr;
+  float4* oh;             // [D] outer hit (x, y, z) and r-z angle of each doublet
   uint32_t* cb;           // [D] first doublet leaving the outer hit
   uint32_t* cdeg;         // [D] number of doublets leaving the outer hit
+  uint32_t* roots;        // [D] root doublets, ascending
   uint32_t* rcnt;         // [D + 1] n-tuplets per root doublet
   uint32_t* roff;         // [D + 1]
   // n-tuplets
@@ -110,6 +111,8 @@ struct Ws {
   uint32_t* fp64_list;    // [T]
   // scan scratch
   uint32_t* block_sums;   // [kScanBlocks + 1]
+  uint64_t* scan_status;  // [max tiles] status words of the single-pass scan
+  uint32_t* epoch;        // [1] call counter (never cleared)
 };
 
 constexpr int kScanBlocks = 512;
@@ -200,6 +203,16 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t 
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
     if (a[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Number of entries of the sorted a[0..n) below v.
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t n, uint32_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
   }
   return lo;
 }

@@ -31,6 +31,17 @@ struct HitD {
   double x, y, z, r;
 };
 
+// A hit from its FP32 coordinates; r is the same FP64 expression the
+// binned arrays hold, so it is bit-identical to the stored radius.
+__device__ __forceinline__ HitD hit_xyz(float x, float y, float z) {
+  HitD h;
+  h.x = (double)x;
+  h.y = (double)y;
+  h.z = (double)z;
+  h.r = sqrt(h.x * h.x + h.y * h.y);
+  return h;
+}
+
 __device__ __forceinline__ HitD load_hit(const Ws& w, uint32_t i) {
   HitD h;
   h.x = (double)w.bx[i];
@@ -206,6 +217,22 @@ __device__ __forceinline__ bool link_xy_pass(const DevCfg& c, const HitD& a, con
     d0 = fabs(aa + 2.0 * ao) / (dc + R);
   }
   return d0 <= c.d0max;
+}
+
+// Direction of a doublet in the r-z plane, in FP32: the angle of
+// (r_o - r_i, z_o - z_i).  For two doublets (a,b), (b,c) the r-z cross
+// product of L1 is l_ab l_bc sin(angle_bc - angle_ab), so L1 can hold only
+// where the angles differ by at most asin(arz), or by at least
+// pi - asin(arz); rz_prefilter tests that with a margin (th_win, th_far)
+// that covers the FP32 error of both angles.  Candidates it rejects fail
+// L1; the ones it keeps go on to the exact cuts.
+__device__ __forceinline__ float rz_angle(const HitD& i, const HitD& o) {
+  return atan2f((float)(o.z - i.z), (float)(o.r - i.r));
+}
+
+__device__ __forceinline__ bool rz_prefilter(const DevCfg& c, float ta, float tc) {
+  const float dd = fabsf(tc - ta);
+  return dd <= c.th_win || dd >= c.th_far;
 }
 
 // Cleaning score of one consecutive hit triple.

@@ -55,14 +55,17 @@ __device__ __forceinline__ double circ_arc(double a, double b, double k) {
   return k == 0.0 ? a : atan2(k * a, 1.0 - k * b) / k;
 }
 
-__device__ inline void fit_geometry(const DevCfg& c, int n, const double* X,
-                                    const double* Y, const double* Z,
-                                    const int* kind, FitGeo& g) {
-  g.n = n;
-  const int m = n / 2;
+// N is the number of hits, a compile-time constant so that every array index
+// is static and the arrays stay in registers.
+template <int N>
+__device__ inline void fit_geometry(const DevCfg& c, const double (&X)[kMaxHits],
+                                    const double (&Y)[kMaxHits], const double (&Z)[kMaxHits],
+                                    const int (&kind)[kMaxHits], FitGeo& g) {
+  constexpr int m = N / 2;
+  g.n = N;
   const double d1x = X[m] - X[0], d1y = Y[m] - Y[0];
-  const double d2x = X[n - 1] - X[0], d2y = Y[n - 1] - Y[0];
-  const double d3x = X[n - 1] - X[m], d3y = Y[n - 1] - Y[m];
+  const double d2x = X[N - 1] - X[0], d2y = Y[N - 1] - Y[0];
+  const double d3x = X[N - 1] - X[m], d3y = Y[N - 1] - Y[m];
   const double cr = d1x * d2y - d1y * d2x;
   const double l1 = sqrt(d1x * d1x + d1y * d1y);
   const double l2 = sqrt(d2x * d2x + d2y * d2y);
@@ -79,25 +82,28 @@ __device__ inline void fit_geometry(const DevCfg& c, int n, const double* X,
   g.ny = g.tx;
   g.x0 = X[0]; g.y0 = Y[0]; g.z0 = Z[0];
   g.kref = k;
-  for (int i = 0; i < n; ++i) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
     const double ex = X[i] - X[0], ey = Y[i] - Y[0];
     const double a = ex * g.tx + ey * g.ty;
     const double b = ex * g.nx + ey * g.ny;
     g.m[i] = circ_dist(a, b, k);
     g.s[i] = circ_arc(a, b, k);
   }
-  g.tref = (Z[n - 1] - Z[0]) / (g.s[n - 1] - g.s[0]);
+  g.tref = (Z[N - 1] - Z[0]) / (g.s[N - 1] - g.s[0]);
   g.sinT = 1.0 / sqrt(1.0 + g.tref * g.tref);
   g.cosT = g.tref * g.sinT;
   const double kabs = fmax(fabs(k), c.c_kappa / c.pt_max);
   const double p = c.c_kappa / (kabs * g.sinT);
-  for (int i = 0; i < n; ++i) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
     const double x = c.x_over_x0 / (kind[i] == PXT_LAYER_BARREL ? g.sinT : fabs(g.cosT));
     g.th0[i] = 0.0136 / p * sqrt(x) * (1.0 + 0.038 * log(x));
     g.sz[i] = kind[i] == PXT_LAYER_BARREL ? c.sigma_z : c.sigma_r * fabs(g.tref);
     g.mz[i] = Z[i] - Z[0] - g.tref * (g.s[i] - g.s[0]);
   }
-  for (int i = 0; i + 1 < n; ++i) g.ds[i] = g.s[i + 1] - g.s[i];
+#pragma unroll
+  for (int i = 0; i + 1 < N; ++i) g.ds[i] = g.s[i + 1] - g.s[i];
 }
 
 // ------------------------------------------------------- linear algebra --
@@ -235,46 +241,58 @@ struct FitOut {
 };
 
 // Fit with the linear algebra in T for a tuple of exactly N hits.
+//
+// The normal matrices are built directly in their Jacobi-scaled form
+// As = D A D with D = diag(A)^-1/2 (the scaled diagonal is exactly 1): the
+// diagonal of A is accumulated in FP64 first, then every kink adds its
+// rank-one term, scaled, to the working-precision matrix.  The kink
+// coefficients are recomputed rather than stored, to keep registers low.
 template <int N, typename T>
 __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
   constexpr int K = N + 1;
-  // ---- transverse normal equations (built in FP64, scaled, solved in T)
-  double A[K][K];
-  double r[K];
+  // ---- transverse: unknowns u_0..u_{N-1}, dk
+  const double wu = 1.0 / (c.sigma_u * c.sigma_u);
+  double inv_ds[N - 1];
+#pragma unroll
+  for (int i = 0; i + 1 < N; ++i) inv_ds[i] = 1.0 / g.ds[i];
+  double Dg[K];
+#pragma unroll
+  for (int i = 0; i < N; ++i) Dg[i] = wu;
+  Dg[N] = 0.0;
+#pragma unroll
+  for (int j = 1; j + 1 < N; ++j) {
+    const double w = g.sinT / g.th0[j];
+    const double v = w * w;
+    const double c0 = inv_ds[j - 1], c1 = -(inv_ds[j - 1] + inv_ds[j]), c2 = inv_ds[j];
+    const double c3 = -(g.ds[j - 1] + g.ds[j]) / 2.0;
+    Dg[j - 1] += v * c0 * c0;
+    Dg[j] += v * c1 * c1;
+    Dg[j + 1] += v * c2 * c2;
+    Dg[N] += v * c3 * c3;
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) Dg[i] = 1.0 / sqrt(Dg[i]);
+  T As[K][K];
+  T y[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    r[i] = 0.0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) A[i][j] = 0.0;
-  }
-  const double wu = 1.0 / (c.sigma_u * c.sigma_u);
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    A[i][i] = wu;
-    r[i] = wu * g.m[i];
+    for (int j = 0; j < K; ++j) As[i][j] = (T)0;
+    As[i][i] = (T)1;
+    y[i] = i < N ? (T)(wu * g.m[i] * Dg[i]) : (T)0;
   }
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
     const double w = g.sinT / g.th0[j];
     const double v = w * w;
     const int idx[4] = {j - 1, j, j + 1, N};
-    const double cf[4] = {1.0 / g.ds[j - 1], -(1.0 / g.ds[j - 1] + 1.0 / g.ds[j]),
-                          1.0 / g.ds[j], -(g.ds[j - 1] + g.ds[j]) / 2.0};
+    const double cf[4] = {inv_ds[j - 1] * Dg[j - 1], -(inv_ds[j - 1] + inv_ds[j]) * Dg[j],
+                          inv_ds[j] * Dg[j + 1], -(g.ds[j - 1] + g.ds[j]) / 2.0 * Dg[N]};
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) A[idx[p]][idx[q]] += v * cf[p] * cf[q];
-  }
-  double Dg[K];
-  T As[K][K];
-  T y[K];
-#pragma unroll
-  for (int i = 0; i < K; ++i) Dg[i] = 1.0 / sqrt(A[i][i]);
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    y[i] = (T)(r[i] * Dg[i]);
-#pragma unroll
-    for (int j = 0; j < K; ++j) As[i][j] = (T)(A[i][j] * Dg[i] * Dg[j]);
+      for (int q = 0; q < 4; ++q)
+        if (p != q) As[idx[p]][idx[q]] += (T)(v * cf[p] * cf[q]);
   }
   const T pr = cholesky<K, T>(As);
   chol_solve<K, T>(As, y);
@@ -301,42 +319,46 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
     const double w = g.sinT / g.th0[j];
-    const double beta = (x[j + 1] - x[j]) / g.ds[j] - (x[j] - x[j - 1]) / g.ds[j - 1] -
+    const double beta = (x[j + 1] - x[j]) * inv_ds[j] - (x[j] - x[j - 1]) * inv_ds[j - 1] -
                         x[N] * (g.ds[j - 1] + g.ds[j]) / 2.0;
     chic += w * w * beta * beta;
   }
-  // ---- longitudinal
-  double B[N][N];
-  double rz[N];
+  // ---- longitudinal: unknowns w_0..w_{N-1}
+  double Dz[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) Dz[i] = 1.0 / (g.sz[i] * g.sz[i]);
+#pragma unroll
+  for (int j = 1; j + 1 < N; ++j) {
+    const double w = g.sinT * g.sinT / g.th0[j];
+    const double v = w * w;
+    const double c0 = inv_ds[j - 1], c1 = -(inv_ds[j - 1] + inv_ds[j]), c2 = inv_ds[j];
+    Dz[j - 1] += v * c0 * c0;
+    Dz[j] += v * c1 * c1;
+    Dz[j + 1] += v * c2 * c2;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) Dz[i] = 1.0 / sqrt(Dz[i]);
+  T Bs[N][N];
+  T yz[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) B[i][j] = 0.0;
-    const double wz = 1.0 / (g.sz[i] * g.sz[i]);
-    B[i][i] = wz;
-    rz[i] = wz * g.mz[i];
+    for (int j = 0; j < N; ++j) Bs[i][j] = (T)0;
+    Bs[i][i] = (T)1;
+    yz[i] = (T)(g.mz[i] / (g.sz[i] * g.sz[i]) * Dz[i]);
   }
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
     const double w = g.sinT * g.sinT / g.th0[j];
     const double v = w * w;
     const int idx[3] = {j - 1, j, j + 1};
-    const double cf[3] = {1.0 / g.ds[j - 1], -(1.0 / g.ds[j - 1] + 1.0 / g.ds[j]), 1.0 / g.ds[j]};
+    const double cf[3] = {inv_ds[j - 1] * Dz[j - 1], -(inv_ds[j - 1] + inv_ds[j]) * Dz[j],
+                          inv_ds[j] * Dz[j + 1]};
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) B[idx[p]][idx[q]] += v * cf[p] * cf[q];
-  }
-  double Dz[N];
-  T Bs[N][N];
-  T yz[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) Dz[i] = 1.0 / sqrt(B[i][i]);
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    yz[i] = (T)(rz[i] * Dz[i]);
-#pragma unroll
-    for (int j = 0; j < N; ++j) Bs[i][j] = (T)(B[i][j] * Dz[i] * Dz[j]);
+      for (int q = 0; q < 3; ++q)
+        if (p != q) Bs[idx[p]][idx[q]] += (T)(v * cf[p] * cf[q]);
   }
   const T prz = cholesky<N, T>(Bs);
   chol_solve<N, T>(Bs, yz);
@@ -363,7 +385,7 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
     const double w = g.sinT * g.sinT / g.th0[j];
-    const double gam = (wv[j + 1] - wv[j]) / g.ds[j] - (wv[j] - wv[j - 1]) / g.ds[j - 1];
+    const double gam = (wv[j + 1] - wv[j]) * inv_ds[j] - (wv[j] - wv[j - 1]) * inv_ds[j - 1];
     chiz += w * w * gam * gam;
   }
   // ---- parameters at the point of closest approach (FP64)
@@ -421,15 +443,27 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
   o.need64 = bad;
 }
 
+template <int N, typename T>
+__device__ inline void fit_n(const DevCfg& c, const double (&X)[kMaxHits],
+                             const double (&Y)[kMaxHits], const double (&Z)[kMaxHits],
+                             const int (&kind)[kMaxHits], FitOut& o) {
+  FitGeo g;
+  fit_geometry<N>(c, X, Y, Z, kind, g);
+  fit_linear<N, T>(c, g, o);
+}
+
+// Fit a tuple of n hits (3..8) given in path order.
 template <typename T>
-__device__ inline void fit_dispatch(const DevCfg& c, const FitGeo& g, FitOut& o) {
-  switch (g.n) {
-    case 3: fit_linear<3, T>(c, g, o); break;
-    case 4: fit_linear<4, T>(c, g, o); break;
-    case 5: fit_linear<5, T>(c, g, o); break;
-    case 6: fit_linear<6, T>(c, g, o); break;
-    case 7: fit_linear<7, T>(c, g, o); break;
-    default: fit_linear<8, T>(c, g, o); break;
+__device__ inline void fit_tuple(const DevCfg& c, int n, const double (&X)[kMaxHits],
+                                 const double (&Y)[kMaxHits], const double (&Z)[kMaxHits],
+                                 const int (&kind)[kMaxHits], FitOut& o) {
+  switch (n) {
+    case 3: fit_n<3, T>(c, X, Y, Z, kind, o); break;
+    case 4: fit_n<4, T>(c, X, Y, Z, kind, o); break;
+    case 5: fit_n<5, T>(c, X, Y, Z, kind, o); break;
+    case 6: fit_n<6, T>(c, X, Y, Z, kind, o); break;
+    case 7: fit_n<7, T>(c, X, Y, Z, kind, o); break;
+    default: fit_n<8, T>(c, X, Y, Z, kind, o); break;
   }
 }
 

@@ -54,6 +54,7 @@ __global__ void k_clear(Ws w, DevCfg c) {
   for (uint32_t i = tid; i < nbins + 1; i += stride) w.bin_cnt[i] = 0;
   for (uint32_t i = tid; i < E; i += stride) per_event_tracks[i] = 0;
   if (tid < C_NCTR) w.ctr[tid] = tid == C_NBINS ? nbins : 0u;
+  if (tid == 0) w.epoch[0] += 1u;
 }
 
 // ------------------------------------------------------- binning (prep) --
@@ -97,8 +98,7 @@ __global__ __launch_bounds__(256) void k_fill(Ws w) {
     w.bx[pos] = xf;
     w.by[pos] = yf;
     w.bz[pos] = z[g];
-    const double X = (double)xf, Y = (double)yf;
-    w.br[pos] = sqrt(X * X + Y * Y);
+    w.br[pos] = hit_xyz(xf, yf, 0.0f).r;
     w.bphi[pos] = atan2f(yf, xf);
     w.bidx[pos] = g - w.evt_off[e];
     w.bevt[pos] = e;
@@ -136,6 +136,14 @@ __device__ __forceinline__ void scan_chunk(uint32_t n, uint32_t& beg, uint32_t& 
   end = min(n, beg + per_r);
 }
 
+// Input transform of a scan: identity, or the number of 64-bit link-mask
+// words needed for a candidate count.
+template <int TR>
+__device__ __forceinline__ uint32_t scan_in(uint32_t v) {
+  return TR == 0 ? v : (v + 63u) >> 6;
+}
+
+template <int TR>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
                                                                const uint32_t* n_dev,
                                                                uint32_t* block_sums,
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
   uint32_t beg, end;
   scan_chunk(n, beg, end);
   uint32_t s = 0;
-  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) s += in[i];
+  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) s += scan_in<TR>(in[i]);
   s = wave_sum(s);
   __shared__ uint32_t part[kScanThreads / kWave];
   if (lane_id() == 0) part[threadIdx.x / kWave] = s;
@@ -168,6 +176,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t* block_sums, uint32_
   if (threadIdx.x == 0) block_sums[nblk] = tot;
 }
 
+template <int TR>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out,
                                                              const uint32_t* n_dev,
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
   uint32_t carry = block_sums[blockIdx.x];
   for (uint32_t base = beg; base < end; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < end ? in[i] : 0u;
+    const uint32_t v = i < end ? scan_in<TR>(in[i]) : 0u;
     uint32_t tot;
     const uint32_t ex = block_excl_scan(v, lds, tot);
     if (i < end) out[i] = carry + ex;
@@ -193,6 +202,164 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
     out[n] = total;
     if (total_dst) *total_dst = total;
   }
+}
+
+// ---------------------------------------------------- single-pass scan --
+// Exclusive scan in one launch by decoupled look-back (Merrill & Garland,
+// "Single-pass parallel prefix scan with decoupled look-back", 2016).  Tile
+// ids are taken from an atomic ticket (zeroed per call by k_clear), so every
+// tile a block waits for belongs to a block that is already running.  Each
+// tile publishes a 64-bit status word [epoch:30 | flag:2 | value:32]
+// (flag 1: tile aggregate, 2: inclusive prefix); the epoch is unique per
+// call and per scan of the call, so words left by earlier scans never match
+// and the status array needs no clearing.  A status word carries its whole
+// message, so it is read and written with relaxed (coherent) atomics: no
+// other memory is published through it, and acquire/release at device
+// scope would write back or invalidate the L2 of the XCD on every access.
+// The look-back spin is bounded: on exhaustion the call fails with
+// PXT_ERR_HIP instead of hanging.
+
+constexpr int kTileItems = 16;
+constexpr int kTile = 256 * kTileItems;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+__device__ __forceinline__ uint64_t scan_word(uint32_t epoch, uint32_t flag, uint32_t v) {
+  return ((uint64_t)(epoch & 0x3fffffffu) << 34) | ((uint64_t)flag << 32) | v;
+}
+
+// Publishes the aggregate of `tile` and returns the exclusive prefix of
+// the tiles before it.  Called by the 64 lanes of the block's first
+// wavefront: lane l inspects predecessor p - l, so one round trip covers 64
+// predecessors; the walk stops at the nearest one holding an inclusive
+// prefix, once every tile between has published its aggregate.
+__device__ uint32_t tile_lookback(Ws& w, uint32_t tile, uint32_t epoch, uint32_t agg) {
+  const uint32_t lane = lane_id();
+  const uint32_t ep = epoch & 0x3fffffffu;
+  if (tile == 0) {
+    if (lane == 0)
+      __hip_atomic_store(&w.scan_status[0], scan_word(epoch, 2, agg), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  if (lane == 0)
+    __hip_atomic_store(&w.scan_status[tile], scan_word(epoch, 1, agg), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t prefix = 0;
+  int32_t p = (int32_t)tile - 1;
+  uint32_t spins = 0;
+  for (;;) {
+    const int32_t q = p - (int32_t)lane;
+    uint32_t flag = 2, val = 0;  // before tile 0: an inclusive zero
+    if (q >= 0) {
+      const uint64_t s =
+          __hip_atomic_load(&w.scan_status[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      flag = (uint32_t)(s >> 34) == ep ? (uint32_t)(s >> 32) & 3u : 0u;
+      val = (uint32_t)s;
+    }
+    const uint64_t incl = __ballot(flag == 2);
+    const uint64_t waiting = __ballot(flag == 0);
+    const uint32_t first = incl ? (uint32_t)__ffsll((unsigned long long)incl) - 1u : 64u;
+    const uint64_t upto = first >= 63u ? ~0ull : (2ull << first) - 1ull;
+    if (waiting & upto) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) set_status(w.ctr, PXT_ERR_HIP);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    prefix += wave_sum(lane <= first ? val : 0u);
+    if (first < 64u) break;
+    p -= 64;
+  }
+  if (lane == 0)
+    __hip_atomic_store(&w.scan_status[tile], scan_word(epoch, 2, prefix + agg), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  return prefix;
+}
+
+// Takes the block's tile from the scan's ticket; returns false for a
+// block beyond the `ntiles` tiles.
+__device__ __forceinline__ bool take_tile(Ws& w, uint32_t scan_id, uint32_t ntiles,
+                                          uint32_t& tile) {
+  __shared__ uint32_t s_tile;
+  if (threadIdx.x == 0) s_tile = atomicAdd(&w.ctr[C_TICKET0 + scan_id], 1u);
+  __syncthreads();
+  tile = s_tile;
+  return tile < ntiles;
+}
+
+template <int TR>
+__global__ __launch_bounds__(256) void k_scan1(const uint32_t* __restrict__ in,
+                                                uint32_t* __restrict__ out, const uint32_t* n_dev,
+                                                uint32_t* total_dst, Ws w, uint32_t scan_id) {
+  if (w.ctr[C_STATUS]) return;
+  __shared__ uint32_t s_prefix;
+  __shared__ uint32_t lds[256 / kWave + 1];
+  const uint32_t n = *n_dev;
+  const uint32_t ntiles = n ? (n + kTile - 1) / kTile : 1u;
+  uint32_t tile;
+  if (!take_tile(w, scan_id, ntiles, tile)) return;
+  const uint32_t epoch = w.epoch[0] * 8u + scan_id;
+  const uint32_t base = tile * kTile + threadIdx.x * kTileItems;
+  uint32_t v[kTileItems];
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    v[i] = base + i < n ? scan_in<TR>(in[base + i]) : 0u;
+    tsum += v[i];
+  }
+  uint32_t agg;
+  const uint32_t texcl = block_excl_scan(tsum, lds, agg);
+  if (threadIdx.x < kWave) {
+    const uint32_t pf = tile_lookback(w, tile, epoch, agg);
+    if (threadIdx.x == 0) s_prefix = pf;
+  }
+  __syncthreads();
+  uint32_t run = s_prefix + texcl;
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (tile == ntiles - 1 && threadIdx.x == 0) {
+    const uint32_t total = s_prefix + agg;
+    out[n] = total;
+    if (total_dst) *total_dst = total;
+  }
+}
+
+// The root doublets of the n-tuplet search -- no inner neighbour, at least
+// one outer neighbour -- listed in ascending order: a stream compaction of
+// the doublets by the same single-pass scan over their root flags.
+__global__ __launch_bounds__(256) void k_roots(Ws w, uint32_t scan_id) {
+  if (w.ctr[C_STATUS]) return;
+  __shared__ uint32_t s_prefix;
+  __shared__ uint32_t lds[256 / kWave + 1];
+  const uint32_t n = w.ctr[C_ND];
+  const uint32_t ntiles = n ? (n + kTile - 1) / kTile : 1u;
+  uint32_t tile;
+  if (!take_tile(w, scan_id, ntiles, tile)) return;
+  const uint32_t epoch = w.epoch[0] * 8u + scan_id;
+  const uint32_t base = tile * kTile + threadIdx.x * kTileItems;
+  uint32_t flags = 0;
+#pragma unroll
+  for (int i = 0; i < kTileItems; ++i)
+    if (base + i < n && !w.has_inner[base + i] && w.nout[base + i] != 0u) flags |= 1u << i;
+  uint32_t agg;
+  const uint32_t texcl = block_excl_scan((uint32_t)__popc(flags), lds, agg);
+  if (threadIdx.x < kWave) {
+    const uint32_t pf = tile_lookback(w, tile, epoch, agg);
+    if (threadIdx.x == 0) s_prefix = pf;
+  }
+  __syncthreads();
+  uint32_t run = s_prefix + texcl;
+  while (flags) {
+    const int i = __ffs(flags) - 1;
+    flags &= flags - 1u;
+    w.roots[run++] = base + (uint32_t)i;
+  }
+  if (tile == ntiles - 1 && threadIdx.x == 0) w.ctr[C_NROOT] = s_prefix + agg;
 }
 
 // ------------------------------------------------------------- doublets --
@@ -302,17 +469,13 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
           w.cin[q] = g;
           w.cout[q] = j;
           const uint32_t jb = w.cell_off[j], deg = w.cell_off[j + 1] - jb;
-          w.mw[q] = (deg + 63u) >> 6;
           w.cb[q] = jb;
           w.cdeg[q] = deg;
           w.has_inner[q] = 0;
           w.ccnt[q] = 0;
-          w.nout[q] = 0;
+          if (!c.link_thread) w.nout[q] = 0;
           const HitD ho = load_hit(w, j);
-          w.ox[q] = (float)ho.x;
-          w.oy[q] = (float)ho.y;
-          w.oz[q] = (float)ho.z;
-          w.orr[q] = ho.r;
+          w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, rz_angle(hi, ho));
         }
         const uint32_t ng = (uint32_t)__popcll(bal & gmask);
         pos += ng;
@@ -326,11 +489,12 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
 // ---------------------------------------------------------------- links --
 // The candidate outer neighbours of doublet (a,b) are the doublets leaving
 // hit b: the contiguous range cell_off[b] .. cell_off[b+1] (doublets are
-// stored grouped by inner hit).  Each doublet carries a copy of its outer
-// hit's coordinates, so the candidates' (r, z) -- all that the r-z cut,
-// which rejects the great majority, needs -- are read sequentially; x, y
-// follow only for candidates that pass it.  The accepted candidates form a
-// bit mask over the range, one 64-bit word per 64 candidates.
+// stored grouped by inner hit).  Each doublet carries its outer hit and its
+// r-z angle in one float4, so a candidate is one load: the FP32 angle
+// prefilter, which passes only a few percent, decides on its fourth
+// component, and the survivors go on to the exact FP64 cuts with the hit
+// already in registers.  The accepted candidates form a bit mask over the
+// range, one 64-bit word per 64.
 
 __device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c, uint32_t nd) {
   const uint32_t nwords = w.moff[nd];
@@ -349,37 +513,47 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   const uint32_t nd = ctr[C_ND];
   if (!links_capacity(w, c, nd)) return;
   uint32_t links = 0;
-  for (uint32_t d = xcd_block() * blockDim.x + threadIdx.x; d < nd;
-       d += gridDim.x * blockDim.x) {
-    const HitD ha = load_hit(w, w.cin[d]);
-    const HitD hb{(double)w.ox[d], (double)w.oy[d], (double)w.oz[d], w.orr[d]};
-    const uint32_t k0 = w.cb[d], deg = w.cdeg[d];
-    const uint32_t mo = w.moff[d];
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t d = xcd_block() * blockDim.x + threadIdx.x;
+  // software pipeline: the set-up loads of the next doublet are issued
+  // before the candidates of the current one are scanned
+  uint32_t na = 0, nkb = 0, ndeg = 0, nmo = 0;
+  float4 nob = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (d < nd) {
+    na = w.cin[d]; nob = w.oh[d]; nkb = w.cb[d]; ndeg = w.cdeg[d]; nmo = w.moff[d];
+  }
+  while (d < nd) {
+    const uint32_t k0 = nkb, deg = ndeg, mo = nmo;
+    const float4 ob = nob;
+    const HitD ha = load_hit(w, na);
+    const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
+    const uint32_t dn = d + stride;
+    if (dn < nd) {
+      na = w.cin[dn]; nob = w.oh[dn]; nkb = w.cb[dn]; ndeg = w.cdeg[dn]; nmo = w.moff[dn];
+    }
     uint32_t nout = 0;
     for (uint32_t wd = 0; wd * 64u < deg; ++wd) {
       uint64_t mask = 0;
       const uint32_t lim = min(64u, deg - wd * 64u);
+      const uint32_t kw = k0 + wd * 64u;
+      uint64_t pass = 0;  // candidates through the prefilter
       for (uint32_t b8 = 0; b8 < lim; b8 += 8) {
-        // issue eight candidates' (r, z) loads before testing them
-        double rc[8];
-        float zc[8];
+        // issue eight candidates' angle loads before testing them
+        float tc[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const uint32_t d2 = k0 + wd * 64u + b8 + u;
-          const bool in = b8 + u < lim;
-          rc[u] = in ? w.orr[d2] : 0.0;
-          zc[u] = in ? w.oz[d2] : 0.0f;
-        }
+        for (int u = 0; u < 8; ++u) tc[u] = b8 + u < lim ? w.oh[kw + b8 + u].w : 0.0f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (b8 + u >= lim) break;
-          const uint32_t d2 = k0 + wd * 64u + b8 + u;
-          if (!link_rz_pass(c, ha, hb, rc[u], (double)zc[u])) continue;
-          const HitD hc{(double)w.ox[d2], (double)w.oy[d2], (double)zc[u], rc[u]};
-          if (link_xy_pass(c, ha, hb, hc)) {
-            mask |= 1ull << (b8 + u);
-            w.has_inner[d2] = 1;
-          }
+        for (int u = 0; u < 8; ++u)
+          if (b8 + u < lim && rz_prefilter(c, ob.w, tc[u])) pass |= 1ull << (b8 + u);
+      }
+      while (pass) {
+        const uint32_t k = (uint32_t)__ffsll((unsigned long long)pass) - 1u;
+        pass &= pass - 1ull;
+        const float4 oc = w.oh[kw + k];
+        const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
+        if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
+          mask |= 1ull << k;
+          w.has_inner[kw + k] = 1;
         }
       }
       w.masks[mo + wd] = mask;
@@ -387,6 +561,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     }
     w.nout[d] = nout;
     links += nout;
+    d = dn;
   }
   links = wave_sum(links);
   if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
@@ -394,12 +569,12 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
 
 // A group of G lanes per doublet (a,b).  Each step covers 64 consecutive
 // candidates: lane l of the group takes candidates l, l + G, ..., issuing
-// the U = 64 / G loads of their (r, z) back to back before the r-z tests.
-// The few candidates that pass the r-z cut are not tested further in place
-// -- the transverse tests (divisions, square roots) would run with almost
-// all lanes idle -- but pushed to a per-wavefront queue in LDS; whenever 64
-// are queued they are tested with all lanes busy.  Accepted links set their
-// bit in the (pre-cleared) mask word with atomicOr and count into nout.
+// the U = 64 / G angle loads back to back before the prefilter.  The few
+// candidates that pass it are not tested further in place -- the exact
+// tests (divisions, square roots) would run with almost all lanes idle --
+// but pushed to a per-wavefront queue in LDS; whenever 64 are queued they
+// are tested with all lanes busy.  Accepted links set their bit in the
+// (pre-cleared) mask word with atomicOr and count into nout.
 
 constexpr int kQueue = 128;  // queue entries per wavefront
 
@@ -409,12 +584,13 @@ __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint2*
   if (lane < n) {
     const uint2 it = q[lane];
     const uint32_t d = it.x, k = it.y;
-    const uint32_t a = w.cin[d];
-    const HitD ha = load_hit(w, a);
-    const HitD hb{(double)w.ox[d], (double)w.oy[d], (double)w.oz[d], w.orr[d]};
+    const HitD ha = load_hit(w, w.cin[d]);
+    const float4 ob = w.oh[d];
+    const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
     const uint32_t d2 = w.cb[d] + k;
-    const HitD hc{(double)w.ox[d2], (double)w.oy[d2], (double)w.oz[d2], w.orr[d2]};
-    if (link_xy_pass(c, ha, hb, hc)) {
+    const float4 oc = w.oh[d2];
+    const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
+    if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[w.moff[d] + (k >> 6)], 1ull << (k & 63u));
       atomicAdd(&w.nout[d], 1u);
       w.has_inner[d2] = 1;
@@ -441,31 +617,24 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
   for (uint32_t base = beg; base < end; base += gpb) {
     const uint32_t d = base + gib;
     uint32_t kb = 0, deg = 0;
-    HitD ha{0.0, 0.0, 0.0, 0.0}, hb{0.0, 0.0, 0.0, 0.0};
+    float ta = 0.0f;
     if (d < end) {
-      ha = load_hit(w, w.cin[d]);
-      hb = HitD{(double)w.ox[d], (double)w.oy[d], (double)w.oz[d], w.orr[d]};
+      ta = w.oh[d].w;
       kb = w.cb[d];
       deg = w.cdeg[d];
     }
     const uint32_t maxw = wave_max((deg + 63u) / 64u);
     for (uint32_t wd = 0; wd < maxw; ++wd) {
-      double rc[U];
-      float zc[U];
+      float tc[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t k = wd * 64u + (uint32_t)(u * G) + sub;
-        rc[u] = 0.0;
-        zc[u] = 0.0f;
-        if (k < deg) {
-          rc[u] = w.orr[kb + k];
-          zc[u] = w.oz[kb + k];
-        }
+        tc[u] = k < deg ? w.oh[kb + k].w : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t k = wd * 64u + (uint32_t)(u * G) + sub;
-        const bool ok = k < deg && link_rz_pass(c, ha, hb, rc[u], (double)zc[u]);
+        const bool ok = k < deg && rz_prefilter(c, ta, tc[u]);
         const uint64_t bal = __ballot(ok);
         if (ok) q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(d, k);
         qn += (uint32_t)__popcll(bal);
@@ -499,7 +668,8 @@ __global__ __launch_bounds__(256) void k_zero_words(Ws w, DevCfg c) {
 }
 
 // ------------------------------------------------------------ n-tuplets --
-// One thread per root doublet (no inner neighbour, at least one outer):
+// One thread per root doublet (no inner neighbour, at least one outer;
+// listed by k_roots, so no lane idles on the other doublets):
 // iterative depth-first search over the outer-neighbour masks; every path
 // that ends at a doublet without outer neighbours is an n-tuplet.  Two
 // passes: the first counts each root's paths, an exclusive scan turns the
@@ -510,34 +680,31 @@ template <bool FILL>
 __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
-  const uint32_t nd = ctr[C_ND];
+  const uint32_t nr = ctr[C_NROOT];
   const uint32_t T = c.cap_tuples;
-  if (FILL && w.roff[nd] > T) {
+  if (FILL && w.roff[nr] > T) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       set_status(ctr, PXT_ERR_CAPACITY);
-      ctr[C_REQ_T] = w.roff[nd];
+      ctr[C_REQ_T] = w.roff[nr];
     }
     return;
   }
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nd; r += gridDim.x * blockDim.x) {
-    if (w.has_inner[r] || w.nout[r] == 0) {
-      if (!FILL) w.rcnt[r] = 0;
-      continue;
-    }
+  for (uint32_t ri = blockIdx.x * blockDim.x + threadIdx.x; ri < nr;
+       ri += gridDim.x * blockDim.x) {
+    const uint32_t r = w.roots[ri];
     uint32_t path[kMaxCells];
     uint32_t word[kMaxCells];   // current mask word per depth
     uint64_t bits[kMaxCells];   // its remaining bits
     uint32_t nwd[kMaxCells];    // mask words per depth
     uint32_t kbase[kMaxCells];  // first candidate doublet per depth
     uint32_t cnt = 0;
-    const uint32_t base = FILL ? w.roff[r] : 0u;
+    const uint32_t base = FILL ? w.roff[ri] : 0u;
     const uint32_t h0 = w.cin[r];
     int depth = 0;
     path[0] = r;
     {
-      const uint32_t b = w.cout[r];
-      kbase[0] = w.cell_off[b];
-      nwd[0] = w.mw[r];
+      kbase[0] = w.cb[r];
+      nwd[0] = (w.cdeg[r] + 63u) >> 6;
       word[0] = 0;
       bits[0] = nwd[0] ? w.masks[w.moff[r]] : 0ull;
     }
@@ -575,13 +742,13 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
         continue;
       }
       ++depth;
-      kbase[depth] = w.cell_off[w.cout[child]];
-      nwd[depth] = w.mw[child];
+      kbase[depth] = w.cb[child];
+      nwd[depth] = (w.cdeg[child] + 63u) >> 6;
       word[depth] = 0;
       bits[depth] = nwd[depth] ? w.masks[w.moff[child]] : 0ull;
     }
     if (overflow) set_status(ctr, PXT_ERR_PATH);
-    if (!FILL) w.rcnt[r] = cnt;
+    if (!FILL) w.rcnt[ri] = cnt;
   }
 }
 
@@ -681,10 +848,12 @@ __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
   for (uint32_t t = tid; t < ntup; t += gridDim.x * blockDim.x)
     if (w.talive[t]) w.surv[w.toff[t]] = t;
   const uint32_t per_ev = (uint32_t)c.n_layers * (uint32_t)c.nphi;
+  const uint32_t nr = w.ctr[C_NROOT];
   for (uint32_t e = tid; e < n_events; e += gridDim.x * blockDim.x) {
-    const uint32_t a = w.toff[w.roff[w.cell_off[w.bin_off[e * per_ev]]]];
-    const uint32_t b = w.toff[w.roff[w.cell_off[w.bin_off[(e + 1) * per_ev]]]];
-    per_event_tracks[e] = b - a;
+    // first root doublet at or after the event's first doublet
+    const uint32_t ra = lower_bound_u32(w.roots, nr, w.cell_off[w.bin_off[e * per_ev]]);
+    const uint32_t rb = lower_bound_u32(w.roots, nr, w.cell_off[w.bin_off[(e + 1) * per_ev]]);
+    per_event_tracks[e] = w.toff[w.roff[rb]] - w.toff[w.roff[ra]];
   }
 }
 
@@ -713,10 +882,8 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
       kind[j] = 0;
     }
   }
-  FitGeo g;
-  fit_geometry(c, n, X, Y, Z, kind, g);
   FitOut f;
-  fit_dispatch<T>(c, g, f);
+  fit_tuple<T>(c, n, X, Y, Z, kind, f);
   if (!fp64 && f.need64) {
     const uint32_t k = atomicAdd(&w.ctr[C_NFP64], 1u);
     w.fp64_list[k] = s;

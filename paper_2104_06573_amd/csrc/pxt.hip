@@ -86,6 +86,14 @@ size_t slot_bytes_for(const pxt_config& c) {
   return desc_bytes() + sizeof(uint32_t) * ((size_t)c.max_events + 1);
 }
 
+// Largest number of elements any scan of a call covers, in scan tiles.
+size_t scan_tiles(const pxt_config& c) {
+  const size_t nbins = (size_t)c.max_events * (size_t)c.n_layers * (size_t)c.phi_bins;
+  const size_t n = std::max({nbins, (size_t)c.max_hits, (size_t)c.max_doublets,
+                             (size_t)c.max_tuples});
+  return (n + kTile - 1) / kTile + 1;
+}
+
 void carve(Carver& cv, const pxt_config& c, Ws& w) {
   const size_t H = c.max_hits, D = c.max_doublets, Wd = c.max_link_words, T = c.max_tuples;
   const size_t nbins = (size_t)c.max_events * (size_t)c.n_layers * (size_t)c.phi_bins;
@@ -110,17 +118,14 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.cell_off = cv.take<uint32_t>(H + 1);
   w.cin = cv.take<uint32_t>(D);
   w.cout = cv.take<uint32_t>(D);
-  w.mw = cv.take<uint32_t>(D + 1);
   w.moff = cv.take<uint32_t>(D + 1);
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
-  w.ox = cv.take<float>(D);
-  w.oy = cv.take<float>(D);
-  w.oz = cv.take<float>(D);
-  w.orr = cv.take<double>(D);
+  w.oh = cv.take<float4>(D);
   w.cb = cv.take<uint32_t>(D);
   w.cdeg = cv.take<uint32_t>(D);
+  w.roots = cv.take<uint32_t>(D);
   w.rcnt = cv.take<uint32_t>(D + 1);
   w.roff = cv.take<uint32_t>(D + 1);
   w.thit = cv.take<uint32_t>(8 * T);
@@ -136,6 +141,8 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.surv = cv.take<uint32_t>(T);
   w.fp64_list = cv.take<uint32_t>(T);
   w.block_sums = cv.take<uint32_t>(kScanBlocks + 1);
+  w.scan_status = cv.take<uint64_t>(scan_tiles(c));
+  w.epoch = cv.take<uint32_t>(1);
 }
 
 int validate_config(const pxt_config* c, std::string& why) {
@@ -203,16 +210,44 @@ void make_devcfg(const pxt_config& c, DevCfg& d) {
   d.cap_words = c.max_link_words;
   d.cap_tuples = c.max_tuples;
   d.link_thread = c.link_kernel == 0;
+  // L1 holds only if the r-z directions of the two doublets differ by at
+  // most asin(arz) or by at least pi - asin(arz).  The FP32 angles carry an
+  // error below 1e-6 rad (inputs rounded to FP32: < 1.2e-7; atan2f: a few
+  // ulp), so a margin of 1e-5 rad keeps the prefilter a strict superset of
+  // the FP64 decision.  arz >= 1 leaves it open.
+  if (c.arz < 1.0) {
+    const double a = std::asin(c.arz) + 1e-5;
+    d.th_win = (float)a;
+    d.th_far = (float)(M_PI - a);
+  } else {
+    d.th_win = 8.0f;
+    d.th_far = 0.0f;
+  }
 }
 
-// Launch the three-kernel exclusive scan of n = *n_dev entries.
+// Blocks of a single-pass scan over at most max_n entries.
+uint32_t scan_grid(uint64_t max_n) {
+  return (uint32_t)std::max<uint64_t>(1, (max_n + kTile - 1) / kTile);
+}
+
+// Single-pass exclusive scan of n = *n_dev entries; `max_n` bounds *n_dev
+// (grid size); scan_id is the scan's index within one call (distinct per
+// call site, below 8).
+template <int TR = 0>
+void launch_scan1(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t* n_dev,
+                  uint32_t* total_dst, uint64_t max_n, uint32_t scan_id, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan1<TR>, dim3(scan_grid(max_n)), dim3(256), 0, s, in, out, n_dev,
+                     total_dst, w, scan_id);
+}
+
+template <int TR = 0>
 void launch_scan(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t* n_dev,
                  uint32_t* total_dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, n_dev,
+  hipLaunchKernelGGL(k_scan_reduce<TR>, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, n_dev,
                      w.block_sums, w.ctr);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, w.block_sums, (uint32_t)kScanBlocks,
                      w.ctr);
-  hipLaunchKernelGGL(k_scan_down, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, out, n_dev,
+  hipLaunchKernelGGL(k_scan_down<TR>, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, out, n_dev,
                      w.block_sums, (uint32_t)kScanBlocks, total_dst, w.ctr);
 }
 
@@ -298,7 +333,7 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     if (timed) sm.mark(1);
     hipLaunchKernelGGL(k_prep, dim3(gh1), dim3(256), 0, s, w, d);
     if (timed) sm.mark(2);
-    launch_scan(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, s);
+    launch_scan1(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, nbins, 0, s);
     if (timed) sm.mark(3);
     hipLaunchKernelGGL(k_fill, dim3(gh1), dim3(256), 0, s, w);
     hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
@@ -308,11 +343,11 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     if (timed) sm.mark(4);
     launch_doublets<false>(G, dim3(gh), dim3(bs), s, w, d);
     if (timed) sm.mark(5);
-    launch_scan(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, s);
+    launch_scan1(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, H, 1, s);
     if (timed) sm.mark(6);
     launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
     if (timed) sm.mark(7);
-    launch_scan(w, w.mw, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, s);
+    launch_scan1<1>(w, w.cdeg, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, cfg.max_doublets, 2, s);
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
     if (cfg.link_kernel) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
     if (timed) sm.mark(8);
@@ -320,21 +355,22 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
                                           : std::max<uint32_t>(8, gd / 8 * 8)),
                  dim3(bs), s, w, d);
     if (timed) sm.mark(9);
+    hipLaunchKernelGGL(k_roots, dim3(scan_grid(cfg.max_doublets)), dim3(256), 0, s, w, 6u);
     hipLaunchKernelGGL(k_tuples<false>, dim3(gd), dim3(bs), 0, s, w, d);
-    launch_scan(w, w.rcnt, w.roff, w.ctr + C_ND, w.ctr + C_NTUP, s);
+    launch_scan1(w, w.rcnt, w.roff, w.ctr + C_NROOT, w.ctr + C_NTUP, cfg.max_doublets, 3, s);
     hipLaunchKernelGGL(k_tuples<true>, dim3(gd), dim3(bs), 0, s, w, d);
     const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
     if (timed) sm.mark(10);
     hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
     if (timed) sm.mark(11);
-    launch_scan(w, w.ccnt, w.coff, w.ctr + C_ND, nullptr, s);
+    launch_scan1(w, w.ccnt, w.coff, w.ctr + C_ND, nullptr, cfg.max_doublets, 4, s);
     if (timed) sm.mark(12);
     hipLaunchKernelGGL(k_cfill, dim3(gt), dim3(bs), 0, s, w, d);
     if (timed) sm.mark(13);
     hipLaunchKernelGGL(k_best, dim3(gd), dim3(bs), 0, s, w, d);
     if (timed) sm.mark(14);
     hipLaunchKernelGGL(k_alive, dim3(gt), dim3(bs), 0, s, w, d);
-    launch_scan(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, s);
+    launch_scan1(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, cfg.max_tuples, 5, s);
     hipLaunchKernelGGL(k_compact, dim3(gt), dim3(bs), 0, s, w, d);
     if (timed) sm.mark(15);
     hipLaunchKernelGGL(k_fit32, dim3(grid_for(cfg.max_tuples, 256, persist)), dim3(256), 0, s, w,
@@ -385,7 +421,7 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->max_tuples = 1u << 22;
   cfg->phi_bins = 256;
   cfg->block_size = 256;
-  cfg->group_lanes = 32;
+  cfg->group_lanes = 16;
   cfg->link_kernel = 0;
   cfg->use_graph = 0;
   cfg->pt_fp64 = 20.0;
@@ -422,6 +458,13 @@ int pxt_create(const pxt_config* cfg, int hip_device, pxt_ctx** out) {
   Carver real;
   real.base = static_cast<char*>(c->arena);
   carve(real, *cfg, c->ws);
+  // the scan status words and the call counter start from zero once; no
+  // other arena is ever initialised
+  if (hipMemset(c->ws.scan_status, 0, sizeof(uint64_t) * scan_tiles(*cfg)) != hipSuccess ||
+      hipMemset(c->ws.epoch, 0, sizeof(uint32_t)) != hipSuccess) {
+    pxt_destroy(c);
+    return fail(nullptr, PXT_ERR_HIP, "arena initialisation failed");
+  }
   c->slot_bytes = slot_bytes_for(*cfg);
   bool ok = hipHostMalloc((void**)&c->h_slots, c->slot_bytes * pxt_ctx::kSlots,
                           hipHostMallocDefault) == hipSuccess;
@@ -555,7 +598,8 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
     } else {
       std::vector<uint32_t> cell_off(nb + 1), mw(nd), moff(nd + 1);
       HIP_OR_FAIL(c, hipMemcpy(cell_off.data(), w.cell_off, 4ull * (nb + 1), hipMemcpyDeviceToHost));
-      if (nd) HIP_OR_FAIL(c, hipMemcpy(mw.data(), w.mw, 4ull * nd, hipMemcpyDeviceToHost));
+      if (nd) HIP_OR_FAIL(c, hipMemcpy(mw.data(), w.cdeg, 4ull * nd, hipMemcpyDeviceToHost));
+      for (auto& v : mw) v = (v + 63u) >> 6;
       HIP_OR_FAIL(c, hipMemcpy(moff.data(), w.moff, 4ull * (nd + 1), hipMemcpyDeviceToHost));
       const uint32_t nwords = moff[nd];
       std::vector<uint64_t> masks(nwords);
