@@ -79,16 +79,18 @@ def algorithmic_bytes(stage, n):
         # binned hit read (29), doublet count written (4)
         "doublet_count": 33 * Nh,
         # binned hit + offset read (33); per doublet written: in/out hits,
-        # mask words, candidate range, flags, counters, outer-hit copy (49)
-        "doublet_fill": 33 * Nh + 49 * Nd,
-        # inner-hit coordinates (20 per hit); per doublet: inner hit, outer-hit
-        # copy, candidate range, mask offset, neighbour count (40) and its
-        # (r, z) as a candidate (12); mask words written (8)
-        "links": 20 * Nh + 52 * Nd + 8 * Nw,
-        # root test and graph walk (25 per doublet), masks, n-tuplets written
-        "tuples": 25 * Nd + 8 * Nw + 61 * Nt,
-        # n-tuplet hits/doublets read (61), hit coordinates, score written (8)
-        "score": (69 + 20 * nbar) * Nt,
+        # candidate range, flag, outer hit and r-z angle (33)
+        "doublet_fill": 33 * Nh + 33 * Nd,
+        # inner-hit coordinates (20 per hit); per doublet: inner hit, outer
+        # hit and angle, candidate range, mask offset (32), its angle read
+        # once as a candidate (4), neighbour count written (4); mask words
+        # written (8)
+        "links": 20 * Nh + 40 * Nd + 8 * Nw,
+        # per n-tuplet: hits, doublets, length (61), hit coordinates, score
+        # written (8), order key min per doublet (8)
+        "score": (69 + 20 * nbar + 8 * (nbar - 1)) * Nt,
+        # per n-tuplet: length, score, doublets (37), per doublet the key (8)
+        "best": (37 + 8 * (nbar - 1)) * Nt,
         # survivor, n-tuplet, hits and ids read (41 + 17 per hit), record written (126)
         "fit32": (41 + 17 * nbar + 126) * Nk,
     }
@@ -99,7 +101,7 @@ def algorithmic_bytes(stage, n):
 STAGE_KERNEL = {"prep": "pxt::k_prep", "fill": "pxt::k_fill",
                 "doublet_count": "pxt::k_doublets<16, false>",
                 "doublet_fill": "pxt::k_doublets<16, true>", "links": "pxt::k_links_thread",
-                "score": "pxt::k_score", "fit32": "pxt::k_fit32"}
+                "score": "pxt::k_score", "best": "pxt::k_best", "fit32": "pxt::k_fit32"}
 
 
 def kernel_source_hash():

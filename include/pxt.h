@@ -216,7 +216,7 @@ int pxt_set_timing(pxt_ctx* ctx, int enable);
  * floats; *n_stages receives the number of stages (PXT_N_STAGES).  Stages
  * skipped by that call (an empty batch) read 0.  Errors:
  * PXT_ERR_INVALID_ARG (no timed call yet, null pointers), PXT_ERR_HIP. */
-#define PXT_N_STAGES 18
+#define PXT_N_STAGES 19
 int pxt_stage_times(pxt_ctx* ctx, float* ms, int cap, int* n_stages);
 
 /* Static name of stage i (0 <= i < PXT_N_STAGES), or NULL. */

@@ -498,11 +498,16 @@ static void dfs(dfs_ctx* d, int depth) {
   }
 }
 
-/* Total order of the cleaning step: returns <0 if tuple a ranks before b. */
+/* Total order of the cleaning step: returns <0 if tuple a ranks before b.
+ * A NaN score (only non-finite hits produce one) ranks after every number
+ * and NaN scores tie, so the order stays total and the best tuple of a
+ * doublet does not depend on the order the tuples are visited in. */
 static int rank_cmp(const uint32_t* ta, int na, double sa, const uint32_t* tb,
                     int nb, double sb) {
   if (na != nb) return na > nb ? -1 : 1;
-  if (sa != sb) return sa < sb ? -1 : 1;
+  const int an = sa != sa, bn = sb != sb;
+  if (an != bn) return an ? 1 : -1;
+  if (!an && sa != sb) return sa < sb ? -1 : 1;
   for (int i = 0; i < ORC_MAX_HITS_PER_TUPLE; ++i)
     if (ta[i] != tb[i]) return ta[i] < tb[i] ? -1 : 1;
   return 0;

@@ -71,6 +71,7 @@ struct Ws {
   uint32_t* bin_cnt;      // [nbins + 1]
   uint32_t* bin_off;      // [nbins + 1]
   uint32_t* rmax;         // [E * L] largest hit radius per layer (float bits)
+  float* rasin;           // [E * L] turning angle to that radius (inf: any)
   // binned hits
   float* bx;
   float* by;
@@ -101,10 +102,8 @@ struct Ws {
   uint8_t* tn;            // [T] hits
   double* tscore;         // [T]
   // cleaning
-  uint32_t* ccnt;         // [D + 1] tuples through each doublet
-  uint32_t* coff;         // [D + 1]
-  uint32_t* clist;        // [7 T]
-  uint32_t* best;         // [D]
+  uint64_t* bkey;         // [D] smallest order key of the tuples through it
+  uint32_t* best;         // [D] best tuple through each doublet
   uint32_t* talive;       // [T + 1] survives the cleaning
   uint32_t* toff;         // [T + 1]
   uint32_t* surv;         // [T]

@@ -108,7 +108,10 @@ __global__ __launch_bounds__(256) void k_fill(Ws w) {
 
 // Largest transverse radius of each (event, layer): one wavefront per
 // segment of the binned array (hits of one layer of one event are
-// contiguous), a max-reduction across lanes.
+// contiguous), a max-reduction across lanes.  Also the turning angle
+// asin(kmax r / 2) of a curvature-kmax circle through the origin out to
+// that radius (slightly enlarged), the outer term of the doublet phi
+// window; infinity where the window is the whole layer.
 __global__ __launch_bounds__(256) void k_rmax(Ws w, DevCfg c) {
   const uint32_t n_layers = (uint32_t)c.n_layers, nphi = (uint32_t)c.nphi;
   const uint32_t nseg = w.call->n_events * n_layers;
@@ -120,7 +123,11 @@ __global__ __launch_bounds__(256) void k_rmax(Ws w, DevCfg c) {
     for (uint32_t i = b0 + lane_id(); i < b1; i += kWave) m = fmaxf(m, (float)w.br[i]);
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, kWave));
-    if (lane_id() == 0) w.rmax[sg] = __float_as_uint(m);
+    if (lane_id() == 0) {
+      w.rmax[sg] = __float_as_uint(m);
+      const float ao = 0.5f * c.kmax_f * (m * 1.000001f);
+      w.rasin[sg] = ao >= 0.70710678f ? __builtin_huge_valf() : asinf(ao);
+    }
   }
 }
 
@@ -220,7 +227,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 // PXT_ERR_HIP instead of hanging.
 
 constexpr int kTileItems = 16;
-constexpr int kTile = 256 * kTileItems;
+constexpr int kScanThreads1 = 1024;  // threads per tile
+constexpr int kTile = kScanThreads1 * kTileItems;
 constexpr uint32_t kSpinLimit = 1u << 24;
 
 __device__ __forceinline__ uint64_t scan_word(uint32_t epoch, uint32_t flag, uint32_t v) {
@@ -290,12 +298,12 @@ __device__ __forceinline__ bool take_tile(Ws& w, uint32_t scan_id, uint32_t ntil
 }
 
 template <int TR>
-__global__ __launch_bounds__(256) void k_scan1(const uint32_t* __restrict__ in,
+__global__ __launch_bounds__(kScanThreads1) void k_scan1(const uint32_t* __restrict__ in,
                                                 uint32_t* __restrict__ out, const uint32_t* n_dev,
                                                 uint32_t* total_dst, Ws w, uint32_t scan_id) {
   if (w.ctr[C_STATUS]) return;
   __shared__ uint32_t s_prefix;
-  __shared__ uint32_t lds[256 / kWave + 1];
+  __shared__ uint32_t lds[kScanThreads1 / kWave + 1];
   const uint32_t n = *n_dev;
   const uint32_t ntiles = n ? (n + kTile - 1) / kTile : 1u;
   uint32_t tile;
@@ -332,10 +340,10 @@ __global__ __launch_bounds__(256) void k_scan1(const uint32_t* __restrict__ in,
 // The root doublets of the n-tuplet search -- no inner neighbour, at least
 // one outer neighbour -- listed in ascending order: a stream compaction of
 // the doublets by the same single-pass scan over their root flags.
-__global__ __launch_bounds__(256) void k_roots(Ws w, uint32_t scan_id) {
+__global__ __launch_bounds__(kScanThreads1) void k_roots(Ws w, uint32_t scan_id) {
   if (w.ctr[C_STATUS]) return;
   __shared__ uint32_t s_prefix;
-  __shared__ uint32_t lds[256 / kWave + 1];
+  __shared__ uint32_t lds[kScanThreads1 / kWave + 1];
   const uint32_t n = w.ctr[C_ND];
   const uint32_t ntiles = n ? (n + kTile - 1) / kTile : 1u;
   uint32_t tile;
@@ -411,21 +419,23 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
       phi = w.bphi[g];
       npairs = c.n_outer[li];
     }
+    const double kir2 = c.kmax2 * (hi.r * hi.r);
+    const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
     uint32_t cnt = 0;
     uint32_t pos = (FILL && active) ? w.cell_off[g] : 0u;
-    const uint32_t maxp = wave_max((uint32_t)npairs);
-    for (uint32_t p = 0; p < maxp; ++p) {
+    for (uint32_t p = 0; __any((int)p < npairs); ++p) {
       uint32_t s0b = 0, s0n = 0, s1b = 0, s1n = 0;
       if (active && (int)p < npairs) {
         const int lo = c.outer[li][p];
-        const float rmo = __uint_as_float(w.rmax[e * c.n_layers + lo]) * 1.000001f;
+        const uint32_t el = e * (uint32_t)c.n_layers + (uint32_t)lo;
+        const float rmo = __uint_as_float(w.rmax[el]) * 1.000001f;
         if (rmo > ri * 0.999999f) {
-          const uint32_t bb = (e * (uint32_t)c.n_layers + (uint32_t)lo) * (uint32_t)c.nphi;
-          const float ao = 0.5f * c.kmax_f * rmo;
+          const uint32_t bb = el * (uint32_t)c.nphi;
+          const float ao = w.rasin[el];
           int blo = 0, bhi = c.nphi - 1;
-          bool full = ao >= 0.70710678f;
+          bool full = !(ao < __builtin_huge_valf());
           if (!full) {
-            const float W = asinf(ao) - asinf(0.5f * c.kmax_f * ri);
+            const float W = ao - ai;
             if (!(W >= 0.0f && W < 4.0f && phi >= -4.0f && phi <= 4.0f)) {
               full = true;  // non-finite input: fall back to the whole layer
             } else {
@@ -454,14 +464,20 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
         }
       }
       const uint32_t tot = s0n + s1n;
-      const uint32_t maxit = wave_max((tot + G - 1) / G);
-      for (uint32_t it = 0; it < maxit; ++it) {
+      for (uint32_t it = 0; __any(it * G < tot); ++it) {
         const uint32_t k = it * G + sub;
-        bool ok = false;
-        uint32_t j = 0;
-        if (k < tot) {
-          j = k < s0n ? s0b + k : s1b + (k - s0n);
-          ok = doublet_ok_fast(c, hi, load_hit(w, j));
+        const bool valid = k < tot;
+        // fill pass: every lane loads a hit (an idle lane the chunk's first
+        // one), so the loads go out together and the cuts run without
+        // branches; count pass: early exits, which issue fewer instructions
+        const uint32_t j = valid ? (k < s0n ? s0b + k : s1b + (k - s0n)) : beg;
+        HitD ho{0.0, 0.0, 0.0, 0.0};
+        bool ok;
+        if (FILL) {
+          ho = load_hit(w, j);
+          ok = valid & doublet_ok_flat(c, hi, ho, kir2);
+        } else {
+          ok = valid && doublet_ok_fast(c, hi, load_hit(w, j));
         }
         const uint64_t bal = __ballot(ok);
         if (FILL && ok) {
@@ -472,9 +488,7 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
           w.cb[q] = jb;
           w.cdeg[q] = deg;
           w.has_inner[q] = 0;
-          w.ccnt[q] = 0;
           if (!c.link_thread) w.nout[q] = 0;
-          const HitD ho = load_hit(w, j);
           w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, rz_angle(hi, ho));
         }
         const uint32_t ng = (uint32_t)__popcll(bal & gmask);
@@ -737,6 +751,11 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
             w.tcell[(size_t)j * T + t] = j <= last ? path[j] : kPad;
           }
           w.tn[t] = (uint8_t)(last + 2);
+          // the cleaning's per-doublet election starts from "no tuple"
+          for (int j = 0; j <= last; ++j) {
+            w.bkey[path[j]] = ~0ull;
+            w.best[path[j]] = kPad;
+          }
         }
         ++cnt;
         continue;
@@ -753,9 +772,24 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
 }
 
 // ------------------------------------------------------------- cleaning --
-// Each doublet keeps only its best n-tuplet under the total order
-// (more hits, lower score, lexicographically smaller event-local hit tuple);
-// a tuple survives iff it is the best at every one of its doublets.
+// Each doublet keeps only its best n-tuplet under the total order: more
+// hits, then lower score (a NaN score after every number, NaN scores
+// equal), then the lexicographically smaller event-local hit tuple; a tuple
+// survives iff it is the best at every one of its doublets.
+//
+// The per-doublet election runs in two rounds of atomics instead of a
+// per-doublet list.  The order key packs (8 - hits) above the score's bits
+// with their lowest three dropped: it never decreases along the order, so
+// the best tuple of a doublet holds the smallest key there (k_score takes
+// the atomicMin).  The tuples holding that key -- almost always just one --
+// then settle the exact order by compare-and-swap on the doublet's best
+// tuple (k_best): a swap only ever installs a better tuple, so the loop
+// ends, and the result does not depend on the order the threads run in.
+
+__device__ __forceinline__ uint64_t order_key(int n, double s) {
+  const uint64_t m = s != s ? 0x7fffffffffffffffull : (uint64_t)__double_as_longlong(s);
+  return ((uint64_t)(kMaxHits - n) << 60) | (m >> 3);
+}
 
 __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
@@ -774,21 +808,10 @@ __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
       h1 = h2;
     }
     w.tscore[t] = s;
-    for (int j = 0; j + 1 < n; ++j) atomicAdd(&w.ccnt[w.tcell[(size_t)j * T + t]], 1u);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_cfill(Ws w, DevCfg c) {
-  if (w.ctr[C_STATUS]) return;
-  const uint32_t ntup = w.ctr[C_NTUP];
-  const uint32_t T = c.cap_tuples;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
-    const int n = w.tn[t];
-    for (int j = 0; j + 1 < n; ++j) {
-      const uint32_t d = w.tcell[(size_t)j * T + t];
-      const uint32_t pos = w.coff[d] + atomicSub(&w.ccnt[d], 1u) - 1u;
-      w.clist[pos] = t;
-    }
+    const uint64_t key = order_key(n, s);
+    for (int j = 0; j + 1 < n; ++j)
+      atomicMin((unsigned long long*)&w.bkey[w.tcell[(size_t)j * T + t]],
+                (unsigned long long)key);
   }
 }
 
@@ -797,7 +820,9 @@ __device__ __forceinline__ bool ranks_before(const Ws& w, uint32_t T, uint32_t a
   const int na = w.tn[a], nbh = w.tn[b];
   if (na != nbh) return na > nbh;
   const double sa = w.tscore[a], sb = w.tscore[b];
-  if (sa != sb) return sa < sb;
+  const bool an = sa != sa, bn = sb != sb;
+  if (an != bn) return bn;
+  if (!an && sa != sb) return sa < sb;
   for (int j = 0; j < kMaxHits; ++j) {
     const uint32_t ha = w.thit[(size_t)j * T + a], hb = w.thit[(size_t)j * T + b];
     const uint32_t ia = ha == kPad ? kPad : w.bidx[ha];
@@ -809,17 +834,21 @@ __device__ __forceinline__ bool ranks_before(const Ws& w, uint32_t T, uint32_t a
 
 __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
-  const uint32_t nd = w.ctr[C_ND];
+  const uint32_t ntup = w.ctr[C_NTUP];
   const uint32_t T = c.cap_tuples;
-  for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
-    const uint32_t b0 = w.coff[d], b1 = w.coff[d + 1];
-    if (b0 == b1) continue;
-    uint32_t best = w.clist[b0];
-    for (uint32_t k = b0 + 1; k < b1; ++k) {
-      const uint32_t t = w.clist[k];
-      if (ranks_before(w, T, t, best)) best = t;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
+    const int n = w.tn[t];
+    const uint64_t key = order_key(n, w.tscore[t]);
+    for (int j = 0; j + 1 < n; ++j) {
+      const uint32_t d = w.tcell[(size_t)j * T + t];
+      if (w.bkey[d] != key) continue;
+      uint32_t cur = w.best[d];
+      while (cur == kPad || ranks_before(w, T, t, cur)) {
+        const uint32_t prev = atomicCAS(&w.best[d], cur, t);
+        if (prev == cur) break;
+        cur = prev;
+      }
     }
-    w.best[d] = best;
   }
 }
 

@@ -106,6 +106,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.bin_cnt = cv.take<uint32_t>(nbins + 1);
   w.bin_off = cv.take<uint32_t>(nbins + 1);
   w.rmax = cv.take<uint32_t>(E * c.n_layers);
+  w.rasin = cv.take<float>(E * c.n_layers);
   w.bx = cv.take<float>(H);
   w.by = cv.take<float>(H);
   w.bz = cv.take<float>(H);
@@ -132,9 +133,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.tcell = cv.take<uint32_t>(7 * T);
   w.tn = cv.take<uint8_t>(T);
   w.tscore = cv.take<double>(T);
-  w.ccnt = cv.take<uint32_t>(D + 1);
-  w.coff = cv.take<uint32_t>(D + 1);
-  w.clist = cv.take<uint32_t>(7 * T);
+  w.bkey = cv.take<uint64_t>(D);
   w.best = cv.take<uint32_t>(D);
   w.talive = cv.take<uint32_t>(T + 1);
   w.toff = cv.take<uint32_t>(T + 1);
@@ -236,7 +235,7 @@ uint32_t scan_grid(uint64_t max_n) {
 template <int TR = 0>
 void launch_scan1(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t* n_dev,
                   uint32_t* total_dst, uint64_t max_n, uint32_t scan_id, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan1<TR>, dim3(scan_grid(max_n)), dim3(256), 0, s, in, out, n_dev,
+  hipLaunchKernelGGL(k_scan1<TR>, dim3(scan_grid(max_n)), dim3(kScanThreads1), 0, s, in, out, n_dev,
                      total_dst, w, scan_id);
 }
 
@@ -252,9 +251,10 @@ void launch_scan(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t*
 }
 
 const char* const kStageNames[PXT_N_STAGES] = {
-    "clear",       "prep",         "bin_scan",      "fill",  "doublet_count", "doublet_scan",
-    "doublet_fill", "word_scan",   "links",         "tuples", "score",        "cell_scan",
-    "cell_fill",   "best",         "survive",       "fit32", "fit64",        "finish"};
+    "clear",       "prep",       "bin_scan",    "fill",       "doublet_count",
+    "doublet_scan", "doublet_fill", "word_scan", "links",     "roots",
+    "tuple_count", "tuple_scan", "tuple_fill",  "score",      "best",
+    "survive",     "fit32",      "fit64",       "finish"};
 
 // Marks the start of stage i when timing is on.
 struct StageMarks {
@@ -355,31 +355,31 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
                                           : std::max<uint32_t>(8, gd / 8 * 8)),
                  dim3(bs), s, w, d);
     if (timed) sm.mark(9);
-    hipLaunchKernelGGL(k_roots, dim3(scan_grid(cfg.max_doublets)), dim3(256), 0, s, w, 6u);
+    hipLaunchKernelGGL(k_roots, dim3(scan_grid(cfg.max_doublets)), dim3(kScanThreads1), 0, s, w,
+                       6u);
+    if (timed) sm.mark(10);
     hipLaunchKernelGGL(k_tuples<false>, dim3(gd), dim3(bs), 0, s, w, d);
+    if (timed) sm.mark(11);
     launch_scan1(w, w.rcnt, w.roff, w.ctr + C_NROOT, w.ctr + C_NTUP, cfg.max_doublets, 3, s);
+    if (timed) sm.mark(12);
     hipLaunchKernelGGL(k_tuples<true>, dim3(gd), dim3(bs), 0, s, w, d);
     const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
-    if (timed) sm.mark(10);
-    hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
-    if (timed) sm.mark(11);
-    launch_scan1(w, w.ccnt, w.coff, w.ctr + C_ND, nullptr, cfg.max_doublets, 4, s);
-    if (timed) sm.mark(12);
-    hipLaunchKernelGGL(k_cfill, dim3(gt), dim3(bs), 0, s, w, d);
     if (timed) sm.mark(13);
-    hipLaunchKernelGGL(k_best, dim3(gd), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
     if (timed) sm.mark(14);
+    hipLaunchKernelGGL(k_best, dim3(gt), dim3(bs), 0, s, w, d);
+    if (timed) sm.mark(15);
     hipLaunchKernelGGL(k_alive, dim3(gt), dim3(bs), 0, s, w, d);
     launch_scan1(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, cfg.max_tuples, 5, s);
     hipLaunchKernelGGL(k_compact, dim3(gt), dim3(bs), 0, s, w, d);
-    if (timed) sm.mark(15);
+    if (timed) sm.mark(16);
     hipLaunchKernelGGL(k_fit32, dim3(grid_for(cfg.max_tuples, 256, persist)), dim3(256), 0, s, w,
                        d);
-    if (timed) sm.mark(16);
+    if (timed) sm.mark(17);
     hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)c->n_cu)), dim3(64),
                        0, s, w, d);
   }
-  if (timed) sm.mark(17);
+  if (timed) sm.mark(18);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, w);
   if (timed) {
     (void)hipEventRecord(c->ev[PXT_N_STAGES], s);
