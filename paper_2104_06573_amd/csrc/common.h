@@ -97,8 +97,8 @@ struct Ws {
   uint32_t* rcnt;         // [D + 1] n-tuplets per root doublet
   uint32_t* roff;         // [D + 1]
   // n-tuplets
-  uint32_t* thit;         // [8][T] binned hits (slot-major)
-  uint32_t* tcell;        // [7][T] doublets
+  uint32_t* thit;         // [T][8] binned hits of each n-tuplet (kPad-padded)
+  uint32_t* tcell;        // [T][8] its doublets (7 used, kPad-padded)
   uint8_t* tn;            // [T] hits
   double* tscore;         // [T]
   // cleaning

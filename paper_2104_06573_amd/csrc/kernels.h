@@ -744,12 +744,21 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
         if (FILL) {
           const uint32_t t = base + cnt;
           const int last = depth + 1;
-          w.thit[t] = h0;
+          uint32_t hh[kMaxHits], cc[kMaxHits];
+          hh[0] = h0;
 #pragma unroll
           for (int j = 0; j < kMaxCells; ++j) {
-            w.thit[(size_t)(j + 1) * T + t] = j <= last ? w.cout[path[j]] : kPad;
-            w.tcell[(size_t)j * T + t] = j <= last ? path[j] : kPad;
+            hh[j + 1] = j <= last ? w.cout[path[j]] : kPad;
+            cc[j] = j <= last ? path[j] : kPad;
           }
+          cc[kMaxCells] = kPad;
+          // one n-tuplet row: two 16-byte stores per array
+          uint4* th4 = reinterpret_cast<uint4*>(w.thit + (size_t)t * kMaxHits);
+          uint4* tc4 = reinterpret_cast<uint4*>(w.tcell + (size_t)t * kMaxHits);
+          th4[0] = make_uint4(hh[0], hh[1], hh[2], hh[3]);
+          th4[1] = make_uint4(hh[4], hh[5], hh[6], hh[7]);
+          tc4[0] = make_uint4(cc[0], cc[1], cc[2], cc[3]);
+          tc4[1] = make_uint4(cc[4], cc[5], cc[6], cc[7]);
           w.tn[t] = (uint8_t)(last + 2);
           // the cleaning's per-doublet election starts from "no tuple"
           for (int j = 0; j <= last; ++j) {
@@ -795,14 +804,15 @@ __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t ntup = ctr[C_NTUP];
-  const uint32_t T = c.cap_tuples;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     const int n = w.tn[t];
-    HitD h0 = load_hit(w, w.thit[t]);
-    HitD h1 = load_hit(w, w.thit[(size_t)T + t]);
+    const uint32_t* th = w.thit + (size_t)t * kMaxHits;
+    const uint32_t* tc = w.tcell + (size_t)t * kMaxHits;
+    HitD h0 = load_hit(w, th[0]);
+    HitD h1 = load_hit(w, th[1]);
     double s = 0.0;
     for (int j = 1; j + 1 < n; ++j) {
-      const HitD h2 = load_hit(w, w.thit[(size_t)(j + 1) * T + t]);
+      const HitD h2 = load_hit(w, th[j + 1]);
       s += triple_score(c, h0, h1, h2);
       h0 = h1;
       h1 = h2;
@@ -810,8 +820,7 @@ __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
     w.tscore[t] = s;
     const uint64_t key = order_key(n, s);
     for (int j = 0; j + 1 < n; ++j)
-      atomicMin((unsigned long long*)&w.bkey[w.tcell[(size_t)j * T + t]],
-                (unsigned long long)key);
+      atomicMin((unsigned long long*)&w.bkey[tc[j]], (unsigned long long)key);
   }
 }
 
@@ -824,7 +833,7 @@ __device__ __forceinline__ bool ranks_before(const Ws& w, uint32_t T, uint32_t a
   if (an != bn) return bn;
   if (!an && sa != sb) return sa < sb;
   for (int j = 0; j < kMaxHits; ++j) {
-    const uint32_t ha = w.thit[(size_t)j * T + a], hb = w.thit[(size_t)j * T + b];
+    const uint32_t ha = w.thit[(size_t)a * kMaxHits + j], hb = w.thit[(size_t)b * kMaxHits + j];
     const uint32_t ia = ha == kPad ? kPad : w.bidx[ha];
     const uint32_t ib = hb == kPad ? kPad : w.bidx[hb];
     if (ia != ib) return ia < ib;
@@ -840,7 +849,7 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
     const int n = w.tn[t];
     const uint64_t key = order_key(n, w.tscore[t]);
     for (int j = 0; j + 1 < n; ++j) {
-      const uint32_t d = w.tcell[(size_t)j * T + t];
+      const uint32_t d = w.tcell[(size_t)t * kMaxHits + j];
       if (w.bkey[d] != key) continue;
       uint32_t cur = w.best[d];
       while (cur == kPad || ranks_before(w, T, t, cur)) {
@@ -855,12 +864,11 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
 __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const uint32_t ntup = w.ctr[C_NTUP];
-  const uint32_t T = c.cap_tuples;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     uint32_t alive = 1;
     const int n = w.tn[t];
     for (int j = 0; j + 1 < n; ++j)
-      if (w.best[w.tcell[(size_t)j * T + t]] != t) alive = 0;
+      if (w.best[w.tcell[(size_t)t * kMaxHits + j]] != t) alive = 0;
     w.talive[t] = alive;
   }
 }
@@ -891,7 +899,6 @@ __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
 template <typename T>
 __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_t s,
                                bool fp64) {
-  const uint32_t TT = c.cap_tuples;
   const uint32_t t = w.surv[s];
   const int n = w.tn[t];
   double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
@@ -899,7 +906,7 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   uint32_t hid[kMaxHits];
 #pragma unroll
   for (int j = 0; j < kMaxHits; ++j) {
-    const uint32_t h = w.thit[(size_t)j * TT + t];
+    const uint32_t h = w.thit[(size_t)t * kMaxHits + j];
     hid[j] = h;
     if (j < n) {
       X[j] = (double)w.bx[h];

@@ -130,7 +130,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.rcnt = cv.take<uint32_t>(D + 1);
   w.roff = cv.take<uint32_t>(D + 1);
   w.thit = cv.take<uint32_t>(8 * T);
-  w.tcell = cv.take<uint32_t>(7 * T);
+  w.tcell = cv.take<uint32_t>(8 * T);
   w.tn = cv.take<uint8_t>(T);
   w.tscore = cv.take<double>(T);
   w.bkey = cv.take<uint64_t>(D);
@@ -628,9 +628,9 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
     if (n) HIP_OR_FAIL(c, hipMemcpy(th.data(), w.thit, 4ull * 8 * T, hipMemcpyDeviceToHost));
     rows.reserve(9ull * n);
     for (uint32_t t = 0; t < n; ++t) {
-      rows.push_back(bevt[th[t]]);
+      rows.push_back(bevt[th[(size_t)t * 8]]);
       for (int j = 0; j < 8; ++j) {
-        const uint32_t h = th[(size_t)j * T + t];
+        const uint32_t h = th[(size_t)t * 8 + j];
         rows.push_back(h == kPad ? kPad : bidx[h]);
       }
     }
