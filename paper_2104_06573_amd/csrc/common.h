@@ -86,7 +86,10 @@ struct Ws {
   uint32_t* cell_off;     // [H + 1] first doublet of each inner hit
   uint32_t* cin;          // [D] inner binned hit
   uint32_t* cout;         // [D] outer binned hit
-  uint32_t* moff;         // [D + 1]
+  uint32_t* moff;         // [D] first link-mask word of each doublet
+  uint32_t* lw;           // [D] the same within its inner hit's doublets
+  uint32_t* wcnt;         // [H + 1] link-mask words of each inner hit
+  uint32_t* wbase;        // [H + 1] their exclusive prefix
   uint64_t* masks;        // [W]
   uint8_t* has_inner;     // [D]
   uint32_t* nout;         // [D] outer links per doublet
@@ -109,13 +112,10 @@ struct Ws {
   uint32_t* surv;         // [T]
   uint32_t* fp64_list;    // [T]
   // scan scratch
-  uint32_t* block_sums;   // [kScanBlocks + 1]
   uint64_t* scan_status;  // [max tiles] status words of the single-pass scan
   uint32_t* epoch;        // [1] call counter (never cleared)
 };
 
-constexpr int kScanBlocks = 512;
-constexpr int kScanThreads = 256;
 
 // ------------------------------------------------------------------------
 // wavefront primitives

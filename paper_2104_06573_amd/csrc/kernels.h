@@ -131,88 +131,10 @@ __global__ __launch_bounds__(256) void k_rmax(Ws w, DevCfg c) {
   }
 }
 
-// -------------------------------------------------- device-wide scan ---
-// Exclusive scan of n = *n_dev entries of `in` into `out[0..n]` (out[n] is
-// the total, also stored in *total_dst when non-null).  Three launches:
-// per-chunk sums, a one-block scan of the chunk sums, per-chunk scans.
-
-__device__ __forceinline__ void scan_chunk(uint32_t n, uint32_t& beg, uint32_t& end) {
-  const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
-  const uint32_t per_r = (per + blockDim.x - 1) / blockDim.x * blockDim.x;
-  beg = min(n, blockIdx.x * per_r);
-  end = min(n, beg + per_r);
-}
-
-// Input transform of a scan: identity, or the number of 64-bit link-mask
-// words needed for a candidate count.
-template <int TR>
-__device__ __forceinline__ uint32_t scan_in(uint32_t v) {
-  return TR == 0 ? v : (v + 63u) >> 6;
-}
-
-template <int TR>
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                               const uint32_t* n_dev,
-                                                               uint32_t* block_sums,
-                                                               const uint32_t* ctr) {
-  if (ctr[C_STATUS]) return;
-  const uint32_t n = *n_dev;
-  uint32_t beg, end;
-  scan_chunk(n, beg, end);
-  uint32_t s = 0;
-  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) s += scan_in<TR>(in[i]);
-  s = wave_sum(s);
-  __shared__ uint32_t part[kScanThreads / kWave];
-  if (lane_id() == 0) part[threadIdx.x / kWave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t t = 0;
-    for (uint32_t k = 0; k < blockDim.x / kWave; ++k) t += part[k];
-    block_sums[blockIdx.x] = t;
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* block_sums, uint32_t nblk,
-                                                   const uint32_t* ctr) {
-  if (ctr[C_STATUS]) return;
-  __shared__ uint32_t lds[1024 / kWave + 1];
-  const uint32_t v = threadIdx.x < nblk ? block_sums[threadIdx.x] : 0u;
-  uint32_t tot;
-  const uint32_t ex = block_excl_scan(v, lds, tot);
-  if (threadIdx.x < nblk) block_sums[threadIdx.x] = ex;
-  if (threadIdx.x == 0) block_sums[nblk] = tot;
-}
-
-template <int TR>
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
-                                                             uint32_t* __restrict__ out,
-                                                             const uint32_t* n_dev,
-                                                             const uint32_t* block_sums,
-                                                             uint32_t nblk, uint32_t* total_dst,
-                                                             const uint32_t* ctr) {
-  if (ctr[C_STATUS]) return;
-  const uint32_t n = *n_dev;
-  uint32_t beg, end;
-  scan_chunk(n, beg, end);
-  __shared__ uint32_t lds[kScanThreads / kWave + 1];
-  uint32_t carry = block_sums[blockIdx.x];
-  for (uint32_t base = beg; base < end; base += blockDim.x) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < end ? scan_in<TR>(in[i]) : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(v, lds, tot);
-    if (i < end) out[i] = carry + ex;
-    carry += tot;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const uint32_t total = block_sums[nblk];
-    out[n] = total;
-    if (total_dst) *total_dst = total;
-  }
-}
-
 // ---------------------------------------------------- single-pass scan --
-// Exclusive scan in one launch by decoupled look-back (Merrill & Garland,
+// Exclusive scan of n = *n_dev entries of `in` into out[0..n] (out[n] is
+// the total, also stored in *total_dst when non-null), in one launch by
+// decoupled look-back (Merrill & Garland,
 // "Single-pass parallel prefix scan with decoupled look-back", 2016).  Tile
 // ids are taken from an atomic ticket (zeroed per call by k_clear), so every
 // tile a block waits for belongs to a block that is already running.  Each
@@ -287,9 +209,12 @@ __device__ uint32_t tile_lookback(Ws& w, uint32_t tile, uint32_t epoch, uint32_t
 }
 
 // Takes the block's tile from the scan's ticket; returns false for a
-// block beyond the `ntiles` tiles.
+// block beyond the `ntiles` tiles.  The grid is sized for the capacity, so
+// blocks past the tile count leave without touching the ticket: exactly
+// the first ntiles blocks take tickets 0 .. ntiles-1.
 __device__ __forceinline__ bool take_tile(Ws& w, uint32_t scan_id, uint32_t ntiles,
                                           uint32_t& tile) {
+  if (blockIdx.x >= ntiles) return false;
   __shared__ uint32_t s_tile;
   if (threadIdx.x == 0) s_tile = atomicAdd(&w.ctr[C_TICKET0 + scan_id], 1u);
   __syncthreads();
@@ -297,7 +222,6 @@ __device__ __forceinline__ bool take_tile(Ws& w, uint32_t scan_id, uint32_t ntil
   return tile < ntiles;
 }
 
-template <int TR>
 __global__ __launch_bounds__(kScanThreads1) void k_scan1(const uint32_t* __restrict__ in,
                                                 uint32_t* __restrict__ out, const uint32_t* n_dev,
                                                 uint32_t* total_dst, Ws w, uint32_t scan_id) {
@@ -314,7 +238,7 @@ __global__ __launch_bounds__(kScanThreads1) void k_scan1(const uint32_t* __restr
   uint32_t tsum = 0;
 #pragma unroll
   for (int i = 0; i < kTileItems; ++i) {
-    v[i] = base + i < n ? scan_in<TR>(in[base + i]) : 0u;
+    v[i] = base + i < n ? in[base + i] : 0u;
     tsum += v[i];
   }
   uint32_t agg;
@@ -423,6 +347,7 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
     const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
     uint32_t cnt = 0;
     uint32_t pos = (FILL && active) ? w.cell_off[g] : 0u;
+    uint32_t wpos = 0;  // fill pass: link-mask words of g's doublets so far
     for (uint32_t p = 0; __any((int)p < npairs); ++p) {
       uint32_t s0b = 0, s0n = 0, s1b = 0, s1n = 0;
       if (active && (int)p < npairs) {
@@ -480,16 +405,42 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
           ok = valid && doublet_ok_fast(c, hi, load_hit(w, j));
         }
         const uint64_t bal = __ballot(ok);
-        if (FILL && ok) {
-          const uint32_t q = pos + (uint32_t)__popcll(bal & below);
-          w.cin[q] = g;
-          w.cout[q] = j;
-          const uint32_t jb = w.cell_off[j], deg = w.cell_off[j + 1] - jb;
-          w.cb[q] = jb;
-          w.cdeg[q] = deg;
+        if (FILL) {
+          // link-mask words of this doublet: one per 64 candidates, the
+          // doublets leaving its outer hit
+          uint32_t jb = 0, deg = 0;
+          if (ok) {
+            jb = w.cell_off[j];
+            deg = w.cell_off[j + 1] - jb;
+          }
+          const uint32_t nw = (deg + 63u) >> 6;
+          uint32_t wex, wgrp;  // words of the group's earlier lanes, of all
+          if (__all(nw <= 1u)) {
+            const uint64_t bw = __ballot(nw != 0u);
+            wex = (uint32_t)__popcll(bw & below);
+            wgrp = (uint32_t)__popcll(bw & gmask);
+          } else {
+            uint32_t inc = nw;
+#pragma unroll
+            for (int dd = 1; dd < G; dd <<= 1) {
+              const uint32_t t = __shfl_up(inc, dd, G);
+              if ((int)sub >= dd) inc += t;
+            }
+            wex = inc - nw;
+            wgrp = __shfl(inc, G - 1, G);
+          }
+          if (ok) {
+            const uint32_t q = pos + (uint32_t)__popcll(bal & below);
+            w.cin[q] = g;
+            w.cout[q] = j;
+            w.cb[q] = jb;
+            w.cdeg[q] = deg;
+            w.lw[q] = wpos + wex;
           w.has_inner[q] = 0;
-          if (!c.link_thread) w.nout[q] = 0;
-          w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, rz_angle(hi, ho));
+            if (!c.link_thread) w.nout[q] = 0;
+            w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, rz_angle(hi, ho));
+          }
+          wpos += wgrp;
         }
         const uint32_t ng = (uint32_t)__popcll(bal & gmask);
         pos += ng;
@@ -497,6 +448,7 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
       }
     }
     if (!FILL && active && sub == 0) w.dcnt[g] = cnt;
+    if (FILL && active && sub == 0) w.wcnt[g] = wpos;
   }
 }
 
@@ -510,8 +462,8 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
 // already in registers.  The accepted candidates form a bit mask over the
 // range, one 64-bit word per 64.
 
-__device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c, uint32_t nd) {
-  const uint32_t nwords = w.moff[nd];
+__device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c) {
+  const uint32_t nwords = w.ctr[C_NWORDS];
   if (nwords <= c.cap_words) return true;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     set_status(w.ctr, PXT_ERR_CAPACITY);
@@ -525,25 +477,28 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
-  if (!links_capacity(w, c, nd)) return;
+  if (!links_capacity(w, c)) return;
   uint32_t links = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
   uint32_t d = xcd_block() * blockDim.x + threadIdx.x;
   // software pipeline: the set-up loads of the next doublet are issued
   // before the candidates of the current one are scanned
-  uint32_t na = 0, nkb = 0, ndeg = 0, nmo = 0;
+  uint32_t na = 0, nkb = 0, ndeg = 0, nlw = 0;
   float4 nob = make_float4(0.f, 0.f, 0.f, 0.f);
   if (d < nd) {
-    na = w.cin[d]; nob = w.oh[d]; nkb = w.cb[d]; ndeg = w.cdeg[d]; nmo = w.moff[d];
+    na = w.cin[d]; nob = w.oh[d]; nkb = w.cb[d]; ndeg = w.cdeg[d]; nlw = w.lw[d];
   }
   while (d < nd) {
-    const uint32_t k0 = nkb, deg = ndeg, mo = nmo;
+    const uint32_t k0 = nkb, deg = ndeg;
     const float4 ob = nob;
     const HitD ha = load_hit(w, na);
     const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
+    // first mask word: the inner hit's base plus the offset within it
+    const uint32_t mo = w.wbase[na] + nlw;
+    w.moff[d] = mo;
     const uint32_t dn = d + stride;
     if (dn < nd) {
-      na = w.cin[dn]; nob = w.oh[dn]; nkb = w.cb[dn]; ndeg = w.cdeg[dn]; nmo = w.moff[dn];
+      na = w.cin[dn]; nob = w.oh[dn]; nkb = w.cb[dn]; ndeg = w.cdeg[dn]; nlw = w.lw[dn];
     }
     uint32_t nout = 0;
     for (uint32_t wd = 0; wd * 64u < deg; ++wd) {
@@ -605,7 +560,8 @@ __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint2*
     const float4 oc = w.oh[d2];
     const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
-      atomicOr((unsigned long long*)&w.masks[w.moff[d] + (k >> 6)], 1ull << (k & 63u));
+      const uint32_t mo = w.wbase[w.cin[d]] + w.lw[d];
+      atomicOr((unsigned long long*)&w.masks[mo + (k >> 6)], 1ull << (k & 63u));
       atomicAdd(&w.nout[d], 1u);
       w.has_inner[d2] = 1;
       ++links;
@@ -620,7 +576,7 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
-  if (!links_capacity(w, c, nd)) return;
+  if (!links_capacity(w, c)) return;
   const uint32_t lane = lane_id(), sub = lane % G;
   uint2* q = queue[threadIdx.x / kWave];
   const uint64_t below = (1ull << lane) - 1ull;
@@ -636,6 +592,7 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
       ta = w.oh[d].w;
       kb = w.cb[d];
       deg = w.cdeg[d];
+      if (sub == 0) w.moff[d] = w.wbase[w.cin[d]] + w.lw[d];
     }
     const uint32_t maxw = wave_max((deg + 63u) / 64u);
     for (uint32_t wd = 0; wd < maxw; ++wd) {
@@ -675,7 +632,7 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
 // Clears the link-mask words ahead of the queued link kernel.
 __global__ __launch_bounds__(256) void k_zero_words(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
-  const uint32_t n = w.moff[w.ctr[C_ND]];
+  const uint32_t n = w.ctr[C_NWORDS];
   if (n > c.cap_words) return;  // reported by the link kernel
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     w.masks[i] = 0;

@@ -119,7 +119,10 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.cell_off = cv.take<uint32_t>(H + 1);
   w.cin = cv.take<uint32_t>(D);
   w.cout = cv.take<uint32_t>(D);
-  w.moff = cv.take<uint32_t>(D + 1);
+  w.moff = cv.take<uint32_t>(D);
+  w.lw = cv.take<uint32_t>(D);
+  w.wcnt = cv.take<uint32_t>(H + 1);
+  w.wbase = cv.take<uint32_t>(H + 1);
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
@@ -139,7 +142,6 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.toff = cv.take<uint32_t>(T + 1);
   w.surv = cv.take<uint32_t>(T);
   w.fp64_list = cv.take<uint32_t>(T);
-  w.block_sums = cv.take<uint32_t>(kScanBlocks + 1);
   w.scan_status = cv.take<uint64_t>(scan_tiles(c));
   w.epoch = cv.take<uint32_t>(1);
 }
@@ -232,23 +234,12 @@ uint32_t scan_grid(uint64_t max_n) {
 // Single-pass exclusive scan of n = *n_dev entries; `max_n` bounds *n_dev
 // (grid size); scan_id is the scan's index within one call (distinct per
 // call site, below 8).
-template <int TR = 0>
 void launch_scan1(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t* n_dev,
                   uint32_t* total_dst, uint64_t max_n, uint32_t scan_id, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan1<TR>, dim3(scan_grid(max_n)), dim3(kScanThreads1), 0, s, in, out, n_dev,
+  hipLaunchKernelGGL(k_scan1, dim3(scan_grid(max_n)), dim3(kScanThreads1), 0, s, in, out, n_dev,
                      total_dst, w, scan_id);
 }
 
-template <int TR = 0>
-void launch_scan(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t* n_dev,
-                 uint32_t* total_dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_reduce<TR>, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, n_dev,
-                     w.block_sums, w.ctr);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, w.block_sums, (uint32_t)kScanBlocks,
-                     w.ctr);
-  hipLaunchKernelGGL(k_scan_down<TR>, dim3(kScanBlocks), dim3(kScanThreads), 0, s, in, out, n_dev,
-                     w.block_sums, (uint32_t)kScanBlocks, total_dst, w.ctr);
-}
 
 const char* const kStageNames[PXT_N_STAGES] = {
     "clear",       "prep",       "bin_scan",    "fill",       "doublet_count",
@@ -347,7 +338,7 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     if (timed) sm.mark(6);
     launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
     if (timed) sm.mark(7);
-    launch_scan1<1>(w, w.cdeg, w.moff, w.ctr + C_ND, w.ctr + C_NWORDS, cfg.max_doublets, 2, s);
+    launch_scan1(w, w.wcnt, w.wbase, w.ctr + C_NBINNED, w.ctr + C_NWORDS, H, 2, s);
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
     if (cfg.link_kernel) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
     if (timed) sm.mark(8);
@@ -596,12 +587,12 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
         rows.push_back(bidx[cout[k]]);
       }
     } else {
-      std::vector<uint32_t> cell_off(nb + 1), mw(nd), moff(nd + 1);
+      std::vector<uint32_t> cell_off(nb + 1), mw(nd), moff(nd);
       HIP_OR_FAIL(c, hipMemcpy(cell_off.data(), w.cell_off, 4ull * (nb + 1), hipMemcpyDeviceToHost));
       if (nd) HIP_OR_FAIL(c, hipMemcpy(mw.data(), w.cdeg, 4ull * nd, hipMemcpyDeviceToHost));
       for (auto& v : mw) v = (v + 63u) >> 6;
-      HIP_OR_FAIL(c, hipMemcpy(moff.data(), w.moff, 4ull * (nd + 1), hipMemcpyDeviceToHost));
-      const uint32_t nwords = moff[nd];
+      if (nd) HIP_OR_FAIL(c, hipMemcpy(moff.data(), w.moff, 4ull * nd, hipMemcpyDeviceToHost));
+      const uint32_t nwords = ctr[C_NWORDS];
       std::vector<uint64_t> masks(nwords);
       if (nwords)
         HIP_OR_FAIL(c, hipMemcpy(masks.data(), w.masks, 8ull * nwords, hipMemcpyDeviceToHost));
