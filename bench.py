@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=0, help="events per batch (default per workload)")
     ap.add_argument("--pool", type=int, default=2, help="distinct batches cycled through")
     ap.add_argument("--plain-events", type=int, default=64)
-    ap.add_argument("--cpu-sample", type=int, default=48, help="events for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=160, help="events for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
     ap.add_argument("--group-lanes", type=int, default=16)
