@@ -45,9 +45,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=160, help="events for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
-    ap.add_argument("--group-lanes", type=int, default=16)
+    ap.add_argument("--group-lanes", type=int, default=8)
     ap.add_argument("--link-kernel", type=int, default=0,
-                    help="0 thread per doublet, 1 lane group + queue")
+                    help="0 thread per doublet, 1 lane group + queue, 2 wavefront + queue")
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (Hz)")
     ap.add_argument("--serve-events", type=int, default=10000)
@@ -99,8 +99,8 @@ def algorithmic_bytes(stage, n):
 
 # kernel that implements each single-kernel stage (for the counter lookup)
 STAGE_KERNEL = {"prep": "pxt::k_prep", "fill": "pxt::k_fill",
-                "doublet_count": "pxt::k_doublets<16, false>",
-                "doublet_fill": "pxt::k_doublets<16, true>", "links": "pxt::k_links_thread",
+                "doublet_count": "pxt::k_doublets<8, false>",
+                "doublet_fill": "pxt::k_doublets<8, true>", "links": "pxt::k_links_thread",
                 "score": "pxt::k_score", "best": "pxt::k_best", "fit32": "pxt::k_fit32"}
 
 
@@ -142,9 +142,11 @@ def roofline(stages, counts, n_hits, peak_gbs, workload, args):
     kname = STAGE_KERNEL.get(dom)
     if dom == "links" and args.link_kernel == 1:
         kname = "pxt::k_links<%d>" % args.group_lanes
+    if dom == "links" and args.link_kernel == 2:
+        kname = "pxt::k_links_wave"
     if dom in ("doublet_count", "doublet_fill"):
-        kname = kname.replace("<16,", "<%d," % args.group_lanes)
-    if (workload == "pu50" and kname and args.link_kernel == 0 and args.group_lanes == 16
+        kname = kname.replace("<8,", "<%d," % args.group_lanes)
+    if (workload == "pu50" and kname and args.link_kernel == 0 and args.group_lanes == 8
             and args.batch in (0, 64)):
         traffic = measured_traffic(kname)
     return {"kernel": kname or dom, "bound": "hbm", "achieved": round(gbs, 2), "peak": peak_gbs,

@@ -24,7 +24,7 @@ import numpy as np
 DEFAULT_SPACE = {
     "phi_bins": (64, 128, 256, 512),
     "group_lanes": (16, 32),
-    "link_kernel": (0, 1),
+    "link_kernel": (0, 2),
     "block_size": (128, 256),
 }
 

@@ -56,7 +56,7 @@ struct DevCfg {
   double kmax2, arz2;                       // squares, for the fast forms
   double c_kappa, sigma_u, sigma_z, sigma_r, x_over_x0, pt_max, pt_fp64;
   uint32_t cap_doublets, cap_words, cap_tuples;
-  int link_thread;                          // one thread per doublet in links
+  int link_kernel;                          // 0 thread, 1 lane group, 2 wave
   float th_win, th_far;                     // r-z angle prefilter of the links
 };
 

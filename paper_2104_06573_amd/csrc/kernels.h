@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
             w.cdeg[q] = deg;
             w.lw[q] = wpos + wex;
           w.has_inner[q] = 0;
-            if (!c.link_thread) w.nout[q] = 0;
+            if (c.link_kernel == 1) w.nout[q] = 0;
             w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, rz_angle(hi, ho));
           }
           wpos += wgrp;
@@ -625,6 +625,136 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
   }
   __threadfence_block();
   links_flush(w, c, q, qn, links);
+  links = wave_sum(links);
+  if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
+}
+
+// Wave-cooperative link kernel.  A wavefront takes 64 consecutive doublets
+// and flattens their candidate ranges (an exclusive prefix sum of the
+// candidate counts over the lanes): in each round every lane takes the next
+// candidate of the flattened list, finds the doublet it belongs to by a
+// binary search over the prefix (lane shuffles) and applies the angle
+// prefilter, so no lane idles on a doublet with few candidates.  Survivors
+// go to a per-wavefront queue in LDS and are tested exactly 64 at a time.
+// The doublets' mask words are staged in LDS (bits set with LDS atomics)
+// and written out once, coalesced; a wavefront whose words exceed the
+// staging area sets them in device memory instead.
+
+constexpr int kWaveWords = 256;  // LDS mask words per wavefront
+
+struct WaveLinks {
+  uint64_t* sm;   // staged mask words of the wavefront
+  uint32_t* cnt;  // accepted links per lane's doublet
+  uint2* q;       // queue: (owner lane, candidate index)
+};
+
+__device__ __forceinline__ void wave_links_flush(Ws& w, const DevCfg& c, const WaveLinks& L,
+                                                 uint32_t n, bool staged, uint32_t a,
+                                                 float4 ob, uint32_t kb, uint32_t wex,
+                                                 uint32_t mo, uint32_t& links) {
+  const uint32_t lane = lane_id();
+  const uint2 it = lane < n ? L.q[lane] : make_uint2(0, 0);
+  const int own = (int)it.x;
+  const uint32_t kk = it.y;
+  // the owner's set-up, fetched from its lane (all lanes take part)
+  const uint32_t ao = __shfl(a, own), kbo = __shfl(kb, own);
+  const uint32_t wo = __shfl(wex, own), moo = __shfl(mo, own);
+  const float bx = __shfl(ob.x, own), by = __shfl(ob.y, own), bz = __shfl(ob.z, own);
+  if (lane < n) {
+    const HitD ha = load_hit(w, ao);
+    const HitD hb = hit_xyz(bx, by, bz);
+    const uint32_t d2 = kbo + kk;
+    const float4 oc = w.oh[d2];
+    const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
+    if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
+      const unsigned long long bit = 1ull << (kk & 63u);
+      if (staged)
+        atomicOr((unsigned long long*)&L.sm[wo + (kk >> 6)], bit);
+      else
+        atomicOr((unsigned long long*)&w.masks[moo + (kk >> 6)], bit);
+      atomicAdd(&L.cnt[own], 1u);
+      w.has_inner[d2] = 1;
+      ++links;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
+  __shared__ uint64_t s_mask[256 / kWave][kWaveWords];
+  __shared__ uint2 s_q[256 / kWave][kQueue];
+  __shared__ uint32_t s_cnt[256 / kWave][kWave];
+  uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t nd = ctr[C_ND];
+  if (!links_capacity(w, c)) return;
+  const uint32_t lane = lane_id(), wib = threadIdx.x / kWave;
+  const WaveLinks L{s_mask[wib], s_cnt[wib], s_q[wib]};
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t wpb = blockDim.x / kWave;
+  const uint32_t nwaves = gridDim.x * wpb;
+  uint32_t links = 0;
+  for (uint32_t base = (xcd_block() * wpb + wib) * kWave; base < nd; base += nwaves * kWave) {
+    const uint32_t d = base + lane;
+    uint32_t a = 0, kb = 0, deg = 0, mo = 0;
+    float4 ob = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (d < nd) {
+      a = w.cin[d];
+      kb = w.cb[d];
+      deg = w.cdeg[d];
+      ob = w.oh[d];
+      mo = w.wbase[a] + w.lw[d];
+      w.moff[d] = mo;
+    }
+    const uint32_t nwd = (deg + 63u) >> 6;
+    const uint32_t cinc = wave_incl_scan(deg), cex = cinc - deg;
+    const uint32_t C = __shfl(cinc, kWave - 1);
+    const uint32_t winc = wave_incl_scan(nwd), wex = winc - nwd;
+    const uint32_t NW = __shfl(winc, kWave - 1);
+    const bool staged = NW <= (uint32_t)kWaveWords;
+    if (staged) {
+      for (uint32_t i = lane; i < NW; i += kWave) L.sm[i] = 0;
+    } else {
+      for (uint32_t j = 0; j < nwd; ++j) w.masks[mo + j] = 0;
+    }
+    L.cnt[lane] = 0;
+    __threadfence_block();
+    uint32_t qn = 0;
+    for (uint32_t r = 0; r * kWave < C; ++r) {
+      const uint32_t k = r * kWave + lane;
+      // owner: the last lane whose range starts at or before k
+      uint32_t own = 0;
+#pragma unroll
+      for (uint32_t step = kWave / 2; step >= 1; step >>= 1)
+        if (__shfl(cex, (int)(own + step)) <= k) own += step;
+      const uint32_t kk = k - __shfl(cex, (int)own);
+      const uint32_t kbo = __shfl(kb, (int)own);
+      const float tao = __shfl(ob.w, (int)own);
+      const bool pass = k < C && rz_prefilter(c, tao, w.oh[kbo + kk].w);
+      const uint64_t bal = __ballot(pass);
+      if (pass) L.q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(own, kk);
+      qn += (uint32_t)__popcll(bal);
+      if (qn >= (uint32_t)kWave) {
+        __threadfence_block();
+        wave_links_flush(w, c, L, kWave, staged, a, ob, kb, wex, mo, links);
+        __threadfence_block();
+        const uint32_t rest = qn - kWave;
+        const uint2 mv = lane < rest ? L.q[kWave + lane] : make_uint2(0, 0);
+        __threadfence_block();
+        if (lane < rest) L.q[lane] = mv;
+        __threadfence_block();
+        qn = rest;
+      }
+    }
+    __threadfence_block();
+    if (qn) wave_links_flush(w, c, L, qn, staged, a, ob, kb, wex, mo, links);
+    __threadfence_block();
+    if (d < nd) {
+      if (staged)
+        for (uint32_t j = 0; j < nwd; ++j) w.masks[mo + j] = L.sm[wex + j];
+      w.nout[d] = L.cnt[lane];
+    }
+    __threadfence_block();
+  }
   links = wave_sum(links);
   if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
 }

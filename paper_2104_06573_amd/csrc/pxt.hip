@@ -176,9 +176,10 @@ int validate_config(const pxt_config* c, std::string& why) {
   if (c->block_size < 64 || c->block_size > 256 || c->block_size % 64)
     return why = "block_size must be 64, 128, 192 or 256", 1;
   if (!(c->pt_fp64 > 0)) return why = "pt_fp64 must be > 0", 1;
-  if (c->group_lanes != 16 && c->group_lanes != 32 && c->group_lanes != 64)
-    return why = "group_lanes must be 16, 32 or 64", 1;
-  if (c->link_kernel != 0 && c->link_kernel != 1) return why = "link_kernel must be 0 or 1", 1;
+  if (c->group_lanes != 8 && c->group_lanes != 16 && c->group_lanes != 32 &&
+      c->group_lanes != 64)
+    return why = "group_lanes must be 8, 16, 32 or 64", 1;
+  if (c->link_kernel < 0 || c->link_kernel > 2) return why = "link_kernel must be 0, 1 or 2", 1;
   if (c->use_graph != 0 && c->use_graph != 1) return why = "use_graph must be 0 or 1", 1;
   return 0;
 }
@@ -210,7 +211,7 @@ void make_devcfg(const pxt_config& c, DevCfg& d) {
   d.cap_doublets = c.max_doublets;
   d.cap_words = c.max_link_words;
   d.cap_tuples = c.max_tuples;
-  d.link_thread = c.link_kernel == 0;
+  d.link_kernel = c.link_kernel;
   // L1 holds only if the r-z directions of the two doublets differ by at
   // most asin(arz) or by at least pi - asin(arz).  The FP32 angles carry an
   // error below 1e-6 rad (inputs rounded to FP32: < 1.2e-7; atan2f: a few
@@ -276,6 +277,7 @@ uint32_t grid_chunked(uint64_t items, int bs, int G, uint32_t cap_blocks) {
 template <bool FILL>
 void launch_doublets(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, const DevCfg& d) {
   switch (G) {
+    case 8: hipLaunchKernelGGL((k_doublets<8, FILL>), grid, block, 0, s, w, d); break;
     case 16: hipLaunchKernelGGL((k_doublets<16, FILL>), grid, block, 0, s, w, d); break;
     case 64: hipLaunchKernelGGL((k_doublets<64, FILL>), grid, block, 0, s, w, d); break;
     default: hipLaunchKernelGGL((k_doublets<32, FILL>), grid, block, 0, s, w, d); break;
@@ -283,11 +285,16 @@ void launch_doublets(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, c
 }
 
 void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, const DevCfg& d) {
-  if (d.link_thread) {
+  if (d.link_kernel == 0) {
     hipLaunchKernelGGL(k_links_thread, grid, block, 0, s, w, d);
     return;
   }
+  if (d.link_kernel == 2) {
+    hipLaunchKernelGGL(k_links_wave, grid, block, 0, s, w, d);
+    return;
+  }
   switch (G) {
+    case 8: hipLaunchKernelGGL((k_links<8>), grid, block, 0, s, w, d); break;
     case 16: hipLaunchKernelGGL((k_links<16>), grid, block, 0, s, w, d); break;
     case 64: hipLaunchKernelGGL((k_links<64>), grid, block, 0, s, w, d); break;
     default: hipLaunchKernelGGL((k_links<32>), grid, block, 0, s, w, d); break;
@@ -340,10 +347,10 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     if (timed) sm.mark(7);
     launch_scan1(w, w.wcnt, w.wbase, w.ctr + C_NBINNED, w.ctr + C_NWORDS, H, 2, s);
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
-    if (cfg.link_kernel) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
+    if (cfg.link_kernel == 1) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
     if (timed) sm.mark(8);
-    launch_links(G, dim3(cfg.link_kernel ? grid_chunked((uint64_t)H * 16, bs, G, persist)
-                                          : std::max<uint32_t>(8, gd / 8 * 8)),
+    launch_links(G, dim3(cfg.link_kernel == 1 ? grid_chunked((uint64_t)H * 16, bs, G, persist)
+                                               : std::max<uint32_t>(8, gd / 8 * 8)),
                  dim3(bs), s, w, d);
     if (timed) sm.mark(9);
     hipLaunchKernelGGL(k_roots, dim3(scan_grid(cfg.max_doublets)), dim3(kScanThreads1), 0, s, w,

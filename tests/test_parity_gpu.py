@@ -147,7 +147,10 @@ def test_batch_equivalence(torch):
 
 @pytest.mark.parametrize("phi_bins,block,group,lk", [(16, 256, 16, 0), (64, 64, 64, 1),
                                                      (1024, 128, 32, 1), (4096, 256, 16, 1),
-                                                     (256, 192, 64, 0), (256, 64, 16, 0)])
+                                                     (256, 192, 64, 0), (256, 64, 16, 0),
+                                                     (256, 256, 16, 2), (128, 64, 32, 2),
+                                                     (512, 192, 16, 2), (256, 256, 8, 0),
+                                                     (64, 128, 8, 1)])
 def test_tuning_invariance(torch, phi_bins, block, group, lk):
     events = [eventgen.generate("pu50", 55), eventgen.generate("tiny", 3)]
     ref = _tracks_by_event(make_rec().run_numpy(events).numpy(), 2)
