@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--link-kernel", type=int, default=0,
                     help="0 thread per doublet, 1 lane group + queue, 2 wavefront + queue")
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
+    ap.add_argument("--inflight", type=int, default=4,
+                    help="batches in flight: contexts, each on its own stream, taking turns")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (Hz)")
     ap.add_argument("--serve-events", type=int, default=10000)
     ap.add_argument("--serve-pool", type=int, default=96, help="distinct events cycled through")
@@ -222,23 +224,32 @@ def main():
     max_hits = max(sum(e.n_hits for e in b) for b in pool)
     per_ev_d = 100_000 if kind == "pu50" else 1_700_000
     per_ev_t = 8_000 if kind == "pu50" else 200_000
-    rec = pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
-                            max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
-                            max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
-                            phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                            link_kernel=args.link_kernel, use_graph=args.graph)
+    K = max(1, args.inflight)
+    recs = [pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
+                              max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
+                              max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
+                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                              link_kernel=args.link_kernel, use_graph=args.graph)
+            for _ in range(K)]
+    rec = recs[0]
+    streams = [torch.cuda.Stream() for _ in range(K)]
     dev_batches = [rec.upload(b) for b in pool]
     torch.cuda.synchronize()
 
     def step(i):
         x, y, z, l, offs = dev_batches[i % len(dev_batches)]
-        rec.launch(x, y, z, l, offs)
+        recs[i % K].launch(x, y, z, l, offs, stream=streams[i % K])
 
     # correctness guard on the first batch (status only; parity is tested)
     step(0)
     torch.cuda.synchronize()
     c0 = rec.read_counts()
     assert c0["status"] == 0, c0
+    for r in recs[1:]:
+        x, y, z, l, offs = dev_batches[0]
+        r.launch(x, y, z, l, offs)
+        torch.cuda.synchronize()
+        assert r.read_counts() == c0
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -298,6 +309,7 @@ def main():
             "hits_per_event": round(hits_per_event, 1),
             "phi_bins": args.phi_bins,
             "group_lanes": args.group_lanes,
+            "batches_in_flight": args.inflight,
             "link_kernel": args.link_kernel,
             "hip_graph": bool(args.graph),
             "path": "batched (one launch sequence per batch)",
