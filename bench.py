@@ -180,7 +180,7 @@ def serving_leg(det, args):
     events = [pool[i % len(pool)] for i in range(args.serve_events)]
     srv = Server(det, n_lanes=args.serve_lanes, max_batch_events=64, doublets_per_hit=40,
                  max_events=64, max_hits=1_400_000, max_doublets=36 << 20,
-                 max_link_words=36 << 20, max_tuples=6 << 20, phi_bins=args.phi_bins,
+                 max_link_words=160 << 20, max_tuples=6 << 20, phi_bins=args.phi_bins,
                  group_lanes=args.group_lanes, link_kernel=args.link_kernel, use_graph=1)
     poisson_run(srv, events[:300], rate_hz=args.serve_rate)          # warm-up
     rep = poisson_run(srv, events, rate_hz=args.serve_rate)
@@ -223,10 +223,11 @@ def main():
     hits_per_event = float(np.mean([e.n_hits for b in pool for e in b]))
     max_hits = max(sum(e.n_hits for e in b) for b in pool)
     per_ev_d = 100_000 if kind == "pu50" else 1_700_000
+    per_ev_w = per_ev_d * (4 if kind == "pu50" else 8)  # link-mask words
     per_ev_t = 8_000 if kind == "pu50" else 200_000
     K = max(1, args.inflight)
     recs = [pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
-                              max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
+                              max_doublets=per_ev_d * B, max_link_words=per_ev_w * B,
                               max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
                               phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                               link_kernel=args.link_kernel, use_graph=args.graph)
@@ -264,7 +265,7 @@ def main():
     # stage breakdown with HIP events on the library's stream (direct mode:
     # events cannot sit inside the replayed graph)
     trec = pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
-                             max_doublets=per_ev_d * B, max_link_words=per_ev_d * B,
+                             max_doublets=per_ev_d * B, max_link_words=per_ev_w * B,
                              max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                              link_kernel=args.link_kernel, use_graph=0)
@@ -274,7 +275,7 @@ def main():
     # plain path: one event per call, synchronised per event
     plain_events = [e for b in pool for e in b][: args.plain_events]
     prec = pxt.Reconstructor(det, max_events=1, max_hits=max(e.n_hits for e in plain_events) + 16,
-                             max_doublets=per_ev_d * 2, max_link_words=per_ev_d * 2,
+                             max_doublets=per_ev_d * 2, max_link_words=per_ev_w * 2,
                              max_tuples=per_ev_t * 2, max_tracks=per_ev_t * 2,
                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                             link_kernel=args.link_kernel, use_graph=args.graph)

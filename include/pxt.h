@@ -89,7 +89,9 @@ typedef struct pxt_config {
   uint32_t max_events;
   uint32_t max_hits;
   uint32_t max_doublets;
-  uint32_t max_link_words;  /* 64-bit link-mask words, about one per doublet */
+  uint32_t max_link_words;  /* 64-bit link-mask words: doublets times
+                               ceil(largest hit out-degree / 64), usually
+                               1-2 per doublet at PU~50, up to ~8 at PU~200 */
   uint32_t max_tuples;      /* raw n-tuplets before cleaning               */
   /* --- tuning ------------------------------------------------------------ */
   int32_t phi_bins;         /* phi bins per layer, 16..4096                */

@@ -159,7 +159,8 @@ def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
     c.max_events = max_events
     c.max_hits = max_hits
     c.max_doublets = max_doublets
-    c.max_link_words = max_link_words if max_link_words is not None else max_doublets
+    c.max_link_words = (max_link_words if max_link_words is not None
+                        else min(4 * max_doublets, 0xfffffff0))
     c.max_tuples = max_tuples
     c.phi_bins = phi_bins
     c.block_size = block_size

@@ -78,7 +78,7 @@ def tune(det, events, caps=None, space=None, repeats=5, use_graph=1, device=0,
     caps.setdefault("max_events", n)
     caps.setdefault("max_hits", hits + 1024)
     caps.setdefault("max_doublets", max(1 << 16, 60 * hits))
-    caps.setdefault("max_link_words", caps["max_doublets"])
+    caps.setdefault("max_link_words", min(8 * caps["max_doublets"], 0xfffffff0))
     caps.setdefault("max_tuples", max(1 << 14, 8 * hits))
     caps.setdefault("max_tracks", caps["max_tuples"])
     keys = sorted(space)

@@ -29,6 +29,7 @@ enum Ctr : int {
   C_NBINNED,         // hits with a valid layer id
   C_ND,              // doublets
   C_NWORDS,          // link-mask words
+  C_WSTRIDE,         // link-mask words per doublet
   C_NLINKS,          // links
   C_NTUP,            // raw n-tuplets
   C_NSURV,           // n-tuplets surviving the cleaning
@@ -86,11 +87,7 @@ struct Ws {
   uint32_t* cell_off;     // [H + 1] first doublet of each inner hit
   uint32_t* cin;          // [D] inner binned hit
   uint32_t* cout;         // [D] outer binned hit
-  uint32_t* moff;         // [D] first link-mask word of each doublet
-  uint32_t* lw;           // [D] the same within its inner hit's doublets
-  uint32_t* wcnt;         // [H + 1] link-mask words of each inner hit
-  uint32_t* wbase;        // [H + 1] their exclusive prefix
-  uint64_t* masks;        // [W]
+  uint64_t* masks;        // [W] link masks, C_WSTRIDE words per doublet
   uint8_t* has_inner;     // [D]
   uint32_t* nout;         // [D] outer links per doublet
   float4* oh;             // [D] outer hit (x, y, z) and r-z angle of each doublet

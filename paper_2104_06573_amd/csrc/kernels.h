@@ -328,6 +328,7 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
   const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
   const uint32_t chunk = (nb + gridDim.x - 1) / gridDim.x;
   const uint32_t beg = min(nb, xcd_block() * chunk), end = min(nb, beg + chunk);
+  uint32_t wneed = 0;  // count pass: link-mask words of the largest out-degree
   for (uint32_t base = beg; base < end; base += gpb) {
     const uint32_t g = base + gib;
     const bool active = g < end;
@@ -347,7 +348,6 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
     const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
     uint32_t cnt = 0;
     uint32_t pos = (FILL && active) ? w.cell_off[g] : 0u;
-    uint32_t wpos = 0;  // fill pass: link-mask words of g's doublets so far
     for (uint32_t p = 0; __any((int)p < npairs); ++p) {
       uint32_t s0b = 0, s0n = 0, s1b = 0, s1n = 0;
       if (active && (int)p < npairs) {
@@ -406,49 +406,40 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
         }
         const uint64_t bal = __ballot(ok);
         if (FILL) {
-          // link-mask words of this doublet: one per 64 candidates, the
-          // doublets leaving its outer hit
-          uint32_t jb = 0, deg = 0;
-          if (ok) {
-            jb = w.cell_off[j];
-            deg = w.cell_off[j + 1] - jb;
-          }
-          const uint32_t nw = (deg + 63u) >> 6;
-          uint32_t wex, wgrp;  // words of the group's earlier lanes, of all
-          if (__all(nw <= 1u)) {
-            const uint64_t bw = __ballot(nw != 0u);
-            wex = (uint32_t)__popcll(bw & below);
-            wgrp = (uint32_t)__popcll(bw & gmask);
-          } else {
-            uint32_t inc = nw;
-#pragma unroll
-            for (int dd = 1; dd < G; dd <<= 1) {
-              const uint32_t t = __shfl_up(inc, dd, G);
-              if ((int)sub >= dd) inc += t;
-            }
-            wex = inc - nw;
-            wgrp = __shfl(inc, G - 1, G);
-          }
           if (ok) {
             const uint32_t q = pos + (uint32_t)__popcll(bal & below);
             w.cin[q] = g;
             w.cout[q] = j;
+            const uint32_t jb = w.cell_off[j];
             w.cb[q] = jb;
-            w.cdeg[q] = deg;
-            w.lw[q] = wpos + wex;
+            w.cdeg[q] = w.cell_off[j + 1] - jb;
           w.has_inner[q] = 0;
             if (c.link_kernel == 1) w.nout[q] = 0;
             w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, rz_angle(hi, ho));
           }
-          wpos += wgrp;
         }
         const uint32_t ng = (uint32_t)__popcll(bal & gmask);
         pos += ng;
         cnt += ng;
       }
     }
-    if (!FILL && active && sub == 0) w.dcnt[g] = cnt;
-    if (FILL && active && sub == 0) w.wcnt[g] = wpos;
+    if (!FILL) {
+      if (active && sub == 0) w.dcnt[g] = cnt;
+      wneed = max(wneed, (cnt + 63u) >> 6);
+    }
+  }
+  if (!FILL) {
+    // link-mask stride: words for the largest out-degree of the batch, one
+    // atomic per block
+    __shared__ uint32_t s_w[256 / kWave];
+    const uint32_t wm = wave_max(wneed);
+    if (lane == 0) s_w[threadIdx.x / kWave] = wm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t m = 0;
+      for (uint32_t i = 0; i < blockDim.x / kWave; ++i) m = max(m, s_w[i]);
+      if (m) atomicMax(&w.ctr[C_WSTRIDE], m);
+    }
   }
 }
 
@@ -462,14 +453,22 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
 // already in registers.  The accepted candidates form a bit mask over the
 // range, one 64-bit word per 64.
 
+// The link masks take C_WSTRIDE words per doublet (one word per 64
+// candidates of the largest out-degree of the batch), stored word-major:
+// word k of doublet d is masks[k * nd + d], so the words that consecutive
+// doublets write are contiguous; only the words a doublet needs are
+// touched.
 __device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c) {
-  const uint32_t nwords = w.ctr[C_NWORDS];
-  if (nwords <= c.cap_words) return true;
+  const uint64_t nwords = (uint64_t)w.ctr[C_ND] * w.ctr[C_WSTRIDE];
+  const bool ok = nwords <= c.cap_words;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    set_status(w.ctr, PXT_ERR_CAPACITY);
-    w.ctr[C_REQ_W] = nwords;
+    w.ctr[C_NWORDS] = (uint32_t)min(nwords, 0xffffffffull);
+    if (!ok) {
+      set_status(w.ctr, PXT_ERR_CAPACITY);
+      w.ctr[C_REQ_W] = (uint32_t)min(nwords, 0xffffffffull);
+    }
   }
-  return false;
+  return ok;
 }
 
 // One thread per doublet (a,b), looping over its candidates.
@@ -483,22 +482,19 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   uint32_t d = xcd_block() * blockDim.x + threadIdx.x;
   // software pipeline: the set-up loads of the next doublet are issued
   // before the candidates of the current one are scanned
-  uint32_t na = 0, nkb = 0, ndeg = 0, nlw = 0;
+  uint32_t na = 0, nkb = 0, ndeg = 0;
   float4 nob = make_float4(0.f, 0.f, 0.f, 0.f);
   if (d < nd) {
-    na = w.cin[d]; nob = w.oh[d]; nkb = w.cb[d]; ndeg = w.cdeg[d]; nlw = w.lw[d];
+    na = w.cin[d]; nob = w.oh[d]; nkb = w.cb[d]; ndeg = w.cdeg[d];
   }
   while (d < nd) {
     const uint32_t k0 = nkb, deg = ndeg;
     const float4 ob = nob;
     const HitD ha = load_hit(w, na);
     const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
-    // first mask word: the inner hit's base plus the offset within it
-    const uint32_t mo = w.wbase[na] + nlw;
-    w.moff[d] = mo;
     const uint32_t dn = d + stride;
     if (dn < nd) {
-      na = w.cin[dn]; nob = w.oh[dn]; nkb = w.cb[dn]; ndeg = w.cdeg[dn]; nlw = w.lw[dn];
+      na = w.cin[dn]; nob = w.oh[dn]; nkb = w.cb[dn]; ndeg = w.cdeg[dn];
     }
     uint32_t nout = 0;
     for (uint32_t wd = 0; wd * 64u < deg; ++wd) {
@@ -525,7 +521,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
           w.has_inner[kw + k] = 1;
         }
       }
-      w.masks[mo + wd] = mask;
+      w.masks[(size_t)wd * nd + d] = mask;
       nout += (uint32_t)__popcll(mask);
     }
     w.nout[d] = nout;
@@ -560,8 +556,8 @@ __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint2*
     const float4 oc = w.oh[d2];
     const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
-      const uint32_t mo = w.wbase[w.cin[d]] + w.lw[d];
-      atomicOr((unsigned long long*)&w.masks[mo + (k >> 6)], 1ull << (k & 63u));
+      atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * w.ctr[C_ND] + d],
+               1ull << (k & 63u));
       atomicAdd(&w.nout[d], 1u);
       w.has_inner[d2] = 1;
       ++links;
@@ -592,7 +588,6 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
       ta = w.oh[d].w;
       kb = w.cb[d];
       deg = w.cdeg[d];
-      if (sub == 0) w.moff[d] = w.wbase[w.cin[d]] + w.lw[d];
     }
     const uint32_t maxw = wave_max((deg + 63u) / 64u);
     for (uint32_t wd = 0; wd < maxw; ++wd) {
@@ -671,7 +666,7 @@ __device__ __forceinline__ void wave_links_flush(Ws& w, const DevCfg& c, const W
       if (staged)
         atomicOr((unsigned long long*)&L.sm[wo + (kk >> 6)], bit);
       else
-        atomicOr((unsigned long long*)&w.masks[moo + (kk >> 6)], bit);
+        atomicOr((unsigned long long*)&w.masks[(size_t)(kk >> 6) * w.ctr[C_ND] + moo], bit);
       atomicAdd(&L.cnt[own], 1u);
       w.has_inner[d2] = 1;
       ++links;
@@ -702,8 +697,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
       kb = w.cb[d];
       deg = w.cdeg[d];
       ob = w.oh[d];
-      mo = w.wbase[a] + w.lw[d];
-      w.moff[d] = mo;
+      mo = d;
     }
     const uint32_t nwd = (deg + 63u) >> 6;
     const uint32_t cinc = wave_incl_scan(deg), cex = cinc - deg;
@@ -714,7 +708,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
     if (staged) {
       for (uint32_t i = lane; i < NW; i += kWave) L.sm[i] = 0;
     } else {
-      for (uint32_t j = 0; j < nwd; ++j) w.masks[mo + j] = 0;
+      for (uint32_t j = 0; j < nwd; ++j) w.masks[(size_t)j * nd + mo] = 0;
     }
     L.cnt[lane] = 0;
     __threadfence_block();
@@ -750,7 +744,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
     __threadfence_block();
     if (d < nd) {
       if (staged)
-        for (uint32_t j = 0; j < nwd; ++j) w.masks[mo + j] = L.sm[wex + j];
+        for (uint32_t j = 0; j < nwd; ++j) w.masks[(size_t)j * nd + mo] = L.sm[wex + j];
       w.nout[d] = L.cnt[lane];
     }
     __threadfence_block();
@@ -762,9 +756,9 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
 // Clears the link-mask words ahead of the queued link kernel.
 __global__ __launch_bounds__(256) void k_zero_words(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
-  const uint32_t n = w.ctr[C_NWORDS];
+  const uint64_t n = (uint64_t)w.ctr[C_ND] * w.ctr[C_WSTRIDE];
   if (n > c.cap_words) return;  // reported by the link kernel
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+  for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     w.masks[i] = 0;
 }
 
@@ -783,6 +777,7 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
   if (ctr[C_STATUS]) return;
   const uint32_t nr = ctr[C_NROOT];
   const uint32_t T = c.cap_tuples;
+  const uint32_t nd = ctr[C_ND];
   if (FILL && w.roff[nr] > T) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       set_status(ctr, PXT_ERR_CAPACITY);
@@ -807,13 +802,13 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       kbase[0] = w.cb[r];
       nwd[0] = (w.cdeg[r] + 63u) >> 6;
       word[0] = 0;
-      bits[0] = nwd[0] ? w.masks[w.moff[r]] : 0ull;
+      bits[0] = nwd[0] ? w.masks[r] : 0ull;
     }
     bool overflow = false;
     while (depth >= 0) {
       if (bits[depth] == 0) {
         if (++word[depth] < nwd[depth]) {
-          bits[depth] = w.masks[w.moff[path[depth]] + word[depth]];
+          bits[depth] = w.masks[(size_t)word[depth] * nd + path[depth]];
           continue;
         }
         --depth;
@@ -860,7 +855,7 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       kbase[depth] = w.cb[child];
       nwd[depth] = (w.cdeg[child] + 63u) >> 6;
       word[depth] = 0;
-      bits[depth] = nwd[depth] ? w.masks[w.moff[child]] : 0ull;
+      bits[depth] = nwd[depth] ? w.masks[child] : 0ull;
     }
     if (overflow) set_status(ctr, PXT_ERR_PATH);
     if (!FILL) w.rcnt[ri] = cnt;

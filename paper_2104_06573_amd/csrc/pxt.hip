@@ -119,10 +119,6 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.cell_off = cv.take<uint32_t>(H + 1);
   w.cin = cv.take<uint32_t>(D);
   w.cout = cv.take<uint32_t>(D);
-  w.moff = cv.take<uint32_t>(D);
-  w.lw = cv.take<uint32_t>(D);
-  w.wcnt = cv.take<uint32_t>(H + 1);
-  w.wbase = cv.take<uint32_t>(H + 1);
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
@@ -244,7 +240,7 @@ void launch_scan1(const Ws& w, const uint32_t* in, uint32_t* out, const uint32_t
 
 const char* const kStageNames[PXT_N_STAGES] = {
     "clear",       "prep",       "bin_scan",    "fill",       "doublet_count",
-    "doublet_scan", "doublet_fill", "word_scan", "links",     "roots",
+    "doublet_scan", "doublet_fill", "mask_clear", "links",    "roots",
     "tuple_count", "tuple_scan", "tuple_fill",  "score",      "best",
     "survive",     "fit32",      "fit64",       "finish"};
 
@@ -345,7 +341,6 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     if (timed) sm.mark(6);
     launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
     if (timed) sm.mark(7);
-    launch_scan1(w, w.wcnt, w.wbase, w.ctr + C_NBINNED, w.ctr + C_NWORDS, H, 2, s);
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
     if (cfg.link_kernel == 1) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
     if (timed) sm.mark(8);
@@ -415,7 +410,7 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->max_events = 64;
   cfg->max_hits = 1u << 20;
   cfg->max_doublets = 1u << 24;
-  cfg->max_link_words = 1u << 24;
+  cfg->max_link_words = 1u << 26;
   cfg->max_tuples = 1u << 22;
   cfg->phi_bins = 256;
   cfg->block_size = 256;
@@ -594,11 +589,10 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
         rows.push_back(bidx[cout[k]]);
       }
     } else {
-      std::vector<uint32_t> cell_off(nb + 1), mw(nd), moff(nd);
+      std::vector<uint32_t> cell_off(nb + 1), mw(nd);
       HIP_OR_FAIL(c, hipMemcpy(cell_off.data(), w.cell_off, 4ull * (nb + 1), hipMemcpyDeviceToHost));
       if (nd) HIP_OR_FAIL(c, hipMemcpy(mw.data(), w.cdeg, 4ull * nd, hipMemcpyDeviceToHost));
       for (auto& v : mw) v = (v + 63u) >> 6;
-      if (nd) HIP_OR_FAIL(c, hipMemcpy(moff.data(), w.moff, 4ull * nd, hipMemcpyDeviceToHost));
       const uint32_t nwords = ctr[C_NWORDS];
       std::vector<uint64_t> masks(nwords);
       if (nwords)
@@ -606,7 +600,7 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
       for (uint32_t k = 0; k < nd; ++k) {
         const uint32_t b = cout[k], k0 = cell_off[b];
         for (uint32_t wd = 0; wd < mw[k]; ++wd) {
-          uint64_t m = masks[moff[k] + wd];
+          uint64_t m = masks[(size_t)wd * nd + k];
           while (m) {
             const int bit = __builtin_ctzll(m);
             m &= m - 1;

@@ -29,7 +29,7 @@ def torch():
 
 def make_rec(**kw):
     import paper_2104_06573_amd as pxt
-    caps = dict(max_events=64, max_hits=1 << 20, max_doublets=1 << 22, max_link_words=1 << 22,
+    caps = dict(max_events=64, max_hits=1 << 20, max_doublets=1 << 22, max_link_words=1 << 24,
                 max_tuples=1 << 20, max_tracks=1 << 19)
     caps.update(kw)
     return pxt.Reconstructor(DET, **caps)
@@ -110,7 +110,7 @@ def test_pu50_batch(torch):
 
 def test_pu200_event(torch):
     events = [eventgen.generate("pu200", 7)]
-    rec = make_rec(max_doublets=3 << 20, max_link_words=3 << 20)
+    rec = make_rec(max_doublets=3 << 20, max_link_words=24 << 20)
     res, out, dumps = run_and_dump(rec, events)
     stats = []
     check_events(events, res, out, dumps, fit_stats=stats)
@@ -198,7 +198,11 @@ def test_capacity_overflow_and_retry(torch):
     events = [eventgen.generate("pu50", 9)]
     o = oracle.reconstruct(events[0].x, events[0].y, events[0].z, events[0].layer, DET)
     nd, nt, nk = len(o["doublets"]), len(o["raw"]), len(o["tracks"])
+    # link-mask words: one stride per doublet, ceil(largest out-degree / 64)
+    outdeg = np.bincount(np.asarray(o["doublets"])[:, 0])
+    nw = nd * int((outdeg.max() + 63) // 64)
     for caps, idx, need in ((dict(max_doublets=nd - 1), 0, nd),
+                            (dict(max_link_words=nw - 1), 1, nw),
                             (dict(max_tuples=nt - 1), 2, nt),
                             (dict(max_tracks=nk - 1), 3, nk)):
         rec = make_rec(**caps)

@@ -9,7 +9,7 @@ import eventgen
 pytestmark = pytest.mark.gpu
 
 DET = eventgen.DETECTOR
-CAPS = dict(max_events=16, max_hits=1 << 17, max_doublets=1 << 21, max_link_words=1 << 21,
+CAPS = dict(max_events=16, max_hits=1 << 17, max_doublets=1 << 21, max_link_words=1 << 23,
             max_tuples=1 << 18, phi_bins=256)
 
 
@@ -82,7 +82,7 @@ def test_oversize_event_fails_alone(torch):
     from paper_2104_06573_amd.serve import Server
     small = [eventgen.generate("pu50", 800 + i, n_tracks=150) for i in range(6)]
     big = eventgen.generate("pu200", 3)
-    caps = dict(CAPS, max_doublets=400_000, max_link_words=400_000)
+    caps = dict(CAPS, max_doublets=400_000, max_link_words=1_600_000)
     srv = Server(DET, n_lanes=1, max_batch_events=8, doublets_per_hit=1, **caps)
     evs = small[:3] + [big] + small[3:]
     tickets = [srv.submit(e.x, e.y, e.z, e.layer) for e in evs]
