@@ -21,6 +21,7 @@ constexpr int kMaxCells = kMaxHits - 1;        // doublets per n-tuplet
 constexpr uint32_t kPad = PXT_PAD;
 constexpr int kWave = 64;
 constexpr float kPiF = 3.14159265358979f;
+constexpr int kQueue = 128;                    // LDS queue entries per wavefront
 
 // Counters kept in device memory for one call (zeroed by k_clear).
 enum Ctr : int {

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
     return;
   }
   const uint32_t lane = lane_id(), sub = lane % G, grp = lane / G;
-  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull) << (grp * G);
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G % 64)) - 1ull) << (grp * G);
   const uint64_t below = gmask & ((1ull << lane) - 1ull);
   const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
   const uint32_t chunk = (nb + gridDim.x - 1) / gridDim.x;
@@ -471,63 +471,128 @@ __device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c) {
   return ok;
 }
 
-// One thread per doublet (a,b), looping over its candidates.
+// One thread per doublet (a,b), looping over its candidates with the
+// angle prefilter, eight loads in flight.  The few survivors are not tested
+// in place -- their exact FP64 tests would run with most lanes idle -- but
+// appended to a per-wavefront queue in LDS (ballot compaction) together
+// with the doublet's two hits, so that whenever 64 are queued they are
+// tested with all lanes busy and only the candidate's hit is loaded.  A
+// doublet's mask words and link count are cleared by its own thread before
+// any of its candidates is queued; accepted links set their bit with
+// atomicOr.
+
+// Queue entry: qa = (doublet, candidate index, candidate doublet, inner x),
+// qb = (inner y, inner z, outer x, outer y), qz = outer z.
+__device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const uint4* qa,
+                                                   const uint4* qb, const float* qz,
+                                                   uint32_t n, uint32_t nd, uint32_t& links) {
+  const uint32_t lane = lane_id();
+  if (lane < n) {
+    const uint4 ea = qa[lane], eb = qb[lane];
+    const uint32_t d = ea.x, k = ea.y, d2 = ea.z;
+    const HitD ha = hit_xyz(__uint_as_float(ea.w), __uint_as_float(eb.x), __uint_as_float(eb.y));
+    const HitD hb = hit_xyz(__uint_as_float(eb.z), __uint_as_float(eb.w), qz[lane]);
+    const float4 oc = w.oh[d2];
+    const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
+    if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
+      atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * nd + d], 1ull << (k & 63u));
+      atomicAdd(&w.nout[d], 1u);
+      w.has_inner[d2] = 1;
+      ++links;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
+  __shared__ uint4 s_qa[256 / kWave][kQueue];
+  __shared__ uint4 s_qb[256 / kWave][kQueue];
+  __shared__ float s_qz[256 / kWave][kQueue];
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
   if (!links_capacity(w, c)) return;
-  uint32_t links = 0;
+  const uint32_t lane = lane_id(), wib = threadIdx.x / kWave;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint4* qa = s_qa[wib];
+  uint4* qb = s_qb[wib];
+  float* qz = s_qz[wib];
+  uint32_t links = 0, qn = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
-  uint32_t d = xcd_block() * blockDim.x + threadIdx.x;
-  // software pipeline: the set-up loads of the next doublet are issued
-  // before the candidates of the current one are scanned
-  uint32_t na = 0, nkb = 0, ndeg = 0;
-  float4 nob = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (d < nd) {
-    na = w.cin[d]; nob = w.oh[d]; nkb = w.cb[d]; ndeg = w.cdeg[d];
-  }
-  while (d < nd) {
-    const uint32_t k0 = nkb, deg = ndeg;
-    const float4 ob = nob;
-    const HitD ha = load_hit(w, na);
-    const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
-    const uint32_t dn = d + stride;
-    if (dn < nd) {
-      na = w.cin[dn]; nob = w.oh[dn]; nkb = w.cb[dn]; ndeg = w.cdeg[dn];
+  // every lane of the wavefront runs the same number of rounds, so the
+  // queue's ballots see all lanes
+  const uint32_t d0 = xcd_block() * blockDim.x + (threadIdx.x & ~(uint32_t)(kWave - 1));
+  for (uint32_t dw = d0; dw < nd; dw += stride) {
+    const uint32_t d = dw + lane;
+    uint32_t k0 = 0, deg = 0;
+    float4 ob = make_float4(0.f, 0.f, 0.f, 0.f);
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    if (d < nd) {
+      const uint32_t a = w.cin[d];
+      k0 = w.cb[d];
+      deg = w.cdeg[d];
+      ob = w.oh[d];
+      ax = w.bx[a];
+      ay = w.by[a];
+      az = w.bz[a];
+      const uint32_t nwd = (deg + 63u) >> 6;
+      for (uint32_t j = 0; j < nwd; ++j) w.masks[(size_t)j * nd + d] = 0;
+      w.nout[d] = 0;
     }
-    uint32_t nout = 0;
-    for (uint32_t wd = 0; wd * 64u < deg; ++wd) {
-      uint64_t mask = 0;
-      const uint32_t lim = min(64u, deg - wd * 64u);
-      const uint32_t kw = k0 + wd * 64u;
-      uint64_t pass = 0;  // candidates through the prefilter
-      for (uint32_t b8 = 0; b8 < lim; b8 += 8) {
-        // issue eight candidates' angle loads before testing them
+    __threadfence_block();
+    for (uint32_t wd = 0; __any(wd * 64u < deg); ++wd) {
+      // one mask word of candidates: eight angle loads in flight at a time
+      const uint32_t kw = wd * 64u;
+      uint64_t pm = 0;
+      for (uint32_t b8 = 0; b8 < 64u && __any(kw + b8 < deg); b8 += 8) {
         float tc[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) tc[u] = b8 + u < lim ? w.oh[kw + b8 + u].w : 0.0f;
+        for (int u = 0; u < 8; ++u)
+          tc[u] = kw + b8 + u < deg ? w.oh[k0 + kw + b8 + u].w : 0.0f;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          if (b8 + u < lim && rz_prefilter(c, ob.w, tc[u])) pass |= 1ull << (b8 + u);
+          if (kw + b8 + u < deg && rz_prefilter(c, ob.w, tc[u])) pm |= 1ull << (b8 + u);
       }
-      while (pass) {
-        const uint32_t k = (uint32_t)__ffsll((unsigned long long)pass) - 1u;
-        pass &= pass - 1ull;
-        const float4 oc = w.oh[kw + k];
-        const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
-        if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
-          mask |= 1ull << k;
-          w.has_inner[kw + k] = 1;
+      // append the survivors, one per lane and round
+      while (__any(pm != 0ull)) {
+        const bool has = pm != 0ull;
+        const uint32_t u = has ? (uint32_t)__ffsll((unsigned long long)pm) - 1u : 0u;
+        pm &= pm - 1ull;
+        const uint64_t bal = __ballot(has);
+        if (has) {
+          const uint32_t slot = qn + (uint32_t)__popcll(bal & below);
+          const uint32_t k = kw + u;
+          qa[slot] = make_uint4(d, k, k0 + k, __float_as_uint(ax));
+          qb[slot] = make_uint4(__float_as_uint(ay), __float_as_uint(az), __float_as_uint(ob.x),
+                                __float_as_uint(ob.y));
+          qz[slot] = ob.z;
+        }
+        qn += (uint32_t)__popcll(bal);
+        if (qn >= (uint32_t)kWave) {
+          __threadfence_block();
+          links_thread_flush(w, c, qa, qb, qz, kWave, nd, links);
+          __threadfence_block();
+          const uint32_t rest = qn - kWave;
+          uint4 ma = make_uint4(0, 0, 0, 0), mb = ma;
+          float mz = 0.f;
+          if (lane < rest) {
+            ma = qa[kWave + lane];
+            mb = qb[kWave + lane];
+            mz = qz[kWave + lane];
+          }
+          __threadfence_block();
+          if (lane < rest) {
+            qa[lane] = ma;
+            qb[lane] = mb;
+            qz[lane] = mz;
+          }
+          __threadfence_block();
+          qn = rest;
         }
       }
-      w.masks[(size_t)wd * nd + d] = mask;
-      nout += (uint32_t)__popcll(mask);
     }
-    w.nout[d] = nout;
-    links += nout;
-    d = dn;
   }
+  __threadfence_block();
+  links_thread_flush(w, c, qa, qb, qz, qn, nd, links);
   links = wave_sum(links);
   if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
 }
@@ -541,7 +606,6 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
 // are tested with all lanes busy.  Accepted links set their bit in the
 // (pre-cleared) mask word with atomicOr and count into nout.
 
-constexpr int kQueue = 128;  // queue entries per wavefront
 
 __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint2* q, uint32_t n,
                                             uint32_t& links) {
