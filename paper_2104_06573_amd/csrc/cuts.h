@@ -171,31 +171,6 @@ __device__ __forceinline__ bool doublet_ok_fast(const DevCfg& c, const HitD& i,
   return lhs <= c.kmax * i.r * o.r * sqrt(ch2);
 }
 
-// The same decision as doublet_ok_fast, evaluated without early exits so
-// that the candidate's loads are all issued at once and the cuts run
-// branch-free; only the rare band case takes the square root.  kir2 is
-// kmax^2 r_i^2, the inner hit's factor of the right-hand side, formed in the
-// same order as there.
-__device__ __forceinline__ bool doublet_ok_flat(const DevCfg& c, const HitD& i, const HitD& o,
-                                                double kir2) {
-  const bool d1 = o.r > i.r;
-  const double dr = o.r - i.r;
-  const double l2 = fabs(i.z * dr - i.r * (o.z - i.z));
-  const bool d2 = l2 <= c.z0max * dr;
-  const bool d4 = i.x * o.x + i.y * o.y > 0.0;
-  const double cr = i.x * o.y - i.y * o.x;
-  const double dx = o.x - i.x, dy = o.y - i.y;
-  const double ch2 = dx * dx + dy * dy;
-  const double lhs = 2.0 * fabs(cr);
-  const double L = lhs * lhs;
-  const double R = kir2 * (o.r * o.r) * ch2;
-  const bool above = L > R * kBandHi;
-  const bool below = L < R * kBandLo;
-  bool d3 = below;
-  if (d1 & d2 & d4 & !above & !below) d3 = lhs <= c.kmax * i.r * o.r * sqrt(ch2);
-  return d1 & d2 & d4 & !above & d3;
-}
-
 // Link cut split in two: the r-z cut L1 needs only (r, z) of the third hit;
 // the transverse cuts L2, L3 need its (x, y).
 __device__ __forceinline__ bool link_rz_pass(const DevCfg& c, const HitD& a, const HitD& b,

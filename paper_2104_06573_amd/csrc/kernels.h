@@ -344,7 +344,6 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
       phi = w.bphi[g];
       npairs = c.n_outer[li];
     }
-    const double kir2 = c.kmax2 * (hi.r * hi.r);
     const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
     uint32_t cnt = 0;
     uint32_t pos = (FILL && active) ? w.cell_off[g] : 0u;
@@ -392,17 +391,15 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
       for (uint32_t it = 0; __any(it * G < tot); ++it) {
         const uint32_t k = it * G + sub;
         const bool valid = k < tot;
-        // fill pass: every lane loads a hit (an idle lane the chunk's first
-        // one), so the loads go out together and the cuts run without
-        // branches; count pass: early exits, which issue fewer instructions
+        // the cuts with early exits: fewer instructions than evaluating
+        // every cut on every lane, which is what counts with several
+        // batches sharing the GPU
         const uint32_t j = valid ? (k < s0n ? s0b + k : s1b + (k - s0n)) : beg;
         HitD ho{0.0, 0.0, 0.0, 0.0};
-        bool ok;
-        if (FILL) {
+        bool ok = false;
+        if (valid) {
           ho = load_hit(w, j);
-          ok = valid & doublet_ok_flat(c, hi, ho, kir2);
-        } else {
-          ok = valid && doublet_ok_fast(c, hi, load_hit(w, j));
+          ok = doublet_ok_fast(c, hi, ho);
         }
         const uint64_t bal = __ballot(ok);
         if (FILL) {
