@@ -108,6 +108,7 @@ struct Ws {
   uint32_t* talive;       // [T + 1] survives the cleaning
   uint32_t* toff;         // [T + 1]
   uint32_t* surv;         // [T]
+  uint32_t* sfit;         // [T] survivor indices in fitting order
   uint32_t* fp64_list;    // [T]
   // scan scratch
   uint64_t* scan_status;  // [max tiles] status words of the single-pass scan

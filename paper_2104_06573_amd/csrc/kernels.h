@@ -1019,14 +1019,42 @@ __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
 // Survivors in n-tuplet order (offsets from the scan of the alive flags);
 // per-event track counts from the event boundaries, which the binned hits,
 // doublets, n-tuplets and survivors all respect in that order.
+//
+// Also the fitting order: the fit is compiled once per tuple length, and a
+// wavefront with mixed lengths runs several of those bodies with lanes
+// masked.  Each block takes 256 consecutive n-tuplets, whose survivors form
+// a contiguous range of survivor indices, and lists that range ordered by
+// length (a counting sort in LDS); the fit walks this list and writes every
+// result to its survivor's slot, so only the work assignment changes.
 __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
+  __shared__ uint32_t s_cnt[kMaxHits + 1];
   if (w.ctr[C_STATUS]) return;
   const uint32_t n_events = w.call->n_events;
   uint32_t* per_event_tracks = w.call->out.per_event_tracks;
   const uint32_t ntup = w.ctr[C_NTUP];
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint32_t t = tid; t < ntup; t += gridDim.x * blockDim.x)
-    if (w.talive[t]) w.surv[w.toff[t]] = t;
+  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < ntup; b0 += gridDim.x * blockDim.x) {
+    const uint32_t t = b0 + threadIdx.x;
+    const bool alive = t < ntup && w.talive[t];
+    const uint32_t sidx = t < ntup ? w.toff[t] : 0u;
+    const uint32_t key = alive ? (uint32_t)w.tn[t] : 0u;
+    if (alive) w.surv[sidx] = t;
+    if (threadIdx.x <= kMaxHits) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t rank = alive ? atomicAdd(&s_cnt[key], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = w.toff[b0];  // first survivor index of the chunk
+      for (int k = 0; k <= kMaxHits; ++k) {
+        const uint32_t v = s_cnt[k];
+        s_cnt[k] = run;
+        run += v;
+      }
+    }
+    __syncthreads();
+    if (alive) w.sfit[s_cnt[key] + rank] = sidx;
+    __syncthreads();
+  }
   const uint32_t per_ev = (uint32_t)c.n_layers * (uint32_t)c.nphi;
   const uint32_t nr = w.ctr[C_NROOT];
   for (uint32_t e = tid; e < n_events; e += gridDim.x * blockDim.x) {
@@ -1095,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c) {
     return;
   }
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x)
-    fit_one<float>(w, c, o, s, false);
+    fit_one<float>(w, c, o, w.sfit[s], false);
 }
 
 __global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c) {

@@ -137,6 +137,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.talive = cv.take<uint32_t>(T + 1);
   w.toff = cv.take<uint32_t>(T + 1);
   w.surv = cv.take<uint32_t>(T);
+  w.sfit = cv.take<uint32_t>(T);
   w.fp64_list = cv.take<uint32_t>(T);
   w.scan_status = cv.take<uint64_t>(scan_tiles(c));
   w.epoch = cv.take<uint32_t>(1);
