@@ -97,7 +97,7 @@ typedef struct pxt_config {
   int32_t phi_bins;         /* phi bins per layer, 16..4096                */
   int32_t block_size;       /* threads per block of the per-item kernels   */
   int32_t group_lanes;      /* lanes per item in doublet/link kernels:
-                               8, 16, 32 or 64                             */
+                               4, 8, 16, 32 or 64                          */
   int32_t link_kernel;      /* link step: 0 one thread per doublet,
                                1 one lane group per doublet, 2 one
                                wavefront per 64 doublets with their

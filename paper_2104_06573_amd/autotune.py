@@ -23,7 +23,7 @@ import numpy as np
 
 DEFAULT_SPACE = {
     "phi_bins": (64, 128, 256, 512),
-    "group_lanes": (16, 32),
+    "group_lanes": (4, 8, 16),
     "link_kernel": (0, 2),
     "block_size": (128, 256),
 }

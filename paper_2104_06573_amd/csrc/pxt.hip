@@ -173,9 +173,9 @@ int validate_config(const pxt_config* c, std::string& why) {
   if (c->block_size < 64 || c->block_size > 256 || c->block_size % 64)
     return why = "block_size must be 64, 128, 192 or 256", 1;
   if (!(c->pt_fp64 > 0)) return why = "pt_fp64 must be > 0", 1;
-  if (c->group_lanes != 8 && c->group_lanes != 16 && c->group_lanes != 32 &&
-      c->group_lanes != 64)
-    return why = "group_lanes must be 8, 16, 32 or 64", 1;
+  if (c->group_lanes != 4 && c->group_lanes != 8 && c->group_lanes != 16 &&
+      c->group_lanes != 32 && c->group_lanes != 64)
+    return why = "group_lanes must be 4, 8, 16, 32 or 64", 1;
   if (c->link_kernel < 0 || c->link_kernel > 2) return why = "link_kernel must be 0, 1 or 2", 1;
   if (c->use_graph != 0 && c->use_graph != 1) return why = "use_graph must be 0 or 1", 1;
   return 0;
@@ -274,6 +274,7 @@ uint32_t grid_chunked(uint64_t items, int bs, int G, uint32_t cap_blocks) {
 template <bool FILL>
 void launch_doublets(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, const DevCfg& d) {
   switch (G) {
+    case 4: hipLaunchKernelGGL((k_doublets<4, FILL>), grid, block, 0, s, w, d); break;
     case 8: hipLaunchKernelGGL((k_doublets<8, FILL>), grid, block, 0, s, w, d); break;
     case 16: hipLaunchKernelGGL((k_doublets<16, FILL>), grid, block, 0, s, w, d); break;
     case 64: hipLaunchKernelGGL((k_doublets<64, FILL>), grid, block, 0, s, w, d); break;
@@ -291,6 +292,7 @@ void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, cons
     return;
   }
   switch (G) {
+    case 4: hipLaunchKernelGGL((k_links<4>), grid, block, 0, s, w, d); break;
     case 8: hipLaunchKernelGGL((k_links<8>), grid, block, 0, s, w, d); break;
     case 16: hipLaunchKernelGGL((k_links<16>), grid, block, 0, s, w, d); break;
     case 64: hipLaunchKernelGGL((k_links<64>), grid, block, 0, s, w, d); break;

@@ -150,7 +150,7 @@ def test_batch_equivalence(torch):
                                                      (256, 192, 64, 0), (256, 64, 16, 0),
                                                      (256, 256, 16, 2), (128, 64, 32, 2),
                                                      (512, 192, 16, 2), (256, 256, 8, 0),
-                                                     (64, 128, 8, 1)])
+                                                     (64, 128, 8, 1), (128, 256, 4, 0)])
 def test_tuning_invariance(torch, phi_bins, block, group, lk):
     events = [eventgen.generate("pu50", 55), eventgen.generate("tiny", 3)]
     ref = _tracks_by_event(make_rec().run_numpy(events).numpy(), 2)
