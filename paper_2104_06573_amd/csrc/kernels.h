@@ -1020,41 +1020,43 @@ __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
 // per-event track counts from the event boundaries, which the binned hits,
 // doublets, n-tuplets and survivors all respect in that order.
 //
-// Also the fitting order: the fit is compiled once per tuple length, and a
-// wavefront with mixed lengths runs several of those bodies with lanes
-// masked.  Each block takes 256 consecutive n-tuplets, whose survivors form
-// a contiguous range of survivor indices, and lists that range ordered by
-// length (a counting sort in LDS); the fit walks this list and writes every
-// result to its survivor's slot, so only the work assignment changes.
+// Also the first step of the fitting order.  The fit is compiled once per
+// tuple length, and one kernel per length keeps each body's register
+// budget its own and its wavefronts uniform; for that the survivors are
+// grouped by length, without atomics: each block counts the lengths of the
+// survivors it meets (bcnt), k_fitbase turns the counts into per-block
+// places, and k_fitorder, walking the same tuples in the same order,
+// writes the survivors there.  Every result still goes to its survivor's
+// slot, so only the work assignment changes.
+constexpr int kFitKeys = kMaxHits + 1;  // length keys 0..8 (3..8 used)
+
 __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
-  __shared__ uint32_t s_cnt[kMaxHits + 1];
+  __shared__ uint32_t s_cnt[kFitKeys];
   if (w.ctr[C_STATUS]) return;
   const uint32_t n_events = w.call->n_events;
   uint32_t* per_event_tracks = w.call->out.per_event_tracks;
   const uint32_t ntup = w.ctr[C_NTUP];
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < ntup; b0 += gridDim.x * blockDim.x) {
-    const uint32_t t = b0 + threadIdx.x;
+  if (threadIdx.x < kFitKeys) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  // every lane of a wavefront runs the same number of rounds (ballots)
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t t0 = tid - lane_id(); t0 < ntup; t0 += stride) {
+    const uint32_t t = t0 + lane_id();
     const bool alive = t < ntup && w.talive[t];
-    const uint32_t sidx = t < ntup ? w.toff[t] : 0u;
-    const uint32_t key = alive ? (uint32_t)w.tn[t] : 0u;
-    if (alive) w.surv[sidx] = t;
-    if (threadIdx.x <= kMaxHits) s_cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t rank = alive ? atomicAdd(&s_cnt[key], 1u) : 0u;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t run = w.toff[b0];  // first survivor index of the chunk
-      for (int k = 0; k <= kMaxHits; ++k) {
-        const uint32_t v = s_cnt[k];
-        s_cnt[k] = run;
-        run += v;
-      }
+    uint32_t key = 0;
+    if (alive) {
+      w.surv[w.toff[t]] = t;
+      key = w.tn[t];
     }
-    __syncthreads();
-    if (alive) w.sfit[s_cnt[key] + rank] = sidx;
-    __syncthreads();
+#pragma unroll
+    for (int k = 3; k < kFitKeys; ++k) {
+      const uint64_t m = __ballot(alive && key == (uint32_t)k);
+      if (lane_id() == 0 && m) atomicAdd(&s_cnt[k], (uint32_t)__popcll(m));
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < kFitKeys) w.bcnt[(size_t)blockIdx.x * kFitKeys + threadIdx.x] = s_cnt[threadIdx.x];
   const uint32_t per_ev = (uint32_t)c.n_layers * (uint32_t)c.nphi;
   const uint32_t nr = w.ctr[C_NROOT];
   for (uint32_t e = tid; e < n_events; e += gridDim.x * blockDim.x) {
@@ -1065,21 +1067,100 @@ __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
   }
 }
 
+// Per-block places of every length in the fitting order: length k takes
+// the range after all shorter lengths, and within it the blocks follow in
+// block order.  One wavefront per length scans the blocks' counts.
+__global__ __launch_bounds__(kFitKeys * kWave) void k_fitbase(Ws w, uint32_t nblocks) {
+  __shared__ uint32_t s_tot[kFitKeys];
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t k = threadIdx.x / kWave, lane = lane_id();
+  uint32_t run = 0;
+  for (uint32_t b0 = 0; b0 < nblocks; b0 += kWave) {
+    const uint32_t b = b0 + lane;
+    const uint32_t v = b < nblocks ? w.bcnt[(size_t)b * kFitKeys + k] : 0u;
+    const uint32_t inc = wave_incl_scan(v);
+    if (b < nblocks) w.bbase[(size_t)b * kFitKeys + k] = run + inc - v;
+    run += __shfl(inc, kWave - 1);
+  }
+  if (lane == 0) s_tot[k] = run;
+  __syncthreads();
+  uint32_t off = 0;
+  for (uint32_t i = 0; i < k; ++i) off += s_tot[i];
+  for (uint32_t b = lane; b < nblocks; b += kWave) w.bbase[(size_t)b * kFitKeys + k] += off;
+  if (lane == 0) {
+    w.ctr[C_FITN0 + k] = run;
+    w.ctr[C_FITO0 + k] = off;
+  }
+}
+
+// Writes each block's survivors to its places, length by length, visiting
+// the tuples in the order k_compact counted them (same grid and stride).
+__global__ __launch_bounds__(256) void k_fitorder(Ws w) {
+  constexpr int NW = 256 / kWave;
+  __shared__ uint32_t s_w[NW][kFitKeys];  // per wavefront and length
+  __shared__ uint32_t s_run[kFitKeys];    // the block's next place per length
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t ntup = w.ctr[C_NTUP];
+  const uint32_t lane = lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const uint64_t below = (1ull << lane) - 1ull;
+  if (threadIdx.x < kFitKeys) s_run[threadIdx.x] = w.bbase[(size_t)blockIdx.x * kFitKeys + threadIdx.x];
+  __syncthreads();
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < ntup; b0 += stride) {
+    const uint32_t t = b0 + threadIdx.x;
+    const bool alive = t < ntup && w.talive[t];
+    const uint32_t key = alive ? (uint32_t)w.tn[t] : 0u;
+    uint32_t rank = 0;  // among this wavefront's survivors of the same length
+#pragma unroll
+    for (int k = 3; k < kFitKeys; ++k) {
+      const uint64_t m = __ballot(alive && key == (uint32_t)k);
+      if (key == (uint32_t)k) rank = (uint32_t)__popcll(m & below);
+      if (lane == 0) s_w[wid][k] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x >= 3 && threadIdx.x < kFitKeys) {
+      const uint32_t k = threadIdx.x;
+      uint32_t run = s_run[k];
+      for (uint32_t i = 0; i < nw; ++i) {
+        const uint32_t v = s_w[i][k];
+        s_w[i][k] = run;
+        run += v;
+      }
+      s_run[k] = run;
+    }
+    __syncthreads();
+    if (alive) w.sfit[s_w[wid][key] + rank] = w.toff[t];
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ fit --
 
-template <typename T>
+// Fit survivor s; NFIX > 0: the tuple is known to have NFIX hits.
+template <typename T, int NFIX = 0>
 __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_t s,
                                bool fp64) {
+  constexpr int NH = NFIX > 0 ? NFIX : kMaxHits;  // hit slots that can be used
   const uint32_t t = w.surv[s];
-  const int n = w.tn[t];
+  const int n = NFIX > 0 ? NFIX : (int)w.tn[t];
   double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
   int kind[kMaxHits];
-  uint32_t hid[kMaxHits];
+  const uint32_t* row = w.thit + (size_t)t * kMaxHits;
+  // the track's hit ids and event go out first, so that the ids are not
+  // held through the fit
+  if (!fp64) {
+#pragma unroll
+    for (int j = 0; j < kMaxHits; ++j) {
+      const uint32_t h = j < NH ? row[j] : kPad;
+      o.hit_idx[(size_t)s * 8 + j] = h == kPad ? kPad : w.bidx[h];
+    }
+    o.n_hits[s] = (uint8_t)n;
+    o.event_id[s] = w.bevt[row[0]];
+  }
 #pragma unroll
   for (int j = 0; j < kMaxHits; ++j) {
-    const uint32_t h = w.thit[(size_t)t * kMaxHits + j];
-    hid[j] = h;
-    if (j < n) {
+    if (j < NH && j < n) {
+      const uint32_t h = row[j];
       X[j] = (double)w.bx[h];
       Y[j] = (double)w.by[h];
       Z[j] = (double)w.bz[h];
@@ -1090,7 +1171,10 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
     }
   }
   FitOut f;
-  fit_tuple<T>(c, n, X, Y, Z, kind, f);
+  if constexpr (NFIX > 0)
+    fit_n<NFIX, T>(c, X, Y, Z, kind, f);
+  else
+    fit_tuple<T>(c, n, X, Y, Z, kind, f);
   if (!fp64 && f.need64) {
     const uint32_t k = atomicAdd(&w.ctr[C_NFP64], 1u);
     w.fp64_list[k] = s;
@@ -1102,28 +1186,29 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   o.chi2[(size_t)s * 2 + 0] = f.chi2[0];
   o.chi2[(size_t)s * 2 + 1] = f.chi2[1];
   o.flags[s] = fp64 ? 1 : 0;
-  if (!fp64) {
-#pragma unroll
-    for (int j = 0; j < kMaxHits; ++j)
-      o.hit_idx[(size_t)s * 8 + j] = hid[j] == kPad ? kPad : w.bidx[hid[j]];
-    o.n_hits[s] = (uint8_t)n;
-    o.event_id[s] = w.bevt[hid[0]];
-  }
 }
 
+// One kernel per tuple length N over that length's range of the fitting
+// order (N = 0: all lengths from 5 up, rarer, in one kernel); the N = 3
+// instance also reports an output overflow.
+template <int N>
 __global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const OutPtrs o = w.call->out;
   const uint32_t ns = w.ctr[C_NSURV];
   if (ns > o.capacity) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (N == 3 && blockIdx.x == 0 && threadIdx.x == 0) {
       set_status(w.ctr, PXT_ERR_CAPACITY);
       w.ctr[C_REQ_K] = ns;
     }
     return;
   }
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x)
-    fit_one<float>(w, c, o, w.sfit[s], false);
+  constexpr int K0 = N > 0 ? N : 5;
+  const uint32_t off = w.ctr[C_FITO0 + K0];
+  uint32_t cnt = 0;
+  for (int k = K0; k <= (N > 0 ? N : kMaxHits); ++k) cnt += w.ctr[C_FITN0 + k];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
+    fit_one<float, N>(w, c, o, w.sfit[off + i], false);
 }
 
 __global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c) {

@@ -138,6 +138,8 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.toff = cv.take<uint32_t>(T + 1);
   w.surv = cv.take<uint32_t>(T);
   w.sfit = cv.take<uint32_t>(T);
+  w.bcnt = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
+  w.bbase = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
   w.fp64_list = cv.take<uint32_t>(T);
   w.scan_status = cv.take<uint64_t>(scan_tiles(c));
   w.epoch = cv.take<uint32_t>(1);
@@ -367,10 +369,23 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     if (timed) sm.mark(15);
     hipLaunchKernelGGL(k_alive, dim3(gt), dim3(bs), 0, s, w, d);
     launch_scan1(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, cfg.max_tuples, 5, s);
-    hipLaunchKernelGGL(k_compact, dim3(gt), dim3(bs), 0, s, w, d);
+    {
+      // survivors, then the fitting order grouped by length (the same grid
+      // for k_compact and k_fitorder: each block meets the same tuples)
+      const uint32_t gc = std::min<uint32_t>(grid_for(cfg.max_tuples, 256, persist),
+                                             kCompactBlocksMax);
+      hipLaunchKernelGGL(k_compact, dim3(gc), dim3(256), 0, s, w, d);
+      hipLaunchKernelGGL(k_fitbase, dim3(1), dim3((kMaxHits + 1) * kWave), 0, s, w, gc);
+      hipLaunchKernelGGL(k_fitorder, dim3(gc), dim3(256), 0, s, w);
+    }
     if (timed) sm.mark(16);
-    hipLaunchKernelGGL(k_fit32, dim3(grid_for(cfg.max_tuples, 256, persist)), dim3(256), 0, s, w,
-                       d);
+    {
+      // fits of 3 and of 4 hits, then the rarer longer ones together
+      const uint32_t gf = grid_for(cfg.max_tuples, 256, persist);
+      hipLaunchKernelGGL(k_fit32<3>, dim3(gf), dim3(256), 0, s, w, d);
+      hipLaunchKernelGGL(k_fit32<4>, dim3(gf), dim3(256), 0, s, w, d);
+      hipLaunchKernelGGL(k_fit32<0>, dim3(gf), dim3(256), 0, s, w, d);
+    }
     if (timed) sm.mark(17);
     hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)c->n_cu)), dim3(64),
                        0, s, w, d);
