@@ -412,7 +412,9 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
             w.cdeg[q] = w.cell_off[j + 1] - jb;
           w.has_inner[q] = 0;
             if (c.link_kernel == 1) w.nout[q] = 0;
-            w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, rz_angle(hi, ho));
+            const float th = rz_angle(hi, ho);
+            w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, th);
+            w.th[q] = th;
           }
         }
         const uint32_t ng = (uint32_t)__popcll(bal & gmask);
@@ -444,10 +446,9 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
 // The candidate outer neighbours of doublet (a,b) are the doublets leaving
 // hit b: the contiguous range cell_off[b] .. cell_off[b+1] (doublets are
 // stored grouped by inner hit).  Each doublet carries its outer hit and its
-// r-z angle in one float4, so a candidate is one load: the FP32 angle
-// prefilter, which passes only a few percent, decides on its fourth
-// component, and the survivors go on to the exact FP64 cuts with the hit
-// already in registers.  The accepted candidates form a bit mask over the
+// r-z angle in one float4, and the angle again in a compact array: the FP32
+// angle prefilter, which passes only a few percent, streams the compact
+// angles, and the survivors go on to the exact FP64 cuts with the float4.  The accepted candidates form a bit mask over the
 // range, one 64-bit word per 64.
 
 // The link masks take C_WSTRIDE words per doublet (one word per 64
@@ -543,8 +544,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       for (uint32_t b8 = 0; b8 < 64u && __any(kw + b8 < deg); b8 += 8) {
         float tc[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          tc[u] = kw + b8 + u < deg ? w.oh[k0 + kw + b8 + u].w : 0.0f;
+        for (int u = 0; u < 8; ++u) tc[u] = kw + b8 + u < deg ? w.th[k0 + kw + b8 + u] : 0.0f;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
           if (kw + b8 + u < deg && rz_prefilter(c, ob.w, tc[u])) pm |= 1ull << (b8 + u);
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
     uint32_t kb = 0, deg = 0;
     float ta = 0.0f;
     if (d < end) {
-      ta = w.oh[d].w;
+      ta = w.th[d];
       kb = w.cb[d];
       deg = w.cdeg[d];
     }
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t k = wd * 64u + (uint32_t)(u * G) + sub;
-        tc[u] = k < deg ? w.oh[kb + k].w : 0.0f;
+        tc[u] = k < deg ? w.th[kb + k] : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -784,7 +784,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
       const uint32_t kk = k - __shfl(cex, (int)own);
       const uint32_t kbo = __shfl(kb, (int)own);
       const float tao = __shfl(ob.w, (int)own);
-      const bool pass = k < C && rz_prefilter(c, tao, w.oh[kbo + kk].w);
+      const bool pass = k < C && rz_prefilter(c, tao, w.th[kbo + kk]);
       const uint64_t bal = __ballot(pass);
       if (pass) L.q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(own, kk);
       qn += (uint32_t)__popcll(bal);

@@ -123,6 +123,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
   w.oh = cv.take<float4>(D);
+  w.th = cv.take<float>(D);
   w.cb = cv.take<uint32_t>(D);
   w.cdeg = cv.take<uint32_t>(D);
   w.roots = cv.take<uint32_t>(D);
