@@ -784,7 +784,9 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
       const uint32_t kk = k - __shfl(cex, (int)own);
       const uint32_t kbo = __shfl(kb, (int)own);
       const float tao = __shfl(ob.w, (int)own);
-      const bool pass = k < C && rz_prefilter(c, tao, w.th[kbo + kk]);
+      // (this kernel reads the angle from the float4: the compact-array load
+      // here makes the gfx950 backend emit an invalid instruction)
+      const bool pass = k < C && rz_prefilter(c, tao, w.oh[kbo + kk].w);
       const uint64_t bal = __ballot(pass);
       if (pass) L.q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(own, kk);
       qn += (uint32_t)__popcll(bal);
