@@ -46,8 +46,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
     ap.add_argument("--group-lanes", type=int, default=8)
-    ap.add_argument("--link-kernel", type=int, default=0,
-                    help="0 thread per doublet, 1 lane group + queue, 2 wavefront + queue")
+    ap.add_argument("--link-kernel", type=int, default=-1,
+                    help="0 thread per doublet, 1 lane group + queue, 2 wavefront + queue "
+                         "(default: 0 for pu50, 1 for pu200, the faster with batches in flight)")
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
     ap.add_argument("--inflight", type=int, default=4,
                     help="batches in flight: contexts, each on its own stream, taking turns")
@@ -201,6 +202,8 @@ def serving_leg(det, args):
 
 def main():
     args = parse()
+    if args.link_kernel < 0:
+        args.link_kernel = 0 if args.workload == "pu50" else 1
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (events are independent; a multi-GPU "
               "deployment is one process per GPU). Use --gpus 1.", file=sys.stderr)
