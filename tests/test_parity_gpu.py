@@ -193,6 +193,31 @@ def test_edge_cases(torch):
     assert r.counts["status"] == 0 and r.counts["n_tracks"] == 0
 
 
+def _dense_middle_event(seed=5, n_out=600):
+    # one barrel-1 hit joined to a few barrel-0 hits and to n_out barrel-2
+    # hits, all within the doublet cuts: a hit whose out-doublets need
+    # several link-mask words (a stride above one)
+    rng = np.random.default_rng(seed)
+    r0, r1, r2 = 2.9, 6.8, 10.9
+    p0 = rng.uniform(-0.01, 0.01, 5)
+    p2 = rng.uniform(-0.05, 0.05, n_out)
+    x = np.concatenate([r0 * np.cos(p0), [r1], r2 * np.cos(p2)])
+    y = np.concatenate([r0 * np.sin(p0), [0.0], r2 * np.sin(p2)])
+    z = np.concatenate([rng.uniform(-1, 1, 5), [0.0], rng.uniform(-3, 3, n_out)])
+    lay = np.concatenate([np.zeros(5), [1], np.full(n_out, 2)])
+    return _Ev(x, y, z, lay)
+
+
+@pytest.mark.parametrize("lk", [0, 1, 2])
+def test_dense_middle_hit(torch, lk):
+    events = [_dense_middle_event(), eventgen.generate("tiny", 4)]
+    rec = make_rec(link_kernel=lk)
+    res, out, dumps = run_and_dump(rec, events)
+    o = oracle.reconstruct(events[0].x, events[0].y, events[0].z, events[0].layer, DET)
+    assert np.bincount(np.asarray(o["doublets"])[:, 0]).max() > 512
+    check_events(events, res, out, dumps)
+
+
 def test_capacity_overflow_and_retry(torch):
     import paper_2104_06573_amd as pxt
     events = [eventgen.generate("pu50", 9)]
