@@ -46,9 +46,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
     ap.add_argument("--group-lanes", type=int, default=8)
-    ap.add_argument("--link-kernel", type=int, default=-1,
-                    help="0 thread per doublet, 1 lane group + queue, 2 wavefront + queue "
-                         "(default: 0 for pu50, 1 for pu200, the faster with batches in flight)")
+    ap.add_argument("--link-kernel", type=int, default=0,
+                    help="0 thread per doublet (the fastest with batches in flight at PU~50 "
+                         "and PU~200), 1 lane group + queue, 2 wavefront + queue")
+    ap.add_argument("--doublet-mode", type=int, default=2,
+                    help="0 count/scan/fill, 1 one pass (LDS records), 2 count+stage/scan/scatter")
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
     ap.add_argument("--inflight", type=int, default=4,
                     help="batches in flight: contexts, each on its own stream, taking turns")
@@ -71,8 +73,11 @@ def gen_events(kind, n, seed0):
 # array the kernel must read or write, touched once (re-reads of candidates
 # from cache are not counted).  Nh binned hits, Nd doublets, Nw link-mask
 # words, Nt raw n-tuplets, Nk tracks, nbar mean hits per track.
-def algorithmic_bytes(stage, n):
+def algorithmic_bytes(stage, n, doublet_mode=0):
     Nh, Nd, Nw, Nt, Nk = n["Nh"], n["Nd"], n["Nw"], n["Nt"], n["Nk"]
+    # staged doublets: a 4-byte record per doublet written by the count
+    # pass and read by the scatter
+    rec = 4 * Nd if doublet_mode == 2 else 0
     nbar = n["nbar"]
     table = {
         # x, y (8) + layer (2) read, bin key (4) written
@@ -80,15 +85,17 @@ def algorithmic_bytes(stage, n):
         # key, x, y, z, layer read (18); binned SoA written (33)
         "fill": 51 * Nh,
         # binned hit read (29), doublet count written (4)
-        "doublet_count": 33 * Nh,
-        # binned hit + offset read (33); per doublet written: in/out hits,
-        # candidate range, flag, outer hit and r-z angle (33)
-        "doublet_fill": 33 * Nh + 33 * Nd,
-        # inner-hit coordinates (20 per hit); per doublet: inner hit, outer
-        # hit and angle, candidate range, mask offset (32), its angle read
-        # once as a candidate (4), neighbour count written (4); mask words
-        # written (8)
-        "links": 20 * Nh + 40 * Nd + 8 * Nw,
+        "doublet_count": 33 * Nh + rec,
+        # binned hit read and offset read or written (33); per doublet
+        # written: in/out hits, flag, outer hit and r-z angle, the angle
+        # again (29).  The one-pass kernel (reported under this stage)
+        # moves the same bytes.
+        "doublet_fill": 33 * Nh + 29 * Nd + rec,
+        # inner-hit coordinates and doublet offsets (24 per hit); per
+        # doublet: inner and outer hit, outer hit coordinates and angle,
+        # candidate range written (32), its angle read once as a candidate
+        # (4), neighbour count written (4); mask words written (8)
+        "links": 24 * Nh + 40 * Nd + 8 * Nw,
         # per n-tuplet: hits, doublets, length (61), hit coordinates, score
         # written (8), order key min per doublet (8)
         "score": (69 + 20 * nbar + 8 * (nbar - 1)) * Nt,
@@ -105,6 +112,23 @@ STAGE_KERNEL = {"prep": "pxt::k_prep", "fill": "pxt::k_fill",
                 "doublet_count": "pxt::k_doublets<8, false>",
                 "doublet_fill": "pxt::k_doublets<8, true>", "links": "pxt::k_links_thread",
                 "score": "pxt::k_score", "best": "pxt::k_best", "fit32": "pxt::k_fit32"}
+
+
+def stage_kernel(stage, args):
+    kname = STAGE_KERNEL.get(stage)
+    if stage == "links" and args.link_kernel == 1:
+        kname = "pxt::k_links<%d>" % args.group_lanes
+    if stage == "links" and args.link_kernel == 2:
+        kname = "pxt::k_links_wave"
+    if stage == "doublet_fill" and args.doublet_mode == 1:
+        kname = "pxt::k_doublets1<8>"
+    if stage == "doublet_fill" and args.doublet_mode == 2:
+        kname = "pxt::k_dscatter<8>"
+    if stage == "doublet_count" and args.doublet_mode == 2:
+        kname = "pxt::k_dstage<8>"
+    if stage in ("doublet_count", "doublet_fill"):
+        kname = kname.replace("<8", "<%d" % args.group_lanes)
+    return kname
 
 
 def kernel_source_hash():
@@ -139,16 +163,10 @@ def roofline(stages, counts, n_hits, peak_gbs, workload, args):
          "Nt": counts["n_raw_tuples"], "Nk": counts["n_tracks"], "nbar": 3.4}
     cand = {k: v for k, v in stages.items() if algorithmic_bytes(k, n) is not None}
     dom = max(cand, key=cand.get)
-    byts = algorithmic_bytes(dom, n)
+    byts = algorithmic_bytes(dom, n, args.doublet_mode)
     gbs = byts / (cand[dom] * 1e-3) / 1e9
     traffic = None
-    kname = STAGE_KERNEL.get(dom)
-    if dom == "links" and args.link_kernel == 1:
-        kname = "pxt::k_links<%d>" % args.group_lanes
-    if dom == "links" and args.link_kernel == 2:
-        kname = "pxt::k_links_wave"
-    if dom in ("doublet_count", "doublet_fill"):
-        kname = kname.replace("<8,", "<%d," % args.group_lanes)
+    kname = stage_kernel(dom, args)
     if (workload == "pu50" and kname and args.link_kernel == 0 and args.group_lanes == 8
             and args.batch in (0, 64)):
         traffic = measured_traffic(kname)
@@ -182,7 +200,8 @@ def serving_leg(det, args):
     srv = Server(det, n_lanes=args.serve_lanes, max_batch_events=64, doublets_per_hit=40,
                  max_events=64, max_hits=1_400_000, max_doublets=36 << 20,
                  max_link_words=160 << 20, max_tuples=6 << 20, phi_bins=args.phi_bins,
-                 group_lanes=args.group_lanes, link_kernel=args.link_kernel, use_graph=1)
+                 group_lanes=args.group_lanes, link_kernel=args.link_kernel, use_graph=1,
+                 doublet_mode=args.doublet_mode)
     poisson_run(srv, events[:300], rate_hz=args.serve_rate)          # warm-up
     rep = poisson_run(srv, events, rate_hz=args.serve_rate)
     sat = poisson_run(srv, events, rate_hz=1e7)
@@ -202,8 +221,6 @@ def serving_leg(det, args):
 
 def main():
     args = parse()
-    if args.link_kernel < 0:
-        args.link_kernel = 0 if args.workload == "pu50" else 1
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (events are independent; a multi-GPU "
               "deployment is one process per GPU). Use --gpus 1.", file=sys.stderr)
@@ -238,7 +255,8 @@ def main():
                               max_doublets=per_ev_d * B, max_link_words=per_ev_w * B,
                               max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
                               phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                              link_kernel=args.link_kernel, use_graph=args.graph)
+                              link_kernel=args.link_kernel, use_graph=args.graph,
+                              doublet_mode=args.doublet_mode)
             for _ in range(K)]
     rec = recs[0]
     streams = [torch.cuda.Stream() for _ in range(K)]
@@ -276,7 +294,8 @@ def main():
                              max_doublets=per_ev_d * B, max_link_words=per_ev_w * B,
                              max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                             link_kernel=args.link_kernel, use_graph=0)
+                             link_kernel=args.link_kernel, use_graph=0,
+                             doublet_mode=args.doublet_mode)
     stages = trec.stage_times(trec.upload(pool[0]), repeats=5)
     trec.close()
 
@@ -286,7 +305,8 @@ def main():
                              max_doublets=per_ev_d * 2, max_link_words=per_ev_w * 2,
                              max_tuples=per_ev_t * 2, max_tracks=per_ev_t * 2,
                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                            link_kernel=args.link_kernel, use_graph=args.graph)
+                            link_kernel=args.link_kernel, use_graph=args.graph,
+                              doublet_mode=args.doublet_mode)
     plain_dev = [prec.upload([e]) for e in plain_events]
     for i in range(min(4, len(plain_dev))):
         prec.launch(*plain_dev[i])
@@ -320,6 +340,7 @@ def main():
             "group_lanes": args.group_lanes,
             "batches_in_flight": args.inflight,
             "link_kernel": args.link_kernel,
+            "doublet_mode": args.doublet_mode,
             "hip_graph": bool(args.graph),
             "path": "batched (one launch sequence per batch)",
         },

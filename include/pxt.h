@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PXT_ABI_VERSION 1
+#define PXT_ABI_VERSION 2
 
 #define PXT_MAX_LAYERS 16
 #define PXT_MAX_PAIRS 32
@@ -105,6 +105,15 @@ typedef struct pxt_config {
   int32_t use_graph;        /* 1: replay the launch sequence as a HIP
                                graph captured at the first call (stage
                                timing is then unavailable)                */
+  int32_t doublet_mode;     /* doublet step: 0 count, scan and fill, each
+                               pass evaluating the cuts; 1 one pass, the
+                               accepted pairs of each tile of
+                               block_size/group_lanes inner hits staged in
+                               LDS, tiles chained by look-back (least
+                               latency on small batches); 2 count and stage
+                               the pairs in device memory, scan, scatter
+                               (most throughput on large batches).  All
+                               modes give the same results.               */
   double pt_fp64;           /* fit tuples with pT_ref above this in FP64   */
 } pxt_config;
 

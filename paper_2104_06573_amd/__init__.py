@@ -35,6 +35,7 @@ EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_de
            "pxt_server_create", "pxt_submit", "pxt_poll", "pxt_server_get_stats",
            "pxt_server_destroy")
 N_STAGES = 19
+ABI_VERSION = 2  # layout of the structs below
 
 
 class PxtConfig(ctypes.Structure):
@@ -55,7 +56,7 @@ class PxtConfig(ctypes.Structure):
         ("max_tuples", ctypes.c_uint32),
         ("phi_bins", ctypes.c_int32), ("block_size", ctypes.c_int32),
         ("group_lanes", ctypes.c_int32), ("link_kernel", ctypes.c_int32),
-        ("use_graph", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("doublet_mode", ctypes.c_int32),
         ("pt_fp64", ctypes.c_double),
     ]
 
@@ -109,6 +110,9 @@ def lib():
             raise ImportError("libpxt.so not built: run python -m paper_2104_06573_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         L.pxt_abi_version.restype = ctypes.c_int
+        if L.pxt_abi_version() != ABI_VERSION:
+            raise ImportError("libpxt.so ABI %d, binding expects %d: rebuild"
+                              % (L.pxt_abi_version(), ABI_VERSION))
         L.pxt_status_str.restype = ctypes.c_char_p
         L.pxt_status_str.argtypes = [ctypes.c_int]
         L.pxt_last_error.restype = ctypes.c_char_p
@@ -138,7 +142,7 @@ def stage_names():
 
 def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
                 max_link_words=None, max_tuples=1 << 19, phi_bins=256, block_size=256,
-                group_lanes=16, link_kernel=0, use_graph=0, pt_fp64=20.0):
+                group_lanes=16, link_kernel=0, use_graph=0, doublet_mode=2, pt_fp64=20.0):
     """pxt_config from a detector dictionary (eventgen.DETECTOR layout)."""
     c = PxtConfig()
     if lib().pxt_config_defaults(ctypes.byref(c)) != OK:
@@ -167,6 +171,7 @@ def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
     c.group_lanes = group_lanes
     c.link_kernel = link_kernel
     c.use_graph = use_graph
+    c.doublet_mode = doublet_mode
     c.pt_fp64 = pt_fp64
     return c
 

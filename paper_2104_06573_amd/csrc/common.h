@@ -104,6 +104,11 @@ struct Ws {
   // n-tuplets
   uint32_t* thit;         // [T][8] binned hits of each n-tuplet (kPad-padded)
   uint32_t* tcell;        // [T][8] its doublets (7 used, kPad-padded)
+  // staged doublets: per-wavefront record regions over roots .. fp64_list,
+  // which hold nothing until the links are done
+  uint32_t* stage;
+  uint32_t stage_words;
+  uint32_t* dwn;          // [blocks * 4] records per wavefront region
   uint8_t* tn;            // [T] hits
   double* tscore;         // [T]
   // cleaning

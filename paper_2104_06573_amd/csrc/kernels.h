@@ -303,13 +303,152 @@ __global__ __launch_bounds__(kScanThreads1) void k_roots(Ws w, uint32_t scan_id)
 // outer radius of the event's layer, plus one guard bin per side.  The cut
 // itself decides, so the window never changes the result.
 //
-// Work split: a group of G lanes (G = 16, 32 or 64) handles one inner hit;
-// its lanes take consecutive candidates of the window, so the candidate
-// loads are coalesced, and a ballot over the group gives each accepted
-// doublet its position (count pass: the popcount; fill pass: the prefix),
-// so the fill writes are coalesced too and keep the candidate order.  Each
-// block processes one contiguous chunk of inner hits (XCD-aware remap).
+// Work split: a group of G lanes handles one inner hit; its lanes take
+// consecutive candidates of the window, so the candidate loads are
+// coalesced, and a ballot over the group gives each accepted doublet its
+// position among the hit's doublets, so the writes are coalesced too and
+// keep the candidate order.  Doublets are stored grouped by inner hit
+// (binned order), in candidate order within a hit.
 
+// Candidate runs of one (inner hit, outer layer) pair: the binned hits of
+// the phi window, two runs when it wraps around; none when the layer lies
+// inside the inner radius.
+struct PairWin {
+  uint32_t s0b, s0n, s1b, s1n;
+};
+
+__device__ __forceinline__ PairWin pair_window(const Ws& w, const DevCfg& c, uint32_t e, int lo,
+                                               float ri, float phi, float ai) {
+  PairWin r{0u, 0u, 0u, 0u};
+  const uint32_t el = e * (uint32_t)c.n_layers + (uint32_t)lo;
+  const float rmo = __uint_as_float(w.rmax[el]) * 1.000001f;
+  if (!(rmo > ri * 0.999999f)) return r;
+  const uint32_t bb = el * (uint32_t)c.nphi;
+  const float ao = w.rasin[el];
+  int blo = 0, bhi = c.nphi - 1;
+  bool full = !(ao < __builtin_huge_valf());
+  if (!full) {
+    const float W = ao - ai;
+    if (!(W >= 0.0f && W < 4.0f && phi >= -4.0f && phi <= 4.0f)) {
+      full = true;  // non-finite input: fall back to the whole layer
+    } else {
+      blo = (int)floorf((phi - W + kPiF) * c.phi_scale) - 1;
+      bhi = (int)floorf((phi + W + kPiF) * c.phi_scale) + 1;
+      full = bhi - blo + 1 >= c.nphi;
+    }
+  }
+  if (full) {
+    r.s0b = w.bin_off[bb];
+    r.s0n = w.bin_off[bb + c.nphi] - r.s0b;
+  } else if (blo < 0) {
+    r.s0b = w.bin_off[bb + blo + c.nphi];
+    r.s0n = w.bin_off[bb + c.nphi] - r.s0b;
+    r.s1b = w.bin_off[bb];
+    r.s1n = w.bin_off[bb + bhi + 1] - r.s1b;
+  } else if (bhi >= c.nphi) {
+    r.s0b = w.bin_off[bb + blo];
+    r.s0n = w.bin_off[bb + c.nphi] - r.s0b;
+    r.s1b = w.bin_off[bb];
+    r.s1n = w.bin_off[bb + bhi - c.nphi + 1] - r.s1b;
+  } else {
+    r.s0b = w.bin_off[bb + blo];
+    r.s0n = w.bin_off[bb + bhi + 1] - r.s0b;
+  }
+  return r;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_mask() {
+  const uint32_t grp = lane_id() / G;
+  return G == 64 ? ~0ull : ((1ull << (G % 64)) - 1ull) << (grp * G);
+}
+
+// The tiles (one round of a block's lane groups: blockDim/G consecutive
+// inner hits) a block visits: each XCD owns a contiguous eighth of the
+// tiles (its events stay in its L2) and its blocks take them in turn, so
+// every block meets hits of all layers (the inner layers have several
+// times the doublets of the outer ones).
+struct TileWalk {
+  uint32_t t, end, step;
+};
+
+__device__ __forceinline__ TileWalk tile_walk(uint32_t ntiles) {
+  if (gridDim.x % 8u) return TileWalk{blockIdx.x, ntiles, gridDim.x};
+  const uint32_t x = blockIdx.x % 8u, per = (ntiles + 7u) / 8u;
+  return TileWalk{x * per + blockIdx.x / 8u, min(ntiles, (x + 1u) * per), gridDim.x / 8u};
+}
+
+// Visits the candidates of inner hit g with its lane group (inactive groups
+// visit none) and calls round(ok, j, hi, ho, bal, cnt) once per round of G
+// candidates with the whole wavefront: ok = lane's candidate j passes the
+// doublet cuts, bal = the wavefront's ballot of ok, cnt = the group's
+// accepted doublets before this round.  Returns the group's total.  The
+// cuts take early exits: fewer instructions than evaluating every cut on
+// every lane, which is what counts with several batches sharing the GPU.
+template <int G, typename F>
+__device__ __forceinline__ uint32_t visit_doublets(const Ws& w, const DevCfg& c, bool active,
+                                                   uint32_t g, F&& round) {
+  const uint32_t sub = lane_id() % G;
+  const uint64_t gmask = group_mask<G>();
+  int li = 0, npairs = 0;
+  uint32_t e = 0;
+  HitD hi{0.0, 0.0, 0.0, 0.0};
+  float ri = 0.0f, phi = 0.0f;
+  if (active) {
+    li = w.blay[g];
+    e = w.bevt[g];
+    hi = load_hit(w, g);
+    ri = (float)hi.r;
+    phi = w.bphi[g];
+    npairs = c.n_outer[li];
+  }
+  const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
+  uint32_t cnt = 0;
+  for (uint32_t p = 0; __any((int)p < npairs); ++p) {
+    PairWin pw{0u, 0u, 0u, 0u};
+    if (active && (int)p < npairs) pw = pair_window(w, c, e, c.outer[li][p], ri, phi, ai);
+    const uint32_t tot = pw.s0n + pw.s1n;
+    for (uint32_t it = 0; __any(it * G < tot); ++it) {
+      const uint32_t k = it * G + sub;
+      const bool valid = k < tot;
+      const uint32_t j = valid ? (k < pw.s0n ? pw.s0b + k : pw.s1b + (k - pw.s0n)) : 0u;
+      HitD ho{0.0, 0.0, 0.0, 0.0};
+      bool ok = false;
+      if (valid) {
+        ho = load_hit(w, j);
+        ok = doublet_ok_fast(c, hi, ho);
+      }
+      const uint64_t bal = __ballot(ok);
+      round(ok, j, hi, ho, bal, cnt);
+      cnt += (uint32_t)__popcll(bal & gmask);
+    }
+  }
+  return cnt;
+}
+
+// The per-doublet arrays written when doublet q = (g, j) is stored; the
+// outer hit's own doublet range (cb, cdeg) is filled by the link kernels.
+__device__ __forceinline__ void store_doublet(Ws& w, const DevCfg& c, uint32_t q, uint32_t g,
+                                              uint32_t j, const HitD& hi, const HitD& ho) {
+  w.cin[q] = g;
+  w.cout[q] = j;
+  w.has_inner[q] = 0;
+  if (c.link_kernel == 1) w.nout[q] = 0;
+  const float th = rz_angle(hi, ho);
+  w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, th);
+  w.th[q] = th;
+}
+
+// Link-mask words of the largest out-degree: C_WSTRIDE is raised only when
+// a block needs more than it already holds (a coherent load first), so the
+// blocks do not all contend for one address.
+__device__ __forceinline__ void raise_stride(Ws& w, uint32_t words) {
+  if (words > __hip_atomic_load(&w.ctr[C_WSTRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&w.ctr[C_WSTRIDE], words);
+}
+
+// Two passes: count (dcnt, then a scan gives cell_off) and fill, each
+// evaluating the cuts.
 template <int G, bool FILL>
 __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
   const uint32_t* ctr = w.ctr;
@@ -322,114 +461,26 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
     }
     return;
   }
-  const uint32_t lane = lane_id(), sub = lane % G, grp = lane / G;
-  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G % 64)) - 1ull) << (grp * G);
-  const uint64_t below = gmask & ((1ull << lane) - 1ull);
+  const uint32_t lane = lane_id(), sub = lane % G;
+  const uint64_t below = group_mask<G>() & ((1ull << lane) - 1ull);
   const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
-  const uint32_t chunk = (nb + gridDim.x - 1) / gridDim.x;
-  const uint32_t beg = min(nb, xcd_block() * chunk), end = min(nb, beg + chunk);
   uint32_t wneed = 0;  // count pass: link-mask words of the largest out-degree
-  for (uint32_t base = beg; base < end; base += gpb) {
-    const uint32_t g = base + gib;
-    const bool active = g < end;
-    int li = 0, npairs = 0;
-    uint32_t e = 0;
-    HitD hi{0.0, 0.0, 0.0, 0.0};
-    float ri = 0.0f, phi = 0.0f;
-    if (active) {
-      li = w.blay[g];
-      e = w.bevt[g];
-      hi = load_hit(w, g);
-      ri = (float)hi.r;
-      phi = w.bphi[g];
-      npairs = c.n_outer[li];
-    }
-    const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
-    uint32_t cnt = 0;
-    uint32_t pos = (FILL && active) ? w.cell_off[g] : 0u;
-    for (uint32_t p = 0; __any((int)p < npairs); ++p) {
-      uint32_t s0b = 0, s0n = 0, s1b = 0, s1n = 0;
-      if (active && (int)p < npairs) {
-        const int lo = c.outer[li][p];
-        const uint32_t el = e * (uint32_t)c.n_layers + (uint32_t)lo;
-        const float rmo = __uint_as_float(w.rmax[el]) * 1.000001f;
-        if (rmo > ri * 0.999999f) {
-          const uint32_t bb = el * (uint32_t)c.nphi;
-          const float ao = w.rasin[el];
-          int blo = 0, bhi = c.nphi - 1;
-          bool full = !(ao < __builtin_huge_valf());
-          if (!full) {
-            const float W = ao - ai;
-            if (!(W >= 0.0f && W < 4.0f && phi >= -4.0f && phi <= 4.0f)) {
-              full = true;  // non-finite input: fall back to the whole layer
-            } else {
-              blo = (int)floorf((phi - W + kPiF) * c.phi_scale) - 1;
-              bhi = (int)floorf((phi + W + kPiF) * c.phi_scale) + 1;
-              full = bhi - blo + 1 >= c.nphi;
-            }
-          }
-          if (full) {
-            s0b = w.bin_off[bb];
-            s0n = w.bin_off[bb + c.nphi] - s0b;
-          } else if (blo < 0) {
-            s0b = w.bin_off[bb + blo + c.nphi];
-            s0n = w.bin_off[bb + c.nphi] - s0b;
-            s1b = w.bin_off[bb];
-            s1n = w.bin_off[bb + bhi + 1] - s1b;
-          } else if (bhi >= c.nphi) {
-            s0b = w.bin_off[bb + blo];
-            s0n = w.bin_off[bb + c.nphi] - s0b;
-            s1b = w.bin_off[bb];
-            s1n = w.bin_off[bb + bhi - c.nphi + 1] - s1b;
-          } else {
-            s0b = w.bin_off[bb + blo];
-            s0n = w.bin_off[bb + bhi + 1] - s0b;
-          }
-        }
-      }
-      const uint32_t tot = s0n + s1n;
-      for (uint32_t it = 0; __any(it * G < tot); ++it) {
-        const uint32_t k = it * G + sub;
-        const bool valid = k < tot;
-        // the cuts with early exits: fewer instructions than evaluating
-        // every cut on every lane, which is what counts with several
-        // batches sharing the GPU
-        const uint32_t j = valid ? (k < s0n ? s0b + k : s1b + (k - s0n)) : beg;
-        HitD ho{0.0, 0.0, 0.0, 0.0};
-        bool ok = false;
-        if (valid) {
-          ho = load_hit(w, j);
-          ok = doublet_ok_fast(c, hi, ho);
-        }
-        const uint64_t bal = __ballot(ok);
-        if (FILL) {
-          if (ok) {
-            const uint32_t q = pos + (uint32_t)__popcll(bal & below);
-            w.cin[q] = g;
-            w.cout[q] = j;
-            const uint32_t jb = w.cell_off[j];
-            w.cb[q] = jb;
-            w.cdeg[q] = w.cell_off[j + 1] - jb;
-          w.has_inner[q] = 0;
-            if (c.link_kernel == 1) w.nout[q] = 0;
-            const float th = rz_angle(hi, ho);
-            w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, th);
-            w.th[q] = th;
-          }
-        }
-        const uint32_t ng = (uint32_t)__popcll(bal & gmask);
-        pos += ng;
-        cnt += ng;
-      }
-    }
+  for (TileWalk tw = tile_walk((nb + gpb - 1) / gpb); tw.t < tw.end; tw.t += tw.step) {
+    const uint32_t g = tw.t * gpb + gib;
+    const bool active = g < nb;
+    const uint32_t pos = (FILL && active) ? w.cell_off[g] : 0u;
+    const uint32_t cnt = visit_doublets<G>(
+        w, c, active, g,
+        [&](bool ok, uint32_t j, const HitD& hi, const HitD& ho, uint64_t bal, uint32_t before) {
+          if (FILL && ok)
+            store_doublet(w, c, pos + before + (uint32_t)__popcll(bal & below), g, j, hi, ho);
+        });
     if (!FILL) {
       if (active && sub == 0) w.dcnt[g] = cnt;
       wneed = max(wneed, (cnt + 63u) >> 6);
     }
   }
   if (!FILL) {
-    // link-mask stride: words for the largest out-degree of the batch, one
-    // atomic per block
     __shared__ uint32_t s_w[256 / kWave];
     const uint32_t wm = wave_max(wneed);
     if (lane == 0) s_w[threadIdx.x / kWave] = wm;
@@ -437,7 +488,249 @@ __global__ __launch_bounds__(256) void k_doublets(Ws w, DevCfg c) {
     if (threadIdx.x == 0) {
       uint32_t m = 0;
       for (uint32_t i = 0; i < blockDim.x / kWave; ++i) m = max(m, s_w[i]);
-      if (m) atomicMax(&w.ctr[C_WSTRIDE], m);
+      if (m) raise_stride(w, m);
+    }
+  }
+}
+
+// One pass: the cuts are evaluated once.  A tile is one round of the
+// block's lane groups (blockDim/G consecutive inner hits); tiles are taken
+// from a ticket and chained by decoupled look-back, like the scan tiles.
+// Accepted candidates are staged in an LDS pool of 32-bit records
+// (hit of the tile: 6 bits, index among that hit's doublets: 9 bits, outer
+// hit relative to the first binned hit of its event: 17 bits); once the
+// first wavefront has scanned the tile's per-hit counts and taken the
+// tile's offset, every record is written to offset + the hit's exclusive
+// count + its index, the same layout as the two-pass kernels.  A tile whose
+// records do not fit (pool full, a hit with 512 doublets or more, an event
+// of 2^17 binned hits or more) evaluates its cuts again and writes in place.
+constexpr uint32_t kPoolKBits = 9, kPoolJBits = 17;
+constexpr uint32_t kPoolRecords = 4096;  // LDS pool of the one-pass kernel (16 KB)
+constexpr uint32_t kDoubletScan = 1;     // scan id of the doublet offsets
+
+__device__ __forceinline__ uint32_t pool_record(uint32_t h, uint32_t k, uint32_t jr) {
+  return (h << (kPoolKBits + kPoolJBits)) | (k << kPoolJBits) | jr;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_doublets1(Ws w, DevCfg c) {
+  constexpr uint32_t pool_cap = kPoolRecords;
+  __shared__ uint32_t s_pool[kPoolRecords];
+  __shared__ uint32_t s_cnt[kWave], s_excl[kWave], s_ebase[kWave];
+  __shared__ uint32_t s_n, s_over, s_prefix, s_agg;
+  const uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t nb = ctr[C_NBINNED];
+  const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
+  const uint32_t ntiles = nb ? (nb + gpb - 1) / gpb : 1u;
+  uint32_t tile;
+  if (!take_tile(w, kDoubletScan, ntiles, tile)) return;
+  const uint32_t epoch = w.epoch[0] * 8u + kDoubletScan;
+  const uint32_t lane = lane_id(), sub = lane % G;
+  const uint64_t lbelow = (1ull << lane) - 1ull;
+  const uint64_t below = group_mask<G>() & lbelow;
+  const uint32_t t0 = tile * gpb, g = t0 + gib;
+  const bool active = g < nb;
+  const uint32_t per_ev = (uint32_t)c.n_layers * (uint32_t)c.nphi;
+  if (threadIdx.x == 0) {
+    s_n = 0;
+    s_over = 0;
+  }
+  if (sub == 0) s_ebase[gib] = active ? w.bin_off[w.bevt[g] * per_ev] : 0u;
+  __syncthreads();
+  const uint32_t ebase = s_ebase[gib];
+  const uint32_t cnt = visit_doublets<G>(
+      w, c, active, g,
+      [&](bool ok, uint32_t j, const HitD&, const HitD&, uint64_t bal, uint32_t before) {
+        if (!bal) return;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0);
+        if (ok) {
+          const uint32_t k = before + (uint32_t)__popcll(bal & below);
+          const uint32_t jr = j - ebase;
+          const uint32_t slot = base + (uint32_t)__popcll(bal & lbelow);
+          if (slot < pool_cap && k < (1u << kPoolKBits) && jr < (1u << kPoolJBits))
+            s_pool[slot] = pool_record(gib, k, jr);
+          else
+            s_over = 1;
+        }
+      });
+  if (sub == 0) s_cnt[gib] = active ? cnt : 0u;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const uint32_t v = lane < gpb ? s_cnt[lane] : 0u;
+    const uint32_t inc = wave_incl_scan(v);
+    const uint32_t agg = __shfl(inc, kWave - 1);
+    s_excl[lane] = inc - v;
+    const uint32_t wm = wave_max((v + 63u) >> 6);
+    const uint32_t pf = tile_lookback(w, tile, epoch, agg);
+    if (lane == 0) {
+      s_prefix = pf;
+      s_agg = agg;
+      if (wm) raise_stride(w, wm);
+      if (tile == ntiles - 1) {
+        const uint32_t total = pf + agg;
+        w.cell_off[nb] = total;
+        w.ctr[C_ND] = total;
+        if (total > c.cap_doublets) {
+          set_status(w.ctr, PXT_ERR_CAPACITY);
+          w.ctr[C_REQ_D] = total;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t prefix = s_prefix;
+  if (active && sub == 0) w.cell_off[g] = prefix + s_excl[gib];
+  if (prefix + s_agg > c.cap_doublets) return;  // the call fails with the capacity status
+  if (!s_over) {
+    const uint32_t n = s_n;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t r = s_pool[i];
+      const uint32_t h = r >> (kPoolKBits + kPoolJBits);
+      const uint32_t k = (r >> kPoolJBits) & ((1u << kPoolKBits) - 1u);
+      const uint32_t gi = t0 + h, j = s_ebase[h] + (r & ((1u << kPoolJBits) - 1u));
+      store_doublet(w, c, prefix + s_excl[h] + k, gi, j, load_hit(w, gi), load_hit(w, j));
+    }
+  } else {
+    const uint32_t pos = prefix + s_excl[gib];
+    visit_doublets<G>(
+        w, c, active, g,
+        [&](bool ok, uint32_t j, const HitD& hi, const HitD& ho, uint64_t bal, uint32_t before) {
+          if (ok) store_doublet(w, c, pos + before + (uint32_t)__popcll(bal & below), g, j, hi, ho);
+        });
+  }
+}
+
+// Staged doublets, for large batches: the cuts are evaluated once, without
+// the one-pass kernel's tile-to-tile wait (a tile's count is known only
+// once its cuts are done, so with very uneven tiles resident blocks queue
+// behind a slow one).  k_dstage is the count pass, which also appends every
+// accepted pair, as an 8-byte record (inner hit << 9 | index among its
+// doublets, outer hit), to its wavefront's region of the staging buffer;
+// the scan turns the per-hit counts into offsets; in k_dscatter (same
+// grid) each wavefront writes its region's records to their hit's offset +
+// index.  Wavefronts work alone (a cursor in registers, no block barrier),
+// and the scatter issues the loads of four records per lane before any
+// store.  A wavefront whose records do not fit (region full, an index of
+// 512 or more, an inner hit beyond 2^23) evaluates the cuts of its hits
+// again in the scatter instead.
+constexpr uint32_t kRecKBits = 9, kRecGMax = 1u << 23;
+constexpr uint32_t kRecOver = 0xffffffffu;  // region count of an overflowed wavefront
+
+__device__ __forceinline__ uint2* stage_region(const Ws& w, uint32_t& cap, uint32_t& id) {
+  const uint32_t nw = blockDim.x / kWave;
+  id = blockIdx.x * nw + threadIdx.x / kWave;
+  cap = (w.stage_words / 2u) / (gridDim.x * nw);
+  return reinterpret_cast<uint2*>(w.stage) + (size_t)id * cap;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_dstage(Ws w, DevCfg c) {
+  __shared__ uint32_t s_w[256 / kWave];
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t nb = w.ctr[C_NBINNED];
+  const uint32_t lane = lane_id(), sub = lane % G, wib = threadIdx.x / kWave;
+  const uint64_t lbelow = (1ull << lane) - 1ull;
+  const uint64_t below = group_mask<G>() & lbelow;
+  const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
+  uint32_t cap, id;
+  uint2* reg = stage_region(w, cap, id);
+  uint32_t run = 0, wneed = 0;
+  bool over = false;
+  for (TileWalk tw = tile_walk((nb + gpb - 1) / gpb); tw.t < tw.end; tw.t += tw.step) {
+    const uint32_t g = tw.t * gpb + gib;
+    const bool active = g < nb;
+    const uint32_t cnt = visit_doublets<G>(
+        w, c, active, g,
+        [&](bool ok, uint32_t j, const HitD&, const HitD&, uint64_t bal, uint32_t before) {
+          if (ok) {
+            const uint32_t k = before + (uint32_t)__popcll(bal & below);
+            const uint32_t slot = run + (uint32_t)__popcll(bal & lbelow);
+            if (slot < cap && k < (1u << kRecKBits) && g < kRecGMax)
+              reg[slot] = make_uint2((g << kRecKBits) | k, j);
+            else
+              over = true;
+          }
+          run += (uint32_t)__popcll(bal);
+        });
+    if (active && sub == 0) w.dcnt[g] = cnt;
+    wneed = max(wneed, (cnt + 63u) >> 6);
+  }
+  const bool wover = __any(over);
+  if (lane == 0) w.dwn[id] = wover ? kRecOver : run;
+  const uint32_t wm = wave_max(wneed);
+  if (lane == 0) s_w[wib] = wm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) m = max(m, s_w[i]);
+    if (m) raise_stride(w, m);
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_dscatter(Ws w, DevCfg c) {
+  if (w.ctr[C_STATUS]) return;
+  const uint32_t nb = w.ctr[C_NBINNED];
+  if (w.cell_off[nb] > c.cap_doublets) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      set_status(w.ctr, PXT_ERR_CAPACITY);
+      w.ctr[C_REQ_D] = w.cell_off[nb];
+    }
+    return;
+  }
+  const uint32_t lane = lane_id();
+  uint32_t cap, id;
+  const uint2* reg = stage_region(w, cap, id);
+  const uint32_t n = w.dwn[id];
+  if (n == kRecOver) {
+    // records incomplete: this wavefront's hits evaluate the cuts again
+    const uint64_t below = group_mask<G>() & ((1ull << lane) - 1ull);
+    const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
+    for (TileWalk tw = tile_walk((nb + gpb - 1) / gpb); tw.t < tw.end; tw.t += tw.step) {
+      const uint32_t g = tw.t * gpb + gib;
+      const bool active = g < nb;
+      const uint32_t pos = active ? w.cell_off[g] : 0u;
+      visit_doublets<G>(
+          w, c, active, g,
+          [&](bool ok, uint32_t j, const HitD& hi, const HitD& ho, uint64_t bal,
+              uint32_t before) {
+            if (ok)
+              store_doublet(w, c, pos + before + (uint32_t)__popcll(bal & below), g, j, hi, ho);
+          });
+    }
+    return;
+  }
+  constexpr int U = 4;
+  for (uint32_t i0 = 0; i0 < n; i0 += U * kWave) {
+    uint2 r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+      r[u] = i < n ? reg[i] : make_uint2(0u, 0u);
+    }
+    // every load of the four records before any store (the stores could
+    // alias the loaded arrays as far as the compiler knows)
+    uint32_t q[U];
+    float iz[U];
+    double ir[U];
+    HitD ho[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t g = r[u].x >> kRecKBits;
+      q[u] = w.cell_off[g] + (r[u].x & ((1u << kRecKBits) - 1u));
+      iz[u] = w.bz[g];
+      ir[u] = w.br[g];
+      ho[u] = load_hit(w, r[u].y);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + (uint32_t)u * kWave + lane < n) {
+        const HitD hi{0.0, 0.0, (double)iz[u], ir[u]};
+        store_doublet(w, c, q[u], r[u].x >> kRecKBits, r[u].y, hi, ho[u]);
+      }
     }
   }
 }
@@ -467,6 +760,20 @@ __device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c) {
     }
   }
   return ok;
+}
+
+// Candidate range of doublet d: the doublets leaving its outer hit, from
+// the per-hit offsets; stored in cb/cdeg (by one lane when `store`) for the
+// n-tuplet search.
+__device__ __forceinline__ void outer_range(Ws& w, uint32_t d, bool store, uint32_t& kb,
+                                            uint32_t& deg) {
+  const uint32_t j = w.cout[d];
+  kb = w.cell_off[j];
+  deg = w.cell_off[j + 1] - kb;
+  if (store) {
+    w.cb[d] = kb;
+    w.cdeg[d] = deg;
+  }
 }
 
 // One thread per doublet (a,b), looping over its candidates with the
@@ -526,8 +833,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     float ax = 0.f, ay = 0.f, az = 0.f;
     if (d < nd) {
       const uint32_t a = w.cin[d];
-      k0 = w.cb[d];
-      deg = w.cdeg[d];
+      outer_range(w, d, true, k0, deg);
       ob = w.oh[d];
       ax = w.bx[a];
       ay = w.by[a];
@@ -604,16 +910,16 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
 // (pre-cleared) mask word with atomicOr and count into nout.
 
 
-__device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint2* q, uint32_t n,
+__device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint3* q, uint32_t n,
                                             uint32_t& links) {
   const uint32_t lane = lane_id();
   if (lane < n) {
-    const uint2 it = q[lane];
+    const uint3 it = q[lane];
     const uint32_t d = it.x, k = it.y;
     const HitD ha = load_hit(w, w.cin[d]);
     const float4 ob = w.oh[d];
     const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
-    const uint32_t d2 = w.cb[d] + k;
+    const uint32_t d2 = it.z;
     const float4 oc = w.oh[d2];
     const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
@@ -629,26 +935,23 @@ __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint2*
 template <int G>
 __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
   constexpr int U = kWave / G;
-  __shared__ uint2 queue[256 / kWave][kQueue];
+  __shared__ uint3 queue[256 / kWave][kQueue];  // (doublet, candidate index, candidate)
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
   if (!links_capacity(w, c)) return;
   const uint32_t lane = lane_id(), sub = lane % G;
-  uint2* q = queue[threadIdx.x / kWave];
+  uint3* q = queue[threadIdx.x / kWave];
   const uint64_t below = (1ull << lane) - 1ull;
   const uint32_t gpb = blockDim.x / G, gib = threadIdx.x / G;
-  const uint32_t chunk = (nd + gridDim.x - 1) / gridDim.x;
-  const uint32_t beg = min(nd, xcd_block() * chunk), end = min(nd, beg + chunk);
   uint32_t links = 0, qn = 0;
-  for (uint32_t base = beg; base < end; base += gpb) {
-    const uint32_t d = base + gib;
+  for (TileWalk tw = tile_walk((nd + gpb - 1) / gpb); tw.t < tw.end; tw.t += tw.step) {
+    const uint32_t d = tw.t * gpb + gib;
     uint32_t kb = 0, deg = 0;
     float ta = 0.0f;
-    if (d < end) {
+    if (d < nd) {
       ta = w.th[d];
-      kb = w.cb[d];
-      deg = w.cdeg[d];
+      outer_range(w, d, sub == 0, kb, deg);
     }
     const uint32_t maxw = wave_max((deg + 63u) / 64u);
     for (uint32_t wd = 0; wd < maxw; ++wd) {
@@ -663,14 +966,14 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
         const uint32_t k = wd * 64u + (uint32_t)(u * G) + sub;
         const bool ok = k < deg && rz_prefilter(c, ta, tc[u]);
         const uint64_t bal = __ballot(ok);
-        if (ok) q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(d, k);
+        if (ok) q[qn + (uint32_t)__popcll(bal & below)] = make_uint3(d, k, kb + k);
         qn += (uint32_t)__popcll(bal);
         if (qn >= (uint32_t)kWave) {
           __threadfence_block();
           links_flush(w, c, q, kWave, links);
           __threadfence_block();
           const uint32_t rest = qn - kWave;
-          const uint2 mv = lane < rest ? q[kWave + lane] : make_uint2(0, 0);
+          const uint3 mv = lane < rest ? q[kWave + lane] : make_uint3(0, 0, 0);
           __threadfence_block();
           if (lane < rest) q[lane] = mv;
           __threadfence_block();
@@ -724,10 +1027,15 @@ __device__ __forceinline__ void wave_links_flush(Ws& w, const DevCfg& c, const W
     const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       const unsigned long long bit = 1ull << (kk & 63u);
+      // LDS at workgroup scope, device memory at agent scope: two distinct
+      // atomics (merged into one on a generic pointer they would need an
+      // aperture check, which the gfx950 backend mis-encodes)
       if (staged)
-        atomicOr((unsigned long long*)&L.sm[wo + (kk >> 6)], bit);
+        __hip_atomic_fetch_or((unsigned long long*)&L.sm[wo + (kk >> 6)], bit, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
       else
-        atomicOr((unsigned long long*)&w.masks[(size_t)(kk >> 6) * w.ctr[C_ND] + moo], bit);
+        __hip_atomic_fetch_or((unsigned long long*)&w.masks[(size_t)(kk >> 6) * w.ctr[C_ND] + moo],
+                              bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       atomicAdd(&L.cnt[own], 1u);
       w.has_inner[d2] = 1;
       ++links;
@@ -755,8 +1063,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
     float4 ob = make_float4(0.f, 0.f, 0.f, 0.f);
     if (d < nd) {
       a = w.cin[d];
-      kb = w.cb[d];
-      deg = w.cdeg[d];
+      outer_range(w, d, true, kb, deg);
       ob = w.oh[d];
       mo = d;
     }
@@ -784,9 +1091,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
       const uint32_t kk = k - __shfl(cex, (int)own);
       const uint32_t kbo = __shfl(kb, (int)own);
       const float tao = __shfl(ob.w, (int)own);
-      // (this kernel reads the angle from the float4: the compact-array load
-      // here makes the gfx950 backend emit an invalid instruction)
-      const bool pass = k < C && rz_prefilter(c, tao, w.oh[kbo + kk].w);
+      const bool pass = k < C && rz_prefilter(c, tao, w.th[kbo + kk]);
       const uint64_t bal = __ballot(pass);
       if (pass) L.q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(own, kk);
       qn += (uint32_t)__popcll(bal);

@@ -91,7 +91,9 @@ size_t scan_tiles(const pxt_config& c) {
   const size_t nbins = (size_t)c.max_events * (size_t)c.n_layers * (size_t)c.phi_bins;
   const size_t n = std::max({nbins, (size_t)c.max_hits, (size_t)c.max_doublets,
                              (size_t)c.max_tuples});
-  return (n + kTile - 1) / kTile + 1;
+  // single-pass doublets: one tile per blockDim/group_lanes binned hits
+  const size_t gpb = (size_t)std::max(1, c.block_size / std::max(1, c.group_lanes));
+  return std::max((n + kTile - 1) / kTile + 1, (size_t)c.max_hits / gpb + 2);
 }
 
 void carve(Carver& cv, const pxt_config& c, Ws& w) {
@@ -142,6 +144,15 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.bcnt = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
   w.bbase = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
   w.fp64_list = cv.take<uint32_t>(T);
+  // the staging buffer of the doublets spans roots .. fp64_list
+  w.stage = w.roots;
+  w.stage_words = cv.base ? (uint32_t)std::min<size_t>(
+                                 (size_t)(reinterpret_cast<char*>(w.fp64_list + T) -
+                                          reinterpret_cast<char*>(w.roots)) /
+                                     sizeof(uint32_t),
+                                 0xfffffffeu)
+                           : 0u;
+  w.dwn = cv.take<uint32_t>((size_t)kCompactBlocksMax * (256 / kWave));
   w.scan_status = cv.take<uint64_t>(scan_tiles(c));
   w.epoch = cv.take<uint32_t>(1);
 }
@@ -181,6 +192,7 @@ int validate_config(const pxt_config* c, std::string& why) {
     return why = "group_lanes must be 4, 8, 16, 32 or 64", 1;
   if (c->link_kernel < 0 || c->link_kernel > 2) return why = "link_kernel must be 0, 1 or 2", 1;
   if (c->use_graph != 0 && c->use_graph != 1) return why = "use_graph must be 0 or 1", 1;
+  if (c->doublet_mode < 0 || c->doublet_mode > 2) return why = "doublet_mode must be 0, 1 or 2", 1;
   return 0;
 }
 
@@ -285,6 +297,18 @@ void launch_doublets(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, c
   }
 }
 
+// kernel template over the group width
+#define PXT_LAUNCH_G(K, G, grid, block, s, ...)                                  \
+  do {                                                                           \
+    switch (G) {                                                                 \
+      case 4: hipLaunchKernelGGL((K<4>), grid, block, 0, s, __VA_ARGS__); break;   \
+      case 8: hipLaunchKernelGGL((K<8>), grid, block, 0, s, __VA_ARGS__); break;   \
+      case 16: hipLaunchKernelGGL((K<16>), grid, block, 0, s, __VA_ARGS__); break; \
+      case 64: hipLaunchKernelGGL((K<64>), grid, block, 0, s, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((K<32>), grid, block, 0, s, __VA_ARGS__); break; \
+    }                                                                            \
+  } while (0)
+
 void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, const DevCfg& d) {
   if (d.link_kernel == 0) {
     hipLaunchKernelGGL(k_links_thread, grid, block, 0, s, w, d);
@@ -339,13 +363,28 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
                        dim3(256), 0, s, w, d);
     const int G = cfg.group_lanes;
-    const uint32_t gh = grid_chunked(H, bs, G, persist);
-    if (timed) sm.mark(4);
-    launch_doublets<false>(G, dim3(gh), dim3(bs), s, w, d);
-    if (timed) sm.mark(5);
-    launch_scan1(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, H, 1, s);
-    if (timed) sm.mark(6);
-    launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
+    const uint32_t gh = grid_chunked(H, bs, G, std::min<uint32_t>(persist, kCompactBlocksMax));
+    if (cfg.doublet_mode == 1) {
+      // one pass (its time shows under doublet_fill)
+      const uint32_t gpb = (uint32_t)(bs / G);
+      if (timed) sm.mark(6);
+      PXT_LAUNCH_G(k_doublets1, G,
+                   dim3((uint32_t)std::max<uint64_t>(1, ((uint64_t)H + gpb - 1) / gpb)), dim3(bs),
+                   s, w, d);
+    } else {
+      if (timed) sm.mark(4);
+      if (cfg.doublet_mode == 2)
+        PXT_LAUNCH_G(k_dstage, G, dim3(gh), dim3(bs), s, w, d);
+      else
+        launch_doublets<false>(G, dim3(gh), dim3(bs), s, w, d);
+      if (timed) sm.mark(5);
+      launch_scan1(w, w.dcnt, w.cell_off, w.ctr + C_NBINNED, w.ctr + C_ND, H, kDoubletScan, s);
+      if (timed) sm.mark(6);
+      if (cfg.doublet_mode == 2)
+        PXT_LAUNCH_G(k_dscatter, G, dim3(gh), dim3(bs), s, w, d);
+      else
+        launch_doublets<true>(G, dim3(gh), dim3(bs), s, w, d);
+    }
     if (timed) sm.mark(7);
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
     if (cfg.link_kernel == 1) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
@@ -436,6 +475,7 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->group_lanes = 16;
   cfg->link_kernel = 0;
   cfg->use_graph = 0;
+  cfg->doublet_mode = 2;
   cfg->pt_fp64 = 20.0;
   return PXT_OK;
 }

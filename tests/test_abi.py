@@ -28,7 +28,7 @@ def test_header_symbols_exported():
 
 def test_version_and_status_strings():
     L = pxt.lib()
-    assert L.pxt_abi_version() == 1
+    assert L.pxt_abi_version() == pxt.ABI_VERSION == 2
     assert L.pxt_status_str(0) == b"ok"
     assert L.pxt_status_str(2) == b"capacity exceeded"
     assert L.pxt_status_str(99) == b"unknown status"
@@ -38,7 +38,7 @@ def test_config_defaults_and_validation():
     L = pxt.lib()
     c = pxt.PxtConfig()
     assert L.pxt_config_defaults(ctypes.byref(c)) == 0
-    assert c.phi_bins == 256 and c.block_size == 256
+    assert c.phi_bins == 256 and c.block_size == 256 and c.doublet_mode == 2
     assert L.pxt_config_defaults(None) == pxt.ERR_INVALID_ARG
     h = ctypes.c_void_p()
     # physics fields zeroed: rejected before any device call
@@ -46,7 +46,8 @@ def test_config_defaults_and_validation():
     assert b"c_kappa" in L.pxt_last_error(None)
     good = pxt.make_config(eventgen.DETECTOR)
     for field, bad in (("phi_bins", 8), ("block_size", 100), ("n_layers", 0), ("max_hits", 0),
-                       ("arz", 0.0), ("pt_fp64", -1.0)):
+                       ("arz", 0.0), ("pt_fp64", -1.0), ("doublet_mode", 3),
+                       ("doublet_mode", -1)):
         c2 = pxt.make_config(eventgen.DETECTOR)
         setattr(c2, field, bad)
         assert L.pxt_create(ctypes.byref(c2), 0, ctypes.byref(h)) == pxt.ERR_INVALID_ARG, field
@@ -74,9 +75,9 @@ def test_struct_sizes_match_header():
 #include <stddef.h>
 #include "pxt.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pxt_config), offsetof(pxt_config, pt_fp64),
-         offsetof(pxt_config, group_lanes), sizeof(pxt_hits), sizeof(pxt_tracks),
-         sizeof(pxt_counts));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(pxt_config), offsetof(pxt_config, pt_fp64),
+         offsetof(pxt_config, group_lanes), offsetof(pxt_config, doublet_mode),
+         sizeof(pxt_hits), sizeof(pxt_tracks), sizeof(pxt_counts));
   return 0;
 }
 '''
@@ -87,7 +88,8 @@ int main(void) {
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
         got = list(map(int, subprocess.check_output([exe]).split()))
     want = [ctypes.sizeof(pxt.PxtConfig), pxt.PxtConfig.pt_fp64.offset,
-            pxt.PxtConfig.group_lanes.offset, ctypes.sizeof(pxt.PxtHits),
+            pxt.PxtConfig.group_lanes.offset, pxt.PxtConfig.doublet_mode.offset,
+            ctypes.sizeof(pxt.PxtHits),
             ctypes.sizeof(pxt.PxtTracks), ctypes.sizeof(pxt.PxtCounts)]
     assert got == want
 

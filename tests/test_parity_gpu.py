@@ -145,17 +145,15 @@ def test_batch_equivalence(torch):
             np.testing.assert_array_equal(alone[2], other[2])
 
 
-@pytest.mark.parametrize("phi_bins,block,group,lk", [(16, 256, 16, 0), (64, 64, 64, 1),
-                                                     (1024, 128, 32, 1), (4096, 256, 16, 1),
-                                                     (256, 192, 64, 0), (256, 64, 16, 0),
-                                                     (256, 256, 16, 2), (128, 64, 32, 2),
-                                                     (512, 192, 16, 2), (256, 256, 8, 0),
-                                                     (64, 128, 8, 1), (128, 256, 4, 0)])
-def test_tuning_invariance(torch, phi_bins, block, group, lk):
+@pytest.mark.parametrize("phi_bins,block,group,lk,mode", [
+    (16, 256, 16, 0, 0), (64, 64, 64, 1, 1), (1024, 128, 32, 1, 2), (4096, 256, 16, 1, 0),
+    (256, 192, 64, 0, 2), (256, 64, 16, 0, 1), (256, 256, 16, 2, 0), (128, 64, 32, 2, 1),
+    (512, 192, 16, 2, 2), (256, 256, 8, 0, 0), (64, 128, 8, 1, 1), (128, 256, 4, 0, 1)])
+def test_tuning_invariance(torch, phi_bins, block, group, lk, mode):
     events = [eventgen.generate("pu50", 55), eventgen.generate("tiny", 3)]
     ref = _tracks_by_event(make_rec().run_numpy(events).numpy(), 2)
     got = _tracks_by_event(make_rec(phi_bins=phi_bins, block_size=block, group_lanes=group,
-                                    link_kernel=lk).run_numpy(events).numpy(), 2)
+                                    link_kernel=lk, doublet_mode=mode).run_numpy(events).numpy(), 2)
     for a, b in zip(ref, got):
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
@@ -218,6 +216,41 @@ def test_dense_middle_hit(torch, lk):
     check_events(events, res, out, dumps)
 
 
+def _runs_are_grouped(rows):
+    # rows (event, inner hit, outer hit) in device order: every inner hit's
+    # doublets form one contiguous run
+    key = rows[:, 0].astype(np.int64) * (1 << 32) + rows[:, 1]
+    starts = np.concatenate([[True], key[1:] != key[:-1]])
+    return np.unique(key).size == int(starts.sum())
+
+
+@pytest.mark.parametrize("group,block", [(4, 256), (8, 256), (16, 128), (64, 64)])
+def test_doublet_modes(torch, group, block):
+    # the one-pass and staged doublet kernels, from their records and from
+    # their recompute paths (the dense hit's 600 doublets exceed the
+    # record's 9-bit index, so its tile or block evaluates the cuts again),
+    # give the two-pass results: doublets grouped by inner hit, and the same
+    # doublets, links, n-tuplets and tracks.  (Hits within a phi bin are
+    # binned in arrival order, so the raw order varies from run to run.)
+    events = [eventgen.generate("pu50", 21), _dense_middle_event(), eventgen.generate("tiny", 5)]
+    n = len(events)
+    ref = None
+    for mode in (0, 1, 2):
+        rec = make_rec(group_lanes=group, block_size=block, doublet_mode=mode)
+        res, out, dumps = run_and_dump(rec, events)
+        assert _runs_are_grouped(np.asarray(dumps["d"]).reshape(-1, 3)), mode
+        if ref is None:
+            check_events(events, res, out, dumps)
+            ref = ({k: per_event_rows(dumps[k], n) for k in ("d", "l", "r")},
+                   _tracks_by_event(out, n))
+            continue
+        for k in ("d", "l", "r"):
+            for e, (a, b) in enumerate(zip(ref[0][k], per_event_rows(dumps[k], n))):
+                np.testing.assert_array_equal(a, b, err_msg="%s ev%d mode %d" % (k, e, mode))
+        for a, b in zip(ref[1], _tracks_by_event(out, n)):
+            np.testing.assert_array_equal(a[0], b[0])
+
+
 def test_capacity_overflow_and_retry(torch):
     import paper_2104_06573_amd as pxt
     events = [eventgen.generate("pu50", 9)]
@@ -235,6 +268,9 @@ def test_capacity_overflow_and_retry(torch):
         assert r.counts["status"] == pxt.ERR_CAPACITY, (caps, r.counts)
         assert r.counts["required"][idx] == need, (caps, r.counts)
         assert r.counts["n_tracks"] == 0
+    for mode in (0, 1):  # the two-pass and one-pass kernels (mode 2 above)
+        r = make_rec(max_doublets=nd - 1, doublet_mode=mode).run_numpy(events)
+        assert r.counts["status"] == pxt.ERR_CAPACITY and r.counts["required"][0] == nd, r.counts
     rec = make_rec(max_doublets=nd, max_tuples=nt, max_tracks=nk)
     r = rec.run_numpy(events)
     assert r.counts["status"] == 0 and r.counts["n_tracks"] == nk
