@@ -403,10 +403,29 @@ __device__ __forceinline__ uint32_t visit_doublets(const Ws& w, const DevCfg& c,
     npairs = c.n_outer[li];
   }
   const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
+  // the windows of all pairs at once, lane sub of the group computing pairs
+  // sub, sub + G, ... (their loads in flight together); the pair loop takes
+  // them from that lane
+  constexpr int NP = (kMaxOuterPerLayer + G - 1) / G;
+  PairWin pws[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int p = (int)sub + u * G;
+    pws[u] = PairWin{0u, 0u, 0u, 0u};
+    if (active && p < npairs) pws[u] = pair_window(w, c, e, c.outer[li][p], ri, phi, ai);
+  }
+  const int gl = (int)(lane_id() - sub);  // the group's first lane
   uint32_t cnt = 0;
   for (uint32_t p = 0; __any((int)p < npairs); ++p) {
-    PairWin pw{0u, 0u, 0u, 0u};
-    if (active && (int)p < npairs) pw = pair_window(w, c, e, c.outer[li][p], ri, phi, ai);
+    const uint32_t u = p / G;
+    PairWin src = pws[0];
+#pragma unroll
+    for (int x = 1; x < NP; ++x)
+      if (u == (uint32_t)x) src = pws[x];
+    const int from = gl + (int)(p % G);
+    PairWin pw{(uint32_t)__shfl((int)src.s0b, from), (uint32_t)__shfl((int)src.s0n, from),
+               (uint32_t)__shfl((int)src.s1b, from), (uint32_t)__shfl((int)src.s1n, from)};
+    if (!(active && (int)p < npairs)) pw = PairWin{0u, 0u, 0u, 0u};
     const uint32_t tot = pw.s0n + pw.s1n;
     for (uint32_t it = 0; __any(it * G < tot); ++it) {
       const uint32_t k = it * G + sub;
@@ -1376,27 +1395,52 @@ __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
 
 // Per-block places of every length in the fitting order: length k takes
 // the range after all shorter lengths, and within it the blocks follow in
-// block order.  One wavefront per length scans the blocks' counts.
-__global__ __launch_bounds__(kFitKeys * kWave) void k_fitbase(Ws w, uint32_t nblocks) {
+// block order.  One block of kFitBaseThreads: each thread sums the counts
+// of a few consecutive blocks, a scan per length over the threads (within
+// wavefronts, then over the wavefront totals) gives their places.
+constexpr int kFitBaseThreads = 1024;
+
+__global__ __launch_bounds__(kFitBaseThreads) void k_fitbase(Ws w, uint32_t nblocks) {
+  constexpr uint32_t NW = kFitBaseThreads / kWave;
+  __shared__ uint32_t s_wsum[kFitKeys][NW];
   __shared__ uint32_t s_tot[kFitKeys];
   if (w.ctr[C_STATUS]) return;
-  const uint32_t k = threadIdx.x / kWave, lane = lane_id();
-  uint32_t run = 0;
-  for (uint32_t b0 = 0; b0 < nblocks; b0 += kWave) {
-    const uint32_t b = b0 + lane;
-    const uint32_t v = b < nblocks ? w.bcnt[(size_t)b * kFitKeys + k] : 0u;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+  const uint32_t per = (nblocks + kFitBaseThreads - 1) / kFitBaseThreads;
+  const uint32_t b0 = min(nblocks, tid * per), b1 = min(nblocks, b0 + per);
+  uint32_t excl[kFitKeys];  // the thread's place within its wavefront, per length
+#pragma unroll
+  for (int k = 3; k < kFitKeys; ++k) {
+    uint32_t v = 0;
+    for (uint32_t b = b0; b < b1; ++b) v += w.bcnt[(size_t)b * kFitKeys + k];
     const uint32_t inc = wave_incl_scan(v);
-    if (b < nblocks) w.bbase[(size_t)b * kFitKeys + k] = run + inc - v;
-    run += __shfl(inc, kWave - 1);
+    excl[k] = inc - v;
+    if (lane == kWave - 1) s_wsum[k][wid] = inc;
   }
-  if (lane == 0) s_tot[k] = run;
   __syncthreads();
-  uint32_t off = 0;
-  for (uint32_t i = 0; i < k; ++i) off += s_tot[i];
-  for (uint32_t b = lane; b < nblocks; b += kWave) w.bbase[(size_t)b * kFitKeys + k] += off;
-  if (lane == 0) {
-    w.ctr[C_FITN0 + k] = run;
-    w.ctr[C_FITO0 + k] = off;
+  if (tid >= 3 && tid < kFitKeys) {
+    uint32_t run = 0;
+    for (uint32_t i = 0; i < NW; ++i) {
+      const uint32_t t = s_wsum[tid][i];
+      s_wsum[tid][i] = run;
+      run += t;
+    }
+    s_tot[tid] = run;
+  }
+  __syncthreads();
+  uint32_t off = 0;  // lengths below k come first
+#pragma unroll
+  for (int k = 3; k < kFitKeys; ++k) {
+    uint32_t run = off + s_wsum[k][wid] + excl[k];
+    for (uint32_t b = b0; b < b1; ++b) {
+      w.bbase[(size_t)b * kFitKeys + k] = run;
+      run += w.bcnt[(size_t)b * kFitKeys + k];
+    }
+    if (tid == 0) {
+      w.ctr[C_FITN0 + k] = s_tot[k];
+      w.ctr[C_FITO0 + k] = off;
+    }
+    off += s_tot[k];
   }
 }
 

@@ -415,7 +415,7 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
       const uint32_t gc = std::min<uint32_t>(grid_for(cfg.max_tuples, 256, persist),
                                              kCompactBlocksMax);
       hipLaunchKernelGGL(k_compact, dim3(gc), dim3(256), 0, s, w, d);
-      hipLaunchKernelGGL(k_fitbase, dim3(1), dim3((kMaxHits + 1) * kWave), 0, s, w, gc);
+      hipLaunchKernelGGL(k_fitbase, dim3(1), dim3(kFitBaseThreads), 0, s, w, gc);
       hipLaunchKernelGGL(k_fitorder, dim3(gc), dim3(256), 0, s, w);
     }
     if (timed) sm.mark(16);
