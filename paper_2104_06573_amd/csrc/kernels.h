@@ -427,16 +427,32 @@ __device__ __forceinline__ uint32_t visit_doublets(const Ws& w, const DevCfg& c,
                (uint32_t)__shfl((int)src.s1b, from), (uint32_t)__shfl((int)src.s1n, from)};
     if (!(active && (int)p < npairs)) pw = PairWin{0u, 0u, 0u, 0u};
     const uint32_t tot = pw.s0n + pw.s1n;
+    // software-pipelined: the next round's candidate is loaded before the
+    // current one is tested
+    auto cand = [&](uint32_t k) { return k < pw.s0n ? pw.s0b + k : pw.s1b + (k - pw.s0n); };
+    float nx = 0.0f, ny = 0.0f, nz = 0.0f;
+    double nr = 0.0;
+    if (sub < tot) {
+      const uint32_t j0 = cand(sub);
+      nx = w.bx[j0];
+      ny = w.by[j0];
+      nz = w.bz[j0];
+      nr = w.br[j0];
+    }
     for (uint32_t it = 0; __any(it * G < tot); ++it) {
       const uint32_t k = it * G + sub;
       const bool valid = k < tot;
-      const uint32_t j = valid ? (k < pw.s0n ? pw.s0b + k : pw.s1b + (k - pw.s0n)) : 0u;
-      HitD ho{0.0, 0.0, 0.0, 0.0};
-      bool ok = false;
-      if (valid) {
-        ho = load_hit(w, j);
-        ok = doublet_ok_fast(c, hi, ho);
+      const uint32_t j = valid ? cand(k) : 0u;
+      const HitD ho{(double)nx, (double)ny, (double)nz, nr};
+      const uint32_t k1 = k + G;
+      if (k1 < tot) {
+        const uint32_t j1 = cand(k1);
+        nx = w.bx[j1];
+        ny = w.by[j1];
+        nz = w.bz[j1];
+        nr = w.br[j1];
       }
+      const bool ok = valid && doublet_ok_fast(c, hi, ho);
       const uint64_t bal = __ballot(ok);
       round(ok, j, hi, ho, bal, cnt);
       cnt += (uint32_t)__popcll(bal & gmask);
