@@ -812,7 +812,7 @@ __device__ __forceinline__ void outer_range(Ws& w, uint32_t d, bool store, uint3
 }
 
 // One thread per doublet (a,b), looping over its candidates with the
-// angle prefilter, eight loads in flight.  The few survivors are not tested
+// angle prefilter, sixteen angles in flight.  The few survivors are not tested
 // in place -- their exact FP64 tests would run with most lanes idle -- but
 // appended to a per-wavefront queue in LDS (ballot compaction) together
 // with the doublet's two hits, so that whenever 64 are queued they are
@@ -879,16 +879,28 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     }
     __threadfence_block();
     for (uint32_t wd = 0; __any(wd * 64u < deg); ++wd) {
-      // one mask word of candidates: eight angle loads in flight at a time
+      // one mask word of candidates (absolute doublet indices lo .. hi-1):
+      // their angles in aligned float4 loads, 16 in flight at a time (one
+      // cache line per lane and load instead of four)
       const uint32_t kw = wd * 64u;
+      const uint32_t lo = k0 + kw, hi = k0 + min(deg, kw + 64u);
       uint64_t pm = 0;
-      for (uint32_t b8 = 0; b8 < 64u && __any(kw + b8 < deg); b8 += 8) {
-        float tc[8];
+      for (uint32_t a = lo & ~3u; __any(a < hi); a += 16u) {
+        float tc[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) tc[u] = kw + b8 + u < deg ? w.th[k0 + kw + b8 + u] : 0.0f;
+        for (int q = 0; q < 4; ++q) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (a + 4u * q < hi) v = reinterpret_cast<const float4*>(w.th)[a / 4u + q];
+          tc[4 * q] = v.x;
+          tc[4 * q + 1] = v.y;
+          tc[4 * q + 2] = v.z;
+          tc[4 * q + 3] = v.w;
+        }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (kw + b8 + u < deg && rz_prefilter(c, ob.w, tc[u])) pm |= 1ull << (b8 + u);
+        for (int u = 0; u < 16; ++u) {
+          const uint32_t idx = a + u;
+          if (idx >= lo && idx < hi && rz_prefilter(c, ob.w, tc[u])) pm |= 1ull << (idx - lo);
+        }
       }
       // append the survivors, one per lane and round
       while (__any(pm != 0ull)) {

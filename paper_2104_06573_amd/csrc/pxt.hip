@@ -125,7 +125,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
   w.oh = cv.take<float4>(D);
-  w.th = cv.take<float>(D);
+  w.th = cv.take<float>(D + 16);  // aligned float4 reads may pass the end by 3
   w.cb = cv.take<uint32_t>(D);
   w.cdeg = cv.take<uint32_t>(D);
   w.roots = cv.take<uint32_t>(D);
