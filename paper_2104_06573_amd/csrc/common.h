@@ -78,11 +78,8 @@ struct Ws {
   uint32_t* rmax;         // [E * L] largest hit radius per layer (float bits)
   float* rasin;           // [E * L] turning angle to that radius (inf: any)
   // binned hits
-  float* bx;
-  float* by;
-  float* bz;
+  float4* bh;             // (x, y, z, phi): one load per candidate
   double* br;             // transverse radius in FP64
-  float* bphi;
   uint32_t* bidx;         // event-local input index
   uint32_t* bevt;         // event id
   uint8_t* blay;          // layer id

@@ -44,9 +44,10 @@ __device__ __forceinline__ HitD hit_xyz(float x, float y, float z) {
 
 __device__ __forceinline__ HitD load_hit(const Ws& w, uint32_t i) {
   HitD h;
-  h.x = (double)w.bx[i];
-  h.y = (double)w.by[i];
-  h.z = (double)w.bz[i];
+  const float4 v = w.bh[i];
+  h.x = (double)v.x;
+  h.y = (double)v.y;
+  h.z = (double)v.z;
   h.r = w.br[i];
   return h;
 }

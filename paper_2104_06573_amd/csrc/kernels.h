@@ -95,11 +95,8 @@ __global__ __launch_bounds__(256) void k_fill(Ws w) {
     const uint32_t e = upper_bound_u32(w.evt_off, E + 1, g) - 1;
     const uint32_t pos = w.bin_off[key] + atomicSub(&w.bin_cnt[key], 1u) - 1u;
     const float xf = x[g], yf = y[g];
-    w.bx[pos] = xf;
-    w.by[pos] = yf;
-    w.bz[pos] = z[g];
+    w.bh[pos] = make_float4(xf, yf, z[g], atan2f(yf, xf));
     w.br[pos] = hit_xyz(xf, yf, 0.0f).r;
-    w.bphi[pos] = atan2f(yf, xf);
     w.bidx[pos] = g - w.evt_off[e];
     w.bevt[pos] = e;
     w.blay[pos] = (uint8_t)layer[g];
@@ -397,9 +394,10 @@ __device__ __forceinline__ uint32_t visit_doublets(const Ws& w, const DevCfg& c,
   if (active) {
     li = w.blay[g];
     e = w.bevt[g];
-    hi = load_hit(w, g);
+    const float4 v = w.bh[g];
+    hi = HitD{(double)v.x, (double)v.y, (double)v.z, w.br[g]};
     ri = (float)hi.r;
-    phi = w.bphi[g];
+    phi = v.w;
     npairs = c.n_outer[li];
   }
   const float ai = asinf(0.5f * c.kmax_f * ri);  // inner term of the phi window
@@ -430,26 +428,22 @@ __device__ __forceinline__ uint32_t visit_doublets(const Ws& w, const DevCfg& c,
     // software-pipelined: the next round's candidate is loaded before the
     // current one is tested
     auto cand = [&](uint32_t k) { return k < pw.s0n ? pw.s0b + k : pw.s1b + (k - pw.s0n); };
-    float nx = 0.0f, ny = 0.0f, nz = 0.0f;
+    float4 nv = make_float4(0.f, 0.f, 0.f, 0.f);
     double nr = 0.0;
     if (sub < tot) {
       const uint32_t j0 = cand(sub);
-      nx = w.bx[j0];
-      ny = w.by[j0];
-      nz = w.bz[j0];
+      nv = w.bh[j0];
       nr = w.br[j0];
     }
     for (uint32_t it = 0; __any(it * G < tot); ++it) {
       const uint32_t k = it * G + sub;
       const bool valid = k < tot;
       const uint32_t j = valid ? cand(k) : 0u;
-      const HitD ho{(double)nx, (double)ny, (double)nz, nr};
+      const HitD ho{(double)nv.x, (double)nv.y, (double)nv.z, nr};
       const uint32_t k1 = k + G;
       if (k1 < tot) {
         const uint32_t j1 = cand(k1);
-        nx = w.bx[j1];
-        ny = w.by[j1];
-        nz = w.bz[j1];
+        nv = w.bh[j1];
         nr = w.br[j1];
       }
       const bool ok = valid && doublet_ok_fast(c, hi, ho);
@@ -756,7 +750,7 @@ __global__ __launch_bounds__(256) void k_dscatter(Ws w, DevCfg c) {
     for (int u = 0; u < U; ++u) {
       const uint32_t g = r[u].x >> kRecKBits;
       q[u] = w.cell_off[g] + (r[u].x & ((1u << kRecKBits) - 1u));
-      iz[u] = w.bz[g];
+      iz[u] = w.bh[g].z;
       ir[u] = w.br[g];
       ho[u] = load_hit(w, r[u].y);
     }
@@ -870,9 +864,10 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       const uint32_t a = w.cin[d];
       outer_range(w, d, true, k0, deg);
       ob = w.oh[d];
-      ax = w.bx[a];
-      ay = w.by[a];
-      az = w.bz[a];
+      const float4 av = w.bh[a];
+      ax = av.x;
+      ay = av.y;
+      az = av.z;
       const uint32_t nwd = (deg + 63u) >> 6;
       for (uint32_t j = 0; j < nwd; ++j) w.masks[(size_t)j * nd + d] = 0;
       w.nout[d] = 0;
@@ -1540,9 +1535,10 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   for (int j = 0; j < kMaxHits; ++j) {
     if (j < NH && j < n) {
       const uint32_t h = row[j];
-      X[j] = (double)w.bx[h];
-      Y[j] = (double)w.by[h];
-      Z[j] = (double)w.bz[h];
+      const float4 v = w.bh[h];
+      X[j] = (double)v.x;
+      Y[j] = (double)v.y;
+      Z[j] = (double)v.z;
       kind[j] = c.layer_kind[w.blay[h]];
     } else {
       X[j] = Y[j] = Z[j] = 0.0;

@@ -109,11 +109,8 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.bin_off = cv.take<uint32_t>(nbins + 1);
   w.rmax = cv.take<uint32_t>(E * c.n_layers);
   w.rasin = cv.take<float>(E * c.n_layers);
-  w.bx = cv.take<float>(H);
-  w.by = cv.take<float>(H);
-  w.bz = cv.take<float>(H);
+  w.bh = cv.take<float4>(H);
   w.br = cv.take<double>(H);
-  w.bphi = cv.take<float>(H);
   w.bidx = cv.take<uint32_t>(H);
   w.bevt = cv.take<uint32_t>(H);
   w.blay = cv.take<uint8_t>(H);
