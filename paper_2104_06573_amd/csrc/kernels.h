@@ -805,8 +805,9 @@ __device__ __forceinline__ void outer_range(Ws& w, uint32_t d, bool store, uint3
   }
 }
 
-// One thread per doublet (a,b), looping over its candidates with the
-// angle prefilter, sixteen angles in flight.  The few survivors are not tested
+// One thread per doublet (a,b) for its set-up (mask words and link count
+// cleared, hits fetched); the angle prefilter over the candidates is spread
+// evenly over the wavefront's lanes (below).  The few survivors are not tested
 // in place -- their exact FP64 tests would run with most lanes idle -- but
 // appended to a per-wavefront queue in LDS (ballot compaction) together
 // with the doublet's two hits, so that whenever 64 are queued they are
@@ -873,43 +874,64 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       w.nout[d] = 0;
     }
     __threadfence_block();
-    for (uint32_t wd = 0; __any(wd * 64u < deg); ++wd) {
-      // one mask word of candidates (absolute doublet indices lo .. hi-1):
-      // their angles in aligned float4 loads, 16 in flight at a time (one
-      // cache line per lane and load instead of four)
-      const uint32_t kw = wd * 64u;
-      const uint32_t lo = k0 + kw, hi = k0 + min(deg, kw + 64u);
-      uint64_t pm = 0;
-      for (uint32_t a = lo & ~3u; __any(a < hi); a += 16u) {
+    // the prefilter in chunks of 16 candidates spread evenly over the lanes:
+    // a doublet's candidates (absolute indices k0 .. k0+deg-1) form the
+    // 4-aligned chunks starting at (k0 & ~3) + 16 i; the wavefront's chunks
+    // are numbered by a prefix sum over its doublets, and in each round
+    // every lane takes the next chunk, finds its doublet by a binary search
+    // of the prefix (shuffles) and reads the 16 angles as four aligned
+    // float4s (one cache line per lane and load)
+    const uint32_t nch = deg ? (k0 + deg - (k0 & ~3u) + 15u) >> 4 : 0u;
+    const uint32_t cinc = wave_incl_scan(nch), cex = cinc - nch;
+    const uint32_t C = __shfl(cinc, kWave - 1);
+    for (uint32_t r0 = 0; r0 < C; r0 += kWave) {
+      const uint32_t q = r0 + lane;
+      // owner: the last lane whose chunks start at or before q
+      uint32_t own = 0;
+#pragma unroll
+      for (uint32_t step = kWave / 2; step >= 1; step >>= 1)
+        if (__shfl(cex, (int)(own + step)) <= q) own += step;
+      const uint32_t ok0 = __shfl(k0, (int)own), odeg = __shfl(deg, (int)own);
+      const float ta = __shfl(ob.w, (int)own);
+      const uint32_t lo = ok0, hi = ok0 + odeg;
+      const uint32_t a0 = (ok0 & ~3u) + 16u * (q - __shfl(cex, (int)own));
+      uint32_t pm = 0;  // bit u: candidate a0 + u passes
+      if (q < C) {
         float tc[16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (a + 4u * q < hi) v = reinterpret_cast<const float4*>(w.th)[a / 4u + q];
-          tc[4 * q] = v.x;
-          tc[4 * q + 1] = v.y;
-          tc[4 * q + 2] = v.z;
-          tc[4 * q + 3] = v.w;
+        for (int v = 0; v < 4; ++v) {
+          float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (a0 + 4u * v < hi) f = reinterpret_cast<const float4*>(w.th)[a0 / 4u + v];
+          tc[4 * v] = f.x;
+          tc[4 * v + 1] = f.y;
+          tc[4 * v + 2] = f.z;
+          tc[4 * v + 3] = f.w;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-          const uint32_t idx = a + u;
-          if (idx >= lo && idx < hi && rz_prefilter(c, ob.w, tc[u])) pm |= 1ull << (idx - lo);
+          const uint32_t idx = a0 + u;
+          if (idx >= lo && idx < hi && rz_prefilter(c, ta, tc[u])) pm |= 1u << u;
         }
       }
+      // the owner's hits travel with its survivors
+      const uint32_t od = dw + own;
+      const float oax = __shfl(ax, (int)own), oay = __shfl(ay, (int)own);
+      const float oaz = __shfl(az, (int)own);
+      const float obx = __shfl(ob.x, (int)own), oby = __shfl(ob.y, (int)own);
+      const float obz = __shfl(ob.z, (int)own);
       // append the survivors, one per lane and round
-      while (__any(pm != 0ull)) {
-        const bool has = pm != 0ull;
-        const uint32_t u = has ? (uint32_t)__ffsll((unsigned long long)pm) - 1u : 0u;
-        pm &= pm - 1ull;
+      while (__any(pm != 0u)) {
+        const bool has = pm != 0u;
+        const uint32_t u = has ? (uint32_t)__ffs(pm) - 1u : 0u;
+        pm &= pm - 1u;
         const uint64_t bal = __ballot(has);
         if (has) {
           const uint32_t slot = qn + (uint32_t)__popcll(bal & below);
-          const uint32_t k = kw + u;
-          qa[slot] = make_uint4(d, k, k0 + k, __float_as_uint(ax));
-          qb[slot] = make_uint4(__float_as_uint(ay), __float_as_uint(az), __float_as_uint(ob.x),
-                                __float_as_uint(ob.y));
-          qz[slot] = ob.z;
+          const uint32_t idx = a0 + u;
+          qa[slot] = make_uint4(od, idx - lo, idx, __float_as_uint(oax));
+          qb[slot] = make_uint4(__float_as_uint(oay), __float_as_uint(oaz), __float_as_uint(obx),
+                                __float_as_uint(oby));
+          qz[slot] = obz;
         }
         qn += (uint32_t)__popcll(bal);
         if (qn >= (uint32_t)kWave) {
