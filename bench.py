@@ -36,8 +36,8 @@ WORKLOADS = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="pu50", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=0, help="events per batch (default per workload)")
     ap.add_argument("--pool", type=int, default=2, help="distinct batches cycled through")

@@ -25,6 +25,7 @@ DEFAULT_SPACE = {
     "phi_bins": (64, 128, 256, 512),
     "group_lanes": (4, 8, 16),
     "link_kernel": (0, 2),
+    "doublet_mode": (1, 2),
     "block_size": (128, 256),
 }
 
