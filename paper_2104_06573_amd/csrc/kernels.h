@@ -231,13 +231,26 @@ __global__ __launch_bounds__(kScanThreads1) void k_scan1(const uint32_t* __restr
   if (!take_tile(w, scan_id, ntiles, tile)) return;
   const uint32_t epoch = w.epoch[0] * 8u + scan_id;
   const uint32_t base = tile * kTile + threadIdx.x * kTileItems;
+  // a thread's 16 consecutive items: four 16-byte loads in a full tile
+  // (each load one cache line per lane instead of sixteen scalar loads)
+  const bool full = base + kTileItems <= n;
   uint32_t v[kTileItems];
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < kTileItems / 4; ++q) {
+      const uint4 t = reinterpret_cast<const uint4*>(in + base)[q];
+      v[4 * q] = t.x;
+      v[4 * q + 1] = t.y;
+      v[4 * q + 2] = t.z;
+      v[4 * q + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) v[i] = base + i < n ? in[base + i] : 0u;
+  }
   uint32_t tsum = 0;
 #pragma unroll
-  for (int i = 0; i < kTileItems; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0u;
-    tsum += v[i];
-  }
+  for (int i = 0; i < kTileItems; ++i) tsum += v[i];
   uint32_t agg;
   const uint32_t texcl = block_excl_scan(tsum, lds, agg);
   if (threadIdx.x < kWave) {
@@ -246,10 +259,23 @@ __global__ __launch_bounds__(kScanThreads1) void k_scan1(const uint32_t* __restr
   }
   __syncthreads();
   uint32_t run = s_prefix + texcl;
+  if (full) {
 #pragma unroll
-  for (int i = 0; i < kTileItems; ++i) {
-    if (base + i < n) out[base + i] = run;
-    run += v[i];
+    for (int q = 0; q < kTileItems / 4; ++q) {
+      uint4 t;
+      t.x = run;
+      t.y = t.x + v[4 * q];
+      t.z = t.y + v[4 * q + 1];
+      t.w = t.z + v[4 * q + 2];
+      run = t.w + v[4 * q + 3];
+      reinterpret_cast<uint4*>(out + base)[q] = t;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i) {
+      if (base + i < n) out[base + i] = run;
+      run += v[i];
+    }
   }
   if (tile == ntiles - 1 && threadIdx.x == 0) {
     const uint32_t total = s_prefix + agg;
@@ -272,9 +298,23 @@ __global__ __launch_bounds__(kScanThreads1) void k_roots(Ws w, uint32_t scan_id)
   const uint32_t epoch = w.epoch[0] * 8u + scan_id;
   const uint32_t base = tile * kTile + threadIdx.x * kTileItems;
   uint32_t flags = 0;
+  if (base + kTileItems <= n) {
+    // 16 flags as one 16-byte load, 16 counts as four
+    const uint4 hv = *reinterpret_cast<const uint4*>(w.has_inner + base);
+    const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
 #pragma unroll
-  for (int i = 0; i < kTileItems; ++i)
-    if (base + i < n && !w.has_inner[base + i] && w.nout[base + i] != 0u) flags |= 1u << i;
+    for (int q = 0; q < kTileItems / 4; ++q) {
+      const uint4 nv = reinterpret_cast<const uint4*>(w.nout + base)[q];
+      const uint32_t nn[4] = {nv.x, nv.y, nv.z, nv.w};
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (((hw[q] >> (8 * b)) & 0xffu) == 0u && nn[b] != 0u) flags |= 1u << (4 * q + b);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTileItems; ++i)
+      if (base + i < n && !w.has_inner[base + i] && w.nout[base + i] != 0u) flags |= 1u << i;
+  }
   uint32_t agg;
   const uint32_t texcl = block_excl_scan((uint32_t)__popc(flags), lds, agg);
   if (threadIdx.x < kWave) {
