@@ -1354,27 +1354,53 @@ __device__ __forceinline__ uint64_t order_key(int n, double s) {
   return ((uint64_t)(kMaxHits - n) << 60) | (m >> 3);
 }
 
+// The eight slots of an n-tuplet row (rows are 32 bytes, 32-byte aligned)
+// as two 16-byte loads, and a slot picked by a run-time index without
+// spilling the row to scratch.
+static_assert(kMaxHits == 8, "n-tuplet rows are two 16-byte vectors");
+__device__ __forceinline__ void load_row(const uint32_t* rows, uint32_t t, uint32_t r[kMaxHits]) {
+  const uint4* p = reinterpret_cast<const uint4*>(rows + (size_t)t * kMaxHits);
+  const uint4 a = p[0], b = p[1];
+  r[0] = a.x;
+  r[1] = a.y;
+  r[2] = a.z;
+  r[3] = a.w;
+  r[4] = b.x;
+  r[5] = b.y;
+  r[6] = b.z;
+  r[7] = b.w;
+}
+
+__device__ __forceinline__ uint32_t pick_slot(const uint32_t r[kMaxHits], int i) {
+  uint32_t v = r[0];
+#pragma unroll
+  for (int j = 1; j < kMaxHits; ++j) v = i == j ? r[j] : v;
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t ntup = ctr[C_NTUP];
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     const int n = w.tn[t];
-    const uint32_t* th = w.thit + (size_t)t * kMaxHits;
-    const uint32_t* tc = w.tcell + (size_t)t * kMaxHits;
+    uint32_t th[kMaxHits], tc[kMaxHits];
+    load_row(w.thit, t, th);
+    load_row(w.tcell, t, tc);
     HitD h0 = load_hit(w, th[0]);
     HitD h1 = load_hit(w, th[1]);
     double s = 0.0;
     for (int j = 1; j + 1 < n; ++j) {
-      const HitD h2 = load_hit(w, th[j + 1]);
+      const HitD h2 = load_hit(w, pick_slot(th, j + 1));
       s += triple_score(c, h0, h1, h2);
       h0 = h1;
       h1 = h2;
     }
     w.tscore[t] = s;
     const uint64_t key = order_key(n, s);
-    for (int j = 0; j + 1 < n; ++j)
-      atomicMin((unsigned long long*)&w.bkey[tc[j]], (unsigned long long)key);
+#pragma unroll
+    for (int j = 0; j < kMaxCells; ++j)
+      if (j + 1 < n) atomicMin((unsigned long long*)&w.bkey[tc[j]], (unsigned long long)key);
   }
 }
 
@@ -1402,8 +1428,12 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     const int n = w.tn[t];
     const uint64_t key = order_key(n, w.tscore[t]);
-    for (int j = 0; j + 1 < n; ++j) {
-      const uint32_t d = w.tcell[(size_t)t * kMaxHits + j];
+    uint32_t tc[kMaxHits];
+    load_row(w.tcell, t, tc);
+#pragma unroll
+    for (int j = 0; j < kMaxCells; ++j) {
+      if (j + 1 >= n) continue;
+      const uint32_t d = tc[j];
       if (w.bkey[d] != key) continue;
       uint32_t cur = w.best[d];
       while (cur == kPad || ranks_before(w, T, t, cur)) {
@@ -1421,8 +1451,11 @@ __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     uint32_t alive = 1;
     const int n = w.tn[t];
-    for (int j = 0; j + 1 < n; ++j)
-      if (w.best[w.tcell[(size_t)t * kMaxHits + j]] != t) alive = 0;
+    uint32_t tc[kMaxHits];
+    load_row(w.tcell, t, tc);
+#pragma unroll
+    for (int j = 0; j < kMaxCells; ++j)
+      if (j + 1 < n && w.best[tc[j]] != t) alive = 0;
     w.talive[t] = alive;
   }
 }
@@ -1581,7 +1614,8 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   const int n = NFIX > 0 ? NFIX : (int)w.tn[t];
   double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
   int kind[kMaxHits];
-  const uint32_t* row = w.thit + (size_t)t * kMaxHits;
+  uint32_t row[kMaxHits];
+  load_row(w.thit, t, row);
   // the track's hit ids and event go out first, so that the ids are not
   // held through the fit
   if (!fp64) {
