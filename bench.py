@@ -50,7 +50,11 @@ def parse():
                     help="0 thread per doublet (the fastest with batches in flight at PU~50 "
                          "and PU~200), 1 lane group + queue, 2 wavefront + queue")
     ap.add_argument("--doublet-mode", type=int, default=2,
-                    help="0 count/scan/fill, 1 one pass (LDS records), 2 count+stage/scan/scatter")
+                    help="batched path: 0 count/scan/fill, 1 one pass (LDS records), "
+                         "2 count+stage/scan/scatter")
+    ap.add_argument("--latency-doublet-mode", type=int, default=1,
+                    help="plain (one event per call) and served paths: the one-pass mode has "
+                         "the least latency on a few events")
     ap.add_argument("--graph", type=int, default=1, help="replay the launch sequence as a HIP graph")
     ap.add_argument("--inflight", type=int, default=4,
                     help="batches in flight: contexts, each on its own stream, taking turns")
@@ -201,7 +205,7 @@ def serving_leg(det, args):
                  max_events=64, max_hits=1_400_000, max_doublets=36 << 20,
                  max_link_words=160 << 20, max_tuples=6 << 20, phi_bins=args.phi_bins,
                  group_lanes=args.group_lanes, link_kernel=args.link_kernel, use_graph=1,
-                 doublet_mode=args.doublet_mode)
+                 doublet_mode=args.latency_doublet_mode)
     poisson_run(srv, events[:300], rate_hz=args.serve_rate)          # warm-up
     rep = poisson_run(srv, events, rate_hz=args.serve_rate)
     sat = poisson_run(srv, events, rate_hz=1e7)
@@ -306,7 +310,7 @@ def main():
                              max_tuples=per_ev_t * 2, max_tracks=per_ev_t * 2,
                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                             link_kernel=args.link_kernel, use_graph=args.graph,
-                              doublet_mode=args.doublet_mode)
+                              doublet_mode=args.latency_doublet_mode)
     plain_dev = [prec.upload([e]) for e in plain_events]
     for i in range(min(4, len(plain_dev))):
         prec.launch(*plain_dev[i])
@@ -341,6 +345,7 @@ def main():
             "batches_in_flight": args.inflight,
             "link_kernel": args.link_kernel,
             "doublet_mode": args.doublet_mode,
+            "latency_doublet_mode": args.latency_doublet_mode,
             "hip_graph": bool(args.graph),
             "path": "batched (one launch sequence per batch)",
         },
