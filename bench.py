@@ -98,8 +98,9 @@ def algorithmic_bytes(stage, n, doublet_mode=0):
         # inner-hit coordinates and doublet offsets (24 per hit); per
         # doublet: inner and outer hit, outer hit coordinates and angle,
         # candidate range written (32), its angle read once as a candidate
-        # (4), neighbour count written (4); mask words written (8)
-        "links": 24 * Nh + 40 * Nd + 8 * Nw,
+        # (4), neighbour count and cleaning-election slots written (16);
+        # mask words written (8)
+        "links": 24 * Nh + 52 * Nd + 8 * Nw,
         # per n-tuplet: hits, doublets, length (61), hit coordinates, score
         # written (8), order key min per doublet (8)
         "score": (69 + 20 * nbar + 8 * (nbar - 1)) * Nt,

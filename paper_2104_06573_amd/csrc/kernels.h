@@ -833,7 +833,7 @@ __device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c) {
 
 // Candidate range of doublet d: the doublets leaving its outer hit, from
 // the per-hit offsets; stored in cb/cdeg (by one lane when `store`) for the
-// n-tuplet search.
+// n-tuplet search, with the cleaning's election slots of d cleared.
 __device__ __forceinline__ void outer_range(Ws& w, uint32_t d, bool store, uint32_t& kb,
                                             uint32_t& deg) {
   const uint32_t j = w.cout[d];
@@ -842,6 +842,10 @@ __device__ __forceinline__ void outer_range(Ws& w, uint32_t d, bool store, uint3
   if (store) {
     w.cb[d] = kb;
     w.cdeg[d] = deg;
+    // the cleaning's per-doublet election starts from "no tuple" (cleared
+    // here, coalesced, for every doublet)
+    w.bkey[d] = ~0ull;
+    w.best[d] = kPad;
   }
 }
 
@@ -1265,11 +1269,16 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
     uint64_t bits[kMaxCells];   // its remaining bits
     uint32_t nwd[kMaxCells];    // mask words per depth
     uint32_t kbase[kMaxCells];  // first candidate doublet per depth
+    uint32_t phit[kMaxHits];    // fill pass: the path's hits (doublet d spans d, d + 1)
     uint32_t cnt = 0;
     const uint32_t base = FILL ? w.roff[ri] : 0u;
     const uint32_t h0 = w.cin[r];
     int depth = 0;
     path[0] = r;
+    if (FILL) {
+      phit[0] = h0;
+      phit[1] = w.cout[r];
+    }
     {
       kbase[0] = w.cb[r];
       nwd[0] = (w.cdeg[r] + 63u) >> 6;
@@ -1294,17 +1303,20 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
         break;
       }
       path[depth + 1] = child;
-      if (w.nout[child] == 0) {
+      // the child's outer hit is loaded with its link count (no extra
+      // round trip at a leaf)
+      const uint32_t nchild = w.nout[child];
+      const uint32_t hchild = FILL ? w.cout[child] : 0u;
+      if (nchild == 0) {
         if (FILL) {
           const uint32_t t = base + cnt;
           const int last = depth + 1;
           uint32_t hh[kMaxHits], cc[kMaxHits];
-          hh[0] = h0;
 #pragma unroll
-          for (int j = 0; j < kMaxCells; ++j) {
-            hh[j + 1] = j <= last ? w.cout[path[j]] : kPad;
-            cc[j] = j <= last ? path[j] : kPad;
-          }
+          for (int j = 0; j < kMaxHits; ++j)
+            hh[j] = j <= last ? phit[j] : (j == last + 1 ? hchild : kPad);
+#pragma unroll
+          for (int j = 0; j < kMaxCells; ++j) cc[j] = j <= last ? path[j] : kPad;
           cc[kMaxCells] = kPad;
           // one n-tuplet row: two 16-byte stores per array
           uint4* th4 = reinterpret_cast<uint4*>(w.thit + (size_t)t * kMaxHits);
@@ -1314,16 +1326,12 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
           tc4[0] = make_uint4(cc[0], cc[1], cc[2], cc[3]);
           tc4[1] = make_uint4(cc[4], cc[5], cc[6], cc[7]);
           w.tn[t] = (uint8_t)(last + 2);
-          // the cleaning's per-doublet election starts from "no tuple"
-          for (int j = 0; j <= last; ++j) {
-            w.bkey[path[j]] = ~0ull;
-            w.best[path[j]] = kPad;
-          }
         }
         ++cnt;
         continue;
       }
       ++depth;
+      if (FILL) phit[depth + 1] = hchild;
       kbase[depth] = w.cb[child];
       nwd[depth] = (w.cdeg[child] + 63u) >> 6;
       word[depth] = 0;
