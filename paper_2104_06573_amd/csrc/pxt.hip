@@ -469,7 +469,7 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->max_tuples = 1u << 22;
   cfg->phi_bins = 256;
   cfg->block_size = 256;
-  cfg->group_lanes = 16;
+  cfg->group_lanes = 8;
   cfg->link_kernel = 0;
   cfg->use_graph = 0;
   cfg->doublet_mode = 2;
