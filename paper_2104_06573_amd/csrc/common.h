@@ -86,8 +86,7 @@ struct Ws {
   // doublets
   uint32_t* dcnt;         // [H + 1] doublets per inner hit
   uint32_t* cell_off;     // [H + 1] first doublet of each inner hit
-  uint32_t* cin;          // [D] inner binned hit
-  uint32_t* cout;         // [D] outer binned hit
+  uint2* cio;             // [D] (inner, outer) binned hits: one store, one load
   uint64_t* masks;        // [W] link masks, C_WSTRIDE words per doublet
   uint8_t* has_inner;     // [D]
   uint32_t* nout;         // [D] outer links per doublet

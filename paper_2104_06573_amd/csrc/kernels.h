@@ -499,8 +499,7 @@ __device__ __forceinline__ uint32_t visit_doublets(const Ws& w, const DevCfg& c,
 // outer hit's own doublet range (cb, cdeg) is filled by the link kernels.
 __device__ __forceinline__ void store_doublet(Ws& w, const DevCfg& c, uint32_t q, uint32_t g,
                                               uint32_t j, const HitD& hi, const HitD& ho) {
-  w.cin[q] = g;
-  w.cout[q] = j;
+  w.cio[q] = make_uint2(g, j);
   w.has_inner[q] = 0;
   if (c.link_kernel == 1) w.nout[q] = 0;
   const float th = rz_angle(hi, ho);
@@ -831,12 +830,11 @@ __device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c) {
   return ok;
 }
 
-// Candidate range of doublet d: the doublets leaving its outer hit, from
+// Candidate range of doublet d (outer hit j): the doublets leaving j, from
 // the per-hit offsets; stored in cb/cdeg (by one lane when `store`) for the
 // n-tuplet search, with the cleaning's election slots of d cleared.
-__device__ __forceinline__ void outer_range(Ws& w, uint32_t d, bool store, uint32_t& kb,
-                                            uint32_t& deg) {
-  const uint32_t j = w.cout[d];
+__device__ __forceinline__ void outer_range(Ws& w, uint32_t d, uint32_t j, bool store,
+                                            uint32_t& kb, uint32_t& deg) {
   kb = w.cell_off[j];
   deg = w.cell_off[j + 1] - kb;
   if (store) {
@@ -906,8 +904,9 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     float4 ob = make_float4(0.f, 0.f, 0.f, 0.f);
     float ax = 0.f, ay = 0.f, az = 0.f;
     if (d < nd) {
-      const uint32_t a = w.cin[d];
-      outer_range(w, d, true, k0, deg);
+      const uint2 io = w.cio[d];
+      const uint32_t a = io.x;
+      outer_range(w, d, io.y, true, k0, deg);
       ob = w.oh[d];
       const float4 av = w.bh[a];
       ax = av.x;
@@ -1024,7 +1023,7 @@ __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint3*
   if (lane < n) {
     const uint3 it = q[lane];
     const uint32_t d = it.x, k = it.y;
-    const HitD ha = load_hit(w, w.cin[d]);
+    const HitD ha = load_hit(w, w.cio[d].x);
     const float4 ob = w.oh[d];
     const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
     const uint32_t d2 = it.z;
@@ -1059,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
     float ta = 0.0f;
     if (d < nd) {
       ta = w.th[d];
-      outer_range(w, d, sub == 0, kb, deg);
+      outer_range(w, d, w.cio[d].y, sub == 0, kb, deg);
     }
     const uint32_t maxw = wave_max((deg + 63u) / 64u);
     for (uint32_t wd = 0; wd < maxw; ++wd) {
@@ -1170,8 +1169,9 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
     uint32_t a = 0, kb = 0, deg = 0, mo = 0;
     float4 ob = make_float4(0.f, 0.f, 0.f, 0.f);
     if (d < nd) {
-      a = w.cin[d];
-      outer_range(w, d, true, kb, deg);
+      const uint2 io = w.cio[d];
+      a = io.x;
+      outer_range(w, d, io.y, true, kb, deg);
       ob = w.oh[d];
       mo = d;
     }
@@ -1272,12 +1272,13 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
     uint32_t phit[kMaxHits];    // fill pass: the path's hits (doublet d spans d, d + 1)
     uint32_t cnt = 0;
     const uint32_t base = FILL ? w.roff[ri] : 0u;
-    const uint32_t h0 = w.cin[r];
+    const uint2 rio = w.cio[r];
+    const uint32_t h0 = rio.x;
     int depth = 0;
     path[0] = r;
     if (FILL) {
       phit[0] = h0;
-      phit[1] = w.cout[r];
+      phit[1] = rio.y;
     }
     {
       kbase[0] = w.cb[r];
@@ -1306,7 +1307,7 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       // the child's outer hit is loaded with its link count (no extra
       // round trip at a leaf)
       const uint32_t nchild = w.nout[child];
-      const uint32_t hchild = FILL ? w.cout[child] : 0u;
+      const uint32_t hchild = FILL ? w.cio[child].y : 0u;
       if (nchild == 0) {
         if (FILL) {
           const uint32_t t = base + cnt;

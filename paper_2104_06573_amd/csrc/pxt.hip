@@ -116,8 +116,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.blay = cv.take<uint8_t>(H);
   w.dcnt = cv.take<uint32_t>(H + 1);
   w.cell_off = cv.take<uint32_t>(H + 1);
-  w.cin = cv.take<uint32_t>(D);
-  w.cout = cv.take<uint32_t>(D);
+  w.cio = cv.take<uint2>(D);
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
@@ -634,8 +633,12 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
   if (what == PXT_DUMP_DOUBLETS || what == PXT_DUMP_LINKS) {
     std::vector<uint32_t> cin(nd), cout(nd);
     if (nd) {
-      HIP_OR_FAIL(c, hipMemcpy(cin.data(), w.cin, 4ull * nd, hipMemcpyDeviceToHost));
-      HIP_OR_FAIL(c, hipMemcpy(cout.data(), w.cout, 4ull * nd, hipMemcpyDeviceToHost));
+      std::vector<uint2> cio(nd);
+      HIP_OR_FAIL(c, hipMemcpy(cio.data(), w.cio, 8ull * nd, hipMemcpyDeviceToHost));
+      for (uint32_t k = 0; k < nd; ++k) {
+        cin[k] = cio[k].x;
+        cout[k] = cio[k].y;
+      }
     }
     if (what == PXT_DUMP_DOUBLETS) {
       rows.reserve(3ull * nd);
