@@ -68,6 +68,18 @@ def parse():
     return ap.parse_args()
 
 
+def batch_caps(kind, n_events, max_hits):
+    """Context capacities for batches of n_events events of workload `kind`
+    holding at most max_hits hits (the timed configuration; the GPU parity
+    tests use the same)."""
+    per_ev_d = 100_000 if kind == "pu50" else 1_700_000
+    per_ev_w = per_ev_d * (4 if kind == "pu50" else 8)  # link-mask words
+    per_ev_t = 8_000 if kind == "pu50" else 200_000
+    return dict(max_events=n_events, max_hits=max_hits + 1024,
+                max_doublets=per_ev_d * n_events, max_link_words=per_ev_w * n_events,
+                max_tuples=per_ev_t * n_events, max_tracks=per_ev_t * n_events)
+
+
 def gen_events(kind, n, seed0):
     import eventgen
     return [eventgen.generate(kind, seed0 + i) for i in range(n)]
@@ -252,16 +264,11 @@ def main():
     pool = [gen_events(kind, B, 1000 + 97 * p) for p in range(args.pool)]
     hits_per_event = float(np.mean([e.n_hits for b in pool for e in b]))
     max_hits = max(sum(e.n_hits for e in b) for b in pool)
-    per_ev_d = 100_000 if kind == "pu50" else 1_700_000
-    per_ev_w = per_ev_d * (4 if kind == "pu50" else 8)  # link-mask words
-    per_ev_t = 8_000 if kind == "pu50" else 200_000
     K = max(1, args.inflight)
-    recs = [pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
-                              max_doublets=per_ev_d * B, max_link_words=per_ev_w * B,
-                              max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
-                              phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+    caps = batch_caps(kind, B, max_hits)
+    recs = [pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                               link_kernel=args.link_kernel, use_graph=args.graph,
-                              doublet_mode=args.doublet_mode)
+                              doublet_mode=args.doublet_mode, **caps)
             for _ in range(K)]
     rec = recs[0]
     streams = [torch.cuda.Stream() for _ in range(K)]
@@ -295,23 +302,19 @@ def main():
 
     # stage breakdown with HIP events on the library's stream (direct mode:
     # events cannot sit inside the replayed graph)
-    trec = pxt.Reconstructor(det, max_events=B, max_hits=max_hits + 1024,
-                             max_doublets=per_ev_d * B, max_link_words=per_ev_w * B,
-                             max_tuples=per_ev_t * B, max_tracks=per_ev_t * B,
-                             phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+    trec = pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                              link_kernel=args.link_kernel, use_graph=0,
-                             doublet_mode=args.doublet_mode)
+                             doublet_mode=args.doublet_mode, **caps)
     stages = trec.stage_times(trec.upload(pool[0]), repeats=5)
     trec.close()
 
     # plain path: one event per call, synchronised per event
     plain_events = [e for b in pool for e in b][: args.plain_events]
-    prec = pxt.Reconstructor(det, max_events=1, max_hits=max(e.n_hits for e in plain_events) + 16,
-                             max_doublets=per_ev_d * 2, max_link_words=per_ev_w * 2,
-                             max_tuples=per_ev_t * 2, max_tracks=per_ev_t * 2,
-                             phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                            link_kernel=args.link_kernel, use_graph=args.graph,
-                              doublet_mode=args.latency_doublet_mode)
+    pcaps = batch_caps(kind, 2, max(e.n_hits for e in plain_events) + 16)
+    pcaps["max_events"] = 1
+    prec = pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                             link_kernel=args.link_kernel, use_graph=args.graph,
+                             doublet_mode=args.latency_doublet_mode, **pcaps)
     plain_dev = [prec.upload([e]) for e in plain_events]
     for i in range(min(4, len(plain_dev))):
         prec.launch(*plain_dev[i])

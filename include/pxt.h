@@ -300,10 +300,14 @@ int pxt_submit(pxt_server* s, const float* x, const float* y, const float* z,
                const int16_t* layer, uint32_t n_hits, uint64_t* ticket);
 
 /* Wait up to timeout_ms (negative: forever) for the event's result and copy
- * it into *out; the ticket is released on success.  Returns PXT_OK,
- * PXT_ERR_NOT_READY (timeout; the ticket stays valid) or
- * PXT_ERR_INVALID_ARG (unknown ticket).  The event's own status (e.g.
- * PXT_ERR_CAPACITY) is in out->status. */
+ * it into *out; the ticket is released once the result has been delivered.
+ * Returns PXT_OK, PXT_ERR_NOT_READY (timeout; the ticket stays valid),
+ * PXT_ERR_CAPACITY (out->capacity is below the event's track count, which
+ * is written to out->n_tracks; nothing is copied and the ticket stays
+ * valid: poll again with buffers of at least that many tracks) or
+ * PXT_ERR_INVALID_ARG (unknown ticket, null buffers).  The event's own
+ * status is in out->status: PXT_ERR_CAPACITY there means the event itself
+ * overflowed the lane's arenas (it has no tracks; the ticket is released). */
 int pxt_poll(pxt_server* s, uint64_t ticket, pxt_event_tracks* out, int timeout_ms);
 
 /* Counters since creation. */

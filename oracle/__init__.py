@@ -67,28 +67,33 @@ def build(force=False):
     return _LIB
 
 
+def load_library(path):
+    """ctypes handle of an oracle build at `path`, with its signatures set."""
+    L = ctypes.CDLL(path)
+    L.orc_run.restype = ctypes.c_void_p
+    L.orc_run.argtypes = [ctypes.POINTER(Config), ctypes.c_uint32,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p]
+    L.orc_status.argtypes = [ctypes.c_void_p]
+    L.orc_count.restype = ctypes.c_uint64
+    L.orc_count.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_data.restype = ctypes.c_void_p
+    L.orc_data.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_free.argtypes = [ctypes.c_void_p]
+    d = ctypes.c_double
+    L.orc_doublet_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 6
+    L.orc_link_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 9
+    L.orc_link_terms.argtypes = [ctypes.POINTER(Config)] + [d] * 9 + [ctypes.c_void_p]
+    L.orc_fit.argtypes = [ctypes.POINTER(Config), ctypes.c_int] + [ctypes.c_void_p] * 8
+    return L
+
+
 def lib():
     global _lib
     with _lock:
         if _lib is None:
             build()
-            L = ctypes.CDLL(_LIB)
-            L.orc_run.restype = ctypes.c_void_p
-            L.orc_run.argtypes = [ctypes.POINTER(Config), ctypes.c_uint32,
-                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                  ctypes.c_void_p]
-            L.orc_status.argtypes = [ctypes.c_void_p]
-            L.orc_count.restype = ctypes.c_uint64
-            L.orc_count.argtypes = [ctypes.c_void_p, ctypes.c_int]
-            L.orc_data.restype = ctypes.c_void_p
-            L.orc_data.argtypes = [ctypes.c_void_p, ctypes.c_int]
-            L.orc_free.argtypes = [ctypes.c_void_p]
-            d = ctypes.c_double
-            L.orc_doublet_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 6
-            L.orc_link_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 9
-            L.orc_link_terms.argtypes = [ctypes.POINTER(Config)] + [d] * 9 + [ctypes.c_void_p]
-            L.orc_fit.argtypes = [ctypes.POINTER(Config), ctypes.c_int] + [ctypes.c_void_p] * 8
-            _lib = L
+            _lib = load_library(_LIB)
     return _lib
 
 

@@ -57,6 +57,14 @@ __global__ void k_clear(Ws w, DevCfg c) {
   if (tid == 0) w.epoch[0] += 1u;
 }
 
+// Fills n 64-bit words with v (used where device memory must be reset
+// without a memset node in a stream that may be captured).
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 // ------------------------------------------------------- binning (prep) --
 
 __global__ __launch_bounds__(256) void k_prep(Ws w, DevCfg c) {

@@ -38,6 +38,11 @@ struct pxt_ctx {
   hipGraph_t graph[kSlots] = {};
   hipGraphExec_t gexec[kSlots] = {};
   int n_cu = 256;
+  // calls made on this context: the scan status words carry a 30-bit tag of
+  // (call, scan), which repeats after 2^27 calls, so they are reset every
+  // kEpochReset calls (a stale word is then at most that many calls old)
+  uint64_t calls = 0;
+  static constexpr uint64_t kEpochReset = 1ull << 26;
   std::string err;
   // per-stage timing
   bool timing = false;
@@ -584,6 +589,12 @@ int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* strea
   std::memcpy(hs, &desc, sizeof(desc));
   std::memcpy(hs + desc_bytes(), in->event_offsets, sizeof(uint32_t) * (E + 1));
 
+  if (c->calls > 0 && c->calls % pxt_ctx::kEpochReset == 0) {
+    const uint64_t n = scan_tiles(cfg);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s,
+                       c->ws.scan_status, n, 0ull);
+  }
+  c->calls++;
   if (cfg.use_graph) {
     if (!c->gexec[slot]) {
       HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -402,9 +402,10 @@ int pxt_poll(pxt_server* s, uint64_t ticket, pxt_event_tracks* out, int timeout_
   out->queue_us = r->queue_us;
   out->batch_events = r->batch_events;
   if (r->status == PXT_OK) {
-    if (n > out->capacity) {
-      out->status = PXT_ERR_CAPACITY;
-    } else if (n) {
+    // a buffer too small keeps the ticket: the caller polls again with room
+    // for out->n_tracks tracks
+    if (n > out->capacity) return PXT_ERR_CAPACITY;
+    if (n) {
       if (!out->hit_idx || !out->n_hits || !out->params || !out->cov || !out->chi2 || !out->flags)
         return PXT_ERR_INVALID_ARG;
       std::memcpy(out->hit_idx, r->hit_idx.data(), 32ull * n);

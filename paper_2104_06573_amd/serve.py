@@ -15,7 +15,8 @@ import time
 
 import numpy as np
 
-from . import OK, ERR_BUSY, ERR_NOT_READY, PxtConfig, PxtError, lib, make_config
+from . import (OK, ERR_BUSY, ERR_CAPACITY, ERR_NOT_READY, PxtConfig, PxtError, lib,
+               make_config)
 
 
 class ServerConfig(ctypes.Structure):
@@ -106,6 +107,12 @@ class Server:
                          b["params"].ctypes.data, b["cov"].ctypes.data, b["chi2"].ctypes.data,
                          b["flags"].ctypes.data, 0, 0, 0.0, 0.0, 0)
         st = lib().pxt_poll(self.h, ticket, ctypes.byref(et), timeout_ms)
+        if st == ERR_CAPACITY:
+            # this thread's buffers are too small for the event: grow them
+            # and poll again (the ticket is still valid)
+            self.cap = max(self.cap, int(et.n_tracks))
+            self._tls.buf = None
+            return self.poll(ticket, timeout_ms)
         if st == ERR_NOT_READY:
             return None
         if st != OK:

@@ -49,3 +49,35 @@ def match_tracks(res, oref, event):
     oo = np.lexsort(oh.T[::-1]) if oh.shape[0] else np.zeros(0, int)
     return (gh[go], res["params"][m][go], res["cov"][m][go], res["chi2"][m][go],
             res["flags"][m][go], oh[oo], oref["params"][oo], oref["cov"][oo], oref["chi2"][oo])
+
+
+def oracle_events(events, det, workers=None):
+    """The oracle on every event, one event per host thread (the C oracle
+    releases the interpreter while it runs)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.lib()
+    if workers is None:
+        try:
+            workers = len(os.sched_getaffinity(0))
+        except AttributeError:
+            workers = os.cpu_count() or 1
+        workers = max(1, min(16, workers))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda e: oracle.reconstruct(e.x, e.y, e.z, e.layer, det), events))
+
+
+def correlations(c15):
+    """Correlation coefficients of packed 5x5 covariances [n, 15] -> [n, 10]
+    (the off-diagonal entries of the lower triangle over sqrt of their
+    diagonals)."""
+    c = np.asarray(c15, np.float64)
+    diag = [0, 2, 5, 9, 14]
+    out = []
+    k = 0
+    for a in range(5):
+        for b in range(a + 1):
+            if a != b:
+                out.append(c[:, k] / np.sqrt(c[:, diag[a]] * c[:, diag[b]]))
+            k += 1
+    return np.stack(out, axis=1) if out else np.zeros((c.shape[0], 0))

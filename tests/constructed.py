@@ -1,0 +1,199 @@
+"""Hand-built events whose cleaning outcome and scores are fixed by geometry.
+
+Shared by the oracle pins (CPU) and the GPU parity tests.  Nothing here
+calls the oracle or the library: the expected values are computed by a
+route of their own -- the r-z turning angle from arctan2, the transverse
+impact from the algebraic circle x^2 + y^2 + D x + E y + F = 0 solved in
+exact rational arithmetic (the origin's distance from that circle is
+|F| / (|C| + R), |C| and R taken to 50 digits) -- from the float32
+coordinates the event actually carries.
+"""
+
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+import numpy as np
+
+from tests import helix_util as hx
+
+
+class Ev:
+    def __init__(self, x, y, z, layer):
+        self.x = np.asarray(x, np.float32)
+        self.y = np.asarray(y, np.float32)
+        self.z = np.asarray(z, np.float32)
+        self.layer = np.asarray(layer, np.int16)
+
+    @property
+    def n_hits(self):
+        return int(self.x.shape[0])
+
+
+def event(points, layers):
+    p = np.asarray(points, np.float64)
+    return Ev(p[:, 0], p[:, 1], p[:, 2], layers)
+
+
+def _hit(ev, i):
+    return float(ev.x[i]), float(ev.y[i]), float(ev.z[i])
+
+
+def rz_sine(pa, pb, pc):
+    """Sine of the turning angle of the r-z segments a->b->c (arctan2 route)."""
+    ra, rb, rc = (np.sqrt(p[0] * p[0] + p[1] * p[1]) for p in (pa, pb, pc))
+    t1 = np.arctan2(pb[2] - pa[2], rb - ra)
+    t2 = np.arctan2(pc[2] - pb[2], rc - rb)
+    return float(np.sin(t2 - t1))
+
+
+def impact_exact(pa, pb, pc):
+    """Distance of the transverse origin from the circle through three
+    points: the circle x^2 + y^2 + D x + E y + F = 0 solved exactly (Cramer's
+    rule over rationals); |C|^2 - R^2 = F, so the distance is
+    |F| / (|C| + R)."""
+    getcontext().prec = 50
+    P = [(Fraction(p[0]), Fraction(p[1])) for p in (pa, pb, pc)]
+    M = [[x, y, Fraction(1)] for x, y in P]
+    rhs = [-(x * x + y * y) for x, y in P]
+
+    def det3(m):
+        return (m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1])
+                - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
+                + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]))
+
+    d = det3(M)
+    sol = []
+    for k in range(3):
+        mk = [row[:] for row in M]
+        for i in range(3):
+            mk[i][k] = rhs[i]
+        sol.append(det3(mk) / d)
+    D, E, F = sol
+    c2 = (D * D + E * E) / 4
+    r2 = c2 - F
+    dec = lambda q: Decimal(q.numerator) / Decimal(q.denominator)
+    C = dec(c2).sqrt()
+    R = dec(r2).sqrt()
+    return float(abs(dec(F)) / (C + R))
+
+
+def triple_score_expected(det, ev, i, j, k):
+    """(rz sine / arz)^2 + (impact / d0max)^2 of hits i, j, k of ev."""
+    pa, pb, pc = _hit(ev, i), _hit(ev, j), _hit(ev, k)
+    q1 = rz_sine(pa, pb, pc) / det["cuts"]["arz"]
+    q2 = impact_exact(pa, pb, pc) / det["cuts"]["d0max"]
+    return q1 * q1 + q2 * q2
+
+
+def scored_quadruplet(det):
+    """Four hits on layers 0..3 lying on a circle that passes 0.06 cm from
+    the origin (pT 2 GeV), with r-z segments turning by +0.009 and then
+    -0.006 rad: a quadruplet whose two triples both carry an r-z term and
+    an impact term."""
+    k = det["c_kappa"] / 2.0
+    phi0, d0 = 0.3, 0.06
+    radii = (2.9, 6.8, 10.9, 16.0)
+    xy = [hx.point(phi0, d0, k, 0.0, 0.0, hx.arc_at_radius(phi0, d0, k, r))[:2]
+          for r in radii]
+    alpha = 0.5
+    turns = (0.0, 0.009, -0.006)
+    z = [1.0]
+    ang = alpha
+    for i in range(1, 4):
+        ang = alpha + sum(turns[:i])
+        z.append(z[-1] + (radii[i] - radii[i - 1]) * np.tan(ang))
+    pts = [(xy[i][0], xy[i][1], z[i]) for i in range(4)]
+    return event(pts, [0, 1, 2, 3])
+
+
+def impact_decides(det):
+    """Two triplets sharing the doublet (a, b) whose third hits are mirror
+    images in y: identical radius and z, so identical r-z terms, but
+    transverse impacts of about 0.053 and 0.0007 cm.  The larger impact sits
+    at the lower hit index, so a score without the impact term would tie and
+    the index order would pick the wrong one.  Returns (event, winner)."""
+    beta, gam = 0.002, 0.004
+    a = (2.9, 0.0, 1.0)
+    b = (6.8 * np.cos(beta), 6.8 * np.sin(beta), 2.95)
+    c_small = (10.9 * np.cos(gam), 10.9 * np.sin(gam), 5.0)
+    c_large = (10.9 * np.cos(gam), -10.9 * np.sin(gam), 5.0)
+    ev = event([a, b, c_large, c_small], [0, 1, 2, 2])
+    return ev, (0, 1, 3)
+
+
+def exact_tie(det, low_first):
+    """Two triplets with bitwise-equal scores: a and b on the +x axis and the
+    third hits mirrored in y, so every difference in the cuts and the score
+    changes only in sign.  Only the hit-index order can decide; the winner
+    is the one whose third hit has the lower index.  low_first puts the
+    +y hit first.  Returns (event, winner)."""
+    gam = 0.003
+    a = (2.9, 0.0, 0.5)
+    b = (6.8, 0.0, 1.3)
+    cp = (10.9 * np.cos(gam), 10.9 * np.sin(gam), 2.2)
+    cm = (10.9 * np.cos(gam), -10.9 * np.sin(gam), 2.2)
+    pts = [a, b, cp, cm] if low_first else [a, b, cm, cp]
+    return event(pts, [0, 1, 2, 2]), (0, 1, 2)
+
+
+def chain_detector(det, n_layers):
+    """A barrel-only detector of n_layers layers at radii 3, 4, ... cm, each
+    layer paired with the next: a straight radial track crosses all of them
+    and forms one path of n_layers hits."""
+    d = dict(det)
+    d["layers"] = [{"id": i, "kind": 0, "r": 3.0 + i, "zmax": 30.0} for i in range(n_layers)]
+    d["pairs"] = [(i, i + 1) for i in range(n_layers - 1)]
+    return d
+
+
+def chain_event(n_layers, phi=0.7, slope=0.25, z0=0.5):
+    pts = [((3.0 + i) * np.cos(phi), (3.0 + i) * np.sin(phi), z0 + slope * (3.0 + i))
+           for i in range(n_layers)]
+    return event(pts, list(range(n_layers)))
+
+
+def longer_beats_lower_score(det):
+    """The scored quadruplet plus a hit on layer 2 that makes a triplet
+    (0, 1, 4) sharing the quadruplet's first doublet with a much lower score
+    (a straight continuation of the first doublet, 0.004 rad off in phi) and
+    no continuation of its own: only the length rule keeps the quadruplet.
+    Returns (event, winner)."""
+    q = scored_quadruplet(det)
+    a = (float(q.x[0]), float(q.y[0]), float(q.z[0]))
+    b = (float(q.x[1]), float(q.y[1]), float(q.z[1]))
+    ra, rb = np.hypot(a[0], a[1]), np.hypot(b[0], b[1])
+    alpha = np.arctan2(b[2] - a[2], rb - ra)
+    pa, pb = np.arctan2(a[1], a[0]), np.arctan2(b[1], b[0])
+    rc = 10.9
+    pc = pb + (pb - pa) * (rc - rb) / (rb - ra) - 0.004
+    c2 = (rc * np.cos(pc), rc * np.sin(pc), b[2] + (rc - rb) * np.tan(alpha))
+    pts = [(q.x[i], q.y[i], q.z[i]) for i in range(4)] + [c2]
+    return event(pts, [0, 1, 2, 3, 2]), (0, 1, 2, 3)
+
+
+def tie_detector(det):
+    """The standard cuts and fit constants on four barrel layers, two of them
+    at the same radius 2.9 cm (ids 0 and 1), paired (1,2), (0,2), (2,3) in
+    that order: the doublets of layer 1 come before those of layer 0."""
+    d = dict(det)
+    d["layers"] = [{"id": 0, "kind": 0, "r": 2.9, "zmax": 26.5},
+                   {"id": 1, "kind": 0, "r": 2.9, "zmax": 26.5},
+                   {"id": 2, "kind": 0, "r": 6.8, "zmax": 26.5},
+                   {"id": 3, "kind": 0, "r": 10.9, "zmax": 26.5}]
+    d["pairs"] = [(1, 2), (0, 2), (2, 3)]
+    return d
+
+
+def tie_across_roots(det):
+    """Two triplets sharing their outer doublet (b, c), b and c on the +x
+    axis, their first hits mirror images in y on the two same-radius layers
+    of tie_detector: bitwise-equal scores, different root doublets.  The
+    lexicographically smaller tuple starts at hit 0 (layer 0), whose root
+    doublet comes second in doublet order, so keeping the first tuple met
+    would pick the wrong one.  Returns (event, detector, winner)."""
+    gam = 0.002
+    p = (2.9 * np.cos(gam), 2.9 * np.sin(gam), 0.4)
+    pm = (2.9 * np.cos(gam), -2.9 * np.sin(gam), 0.4)
+    b = (6.8, 0.0, 1.2)
+    c = (10.9, 0.0, 2.1)
+    return event([p, pm, b, c], [0, 1, 2, 3]), tie_detector(det), (0, 2, 3)

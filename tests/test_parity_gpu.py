@@ -12,7 +12,9 @@ import pytest
 
 import eventgen
 import oracle
-from tests.compare import FIT_RTOL, canon_rows, fit_errors, match_tracks, per_event_rows
+from tests import constructed as cs
+from tests.compare import (FIT_RTOL, canon_rows, correlations, fit_errors, match_tracks,
+                           oracle_events, per_event_rows)
 
 pytestmark = pytest.mark.gpu
 
@@ -27,12 +29,12 @@ def torch():
     return t
 
 
-def make_rec(**kw):
+def make_rec(det=DET, **kw):
     import paper_2104_06573_amd as pxt
     caps = dict(max_events=64, max_hits=1 << 20, max_doublets=1 << 22, max_link_words=1 << 24,
                 max_tuples=1 << 20, max_tracks=1 << 19)
     caps.update(kw)
-    return pxt.Reconstructor(DET, **caps)
+    return pxt.Reconstructor(det, **caps)
 
 
 def run_and_dump(rec, events):
@@ -45,18 +47,27 @@ def run_and_dump(rec, events):
     return res, out, dumps
 
 
-def check_events(events, res, out, dumps, check_cov=True, fit_stats=None):
+def check_events(events, res, out, dumps, check_cov=True, fit_stats=None, det=DET, oref=None):
+    """Every event of a call against the oracle: doublets, links, raw
+    n-tuplets (when dumps are given) and tracks bit-exact; fits within
+    FIT_RTOL; covariance diagonal (square roots) within 1e-3 relative and
+    its correlation coefficients within 1e-3; chi2 within 2e-3."""
     n = len(events)
-    D = per_event_rows(dumps["d"], n)
-    L = per_event_rows(dumps["l"], n)
-    R = per_event_rows(dumps["r"], n)
+    if oref is None:
+        oref = oracle_events(events, det)
+    if dumps is not None:
+        D = per_event_rows(dumps["d"], n)
+        L = per_event_rows(dumps["l"], n)
+        R = per_event_rows(dumps["r"], n)
     tot_tracks = 0
     for e, ev in enumerate(events):
-        o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, DET)
+        o = oref[e]
         assert o["status"] == 0
-        np.testing.assert_array_equal(D[e], canon_rows(o["doublets"]), err_msg="doublets ev%d" % e)
-        np.testing.assert_array_equal(L[e], canon_rows(o["links"]), err_msg="links ev%d" % e)
-        np.testing.assert_array_equal(R[e], canon_rows(o["raw"]), err_msg="raw tuples ev%d" % e)
+        if dumps is not None:
+            np.testing.assert_array_equal(D[e], canon_rows(o["doublets"]),
+                                          err_msg="doublets ev%d" % e)
+            np.testing.assert_array_equal(L[e], canon_rows(o["links"]), err_msg="links ev%d" % e)
+            np.testing.assert_array_equal(R[e], canon_rows(o["raw"]), err_msg="raw tuples ev%d" % e)
         gh, gp, gc, gx, gf, oh, op, oc, ox = match_tracks(out, o, e)
         np.testing.assert_array_equal(gh, oh, err_msg="tracks ev%d" % e)
         assert int(out["per_event_tracks"][e]) == oh.shape[0]
@@ -73,6 +84,8 @@ def check_events(events, res, out, dumps, check_cov=True, fit_stats=None):
             sg = np.sqrt(gc[:, diag].astype(np.float64))
             so = np.sqrt(oc[:, diag])
             np.testing.assert_allclose(sg, so, rtol=1e-3, err_msg="cov diag ev%d" % e)
+            np.testing.assert_allclose(correlations(gc), correlations(oc), rtol=0, atol=1e-3,
+                                       err_msg="cov correlations ev%d" % e)
             np.testing.assert_allclose(gx, ox, rtol=2e-3, atol=2e-3, err_msg="chi2 ev%d" % e)
     assert res.counts["n_tracks"] == tot_tracks
 
@@ -323,3 +336,41 @@ def test_graph_replays_match_direct(torch):
     r = small.run_numpy([eventgen.generate("pu50", 3)])
     assert r.counts["status"] == 2
     assert small.run_numpy([eventgen.generate("tiny", 5)]).counts["status"] == 0
+
+
+def test_constructed_cleaning_cases(torch):
+    # hand-built events whose winner is fixed by geometry (tests/constructed):
+    # the score's closed form, the impact term deciding, the length rule
+    # beating a lower score, bitwise-equal scores decided by the hit order
+    # (within one root and across roots), the longest path of 8 hits
+    cases = [(cs.scored_quadruplet(DET), DET), (cs.impact_decides(DET)[0], DET),
+             (cs.longer_beats_lower_score(DET)[0], DET), (cs.exact_tie(DET, True)[0], DET),
+             (cs.exact_tie(DET, False)[0], DET)]
+    ev, d, _ = cs.tie_across_roots(DET)
+    cases.append((ev, d))
+    cases.append((cs.chain_event(8), cs.chain_detector(DET, 8)))
+    for mode in (0, 1, 2):
+        for ev, d in cases:
+            rec = make_rec(det=d, max_events=4, max_hits=4096, max_doublets=1 << 16,
+                           max_tuples=1 << 14, max_tracks=1 << 14, doublet_mode=mode)
+            res, out, dumps = run_and_dump(rec, [ev])
+            check_events([ev], res, out, dumps, det=d)
+            rec.close()
+
+
+def test_path_longer_than_eight_hits(torch):
+    import paper_2104_06573_amd as pxt
+    d9 = cs.chain_detector(DET, 9)
+    ev9 = cs.chain_event(9)
+    o = oracle.reconstruct(ev9.x, ev9.y, ev9.z, ev9.layer, d9)
+    assert o["status"] == 1
+    rec = make_rec(det=d9, max_events=4, max_hits=4096, max_doublets=1 << 16,
+                   max_tuples=1 << 14, max_tracks=1 << 14)
+    r = rec.run_numpy([eventgen.generate("tiny", 1, det=DET), ev9])
+    assert r.counts["status"] == pxt.ERR_PATH, r.counts
+    assert r.counts["n_tracks"] == 0
+    # the context recovers: the same track on eight of the nine layers
+    keep = np.arange(8)
+    ev8 = cs.Ev(ev9.x[keep], ev9.y[keep], ev9.z[keep], ev9.layer[keep])
+    res, out, dumps = run_and_dump(rec, [ev8])
+    check_events([ev8], res, out, dumps, det=d9)

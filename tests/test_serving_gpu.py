@@ -45,12 +45,15 @@ def test_mix_equals_solo(torch):
     events = eventgen.make_batch("serve", 24, seed=5)
     solo = _solo(events)
     srv = Server(DET, n_lanes=3, max_batch_events=8, **CAPS)
-    rep = poisson_run(srv, events, rate_hz=3000.0, keep_results=True)
+    # arrivals 50 us apart on average, several times faster than a batch
+    # takes on the device: requests arrive while others are on the GPU, so
+    # some are admitted together into one batch
+    rep = poisson_run(srv, events, rate_hz=20000.0, keep_results=True)
     st = srv.stats()
     srv.close()
     assert rep["failed"] == 0
     assert st["completed"] == len(events) and st["failed"] == 0
-    assert rep["mean_batch"] >= 1.0
+    assert max(r["batch_events"] for r in rep["results"]) > 1, st
     for i, (res, ref) in enumerate(zip(rep["results"], solo)):
         got = _canon(res)
         np.testing.assert_array_equal(got[0], ref[0], err_msg="tracks of event %d" % i)
