@@ -38,6 +38,7 @@ def _rec(kind, events, n_events=None, **tuning):
         caps = bench.batch_caps(kind, len(events), sum(e.n_hits for e in events))
     else:
         caps = bench.batch_caps(kind, n_events, max(e.n_hits for e in events) * n_events)
+    caps.update({k: tuning.pop(k) for k in list(tuning) if k.startswith("max_")})
     kw = dict(phi_bins=256, group_lanes=8, link_kernel=0, use_graph=1, doublet_mode=2)
     kw.update(tuning)
     return pxt.Reconstructor(DET, **caps, **kw)
@@ -97,9 +98,11 @@ def test_pu200_batch_graph(torch):
 
 def test_ragged_batch64_graph(torch):
     # the ragged mix: 64 events with U{300..3000} tracks each
+    # (doublets grow with the square of the hits: the mix's 3000-track events
+    # need more than the PU~50 recipe's 100k per event)
     events = eventgen.make_batch("batch", 64, seed=7)
     oref = oracle_events(events, DET)
-    rec = _rec("pu50", events)
+    rec = _rec("pu50", events, max_doublets=12 << 20, max_link_words=48 << 20)
     d = rec.upload(events)
     rec.launch(*d)
     torch.cuda.synchronize()
