@@ -65,6 +65,15 @@ DETECTOR = {
         # curvature floor for the scattering momentum estimate: pT <= 1e4 GeV
         "pt_max": 1.0e4,
     },
+    "vertex": {
+        # tracks used: at least this many hits and pT at least pt_min (GeV)
+        "min_hits": 4,
+        "pt_min": 0.5,
+        # density clustering of z0: neighbours within eps (cm), a core has
+        # at least min_pts neighbours (itself included)
+        "eps": 0.02,
+        "min_pts": 6,
+    },
 }
 
 

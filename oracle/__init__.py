@@ -57,6 +57,11 @@ class Config(ctypes.Structure):
     ]
 
 
+class VtxConfig(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("min_pts", ctypes.c_int), ("min_hits", ctypes.c_int),
+                ("qopt_max", ctypes.c_float)]
+
+
 def build(force=False):
     """Compile the C oracle with gcc (FP64, no FMA contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -85,6 +90,9 @@ def load_library(path):
     L.orc_link_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 9
     L.orc_link_terms.argtypes = [ctypes.POINTER(Config)] + [d] * 9 + [ctypes.c_void_p]
     L.orc_fit.argtypes = [ctypes.POINTER(Config), ctypes.c_int] + [ctypes.c_void_p] * 8
+    L.orc_vertices.restype = ctypes.c_int
+    L.orc_vertices.argtypes = [ctypes.POINTER(VtxConfig), ctypes.c_uint32] + \
+        [ctypes.c_void_p] * 9 + [ctypes.c_uint32]
     return L
 
 
@@ -212,3 +220,46 @@ def canonical(tuples):
         return t
     keys = tuple(t[:, i] for i in range(t.shape[1] - 1, -1, -1))
     return t[np.lexsort(keys)]
+
+
+def vtx_config(det):
+    """Vertex-finding constants of the detector dictionary; qopt_max is
+    1/pT_min rounded to single precision (the selection compares single
+    precision values)."""
+    v = det["vertex"]
+    return VtxConfig(float(v["eps"]), int(v["min_pts"]), int(v["min_hits"]),
+                     float(np.float32(1.0 / v["pt_min"])))
+
+
+def vertices(z0, var, qopt, nhits, det=None, cfg=None):
+    """Vertices of one event from its tracks' single-precision z0, var(z0),
+    q/pT and hit counts (the reading is stated in pxt_oracle.c).  Returns a
+    dict: z, z_err, chi2 (float64 [nv]), n_tracks (uint32 [nv]), assign
+    (int32 [n], -1 for tracks in no vertex)."""
+    L = lib()
+    c = cfg if cfg is not None else vtx_config(det)
+    z0 = np.ascontiguousarray(z0, np.float32)
+    var = np.ascontiguousarray(var, np.float32)
+    qopt = np.ascontiguousarray(qopt, np.float32)
+    nhits = np.ascontiguousarray(nhits, np.uint8)
+    n = z0.shape[0]
+    assign = np.zeros(n, np.int32)
+    cap = n + 1
+    vz = np.zeros(cap); ve = np.zeros(cap); vc = np.zeros(cap)
+    vn = np.zeros(cap, np.uint32)
+    nv = L.orc_vertices(ctypes.byref(c), n, _ptr(z0), _ptr(var), _ptr(qopt), _ptr(nhits),
+                        _ptr(assign), _ptr(vz), _ptr(ve), _ptr(vc), _ptr(vn), cap)
+    return {"z": vz[:nv], "z_err": ve[:nv], "chi2": vc[:nv], "n_tracks": vn[:nv],
+            "assign": assign}
+
+
+def event_vertices(o, det):
+    """Vertices of an event from the oracle's own reconstruction `o` (the
+    dict of reconstruct()), its fitted values rounded to single precision
+    as the library hands them over."""
+    p = np.asarray(o["params"], np.float32)
+    cv = np.asarray(o["cov"], np.float32)
+    nh = (np.asarray(o["tracks"]) != PAD).sum(axis=1).astype(np.uint8)
+    if p.shape[0] == 0:
+        return vertices(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), det)
+    return vertices(p[:, 4], cv[:, 14], p[:, 2], nh, det)

@@ -237,3 +237,67 @@ def reconstruct(x, y, z, layer, det):
     S = scores(T, x, y, z, det)
     keep = clean(T, S) if T.shape[0] else np.zeros(0, bool)
     return dict(doublets=D, links=L, raw=T, raw_score=S, keep=keep, tracks=T[keep])
+
+
+def vertices(z0, var, qopt, nhits, eps, min_pts, min_hits, qopt_max):
+    """Vertices by textbook DBSCAN (Ester et al. 1996): the full pairwise
+    distance matrix, clusters grown from each unvisited core by breadth-first
+    expansion over core neighbours, borders to the nearest core (ties to the
+    smaller z0, then the smaller index), weighted means by numpy sums.
+    Returns (z, z_err, chi2, n_tracks, assign) with vertices in increasing z."""
+    z0 = np.asarray(z0, np.float32)
+    var = np.asarray(var, np.float32)
+    qopt = np.asarray(qopt, np.float32)
+    nhits = np.asarray(nhits)
+    n = z0.shape[0]
+    sel = ((nhits >= min_hits) & (np.abs(qopt) <= np.float32(qopt_max)) & np.isfinite(z0)
+           & np.isfinite(var) & (var > 0))
+    idx = np.nonzero(sel)[0]
+    z = z0[idx].astype(np.float64)
+    dist = np.abs(z[:, None] - z[None, :])
+    nb = dist <= eps
+    core = nb.sum(axis=1) >= min_pts
+    label = -np.ones(idx.size, np.int64)
+    k = 0
+    for s in range(idx.size):
+        if not core[s] or label[s] >= 0:
+            continue
+        label[s] = k
+        queue = [s]
+        while queue:
+            a = queue.pop(0)
+            for b in np.nonzero(nb[a] & core)[0]:
+                if label[b] < 0:
+                    label[b] = k
+                    queue.append(b)
+        k += 1
+    cores = np.nonzero(core)[0]
+    for a in range(idx.size):
+        if core[a] or cores.size == 0:
+            continue
+        d = dist[a, cores]
+        ok = d <= eps
+        if not ok.any():
+            continue
+        cand = cores[ok]
+        dc = d[ok]
+        best = cand[dc == dc.min()]
+        # nearest; ties to the smaller z0, then the smaller track index
+        best = sorted(best, key=lambda b: (z[b], idx[b]))[0]
+        label[a] = label[best]
+    # number the clusters by increasing z of their members
+    order = sorted(set(label[label >= 0].tolist()), key=lambda c: z[label == c].min())
+    ren = {c: i for i, c in enumerate(order)}
+    assign = -np.ones(n, np.int32)
+    vz, ve, vc, vn = [], [], [], []
+    for c in order:
+        m = label == c
+        assign[idx[m]] = ren[c]
+        w = 1.0 / var[idx[m]].astype(np.float64)
+        zm = z[m]
+        zv = np.sum(w * zm) / np.sum(w)
+        vz.append(zv)
+        ve.append(np.sqrt(1.0 / np.sum(w)))
+        vc.append(np.sum(w * (zm - zv) ** 2))
+        vn.append(int(m.sum()))
+    return (np.array(vz), np.array(ve), np.array(vc), np.array(vn, np.uint32), assign)

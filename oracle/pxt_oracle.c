@@ -670,3 +670,149 @@ void orc_free(orc_result* R) {
   for (int i = 0; i < ORC_NITEMS; ++i) free(R->item[i].p);
   free(R);
 }
+
+/* ------------------------------------------------------------------ */
+/* Vertices (the paper's Vertices module, Sec. 2 and Fig. 1: vertices are
+ * formed from the pixel tracks).  The paper gives no algorithm; the reading
+ * here is one-dimensional density-based clustering (DBSCAN, Ester et al.,
+ * KDD 1996) of the tracks' longitudinal impact parameters z0:
+ *
+ *   selection  tracks with at least min_hits hits, |q/pT| <= qopt_max
+ *              (single precision, as the values are given), finite z0 and
+ *              a finite positive variance of z0;
+ *   neighbours tracks i, j with |z0_j - z0_i| <= eps (the difference of the
+ *              single-precision values taken in double precision, which is
+ *              exact), each track its own neighbour;
+ *   core       a track with at least min_pts neighbours;
+ *   clusters   connected components of the cores under the neighbour
+ *              relation;
+ *   border     a non-core track with a core neighbour joins the cluster of
+ *              its nearest core neighbour (on a tie, the core with the
+ *              smaller z0, then the smaller index); other tracks are noise;
+ *   vertex     per cluster, over its members in increasing (z0, index):
+ *              w = 1/var, z = sum(w z0)/sum(w), sigma_z = sqrt(1/sum(w)),
+ *              chi2 = sum(w (z0 - z)^2), summed in that order.
+ *
+ * Vertices come out in increasing z (clusters are disjoint intervals of the
+ * sorted track list).  assign[i] = the vertex of track i, or -1. */
+
+typedef struct {
+  double eps;
+  int min_pts;
+  int min_hits;
+  float qopt_max;
+} orc_vtx_config;
+
+typedef struct {
+  float z;
+  uint32_t i;
+} orc_zi;
+
+static int zi_cmp(const void* a, const void* b) {
+  const orc_zi* p = (const orc_zi*)a;
+  const orc_zi* q = (const orc_zi*)b;
+  if (p->z != q->z) return p->z < q->z ? -1 : 1;
+  return p->i < q->i ? -1 : (p->i > q->i ? 1 : 0);
+}
+
+static uint32_t uf_find(uint32_t* par, uint32_t a) {
+  while (par[a] != a) {
+    par[a] = par[par[a]];
+    a = par[a];
+  }
+  return a;
+}
+
+int orc_vertices(const orc_vtx_config* c, uint32_t n, const float* z0, const float* var,
+                 const float* qopt, const uint8_t* nhits, int32_t* assign, double* vz,
+                 double* verr, double* vchi2, uint32_t* vn, uint32_t cap) {
+  orc_zi* s = (orc_zi*)malloc(sizeof(orc_zi) * (n + 1));
+  uint32_t m = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    assign[i] = -1;
+    const int ok = nhits[i] >= c->min_hits && fabsf(qopt[i]) <= c->qopt_max &&
+                   isfinite(z0[i]) && isfinite(var[i]) && var[i] > 0.0f;
+    if (ok) {
+      s[m].z = z0[i];
+      s[m].i = i;
+      ++m;
+    }
+  }
+  qsort(s, m, sizeof(orc_zi), zi_cmp);
+  /* cores: neighbours counted over all selected tracks */
+  uint8_t* core = (uint8_t*)calloc(m + 1, 1);
+  for (uint32_t a = 0; a < m; ++a) {
+    int cnt = 0;
+    for (uint32_t b = 0; b < m; ++b)
+      if (fabs((double)s[b].z - (double)s[a].z) <= c->eps) ++cnt;
+    core[a] = cnt >= c->min_pts;
+  }
+  /* clusters: union of every pair of neighbouring cores */
+  uint32_t* par = (uint32_t*)malloc(sizeof(uint32_t) * (m + 1));
+  for (uint32_t a = 0; a < m; ++a) par[a] = a;
+  for (uint32_t a = 0; a < m; ++a)
+    for (uint32_t b = a + 1; b < m; ++b)
+      if (core[a] && core[b] && fabs((double)s[b].z - (double)s[a].z) <= c->eps) {
+        const uint32_t ra = uf_find(par, a), rb = uf_find(par, b);
+        if (ra != rb) par[ra > rb ? ra : rb] = ra < rb ? ra : rb;
+      }
+  /* label of each sorted track: the root of its core (cores), or of its
+   * nearest core neighbour (borders); UINT32_MAX for noise */
+  uint32_t* lab = (uint32_t*)malloc(sizeof(uint32_t) * (m + 1));
+  for (uint32_t a = 0; a < m; ++a) {
+    lab[a] = 0xffffffffu;
+    if (core[a]) {
+      lab[a] = uf_find(par, a);
+      continue;
+    }
+    double bd = 0.0;
+    int64_t bb = -1;
+    for (uint32_t b = 0; b < m; ++b) {
+      if (!core[b]) continue;
+      const double d = fabs((double)s[b].z - (double)s[a].z);
+      if (d > c->eps) continue;
+      /* b runs in increasing (z0, index): a later core wins only if nearer */
+      if (bb < 0 || d < bd) {
+        bd = d;
+        bb = b;
+      }
+    }
+    if (bb >= 0) lab[a] = uf_find(par, (uint32_t)bb);
+  }
+  /* vertices in increasing z: a cluster's number is fixed by its first
+   * member in sorted order */
+  int32_t* vid = (int32_t*)malloc(sizeof(int32_t) * (m + 1));
+  for (uint32_t a = 0; a < m; ++a) vid[a] = -1;
+  uint32_t nv = 0;
+  for (uint32_t a = 0; a < m; ++a) {
+    if (lab[a] == 0xffffffffu) continue;
+    if (vid[lab[a]] < 0) vid[lab[a]] = (int32_t)nv++;
+  }
+  for (uint32_t v = 0; v < nv && v < cap; ++v) {
+    double sw = 0.0, swz = 0.0;
+    uint32_t k = 0;
+    for (uint32_t a = 0; a < m; ++a) {
+      if (lab[a] == 0xffffffffu || vid[lab[a]] != (int32_t)v) continue;
+      const double w = 1.0 / (double)var[s[a].i];
+      sw += w;
+      swz += w * (double)s[a].z;
+      ++k;
+    }
+    const double zv = swz / sw;
+    double chi2 = 0.0;
+    for (uint32_t a = 0; a < m; ++a) {
+      if (lab[a] == 0xffffffffu || vid[lab[a]] != (int32_t)v) continue;
+      const double w = 1.0 / (double)var[s[a].i];
+      const double r = (double)s[a].z - zv;
+      chi2 += w * r * r;
+    }
+    vz[v] = zv;
+    verr[v] = sqrt(1.0 / sw);
+    vchi2[v] = chi2;
+    vn[v] = k;
+  }
+  for (uint32_t a = 0; a < m; ++a)
+    if (lab[a] != 0xffffffffu) assign[s[a].i] = vid[lab[a]];
+  free(s); free(core); free(par); free(lab); free(vid);
+  return (int)nv;
+}

@@ -15,6 +15,7 @@ import pytest
 import oracle
 from tests import test_oracle as pins
 from tests import test_oracle_cleaning as cpins
+from tests import test_oracle_vertices as vpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "pxt_oracle.c")
 
@@ -52,6 +53,31 @@ PINS = [
 ]
 
 
+# vertex finding: an exclusive neighbour distance, a core threshold off by
+# one, an unweighted mean, a border tie sent to the upper core, a strict pT
+# selection, chi2 without the weights
+VTX_MUTANTS = {
+    "vtx_eps_exclusive": ("if (fabs((double)s[b].z - (double)s[a].z) <= c->eps) ++cnt;",
+                          "if (fabs((double)s[b].z - (double)s[a].z) < c->eps) ++cnt;"),
+    "vtx_core_off_by_one": ("core[a] = cnt >= c->min_pts;", "core[a] = cnt > c->min_pts;"),
+    "vtx_unweighted_mean": ("swz += w * (double)s[a].z;", "swz += (double)s[a].z;"),
+    "vtx_border_tie_upper": ("if (bb < 0 || d < bd) {", "if (bb < 0 || d <= bd) {"),
+    "vtx_pt_selection_strict": ("fabsf(qopt[i]) <= c->qopt_max", "fabsf(qopt[i]) < c->qopt_max"),
+    "vtx_chi2_unweighted": ("chi2 += w * r * r;", "chi2 += r * r;"),
+}
+
+VTX_PINS = [
+    vpins.test_two_groups_closed_form,
+    vpins.test_weighted_mean_and_chi2_exact,
+    vpins.test_core_threshold,
+    vpins.test_neighbour_distance_is_inclusive,
+    vpins.test_chain_of_cores_is_one_vertex_and_a_gap_splits,
+    vpins.test_border_tie_goes_to_the_lower_vertex,
+    vpins.test_nearest_core_wins_a_border,
+    vpins.test_selection_boundaries,
+]
+
+
 @pytest.fixture(scope="module")
 def workdir():
     if shutil.which("gcc") is None:
@@ -59,6 +85,31 @@ def workdir():
     d = tempfile.mkdtemp()
     yield d
     shutil.rmtree(d, ignore_errors=True)
+
+
+def _mutant_lib(workdir, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not unique: %s" % name
+    path = os.path.join(workdir, name + ".c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    so = os.path.join(workdir, name + ".so")
+    subprocess.check_call(["gcc", "-O1", "-ffp-contract=off", "-shared", "-fPIC", "-o", so,
+                           path, "-lm"])
+    oracle.lib()  # the real one built and cached first
+    return oracle.load_library(so)
+
+
+@pytest.mark.parametrize("name", sorted(VTX_MUTANTS))
+def test_vertex_mutant_is_caught(workdir, name, monkeypatch):
+    monkeypatch.setattr(oracle, "_lib", _mutant_lib(workdir, name, *VTX_MUTANTS[name]))
+    failed = []
+    for pin in VTX_PINS:
+        try:
+            pin()
+        except (AssertionError, ValueError):
+            failed.append(pin)
+    assert failed, "no pin fails for mutant %s" % name
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
