@@ -235,6 +235,30 @@ int pxt_stage_times(pxt_ctx* ctx, float* ms, int cap, int* n_stages);
 /* Static name of stage i (0 <= i < PXT_N_STAGES), or NULL. */
 const char* pxt_stage_name(int stage);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the same
+ * computation as pxt_reconstruct on a context created from the same cfg,
+ * with no context and no allocation.  Every arena of the call is carved from
+ * one library-owned device buffer of PXT_STATIC_SCRATCH_BYTES per device,
+ * which each device that ran such a call holds until the process ends; the
+ * first call on a device only looks up the buffer's address.  cfg is
+ * validated as by pxt_create; its capacities must fit the buffer and
+ * in->n_events must not exceed PXT_STATIC_MAX_EVENTS, else
+ * PXT_ERR_CAPACITY is returned before anything is launched (the message,
+ * from pxt_last_error(NULL), gives the bytes the capacities need).  Always
+ * direct launches (cfg->use_graph is ignored), no stage timing, no debug
+ * dumps.  Asynchronous on `hip_stream` like pxt_reconstruct, with the same
+ * input/output contract and device status in out->counts.  All calls on one
+ * device share the buffer and keep nothing from one call to the next: calls
+ * that overlap on one device (different streams, or host threads without
+ * ordering) race and give wrong results; order them on one stream.  Other
+ * errors: PXT_ERR_INVALID_ARG, PXT_ERR_HIP (message from
+ * pxt_last_error(NULL), thread-local). */
+#define PXT_STATIC_SCRATCH_BYTES (64u << 20)
+#define PXT_STATIC_MAX_EVENTS 64
+int pxt_reconstruct_static(const pxt_config* cfg, int hip_device, const pxt_hits* in,
+                           pxt_tracks* out, void* hip_stream);
+
 /* ------------------------------------------------------------------ */
 /* Serving: continuous batching over several concurrent lanes.          */
 /*                                                                      */

@@ -33,7 +33,9 @@ EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_de
            "pxt_create", "pxt_destroy", "pxt_reconstruct", "pxt_debug_dump",
            "pxt_set_timing", "pxt_stage_times", "pxt_stage_name",
            "pxt_server_create", "pxt_submit", "pxt_poll", "pxt_server_get_stats",
-           "pxt_server_destroy")
+           "pxt_server_destroy", "pxt_reconstruct_static")
+STATIC_SCRATCH_BYTES = 64 << 20
+STATIC_MAX_EVENTS = 64
 N_STAGES = 19
 ABI_VERSION = 2  # layout of the structs below
 
@@ -132,6 +134,9 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int)]
         L.pxt_stage_name.restype = ctypes.c_char_p
         L.pxt_stage_name.argtypes = [ctypes.c_int]
+        L.pxt_reconstruct_static.argtypes = [ctypes.POINTER(PxtConfig), ctypes.c_int,
+                                             ctypes.POINTER(PxtHits), ctypes.POINTER(PxtTracks),
+                                             ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -267,6 +272,21 @@ class Reconstructor:
                                    self._stream(stream))
         if st != OK:
             raise PxtError(st, lib().pxt_last_error(self.h).decode())
+        return offs.shape[0] - 1
+
+    def launch_static(self, x, y, z, layer, offsets, stream=None):
+        """As launch(), through pxt_reconstruct_static: the same config and
+        output buffers, arenas in the library's fixed device buffer instead
+        of this object's context."""
+        offs = np.ascontiguousarray(offsets, dtype=np.uint32)
+        self._offs = offs
+        hits = PxtHits(offs.shape[0] - 1, offs.ctypes.data, x.data_ptr(), y.data_ptr(),
+                       z.data_ptr(), layer.data_ptr(), None)
+        st = lib().pxt_reconstruct_static(ctypes.byref(self.cfg), self.device.index or 0,
+                                          ctypes.byref(hits), ctypes.byref(self._tracks),
+                                          self._stream(stream))
+        if st != OK:
+            raise PxtError(st, lib().pxt_last_error(None).decode())
         return offs.shape[0] - 1
 
     def read_counts(self):

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -261,12 +262,12 @@ const char* const kStageNames[PXT_N_STAGES] = {
     "tuple_count", "tuple_scan", "tuple_fill",  "score",      "best",
     "survive",     "fit32",      "fit64",       "finish"};
 
-// Marks the start of stage i when timing is on.
+// Marks the start of stage i when timing is on (c == nullptr: no timing).
 struct StageMarks {
   pxt_ctx* c;
   hipStream_t s;
   void mark(int i) {
-    if (!c->timing) return;
+    if (!c || !c->timing) return;
     (void)hipEventRecord(c->ev[i], s);
     c->stage_run[i] = true;
   }
@@ -328,26 +329,22 @@ void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, cons
   }
 }
 
-// The launch sequence of one call on stream s.  In graph mode it is
-// captured once per slot: work sizes come from the capacities and every
-// kernel reads the call's actual sizes from the descriptor; in direct mode
-// the grids are sized from this call's hits (H) and events (E).
-void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, uint32_t E) {
-  const pxt_config& cfg = c->cfg;
-  const Ws& w = c->ws;
-  const DevCfg& d = c->dc;
+// The kernels of one call on stream s, after its descriptor is in place.
+// In graph mode the sequence is captured once per slot: work sizes come
+// from the capacities and every kernel reads the call's actual sizes from
+// the descriptor; in direct mode the grids are sized from this call's hits
+// (H) and events (E).  c supplies the stage timing (nullptr: none).
+void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& d, int n_cu,
+                  hipStream_t s, bool graph_mode, uint32_t H, uint32_t E) {
   const int bs = cfg.block_size;
-  const uint32_t persist = (uint32_t)c->n_cu * 8u;
-  const size_t copy = graph_mode ? c->slot_bytes : desc_bytes() + sizeof(uint32_t) * (E + 1);
-  (void)hipMemcpyAsync(const_cast<CallDesc*>(w.call), c->h_slots + (size_t)slot * c->slot_bytes,
-                       copy, hipMemcpyHostToDevice, s);
+  const uint32_t persist = (uint32_t)n_cu * 8u;
   if (graph_mode) {
     H = cfg.max_hits;
     E = cfg.max_events;
   }
   const uint32_t nbins = E * (uint32_t)cfg.n_layers * (uint32_t)cfg.phi_bins;
   StageMarks sm{c, s};
-  const bool timed = c->timing && !graph_mode;
+  const bool timed = c && c->timing && !graph_mode;
   if (timed)
     for (int i = 0; i < PXT_N_STAGES; ++i) c->stage_run[i] = false;
   if (timed) sm.mark(0);
@@ -428,7 +425,7 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
       hipLaunchKernelGGL(k_fit32<0>, dim3(gf), dim3(256), 0, s, w, d);
     }
     if (timed) sm.mark(17);
-    hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)c->n_cu)), dim3(64),
+    hipLaunchKernelGGL(k_fit64, dim3(grid_for(cfg.max_tuples, 64, (uint32_t)n_cu)), dim3(64),
                        0, s, w, d);
   }
   if (timed) sm.mark(18);
@@ -438,6 +435,83 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
     c->timed_valid = true;
   }
 }
+
+// One call of a context: its descriptor and event offsets from the pinned
+// slot, then the kernels.
+void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, uint32_t E) {
+  const size_t copy = graph_mode ? c->slot_bytes : desc_bytes() + sizeof(uint32_t) * (E + 1);
+  (void)hipMemcpyAsync(const_cast<CallDesc*>(c->ws.call),
+                       c->h_slots + (size_t)slot * c->slot_bytes, copy, hipMemcpyHostToDevice, s);
+  enqueue_path(c, c->cfg, c->ws, c->dc, c->n_cu, s, graph_mode, H, E);
+}
+
+// Checks of one call's input and output descriptions against cfg.
+int validate_call(const pxt_config& cfg, const pxt_hits* in, const pxt_tracks* out,
+                  std::string& why) {
+  if (!in || !out) return why = "null argument", 1;
+  const uint32_t E = in->n_events;
+  if (E > cfg.max_events) return why = "n_events above max_events", 1;
+  if (!in->event_offsets) return why = "null event_offsets", 1;
+  if (in->event_offsets[0] != 0) return why = "event_offsets[0] != 0", 1;
+  for (uint32_t e = 0; e < E; ++e)
+    if (in->event_offsets[e + 1] < in->event_offsets[e]) return why = "decreasing event_offsets", 1;
+  const uint32_t H = in->event_offsets[E];
+  if (H > cfg.max_hits) return why = "more hits than max_hits", 1;
+  if (H > 0 && (!in->x || !in->y || !in->z || !in->layer)) return why = "null hit array", 1;
+  if (!out->counts || (E > 0 && !out->per_event_tracks))
+    return why = "null counts / per_event_tracks", 1;
+  if (out->capacity > 0 && (!out->hit_idx || !out->n_hits || !out->event_id || !out->params ||
+                            !out->cov || !out->chi2 || !out->flags))
+    return why = "null track buffer", 1;
+  return 0;
+}
+
+CallDesc make_desc(const pxt_hits* in, const pxt_tracks* out) {
+  CallDesc desc{};
+  desc.n_events = in->n_events;
+  desc.n_hits = in->event_offsets[in->n_events];
+  desc.x = in->x;
+  desc.y = in->y;
+  desc.z = in->z;
+  desc.layer = in->layer;
+  desc.out = OutPtrs{out->capacity, out->hit_idx, out->n_hits, out->event_id, out->params,
+                     out->cov, out->chi2, out->flags, out->per_event_tracks, out->counts};
+  return desc;
+}
+
+// ------------------------------------------- calls without allocation --
+// pxt_reconstruct_static carves the arenas of one call from this buffer
+// instead of a context's allocation.  In host code `scratch` names a
+// host-side stand-in: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// ever passed to kernels.
+static __device__ __align__(256) unsigned char scratch[PXT_STATIC_SCRATCH_BYTES];
+
+// A call's descriptor and event offsets, passed by value to the kernel
+// that writes them where the other kernels read them.
+struct StaticCall {
+  CallDesc desc;
+  uint32_t offsets[PXT_STATIC_MAX_EVENTS + 1];
+};
+
+__global__ void k_set_call(CallDesc* dst, uint32_t* evt_off, StaticCall sc, uint32_t n_off,
+                           uint32_t* epoch) {
+  if (threadIdx.x == 0) {
+    *dst = sc.desc;
+    *epoch = 0u;
+  }
+  for (uint32_t i = threadIdx.x; i < n_off; i += blockDim.x) evt_off[i] = sc.offsets[i];
+}
+
+struct StaticDevice {
+  std::once_flag once;
+  hipError_t err = hipSuccess;
+  void* ptr = nullptr;  // device address of `scratch` on this device
+  int n_cu = 256;
+};
+
+constexpr int kStaticDevicesMax = 64;
+StaticDevice g_static[kStaticDevicesMax];
 
 }  // namespace
 
@@ -551,24 +625,11 @@ void pxt_destroy(pxt_ctx* c) {
 
 int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* stream) {
   if (!c) return PXT_ERR_INVALID_ARG;
-  if (!in || !out) return fail(c, PXT_ERR_INVALID_ARG, "null argument");
   const pxt_config& cfg = c->cfg;
+  std::string why;
+  if (validate_call(cfg, in, out, why)) return fail(c, PXT_ERR_INVALID_ARG, why);
   const uint32_t E = in->n_events;
-  if (E > cfg.max_events) return fail(c, PXT_ERR_INVALID_ARG, "n_events above max_events");
-  if (!in->event_offsets) return fail(c, PXT_ERR_INVALID_ARG, "null event_offsets");
-  if (in->event_offsets[0] != 0) return fail(c, PXT_ERR_INVALID_ARG, "event_offsets[0] != 0");
-  for (uint32_t e = 0; e < E; ++e)
-    if (in->event_offsets[e + 1] < in->event_offsets[e])
-      return fail(c, PXT_ERR_INVALID_ARG, "decreasing event_offsets");
   const uint32_t H = in->event_offsets[E];
-  if (H > cfg.max_hits) return fail(c, PXT_ERR_INVALID_ARG, "more hits than max_hits");
-  if (H > 0 && (!in->x || !in->y || !in->z || !in->layer))
-    return fail(c, PXT_ERR_INVALID_ARG, "null hit array");
-  if (!out->counts || (E > 0 && !out->per_event_tracks))
-    return fail(c, PXT_ERR_INVALID_ARG, "null counts / per_event_tracks");
-  if (out->capacity > 0 && (!out->hit_idx || !out->n_hits || !out->event_id || !out->params ||
-                            !out->cov || !out->chi2 || !out->flags))
-    return fail(c, PXT_ERR_INVALID_ARG, "null track buffer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_OR_FAIL(c, hipSetDevice(c->device));
 
@@ -577,15 +638,7 @@ int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* strea
   c->next_slot = (slot + 1) % pxt_ctx::kSlots;
   if (c->slot_pending[slot]) HIP_OR_FAIL(c, hipEventSynchronize(c->slot_free[slot]));
   char* hs = c->h_slots + (size_t)slot * c->slot_bytes;
-  CallDesc desc{};
-  desc.n_events = E;
-  desc.n_hits = H;
-  desc.x = in->x;
-  desc.y = in->y;
-  desc.z = in->z;
-  desc.layer = in->layer;
-  desc.out = OutPtrs{out->capacity, out->hit_idx, out->n_hits, out->event_id, out->params,
-                     out->cov, out->chi2, out->flags, out->per_event_tracks, out->counts};
+  const CallDesc desc = make_desc(in, out);
   std::memcpy(hs, &desc, sizeof(desc));
   std::memcpy(hs + desc_bytes(), in->event_offsets, sizeof(uint32_t) * (E + 1));
 
@@ -736,6 +789,66 @@ int pxt_stage_times(pxt_ctx* c, float* ms, int cap, int* n_stages) {
 
 const char* pxt_stage_name(int i) {
   return (i >= 0 && i < PXT_N_STAGES) ? kStageNames[i] : nullptr;
+}
+
+int pxt_reconstruct_static(const pxt_config* cfg, int hip_device, const pxt_hits* in,
+                           pxt_tracks* out, void* stream) {
+  if (!cfg) return fail(nullptr, PXT_ERR_INVALID_ARG, "null config");
+  std::string why;
+  if (validate_config(cfg, why)) return fail(nullptr, PXT_ERR_INVALID_ARG, why);
+  if (validate_call(*cfg, in, out, why)) return fail(nullptr, PXT_ERR_INVALID_ARG, why);
+  const uint32_t E = in->n_events;
+  if (E > PXT_STATIC_MAX_EVENTS)
+    return fail(nullptr, PXT_ERR_CAPACITY,
+                "n_events above PXT_STATIC_MAX_EVENTS (" +
+                    std::to_string(PXT_STATIC_MAX_EVENTS) + ")");
+  Carver size_pass;
+  Ws w{};
+  carve(size_pass, *cfg, w);
+  if (size_pass.off > (size_t)PXT_STATIC_SCRATCH_BYTES)
+    return fail(nullptr, PXT_ERR_CAPACITY,
+                "the configured capacities need " + std::to_string(size_pass.off) +
+                    " bytes of arenas, above PXT_STATIC_SCRATCH_BYTES (" +
+                    std::to_string((size_t)PXT_STATIC_SCRATCH_BYTES) + ")");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev ||
+      hip_device >= kStaticDevicesMax)
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "no such HIP device");
+  if (hipSetDevice(hip_device) != hipSuccess)
+    return fail(nullptr, PXT_ERR_HIP, "hipSetDevice failed");
+  StaticDevice& sd = g_static[hip_device];
+  std::call_once(sd.once, [&sd, hip_device]() {
+    sd.err = hipGetSymbolAddress(&sd.ptr, HIP_SYMBOL(scratch));
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, hip_device) ==
+            hipSuccess && n > 0)
+      sd.n_cu = n;
+  });
+  if (sd.err != hipSuccess || !sd.ptr)
+    return fail(nullptr, PXT_ERR_HIP,
+                std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(sd.err));
+  Carver real;
+  real.base = static_cast<char*>(sd.ptr);
+  carve(real, *cfg, w);
+  DevCfg dc;
+  make_devcfg(*cfg, dc);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the buffer keeps the previous call's contents: the scan status words
+  // and the call counter start again from zero, the rest is never read
+  // before this call writes it
+  const uint64_t ntiles = scan_tiles(*cfg);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(ntiles, 256, 1024)), dim3(256), 0, s,
+                     w.scan_status, ntiles, 0ull);
+  StaticCall sc{};
+  sc.desc = make_desc(in, out);
+  std::memcpy(sc.offsets, in->event_offsets, sizeof(uint32_t) * (E + 1));
+  hipLaunchKernelGGL(k_set_call, dim3(1), dim3(64), 0, s, const_cast<CallDesc*>(w.call),
+                     w.evt_off, sc, E + 1, w.epoch);
+  enqueue_path(nullptr, *cfg, w, dc, sd.n_cu, s, false, in->event_offsets[E], E);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(nullptr, PXT_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+  return PXT_OK;
 }
 
 }  // extern "C"

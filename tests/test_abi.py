@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 import eventgen
@@ -109,3 +111,32 @@ def test_server_argument_validation():
     assert L.pxt_submit(None, None, None, None, None, 0, ctypes.byref(t)) == pxt.ERR_INVALID_ARG
     assert L.pxt_poll(None, 1, None, 0) == pxt.ERR_INVALID_ARG
     L.pxt_server_destroy(None)
+
+
+def test_static_entry_point_validation():
+    # checked on the host before any device call: capacities beyond the
+    # fixed buffer, more events than it admits, a bad config
+    L = pxt.lib()
+    cnt = (ctypes.c_uint32 * 32)()
+    per = (ctypes.c_uint32 * 128)()
+    out = pxt.PxtTracks(0, None, None, None, None, None, None, None,
+                        ctypes.addressof(per), ctypes.addressof(cnt))
+    offs = np.zeros(2, np.uint32)
+    hits = pxt.PxtHits(1, offs.ctypes.data, None, None, None, None, None)
+    big = pxt.make_config(eventgen.DETECTOR, max_events=4, max_doublets=1 << 24)
+    assert L.pxt_reconstruct_static(ctypes.byref(big), 0, ctypes.byref(hits), ctypes.byref(out),
+                                    None) == pxt.ERR_CAPACITY
+    assert b"PXT_STATIC_SCRATCH_BYTES" in L.pxt_last_error(None)
+    many = pxt.make_config(eventgen.DETECTOR, max_events=100, max_hits=1024,
+                           max_doublets=1024, max_tuples=1024)
+    offs2 = np.zeros(101, np.uint32)
+    hits2 = pxt.PxtHits(100, offs2.ctypes.data, None, None, None, None, None)
+    assert L.pxt_reconstruct_static(ctypes.byref(many), 0, ctypes.byref(hits2),
+                                    ctypes.byref(out), None) == pxt.ERR_CAPACITY
+    assert b"PXT_STATIC_MAX_EVENTS" in L.pxt_last_error(None)
+    bad = pxt.make_config(eventgen.DETECTOR)
+    bad.phi_bins = 8
+    assert L.pxt_reconstruct_static(ctypes.byref(bad), 0, ctypes.byref(hits), ctypes.byref(out),
+                                    None) == pxt.ERR_INVALID_ARG
+    assert L.pxt_reconstruct_static(None, 0, ctypes.byref(hits), ctypes.byref(out),
+                                    None) == pxt.ERR_INVALID_ARG
