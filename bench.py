@@ -1,15 +1,29 @@
 """Throughput benchmark of the pixel-track reconstruction path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload pu50|pu200]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--trials T]
 
 A step is one pxt_reconstruct call over one batch of synthetic events already
-resident in HBM (the whole path: binning, doublets, links, n-tuplets,
-cleaning, fit, output).  The timed region is K steps bracketed by device
-synchronisation; value = events/s of the batched path.  The same run also
-times the plain path (one event per call, synchronised per event, as the
-paper's one-concurrent-event mode), a per-stage breakdown from HIP events on
-the library's stream, and the CPU oracle on the host cores (one event per
-thread) on a bounded sample.  Prints one JSON line.
+resident in HBM: the whole path (binning, doublets, links, n-tuplets,
+cleaning, fit, output).  The timed region is K steps in T trials, each trial
+bracketed by device synchronisation; value = events/s of the batched PU~50
+path over all K steps (64 events per batch, several batches in flight on
+their own streams), with the trials' mean and sample standard deviation
+beside it.  The same run prints, in the same JSON line:
+
+* the PU~50 batched rate with the host->device copy of the hits and the
+  device->host copy of the tracks inside the timed loop (pinned buffers,
+  async on each batch's stream) -- the paper counts the per-event copy;
+* the PU~200 batched (32 events per batch) and plain legs;
+* the plain path (one event per call, synchronised per event);
+* the paper's two scheduling levers measured natively: k one-event contexts
+  on k streams (concurrent events) and a context created per event (no
+  memory pool);
+* a per-stage breakdown from HIP events on the library's stream, the HBM
+  roofline by the method's algorithmic bytes (whole path and the dominant
+  kernel), the measured streaming-copy bandwidth as a second denominator and
+  the counter bytes of the last profile while the kernels are unchanged;
+* the serving leg (Poisson arrivals over a PU 30..140 mix, continuous
+  batching) and the CPU oracle on the host cores.
 """
 
 import argparse
@@ -24,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HOST_WORKERS = 16  # the GPU machine's CPU share for one GPU
 WORKLOADS = {
     # name: (generator recipe, events per batch, description)
     "pu50": ("pu50", 64, "PU~50 events: 1500 tracks, 10 vertices, 4 barrel layers + 3 disks "
@@ -33,16 +48,26 @@ WORKLOADS = {
 }
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="pu50", choices=sorted(WORKLOADS))
+    ap.add_argument("--trials", type=int, default=8, help="the K steps are timed as T trials")
+    ap.add_argument("--workload", default="pu50", choices=sorted(WORKLOADS),
+                    help="workload of the headline value")
     ap.add_argument("--batch", type=int, default=0, help="events per batch (default per workload)")
     ap.add_argument("--pool", type=int, default=2, help="distinct batches cycled through")
-    ap.add_argument("--plain-events", type=int, default=64)
-    ap.add_argument("--cpu-sample", type=int, default=160, help="events for the CPU baseline")
+    ap.add_argument("--plain-events", type=int, default=512,
+                    help="one-event calls timed on the plain path (cycled over the pool)")
+    ap.add_argument("--pu200-steps", type=int, default=100)
+    ap.add_argument("--no-pu200", action="store_true")
+    ap.add_argument("--no-pcie", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048,
+                    help="events for the CPU baseline (cycled over the pool)")
+    ap.add_argument("--cpu-sample-1t", type=int, default=64,
+                    help="events for the one-thread CPU figure")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--phi-bins", type=int, default=256)
     ap.add_argument("--group-lanes", type=int, default=8)
@@ -65,7 +90,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (calibrates HBM byte counters)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def batch_caps(kind, n_events, max_hits):
@@ -80,59 +105,77 @@ def batch_caps(kind, n_events, max_hits):
                 max_tuples=per_ev_t * n_events, max_tracks=per_ev_t * n_events)
 
 
-def gen_events(kind, n, seed0):
+def _gen_one(a):
     import eventgen
-    return [eventgen.generate(kind, seed0 + i) for i in range(n)]
+    return eventgen.generate(a[0], a[1])
 
 
-# Algorithmic HBM bytes of one launch of each single-kernel stage: every
-# array the kernel must read or write, touched once (re-reads of candidates
-# from cache are not counted).  Nh binned hits, Nd doublets, Nw link-mask
-# words, Nt raw n-tuplets, Nk tracks, nbar mean hits per track.
-def algorithmic_bytes(stage, n, doublet_mode=0):
-    Nh, Nd, Nw, Nt, Nk = n["Nh"], n["Nd"], n["Nw"], n["Nt"], n["Nk"]
-    # staged doublets: a 4-byte record per doublet written by the count
-    # pass and read by the scatter
-    rec = 4 * Nd if doublet_mode == 2 else 0
-    nbar = n["nbar"]
+def gen_events(kind, n, seed0, workers=1):
+    """Events seed0 .. seed0+n-1 of workload `kind` (in processes when
+    workers > 1; the generator is seeded per event, so the result is the
+    same)."""
+    args = [(kind, seed0 + i) for i in range(n)]
+    if workers <= 1 or n <= 2:
+        return [_gen_one(a) for a in args]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(workers, n),
+                             mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_gen_one, args, chunksize=max(1, n // (4 * workers))))
+
+
+# Algorithmic HBM bytes: what the method must move, every product written
+# once by its producer and read once by its consumer.  Per event (or batch):
+#   14 Nh  hits in (x, y, z f32, layer i16)
+#   48 Nh  binned hits written and read (24 B each)
+#   16 Nd  doublets (inner, outer hit) written and read
+#    8 (Nh + Nd)  incoming-doublet CSR (offsets per hit, entries) w + r
+#    8 Nl  links written and read
+#   66 Nt  raw n-tuplets written and read (8 hit ids + length, 33 B)
+#   12 nbar Nk  hit coordinates gathered by the fit
+#  120 Nk  tracks out (8 hit ids, 5 parameters, 15 covariances, 2 chi2, ...)
+# Nh input hits, Nd doublets, Nl links, Nt raw n-tuplets, Nk tracks, nbar
+# mean hits per track.  Each step's share is what it reads of its
+# predecessor's product plus what it writes of its own.
+def path_bytes(n):
+    Nh, Nd, Nl, Nt, Nk, nbar = n["Nh"], n["Nd"], n["Nl"], n["Nt"], n["Nk"], n["nbar"]
+    return (14 * Nh + 48 * Nh + 16 * Nd + 8 * (Nh + Nd) + 8 * Nl + 66 * Nt
+            + 12 * nbar * Nk + 120 * Nk)
+
+
+def step_bytes(step, n):
+    Nh, Nd, Nl, Nt, Nk, nbar = n["Nh"], n["Nd"], n["Nl"], n["Nt"], n["Nk"], n["nbar"]
     table = {
-        # x, y (8) + layer (2) read, bin key (4) written
-        "prep": 14 * Nh,
-        # key, x, y, z, layer read (18); binned SoA written (33)
-        "fill": 51 * Nh,
-        # binned hit read (29), doublet count written (4)
-        "doublet_count": 33 * Nh + rec,
-        # binned hit read and offset read or written (33); per doublet
-        # written: in/out hits, flag, outer hit and r-z angle, the angle
-        # again (29).  The one-pass kernel (reported under this stage)
-        # moves the same bytes.
-        "doublet_fill": 33 * Nh + 29 * Nd + rec,
-        # inner-hit coordinates and doublet offsets (24 per hit); per
-        # doublet: inner and outer hit, outer hit coordinates and angle,
-        # candidate range written (32), its angle read once as a candidate
-        # (4), neighbour count and cleaning-election slots written (16);
-        # mask words written (8)
-        "links": 24 * Nh + 52 * Nd + 8 * Nw,
-        # per n-tuplet: hits, doublets, length (61), hit coordinates, score
-        # written (8), order key min per doublet (8)
-        "score": (69 + 20 * nbar + 8 * (nbar - 1)) * Nt,
-        # per n-tuplet: length, score, doublets (37), per doublet the key (8)
-        "best": (37 + 8 * (nbar - 1)) * Nt,
-        # survivor, n-tuplet, hits and ids read (41 + 17 per hit), record written (126)
-        "fit32": (41 + 17 * nbar + 126) * Nk,
+        "prep": 14 * Nh,                                    # hits read
+        "binning": 24 * Nh,                                 # binned hits written
+        "doublets": 24 * Nh + 8 * Nd + 4 * (Nh + Nd),       # binned read, doublets + CSR written
+        "links": 8 * Nd + 4 * (Nh + Nd) + 4 * Nl,           # doublets + CSR read, links written
+        "ntuplets": 4 * Nl + 33 * Nt,                       # links read, raw n-tuplets written
+        "cleaning": 33 * Nt,                                # raw n-tuplets read
+        "fit": 12 * nbar * Nk + 120 * Nk,                   # hit gathers, tracks written
     }
-    return table.get(stage)
+    return table.get(step)
 
 
-# kernel that implements each single-kernel stage (for the counter lookup)
-STAGE_KERNEL = {"prep": "pxt::k_prep", "fill": "pxt::k_fill",
-                "doublet_count": "pxt::k_doublets<8, false>",
-                "doublet_fill": "pxt::k_doublets<8, true>", "links": "pxt::k_links_thread",
-                "score": "pxt::k_score", "best": "pxt::k_best", "fit32": "pxt::k_fit32"}
+# library stages (pxt_stage_name) of each step of the path
+STEP_STAGES = {
+    "prep": ("clear", "prep"),
+    "binning": ("bin_scan", "fill"),
+    "doublets": ("doublet_count", "doublet_scan", "doublet_fill"),
+    "links": ("mask_clear", "links"),
+    "ntuplets": ("roots", "tuple_count", "tuple_scan", "tuple_fill"),
+    "cleaning": ("score", "best", "survive"),
+    "fit": ("fit32", "fit64", "finish"),
+}
 
 
 def stage_kernel(stage, args):
-    kname = STAGE_KERNEL.get(stage)
+    """The kernel of a single-kernel stage (for the counter lookup)."""
+    base = {"prep": "pxt::k_prep", "fill": "pxt::k_fill",
+            "doublet_count": "pxt::k_doublets<8, false>",
+            "doublet_fill": "pxt::k_doublets<8, true>", "links": "pxt::k_links_thread",
+            "score": "pxt::k_score", "best": "pxt::k_best", "fit32": "pxt::k_fit32"}
+    kname = base.get(stage)
     if stage == "links" and args.link_kernel == 1:
         kname = "pxt::k_links<%d>" % args.group_lanes
     if stage == "links" and args.link_kernel == 2:
@@ -174,37 +217,67 @@ def measured_traffic(kernel):
     return blob["bytes_per_launch"].get(kernel)
 
 
-def roofline(stages, counts, n_hits, peak_gbs, workload, args):
-    """Roofline entry of the dominant single-kernel stage."""
-    n = {"Nh": n_hits, "Nd": counts["n_doublets"], "Nw": counts["n_words"],
-         "Nt": counts["n_raw_tuples"], "Nk": counts["n_tracks"], "nbar": 3.4}
-    cand = {k: v for k, v in stages.items() if algorithmic_bytes(k, n) is not None}
-    dom = max(cand, key=cand.get)
-    byts = algorithmic_bytes(dom, n, args.doublet_mode)
-    gbs = byts / (cand[dom] * 1e-3) / 1e9
+def roofline(stages, n, batches_per_s, peak_gbs, copy_gbs, workload, args):
+    """HBM roofline by the method's algorithmic bytes: the dominant kernel
+    (the link kernel: its step's bytes over its mean launch time) and the
+    whole path (bytes per batch times batches per second)."""
+    links_ms = stages.get("links", 0.0)
+    lb = step_bytes("links", n)
+    gbs = lb / (links_ms * 1e-3) / 1e9 if links_ms > 0 else 0.0
+    kname = stage_kernel("links", args)
     traffic = None
-    kname = stage_kernel(dom, args)
-    if (workload == "pu50" and kname and args.link_kernel == 0 and args.group_lanes == 8
-            and args.batch in (0, 64)):
+    if workload == "pu50" and args.link_kernel == 0 and args.group_lanes == 8 and \
+            args.batch in (0, 64):
         traffic = measured_traffic(kname)
-    return {"kernel": kname or dom, "bound": "hbm", "achieved": round(gbs, 2), "peak": peak_gbs,
-            "unit": "GB/s", "frac": round(gbs / peak_gbs, 5), "traffic": traffic,
-            "algorithmic_bytes_per_launch": int(byts), "avg_launch_ms": round(cand[dom], 5)}
+    pb = path_bytes(n)
+    path_gbs = pb * batches_per_s / 1e9
+    out = {"kernel": kname, "bound": "hbm", "achieved": round(gbs, 2), "peak": peak_gbs,
+           "unit": "GB/s", "frac": round(gbs / peak_gbs, 5), "traffic": traffic,
+           "algorithmic_bytes_per_launch": int(lb), "avg_launch_ms": round(links_ms, 5),
+           "path": {"algorithmic_bytes_per_batch": int(pb), "achieved": round(path_gbs, 2),
+                    "frac": round(path_gbs / peak_gbs, 5)},
+           "steps": {}}
+    for step, stg in STEP_STAGES.items():
+        ms = sum(stages.get(s, 0.0) for s in stg)
+        b = step_bytes(step, n)
+        out["steps"][step] = {"ms": round(ms, 5), "bytes": int(b),
+                              "frac": round(b / (ms * 1e-3) / 1e9 / peak_gbs, 5) if ms else None}
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / lb, 3)
+    if copy_gbs:
+        out["copy_peak_gbs"] = round(copy_gbs, 1)
+        out["frac_of_copy_peak"] = round(gbs / copy_gbs, 5)
+        out["path"]["frac_of_copy_peak"] = round(path_gbs / copy_gbs, 5)
+    return out
 
 
-def cpu_baseline(events, det):
-    """The oracle as it stands, one event per thread over the host cores."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(events, det, threads):
+    """The oracle as it stands, one event per thread over `threads` host
+    threads."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     oracle.lib()
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16))
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=cores) as ex:
+    with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(lambda e: oracle.reconstruct(e.x, e.y, e.z, e.layer, det)["status"], events))
     dt = time.perf_counter() - t0
-    return len(events) / dt, cores, dt
+    return len(events) / dt, dt
+
+
+def host_threads():
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, min(cores or 1, HOST_WORKERS))
 
 
 def serving_leg(det, args):
@@ -236,12 +309,213 @@ def serving_leg(det, args):
     }
 
 
-def main():
-    args = parse()
+def stats(values):
+    v = np.asarray(values, np.float64)
+    return {"mean": round(float(v.mean()), 2),
+            "std": round(float(v.std(ddof=1)), 2) if v.size > 1 else 0.0, "n": int(v.size)}
+
+
+class Batched:
+    """K contexts (batches in flight), each on its own stream, taking the
+    steps in turn over a pool of device-resident batches."""
+
+    def __init__(self, torch, pxt, det, kind, batches, args, inflight, doublet_mode, graph):
+        self.torch = torch
+        B = len(batches[0])
+        max_hits = max(sum(e.n_hits for e in b) for b in batches)
+        caps = batch_caps(kind, B, max_hits)
+        self.recs = [pxt.Reconstructor(det, phi_bins=args.phi_bins,
+                                       group_lanes=args.group_lanes,
+                                       link_kernel=args.link_kernel, use_graph=graph,
+                                       doublet_mode=doublet_mode, **caps)
+                     for _ in range(inflight)]
+        self.streams = [torch.cuda.Stream() for _ in range(inflight)]
+        self.dev = [self.recs[0].upload(b) for b in batches]
+        self.B = B
+        self.caps = caps
+        torch.cuda.synchronize()
+
+    def step(self, i):
+        K = len(self.recs)
+        self.recs[i % K].launch(*self.dev[i % len(self.dev)], stream=self.streams[i % K])
+
+    def check(self):
+        """Status of every context on the first batch (parity is tested
+        separately); returns the counts."""
+        c0 = None
+        for r in self.recs:
+            r.launch(*self.dev[0])
+            self.torch.cuda.synchronize()
+            c = r.read_counts()
+            assert c["status"] == 0, c
+            assert c0 is None or c == c0, (c, c0)
+            c0 = c
+        return c0
+
+    def timed(self, steps, warmup, trials, step=None):
+        step = step or self.step
+        torch = self.torch
+        for i in range(warmup):
+            step(i)
+        torch.cuda.synchronize()
+        T = max(1, min(trials, steps))
+        sizes = [steps // T + (1 if i < steps % T else 0) for i in range(T)]
+        rates, total_dt, done = [], 0.0, 0
+        for n in sizes:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(done, done + n):
+                step(i)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rates.append(self.B * n / dt)
+            total_dt += dt
+            done += n
+        return self.B * steps / total_dt, total_dt / steps * 1e3, stats(rates)
+
+    def close(self):
+        for r in self.recs:
+            r.close()
+
+
+def pcie_leg(torch, bat, batches, counts, args):
+    """Batched PU~50 with the hits copied in from pinned host memory and the
+    tracks copied out to it inside the timed loop (async, on each batch's
+    stream): the paper counts the per-event input copy."""
+    K = len(bat.recs)
+    host = []
+    for b in batches:
+        cat = lambda f, dt: torch.from_numpy(np.ascontiguousarray(
+            np.concatenate([getattr(e, f) for e in b]), dt)).pin_memory()
+        host.append((cat("x", np.float32), cat("y", np.float32), cat("z", np.float32),
+                     cat("layer", np.int16), bat.dev[len(host)][4]))
+    dev_in = []
+    for k in range(K):
+        n = max(h[0].shape[0] for h in host)
+        dev_in.append(tuple(torch.empty(n, dtype=d, device="cuda")
+                            for d in (torch.float32, torch.float32, torch.float32, torch.int16)))
+    nk = counts["n_tracks"]
+    outs = []
+    for r in bat.recs:
+        t = {name: getattr(r, "o_" + name) for name in
+             ("hit_idx", "n_hits", "event_id", "params", "cov", "chi2", "flags")}
+        outs.append({name: (v, torch.empty((nk,) + tuple(v.shape[1:]), dtype=v.dtype,
+                                           pin_memory=True)) for name, v in t.items()})
+    ev_bytes = [0]
+
+    def step(i):
+        k = i % K
+        h = host[i % len(host)]
+        s = bat.streams[k]
+        x, y, z, l = dev_in[k]
+        n = h[0].shape[0]
+        with torch.cuda.stream(s):
+            for dst, src in zip((x, y, z, l), h[:4]):
+                dst[:n].copy_(src, non_blocking=True)
+        bat.recs[k].launch(x[:n], y[:n], z[:n], l[:n], h[4], stream=s)
+        with torch.cuda.stream(s):
+            for dev, hb in outs[k].values():
+                hb.copy_(dev[:nk], non_blocking=True)
+
+    v, ms, st = bat.timed(args.steps, args.warmup, args.trials, step=step)
+    per_batch = 14 * host[0][0].shape[0] + sum(
+        hb.numel() * hb.element_size() for _, hb in outs[0].values())
+    return {"events_per_s": round(v, 2), "ms_per_step": round(ms, 4), "trials": st,
+            "pcie_bytes_per_batch": int(per_batch),
+            "note": "hits copied in and tracks copied out per batch (pinned host buffers, "
+                    "async on each batch's stream)"}
+
+
+def plain_leg(torch, pxt, det, kind, events, args, n_calls, streams=1):
+    """One event per call, each call waited for before its context is
+    reused; `streams` contexts on their own streams keep that many events
+    in flight (the paper's concurrent events)."""
+    caps = batch_caps(kind, 2, max(e.n_hits for e in events) + 16)
+    caps["max_events"] = 1
+    recs = [pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                              link_kernel=args.link_kernel, use_graph=args.graph,
+                              doublet_mode=args.latency_doublet_mode, **caps)
+            for _ in range(streams)]
+    ss = [torch.cuda.Stream() for _ in range(streams)]
+    dev = [recs[0].upload([e]) for e in events]
+    for i in range(min(4 * streams, len(dev))):
+        recs[i % streams].launch(*dev[i % len(dev)], stream=ss[i % streams])
+    torch.cuda.synchronize()
+    done = [None] * streams
+    t0 = time.perf_counter()
+    for i in range(n_calls):
+        k = i % streams
+        if done[k] is not None:
+            done[k].synchronize()
+        recs[k].launch(*dev[i % len(dev)], stream=ss[k])
+        done[k] = torch.cuda.Event()
+        done[k].record(ss[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for r in recs:
+        r.close()
+    return n_calls / dt
+
+
+def plain_malloc_per_event(torch, pxt, det, kind, events, args, n_calls):
+    """One event per call with its context (all device arenas) created and
+    destroyed around the call: the paper's memory-pool-disabled mode."""
+    caps = batch_caps(kind, 2, max(e.n_hits for e in events) + 16)
+    caps["max_events"] = 1
+    dev = [pxt.upload_events([e]) for e in events]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_calls):
+        r = pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                              link_kernel=args.link_kernel, use_graph=0,
+                              doublet_mode=args.latency_doublet_mode, **caps)
+        r.launch(*dev[i % len(dev)])
+        torch.cuda.synchronize()
+        r.close()
+    dt = time.perf_counter() - t0
+    return n_calls / dt
+
+
+def copy_peak(torch, nbytes=1 << 30, reps=10):
+    """Streaming-copy bandwidth of one large device copy (read + write)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def path_counts(rec, counts, n_hits):
+    nk = counts["n_tracks"]
+    nh = rec.o_n_hits[:nk].cpu().numpy()
+    return {"Nh": n_hits, "Nd": counts["n_doublets"], "Nl": counts["n_links"],
+            "Nt": counts["n_raw_tuples"], "Nk": nk, "nbar": float(nh.mean()) if nk else 0.0}
+
+
+def main(argv=None):
+    args = parse(argv)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (events are independent; a multi-GPU "
               "deployment is one process per GPU). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    # every input is generated before the GPU is touched (worker processes)
+    kind, batch_default, desc = WORKLOADS[args.workload]
+    B = args.batch or batch_default
+    flat = gen_events(kind, B * args.pool, 1000, workers=HOST_WORKERS)
+    pool = [flat[p * B:(p + 1) * B] for p in range(args.pool)]
+    pu200 = None
+    if not args.no_pu200 and args.workload == "pu50":
+        f2 = gen_events("pu200", 64, 5000, workers=HOST_WORKERS)
+        pu200 = [f2[:32], f2[32:]]
+
     import torch
 
     import eventgen
@@ -259,73 +533,67 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    kind, batch_default, desc = WORKLOADS[args.workload]
-    B = args.batch or batch_default
-    pool = [gen_events(kind, B, 1000 + 97 * p) for p in range(args.pool)]
     hits_per_event = float(np.mean([e.n_hits for b in pool for e in b]))
-    max_hits = max(sum(e.n_hits for e in b) for b in pool)
-    K = max(1, args.inflight)
-    caps = batch_caps(kind, B, max_hits)
-    recs = [pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                              link_kernel=args.link_kernel, use_graph=args.graph,
-                              doublet_mode=args.doublet_mode, **caps)
-            for _ in range(K)]
-    rec = recs[0]
-    streams = [torch.cuda.Stream() for _ in range(K)]
-    dev_batches = [rec.upload(b) for b in pool]
-    torch.cuda.synchronize()
 
-    def step(i):
-        x, y, z, l, offs = dev_batches[i % len(dev_batches)]
-        recs[i % K].launch(x, y, z, l, offs, stream=streams[i % K])
-
-    # correctness guard on the first batch (status only; parity is tested)
-    step(0)
-    torch.cuda.synchronize()
-    c0 = rec.read_counts()
-    assert c0["status"] == 0, c0
-    for r in recs[1:]:
-        x, y, z, l, offs = dev_batches[0]
-        r.launch(x, y, z, l, offs)
-        torch.cuda.synchronize()
-        assert r.read_counts() == c0
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    ev_per_s = B * args.steps / dt
+    bat = Batched(torch, pxt, det, kind, pool, args, max(1, args.inflight), args.doublet_mode,
+                  args.graph)
+    c0 = bat.check()
+    ev_per_s, ms_per_step, trials = bat.timed(args.steps, args.warmup, args.trials)
 
     # stage breakdown with HIP events on the library's stream (direct mode:
     # events cannot sit inside the replayed graph)
     trec = pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                              link_kernel=args.link_kernel, use_graph=0,
-                             doublet_mode=args.doublet_mode, **caps)
-    stages = trec.stage_times(trec.upload(pool[0]), repeats=5)
+                             doublet_mode=args.doublet_mode, **bat.caps)
+    tb = trec.upload(pool[0])
+    stages = trec.stage_times(tb, repeats=5)
+    n = path_counts(trec, trec.read_counts(), int(tb[4][-1]))
     trec.close()
 
-    # plain path: one event per call, synchronised per event
-    plain_events = [e for b in pool for e in b][: args.plain_events]
-    pcaps = batch_caps(kind, 2, max(e.n_hits for e in plain_events) + 16)
-    pcaps["max_events"] = 1
-    prec = pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
-                             link_kernel=args.link_kernel, use_graph=args.graph,
-                             doublet_mode=args.latency_doublet_mode, **pcaps)
-    plain_dev = [prec.upload([e]) for e in plain_events]
-    for i in range(min(4, len(plain_dev))):
-        prec.launch(*plain_dev[i])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for d in plain_dev:
-        prec.launch(*d)
-        torch.cuda.synchronize()
-    plain_dt = time.perf_counter() - t0
-    plain_ev_s = len(plain_dev) / plain_dt
+    pcie = None
+    if not args.no_pcie:
+        pcie = pcie_leg(torch, bat, pool, c0, args)
+    bat.close()
+    del bat
 
+    # plain path: one event per call, synchronised per event
+    plain_events = [e for b in pool for e in b]
+    plain_ev_s = plain_leg(torch, pxt, det, kind, plain_events, args, args.plain_events)
+
+    ablations = None
+    if not args.no_ablations:
+        ablations = {
+            "workload": "plain path (one event per call) over the %d %s events of the pool" %
+                        (len(plain_events), args.workload),
+            "concurrent_events_events_per_s": {
+                str(k): round(plain_leg(torch, pxt, det, kind, plain_events, args,
+                                        args.plain_events, streams=k), 2)
+                for k in (1, 2, 4, 8)},
+            "context_per_event_events_per_s": round(
+                plain_malloc_per_event(torch, pxt, det, kind, plain_events, args, 32), 2),
+        }
+        base = ablations["concurrent_events_events_per_s"]["1"]
+        ablations["concurrent_events_gain"] = {
+            k: round(v / base, 2) for k, v in ablations["concurrent_events_events_per_s"].items()}
+        ablations["memory_pool_gain"] = round(base / ablations["context_per_event_events_per_s"], 2)
+
+    p200 = None
+    if pu200 is not None:
+        b2 = Batched(torch, pxt, det, "pu200", pu200, args, max(1, args.inflight),
+                     args.doublet_mode, args.graph)
+        b2.check()
+        v2, ms2, st2 = b2.timed(args.pu200_steps, 5, args.trials)
+        b2.close()
+        del b2
+        pv2 = plain_leg(torch, pxt, det, "pu200", [e for b in pu200 for e in b], args, 128)
+        p200 = {"workload": WORKLOADS["pu200"][2] + ", 32 events per batch",
+                "hits_per_event": round(float(np.mean([e.n_hits for b in pu200 for e in b])), 1),
+                "batched_events_per_s": round(v2, 2), "ms_per_step": round(ms2, 4),
+                "steps": args.pu200_steps, "trials": st2,
+                "plain_events_per_s": round(pv2, 2),
+                "batched_over_plain": round(v2 / pv2, 2)}
+
+    cgbs = copy_peak(torch)
     counts = c0
     out = {
         "metric": "events/s at PU50/PU200 on 1 MI355X (batched/served vs plain)",
@@ -351,8 +619,9 @@ def main():
             "doublet_mode": args.doublet_mode,
             "latency_doublet_mode": args.latency_doublet_mode,
             "hip_graph": bool(args.graph),
-            "path": "batched (one launch sequence per batch)",
+            "path": "batched (one launch sequence per batch), inputs resident in HBM",
         },
+        "trials": trials,
         "plain_events_per_s": round(plain_ev_s, 2),
         "batched_over_plain": round(ev_per_s / plain_ev_s, 2),
         "hits_per_s": round(ev_per_s * hits_per_event, 1),
@@ -360,17 +629,29 @@ def main():
                                                     "n_tracks", "n_fp64")},
         "stage_ms": stages,
     }
-    roof = roofline(stages, counts, int(dev_batches[0][4][-1]), HBM_PEAK_GBS, args.workload, args)
-    out["roofline"] = roof
+    if pcie is not None:
+        out["pcie_inclusive"] = pcie
+    if p200 is not None:
+        out["pu200"] = p200
+    if ablations is not None:
+        out["ablations"] = ablations
+    out["roofline"] = roofline(stages, n, ev_per_s / B, HBM_PEAK_GBS, cgbs, args.workload, args)
     if served is not None:
         out["served"] = served
     if not args.no_cpu:
-        sample = [e for b in pool for e in b][: args.cpu_sample]
-        v, cores, cdt = cpu_baseline(sample, det)
-        out["cpu_baseline"] = {"value": round(v, 2), "unit": "events/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": "%d %s events, one per thread, %.1f s wall" %
-                                         (len(sample), args.workload, cdt)}
+        threads = host_threads()
+        sample = [plain_events[i % len(plain_events)] for i in range(args.cpu_sample)]
+        v, cdt = cpu_baseline(sample, det, threads)
+        v1, cdt1 = cpu_baseline([plain_events[i % len(plain_events)]
+                                 for i in range(args.cpu_sample_1t)], det, 1)
+        out["cpu_baseline"] = {"value": round(v, 2), "unit": "events/s", "cores": threads,
+                               "kind": "oracle", "cpu_model": cpu_model(),
+                               "one_thread_events_per_s": round(v1, 2),
+                               "sample": "%d %s events (the %d of the pool cycled), one per "
+                                         "thread on %d threads, %.1f s wall; one thread: %d "
+                                         "events, %.1f s" %
+                                         (len(sample), args.workload, len(plain_events),
+                                          threads, cdt, args.cpu_sample_1t, cdt1)}
     print(json.dumps(out), flush=True)
 
 

@@ -210,6 +210,20 @@ def counts_dict(words):
                 required=list(c.required))
 
 
+def upload_events(events, device=0):
+    """Concatenate host events (objects with x, y, z, layer arrays) into one
+    ragged batch on the device; returns (x, y, z, layer, offsets) with the
+    offsets on the host."""
+    import torch as t
+    dev = t.device("cuda", device) if isinstance(device, int) else device
+    offs = np.zeros(len(events) + 1, dtype=np.uint32)
+    offs[1:] = np.cumsum([len(e.x) for e in events])
+    cat = lambda f, dt: t.from_numpy(np.ascontiguousarray(
+        np.concatenate([getattr(e, f) for e in events]) if events else np.zeros(0), dt)).to(dev)
+    return (cat("x", np.float32), cat("y", np.float32), cat("z", np.float32),
+            cat("layer", np.int16), offs)
+
+
 class Reconstructor:
     """One libpxt context on one GPU with its output buffers.
 
@@ -307,14 +321,7 @@ class Reconstructor:
     def upload(self, events):
         """Concatenate host events (objects with x, y, z, layer arrays) into
         one ragged batch on the device; returns (x, y, z, layer, offsets)."""
-        t = self.torch
-        dev = self.device
-        offs = np.zeros(len(events) + 1, dtype=np.uint32)
-        offs[1:] = np.cumsum([len(e.x) for e in events])
-        cat = lambda f, dt: t.from_numpy(np.ascontiguousarray(
-            np.concatenate([getattr(e, f) for e in events]) if events else np.zeros(0), dt)).to(dev)
-        return (cat("x", np.float32), cat("y", np.float32), cat("z", np.float32),
-                cat("layer", np.int16), offs)
+        return upload_events(events, self.device)
 
     def run_numpy(self, events):
         x, y, z, layer, offs = self.upload(events)

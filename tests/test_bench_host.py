@@ -37,35 +37,40 @@ def test_more_than_one_gpu_is_refused():
     ("doublet_fill", dict(doublet_mode=1, group_lanes=4), "pxt::k_doublets1<4>"),
     ("doublet_count", dict(doublet_mode=0), "pxt::k_doublets<8, false>"),
     ("doublet_fill", dict(doublet_mode=0, group_lanes=16), "pxt::k_doublets<16, true>"),
-    ("fit32", {}, "pxt::k_fit32"),
 ])
 def test_stage_kernel_names(stage, kw, name):
     assert bench.stage_kernel(stage, _args(**kw)) == name
 
 
-def test_algorithmic_bytes_table():
-    n = dict(Nh=1000, Nd=20000, Nw=30000, Nt=500, Nk=300, nbar=3.4)
-    # the staged doublets add one 4-byte record per doublet to each pass
-    assert (bench.algorithmic_bytes("doublet_count", n, 2)
-            - bench.algorithmic_bytes("doublet_count", n, 0)) == 4 * n["Nd"]
-    assert (bench.algorithmic_bytes("doublet_fill", n, 2)
-            - bench.algorithmic_bytes("doublet_fill", n, 0)) == 4 * n["Nd"]
-    assert bench.algorithmic_bytes("links", n) == 24 * 1000 + 52 * 20000 + 8 * 30000
-    assert bench.algorithmic_bytes("no_such_stage", n) is None
+def test_algorithmic_bytes_follow_the_method_formula():
+    n = dict(Nh=1000, Nd=20000, Nl=3000, Nt=500, Nk=300, nbar=3.5)
+    total = (14 * 1000 + 48 * 1000 + 16 * 20000 + 8 * (1000 + 20000) + 8 * 3000 + 66 * 500
+             + 12 * 3.5 * 300 + 120 * 300)
+    assert bench.path_bytes(n) == pytest.approx(total)
+    # the steps' shares add up to the whole path
+    assert sum(bench.step_bytes(s, n) for s in bench.STEP_STAGES) == pytest.approx(total)
+    assert bench.step_bytes("links", n) == 8 * 20000 + 4 * (1000 + 20000) + 4 * 3000
+    assert bench.step_bytes("no_such_step", n) is None
 
 
-def test_roofline_picks_the_slowest_priced_stage():
+def test_roofline_entry():
     stages = {"links": 0.2, "doublet_count": 0.1, "doublet_fill": 0.05, "tuple_scan": 0.9}
-    counts = dict(n_doublets=20000, n_words=30000, n_raw_tuples=500, n_tracks=300)
-    r = bench.roofline(stages, counts, 1000, bench.HBM_PEAK_GBS, "pu200", _args())
-    # tuple_scan has no byte entry, so the links stage is the dominant one
+    n = dict(Nh=10 ** 6, Nd=2 * 10 ** 7, Nl=3 * 10 ** 6, Nt=5 * 10 ** 5, Nk=3 * 10 ** 5, nbar=3.5)
+    r = bench.roofline(stages, n, 100.0, bench.HBM_PEAK_GBS, 5000.0, "pu200", _args())
     assert r["kernel"] == "pxt::k_links_thread"
-    byts = bench.algorithmic_bytes("links", dict(Nh=1000, Nd=20000, Nw=30000, Nt=500,
-                                                 Nk=300, nbar=3.4))
-    assert r["algorithmic_bytes_per_launch"] == byts
-    assert r["achieved"] == pytest.approx(byts / 0.2e-3 / 1e9, rel=1e-6)
+    lb = bench.step_bytes("links", n)
+    assert r["algorithmic_bytes_per_launch"] == lb
+    assert r["achieved"] == pytest.approx(lb / 0.2e-3 / 1e9, rel=1e-4)
     assert r["frac"] == pytest.approx(r["achieved"] / bench.HBM_PEAK_GBS, abs=1e-5)
+    assert r["path"]["achieved"] == pytest.approx(bench.path_bytes(n) * 100.0 / 1e9, rel=1e-4)
+    assert r["frac_of_copy_peak"] == pytest.approx(r["achieved"] / 5000.0, abs=1e-5)
+    assert r["steps"]["doublets"]["ms"] == pytest.approx(0.15)
     assert r["traffic"] is None  # counters are only taken for the PU~50 workload
+
+
+def test_trial_statistics():
+    st = bench.stats([1.0, 2.0, 3.0])
+    assert st == {"mean": 2.0, "std": 1.0, "n": 3}
 
 
 def test_measured_traffic_follows_the_source_hash():
