@@ -90,6 +90,9 @@ def load_library(path):
     L.orc_link_ok.argtypes = [ctypes.POINTER(Config)] + [d] * 9
     L.orc_link_terms.argtypes = [ctypes.POINTER(Config)] + [d] * 9 + [ctypes.c_void_p]
     L.orc_fit.argtypes = [ctypes.POINTER(Config), ctypes.c_int] + [ctypes.c_void_p] * 8
+    L.orc_rechits.restype = ctypes.c_uint32
+    L.orc_rechits.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                              ctypes.c_uint32] + [ctypes.c_void_p] * 12
     L.orc_vertices.restype = ctypes.c_int
     L.orc_vertices.argtypes = [ctypes.POINTER(VtxConfig), ctypes.c_uint32] + \
         [ctypes.c_void_p] * 9 + [ctypes.c_uint32]
@@ -263,3 +266,30 @@ def event_vertices(o, det):
     if p.shape[0] == 0:
         return vertices(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), det)
     return vertices(p[:, 4], cv[:, 14], p[:, 2], nh, det)
+
+
+def rechits(cl, table, max_per_module):
+    """3-D hits of one event's clusters (the reading is stated in
+    pxt_oracle.c).  cl: dict of module (uint16, grouped or not),
+    pixel_offsets (uint32 [nc + 1], from 0), pix_u, pix_v, charge (uint16);
+    table: float64 [n_modules, 10].  Returns a dict: module_start (uint32
+    [n_modules + 1]), x, y, z (float32), layer (int16), module (uint16),
+    cluster (uint32), one entry per hit in module order."""
+    L = lib()
+    table = np.ascontiguousarray(table, np.float64)
+    nm = table.shape[0]
+    mod = np.ascontiguousarray(cl["module"], np.uint16)
+    nc = mod.shape[0]
+    po = np.ascontiguousarray(cl["pixel_offsets"], np.uint32)
+    pu = np.ascontiguousarray(cl["pix_u"], np.uint16)
+    pv = np.ascontiguousarray(cl["pix_v"], np.uint16)
+    q = np.ascontiguousarray(cl["charge"], np.uint16)
+    ms = np.zeros(nm + 1, np.uint32)
+    cap = max(nc, 1)
+    x = np.zeros(cap, np.float32); y = np.zeros(cap, np.float32); z = np.zeros(cap, np.float32)
+    lay = np.zeros(cap, np.int16); hm = np.zeros(cap, np.uint16); ch = np.zeros(cap, np.uint32)
+    nh = L.orc_rechits(_ptr(table), nm, int(max_per_module), nc, _ptr(mod), _ptr(po), _ptr(pu),
+                       _ptr(pv), _ptr(q), _ptr(ms), _ptr(x), _ptr(y), _ptr(z), _ptr(lay),
+                       _ptr(hm), _ptr(ch))
+    return dict(module_start=ms, x=x[:nh], y=y[:nh], z=z[:nh], layer=lay[:nh], module=hm[:nh],
+                cluster=ch[:nh])

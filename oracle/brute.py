@@ -301,3 +301,53 @@ def vertices(z0, var, qopt, nhits, eps, min_pts, min_hits, qopt_max):
         vc.append(np.sum(w * (zm - zv) ** 2))
         vn.append(int(m.sum()))
     return (np.array(vz), np.array(ve), np.array(vc), np.array(vn, np.uint32), assign)
+
+
+def rechits(cl, table, max_per_module):
+    """3-D hits of one event's clusters by a different route: per-cluster
+    sums with numpy reduceat, ranks from a stable sort by module, local to
+    global through the azimuth (barrel: phi_c + atan2(u, r) on the cylinder
+    of radius r; disk: rotation of (r + u, v) by phi_c).  Returns the same
+    dict as the C tier."""
+    mod = np.asarray(cl["module"], np.int64)
+    nc = mod.shape[0]
+    nm = table.shape[0]
+    cnt = np.bincount(mod, minlength=nm) if nc else np.zeros(nm, np.int64)
+    ms = np.concatenate([[0], np.cumsum(np.minimum(cnt, max_per_module))]).astype(np.uint32)
+    order = np.argsort(mod, kind="stable")
+    rank = np.zeros(nc, np.int64)
+    if nc:
+        first = np.searchsorted(mod[order], mod[order], side="left")
+        rank[order] = np.arange(nc) - first
+    po = np.asarray(cl["pixel_offsets"], np.int64)
+    q = np.asarray(cl["charge"], np.float64)
+    pu = np.asarray(cl["pix_u"], np.float64) + 0.5
+    pv = np.asarray(cl["pix_v"], np.float64) + 0.5
+    nh = int(ms[-1])
+    out = dict(module_start=ms, x=np.zeros(nh, np.float32), y=np.zeros(nh, np.float32),
+               z=np.zeros(nh, np.float32), layer=np.zeros(nh, np.int16),
+               module=np.zeros(nh, np.uint16), cluster=np.zeros(nh, np.uint32))
+    for i in range(nc):
+        if rank[i] >= max_per_module:
+            continue
+        h = int(ms[mod[i]] + rank[i])
+        a, b = po[i], po[i + 1]
+        Q = q[a:b].sum()
+        out["module"][h] = mod[i]
+        out["cluster"][h] = i
+        if not Q > 0:
+            out["layer"][h] = -1
+            continue
+        T = table[mod[i]]
+        u = T[6] + T[8] * (np.dot(q[a:b], pu[a:b]) / Q)
+        v = T[7] + T[9] * (np.dot(q[a:b], pv[a:b]) / Q)
+        pc = np.arctan2(T[3], T[2])
+        if T[1] == 0:
+            ph = pc + np.arctan2(u, T[4])
+            out["x"][h], out["y"][h], out["z"][h] = T[4] * np.cos(ph), T[4] * np.sin(ph), T[5] + v
+        else:
+            R = np.hypot(T[4] + u, v)
+            ph = pc + np.arctan2(v, T[4] + u)
+            out["x"][h], out["y"][h], out["z"][h] = R * np.cos(ph), R * np.sin(ph), T[5]
+        out["layer"][h] = int(T[0])
+    return out

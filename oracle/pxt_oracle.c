@@ -816,3 +816,88 @@ int orc_vertices(const orc_vtx_config* c, uint32_t n, const float* z0, const flo
   free(s); free(core); free(par); free(lab); free(vid);
   return (int)nv;
 }
+
+/* ------------------------------------------------------------------ */
+/* RecHits (the paper's RecHits module, Sec. 2: it estimates the 3-D
+ * position of each cluster, forming hits; its Fig. 3 shows the per-module
+ * step that limits each module's cluster count and turns the counts into
+ * the modules' first-hit offsets).  Reading, for one event:
+ *
+ *   counts     c[m] = clusters of module m, limited to max_per_module;
+ *   offsets    module_start[0] = 0, module_start[m+1] = module_start[m] + c[m];
+ *   rank       of cluster i: the number of earlier clusters (lower index)
+ *              of its module; clusters ranked max_per_module or beyond make
+ *              no hit, cluster i otherwise makes hit module_start[m] + rank;
+ *   centroid   Q = sum q, SU = sum q (iu + 1/2), SV = sum q (iv + 1/2) over
+ *              its pixels in order (double precision), local
+ *              u = u0 + pitch_u (SU / Q), v = v0 + pitch_v (SV / Q);
+ *   3-D        barrel module (direction c, s; radius r; centre z_c): the
+ *              point r n + u t of the tangent plane projected radially
+ *              onto the cylinder, p = (r c - u s, r s + u c) r / sqrt(r r +
+ *              u u), z = z_c + v; disk module (ring centre r, disk z): x =
+ *              (r + u) c - v s, y = (r + u) s + v c, z = z_disk;
+ *   output     single precision x, y, z, the module's layer, the module id
+ *              and the cluster index; a cluster with no charge makes a hit
+ *              with layer -1 at the origin (it takes part in nothing).
+ *
+ * The module table is float64 rows (layer, kind, cos phi_c, sin phi_c, r,
+ * z, u0, v0, pitch_u, pitch_v).  Returns the number of hits. */
+uint32_t orc_rechits(const double* table, uint32_t n_modules, uint32_t max_per_module,
+                     uint32_t nc, const uint16_t* module, const uint32_t* pixel_offsets,
+                     const uint16_t* pix_u, const uint16_t* pix_v, const uint16_t* charge,
+                     uint32_t* module_start, float* x, float* y, float* z, int16_t* layer,
+                     uint16_t* hit_module, uint32_t* cluster_of_hit) {
+  uint32_t* cnt = (uint32_t*)calloc(n_modules + 1, sizeof(uint32_t));
+  for (uint32_t i = 0; i < nc; ++i) cnt[module[i]]++;
+  module_start[0] = 0;
+  for (uint32_t m = 0; m < n_modules; ++m) {
+    const uint32_t c = cnt[m] < max_per_module ? cnt[m] : max_per_module;
+    module_start[m + 1] = module_start[m] + c;
+  }
+  uint32_t* seen = (uint32_t*)calloc(n_modules + 1, sizeof(uint32_t));
+  for (uint32_t i = 0; i < nc; ++i) {
+    const uint32_t m = module[i];
+    const uint32_t rank = seen[m]++;
+    if (rank >= max_per_module) continue;
+    const uint32_t h = module_start[m] + rank;
+    const double* T = table + 10 * (size_t)m;
+    double Q = 0.0, SU = 0.0, SV = 0.0;
+    for (uint32_t p = pixel_offsets[i]; p < pixel_offsets[i + 1]; ++p) {
+      const double q = (double)charge[p];
+      Q += q;
+      SU += q * ((double)pix_u[p] + 0.5);
+      SV += q * ((double)pix_v[p] + 0.5);
+    }
+    hit_module[h] = (uint16_t)m;
+    cluster_of_hit[h] = i;
+    if (!(Q > 0.0)) {
+      x[h] = 0.0f;
+      y[h] = 0.0f;
+      z[h] = 0.0f;
+      layer[h] = -1;
+      continue;
+    }
+    const double c = T[2], s = T[3], r = T[4], zc = T[5];
+    const double u = T[6] + T[8] * (SU / Q);
+    const double v = T[7] + T[9] * (SV / Q);
+    double gx, gy, gz;
+    if (T[1] == 0.0) {
+      const double f = r / sqrt(r * r + u * u);
+      gx = (r * c - u * s) * f;
+      gy = (r * s + u * c) * f;
+      gz = zc + v;
+    } else {
+      gx = (r + u) * c - v * s;
+      gy = (r + u) * s + v * c;
+      gz = zc;
+    }
+    x[h] = (float)gx;
+    y[h] = (float)gy;
+    z[h] = (float)gz;
+    layer[h] = (int16_t)T[0];
+  }
+  const uint32_t nh = module_start[n_modules];
+  free(cnt);
+  free(seen);
+  return nh;
+}

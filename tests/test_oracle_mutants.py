@@ -15,6 +15,7 @@ import pytest
 import oracle
 from tests import test_oracle as pins
 from tests import test_oracle_cleaning as cpins
+from tests import test_oracle_rechits as rpins
 from tests import test_oracle_vertices as vpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "pxt_oracle.c")
@@ -66,6 +67,25 @@ VTX_MUTANTS = {
     "vtx_chi2_unweighted": ("chi2 += w * r * r;", "chi2 += r * r;"),
 }
 
+# RecHits: the pixel centre offset dropped, u and v pitches swapped, no
+# radial projection, the limit off by one, the disk rotation's sign
+RH_MUTANTS = {
+    "rh_no_pixel_centre": ("SU += q * ((double)pix_u[p] + 0.5);", "SU += q * (double)pix_u[p];"),
+    "rh_pitches_swapped": ("const double u = T[6] + T[8] * (SU / Q);",
+                           "const double u = T[6] + T[9] * (SU / Q);"),
+    "rh_no_projection": ("const double f = r / sqrt(r * r + u * u);", "const double f = 1.0;"),
+    "rh_limit_off_by_one": ("if (rank >= max_per_module) continue;",
+                            "if (rank > max_per_module) continue;"),
+    "rh_disk_rotation_sign": ("gy = (r + u) * s + v * c;", "gy = (r + u) * s - v * c;"),
+}
+
+RH_PINS = [
+    lambda: rpins.test_barrel_single_pixel_on_the_cylinder(1, 37, 200),
+    lambda: rpins.test_disk_single_pixel(4),
+    rpins.test_charge_weighted_centroid,
+    rpins.test_limit_and_offsets,
+]
+
 VTX_PINS = [
     vpins.test_two_groups_closed_form,
     vpins.test_weighted_mean_and_chi2_exact,
@@ -98,6 +118,18 @@ def _mutant_lib(workdir, name, old, new):
                            path, "-lm"])
     oracle.lib()  # the real one built and cached first
     return oracle.load_library(so)
+
+
+@pytest.mark.parametrize("name", sorted(RH_MUTANTS))
+def test_rechits_mutant_is_caught(workdir, name, monkeypatch):
+    monkeypatch.setattr(oracle, "_lib", _mutant_lib(workdir, name, *RH_MUTANTS[name]))
+    failed = []
+    for pin in RH_PINS:
+        try:
+            pin()
+        except (AssertionError, ValueError):
+            failed.append(pin)
+    assert failed, "no pin fails for mutant %s" % name
 
 
 @pytest.mark.parametrize("name", sorted(VTX_MUTANTS))
