@@ -38,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VTX_SLOTS = 256  # vertex slots per event
 HOST_WORKERS = 16  # the GPU machine's CPU share for one GPU
 WORKLOADS = {
     # name: (generator recipe, events per batch, description)
@@ -88,6 +89,9 @@ def parse(argv=None):
     ap.add_argument("--serve-pool", type=int, default=96, help="distinct events cycled through")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--vertices", type=int, default=1,
+                    help="find the vertices of the tracks in every step (the serving leg "
+                         "returns tracks only)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (calibrates HBM byte counters)")
     return ap.parse_args(argv)
@@ -134,13 +138,18 @@ def gen_events(kind, n, seed0, workers=1):
 #   66 Nt  raw n-tuplets written and read (8 hit ids + length, 33 B)
 #   12 nbar Nk  hit coordinates gathered by the fit
 #  120 Nk  tracks out (8 hit ids, 5 parameters, 15 covariances, 2 chi2, ...)
+# and, when the vertices are found, 17 Nk (hit count, q/pT, z0, var(z0)
+# read, vertex of each track written) + 16 Nv (vertices written).
 # Nh input hits, Nd doublets, Nl links, Nt raw n-tuplets, Nk tracks, nbar
-# mean hits per track.  Each step's share is what it reads of its
-# predecessor's product plus what it writes of its own.
+# mean hits per track, Nv vertices.  Each step's share is what it reads of
+# its predecessor's product plus what it writes of its own.
 def path_bytes(n):
     Nh, Nd, Nl, Nt, Nk, nbar = n["Nh"], n["Nd"], n["Nl"], n["Nt"], n["Nk"], n["nbar"]
-    return (14 * Nh + 48 * Nh + 16 * Nd + 8 * (Nh + Nd) + 8 * Nl + 66 * Nt
-            + 12 * nbar * Nk + 120 * Nk)
+    b = (14 * Nh + 48 * Nh + 16 * Nd + 8 * (Nh + Nd) + 8 * Nl + 66 * Nt
+         + 12 * nbar * Nk + 120 * Nk)
+    if n.get("Nv") is not None:
+        b += 17 * Nk + 16 * n["Nv"]
+    return b
 
 
 def step_bytes(step, n):
@@ -154,6 +163,8 @@ def step_bytes(step, n):
         "cleaning": 33 * Nt,                                # raw n-tuplets read
         "fit": 12 * nbar * Nk + 120 * Nk,                   # hit gathers, tracks written
     }
+    if n.get("Nv") is not None:
+        table["vertices"] = 17 * Nk + 16 * n["Nv"]          # track values read, vertices written
     return table.get(step)
 
 
@@ -166,6 +177,7 @@ STEP_STAGES = {
     "ntuplets": ("roots", "tuple_count", "tuple_scan", "tuple_fill"),
     "cleaning": ("score", "best", "survive"),
     "fit": ("fit32", "fit64", "finish"),
+    "vertices": ("vertices",),
 }
 
 
@@ -240,6 +252,8 @@ def roofline(stages, n, batches_per_s, peak_gbs, copy_gbs, workload, args):
     for step, stg in STEP_STAGES.items():
         ms = sum(stages.get(s, 0.0) for s in stg)
         b = step_bytes(step, n)
+        if b is None:
+            continue
         out["steps"][step] = {"ms": round(ms, 5), "bytes": int(b),
                               "frac": round(b / (ms * 1e-3) / 1e9 / peak_gbs, 5) if ms else None}
     if traffic:
@@ -327,7 +341,8 @@ class Batched:
         self.recs = [pxt.Reconstructor(det, phi_bins=args.phi_bins,
                                        group_lanes=args.group_lanes,
                                        link_kernel=args.link_kernel, use_graph=graph,
-                                       doublet_mode=doublet_mode, **caps)
+                                       doublet_mode=doublet_mode,
+                                       max_vertices_per_event=VTX_SLOTS * args.vertices, **caps)
                      for _ in range(inflight)]
         self.streams = [torch.cuda.Stream() for _ in range(inflight)]
         self.dev = [self.recs[0].upload(b) for b in batches]
@@ -434,7 +449,8 @@ def plain_leg(torch, pxt, det, kind, events, args, n_calls, streams=1):
     caps["max_events"] = 1
     recs = [pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                               link_kernel=args.link_kernel, use_graph=args.graph,
-                              doublet_mode=args.latency_doublet_mode, **caps)
+                              doublet_mode=args.latency_doublet_mode,
+                              max_vertices_per_event=VTX_SLOTS * args.vertices, **caps)
             for _ in range(streams)]
     ss = [torch.cuda.Stream() for _ in range(streams)]
     dev = [recs[0].upload([e]) for e in events]
@@ -468,7 +484,8 @@ def plain_malloc_per_event(torch, pxt, det, kind, events, args, n_calls):
     for i in range(n_calls):
         r = pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                               link_kernel=args.link_kernel, use_graph=0,
-                              doublet_mode=args.latency_doublet_mode, **caps)
+                              doublet_mode=args.latency_doublet_mode,
+                              max_vertices_per_event=VTX_SLOTS * args.vertices, **caps)
         r.launch(*dev[i % len(dev)])
         torch.cuda.synchronize()
         r.close()
@@ -493,11 +510,16 @@ def copy_peak(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def path_counts(rec, counts, n_hits):
+def path_counts(rec, counts, n_hits, n_events):
     nk = counts["n_tracks"]
     nh = rec.o_n_hits[:nk].cpu().numpy()
-    return {"Nh": n_hits, "Nd": counts["n_doublets"], "Nl": counts["n_links"],
-            "Nt": counts["n_raw_tuples"], "Nk": nk, "nbar": float(nh.mean()) if nk else 0.0}
+    n = {"Nh": n_hits, "Nd": counts["n_doublets"], "Nl": counts["n_links"],
+         "Nt": counts["n_raw_tuples"], "Nk": nk, "nbar": float(nh.mean()) if nk else 0.0}
+    if rec.vtx is not None:
+        summary, _, _ = rec.vtx.read(n_events, 0)
+        assert summary["status"] == 0, summary
+        n["Nv"] = summary["n_vertices"]
+    return n
 
 
 def main(argv=None):
@@ -544,10 +566,11 @@ def main(argv=None):
     # events cannot sit inside the replayed graph)
     trec = pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
                              link_kernel=args.link_kernel, use_graph=0,
-                             doublet_mode=args.doublet_mode, **bat.caps)
+                             doublet_mode=args.doublet_mode,
+                             max_vertices_per_event=VTX_SLOTS * args.vertices, **bat.caps)
     tb = trec.upload(pool[0])
     stages = trec.stage_times(tb, repeats=5)
-    n = path_counts(trec, trec.read_counts(), int(tb[4][-1]))
+    n = path_counts(trec, trec.read_counts(), int(tb[4][-1]), B)
     trec.close()
 
     pcie = None
@@ -620,13 +643,15 @@ def main(argv=None):
             "latency_doublet_mode": args.latency_doublet_mode,
             "hip_graph": bool(args.graph),
             "path": "batched (one launch sequence per batch), inputs resident in HBM",
+            "vertices": bool(args.vertices),
         },
         "trials": trials,
         "plain_events_per_s": round(plain_ev_s, 2),
         "batched_over_plain": round(ev_per_s / plain_ev_s, 2),
         "hits_per_s": round(ev_per_s * hits_per_event, 1),
-        "per_batch_counts": {k: counts[k] for k in ("n_doublets", "n_links", "n_raw_tuples",
-                                                    "n_tracks", "n_fp64")},
+        "per_batch_counts": dict({k: counts[k] for k in ("n_doublets", "n_links",
+                                                         "n_raw_tuples", "n_tracks", "n_fp64")},
+                                 **({"n_vertices": n["Nv"]} if "Nv" in n else {})),
         "stage_ms": stages,
     }
     if pcie is not None:

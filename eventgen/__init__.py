@@ -28,7 +28,7 @@ from .detector import (DETECTOR, WORKLOADS, BARREL, DISK, BATCH_TRACKS,
 __all__ = ["DETECTOR", "WORKLOADS", "Event", "generate", "generate_custom",
            "make_batch", "concat_events", "workload_params", "BARREL", "DISK"]
 
-_WORKLOAD_IDS = {"tiny": 1, "pu50": 2, "batch": 3, "serve": 4, "pu200": 5}
+_WORKLOAD_IDS = {"tiny": 1, "pu50": 2, "batch": 3, "serve": 4, "pu200": 5, "vertex": 6}
 
 
 @dataclass
@@ -352,3 +352,44 @@ def concat_events(events):
     z = cat([e.z for e in events]).astype(np.float32)
     layer = cat([e.layer for e in events]).astype(np.int16)
     return x, y, z, layer, offs
+
+
+def vertex_track_lists(seed, n_events=8, max_tracks=3000):
+    """Seeded synthetic track lists for the vertex step alone (inputs only):
+    per event, arrays z0, var(z0), q/pT (float32) and hit counts (uint8) of
+    tracks drawn around a few vertices (z ~ N(0, 5 cm), track spread
+    0.002-0.05 cm) plus uniform background, on a coarse 1/512 cm grid in
+    every second event (exact distances and ties), with edge cases mixed in:
+    an empty event, a one-track event, identical z0 values, +-0.0, NaN z0,
+    zero and negative variances, 3-hit tracks and |q/pT| around the cut."""
+    rng = np.random.default_rng([_WORKLOAD_IDS["vertex"], int(seed)])
+    out = []
+    for e in range(n_events):
+        if e == 0:
+            n = 0
+        elif e == 1:
+            n = 1
+        else:
+            n = int(rng.integers(2, max_tracks))
+        nv = int(rng.integers(1, 41))
+        vz = rng.normal(0.0, 5.0, nv)
+        z = vz[rng.integers(0, nv, n)] + rng.normal(0.0, 1.0, n) * rng.uniform(0.002, 0.05, n)
+        bg = rng.uniform(0.0, 1.0, n) < 0.2
+        z[bg] = rng.uniform(-15.0, 15.0, int(bg.sum()))
+        if e % 2 == 0:
+            z = np.round(z * 512.0) / 512.0
+        z = z.astype(np.float32)
+        var = (rng.uniform(0.001, 0.03, n) ** 2).astype(np.float32)
+        qopt = rng.uniform(-3.3, 3.3, n).astype(np.float32)
+        nh = rng.integers(3, 7, n).astype(np.uint8)
+        if n > 20:
+            z[:6] = z[6]                       # identical values
+            z[7] = np.float32(-0.0)
+            z[8] = np.float32(0.0)
+            z[9] = np.float32(np.nan)
+            var[10] = 0.0
+            var[11] = -1e-4
+            qopt[12] = np.float32(2.0)          # exactly 1 / 0.5 GeV
+            qopt[13] = np.nextafter(np.float32(2.0), np.float32(3.0))
+        out.append(dict(z0=z, var=var, qopt=qopt, nhits=nh))
+    return out

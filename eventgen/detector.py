@@ -65,6 +65,17 @@ DETECTOR = {
         # curvature floor for the scattering momentum estimate: pT <= 1e4 GeV
         "pt_max": 1.0e4,
     },
+    "quality": {
+        # output selection: n-tuplets with fewer hits are not output
+        # (3: triplets and longer; 4: quadruplets and longer only)
+        "min_hits": 3,
+        # LOOSE flag: chi2 per degree of freedom at most this in both planes
+        "chi2": 5.0,
+        # STRICT flag: LOOSE and pT (GeV), |d0| (cm), |z0| (cm) within these
+        "pt_min": 0.5,
+        "d0_max": 0.05,
+        "z0_max": 15.0,
+    },
     "vertex": {
         # tracks used: at least this many hits and pT at least pt_min (GeV)
         "min_hits": 4,

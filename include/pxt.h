@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PXT_ABI_VERSION 2
+#define PXT_ABI_VERSION 3
 
 #define PXT_MAX_LAYERS 16
 #define PXT_MAX_PAIRS 32
@@ -115,7 +115,30 @@ typedef struct pxt_config {
                                (most throughput on large batches).  All
                                modes give the same results.               */
   double pt_fp64;           /* fit tuples with pT_ref above this in FP64   */
+  /* --- output selection and track quality (pxt_tracks.flags) ---------- */
+  int32_t min_hits;         /* tracks with fewer hits are not output:
+                               3 keeps triplets and longer, 4 gives
+                               quadruplets and longer only (3..8).  The
+                               cleaning is unchanged: a shorter n-tuplet
+                               never outranks a longer one.              */
+  float q_chi2;             /* PXT_FLAG_LOOSE: chi2 / ndf at most this in
+                               both planes (ndf n-3 transverse, at least
+                               1; n-2 longitudinal)                       */
+  float q_pt_min;           /* PXT_FLAG_STRICT: pT at least [GeV]          */
+  float q_d0_max;           /* PXT_FLAG_STRICT: |d0| at most [cm]          */
+  float q_z0_max;           /* PXT_FLAG_STRICT: |z0| at most [cm]          */
+  /* --- vertices (pxt_tracks.vertices, pxt_find_vertices) -------------- */
+  double vtx_eps;           /* z0 neighbour distance [cm]                  */
+  int32_t vtx_min_pts;      /* neighbours (itself included) of a core      */
+  int32_t vtx_min_hits;     /* tracks used: at least this many hits ...    */
+  double vtx_pt_min;        /* ... and pT at least this [GeV]              */
 } pxt_config;
+
+/* pxt_tracks.flags bits */
+#define PXT_FLAG_FP64 1u   /* fitted on the FP64 path                        */
+#define PXT_FLAG_LOOSE 2u  /* parameters finite, chi2/ndf within q_chi2      */
+#define PXT_FLAG_STRICT 4u /* LOOSE, pT >= q_pt_min, |d0| <= q_d0_max,
+                              |z0| <= q_z0_max                               */
 
 /* One call's input: a ragged batch of events in structure-of-arrays form.
  * x, y, z, layer are DEVICE pointers with event_offsets[n_events] entries;
@@ -155,8 +178,50 @@ typedef struct pxt_counts {
  * approach to the transverse origin; d0 > 0 when the origin is left of the
  * direction of motion.  cov = packed lower triangle of the 5x5 covariance
  * (row-major: (0,0),(1,0),(1,1),(2,0),...).  chi2 = (transverse, long.).
- * flags bit 0: fitted on the FP64 path.  per_event_tracks[e] receives the
- * number of tracks of event e.  counts receives the summary. */
+ * flags: PXT_FLAG_* bits.  per_event_tracks[e] receives the number of
+ * tracks of event e.  counts receives the summary. */
+/* Vertices of a call's tracks (the Vertices module that follows the Tracks
+ * module in the paper's chain, Sec. 2 and Fig. 1; the paper gives no
+ * algorithm).  Reading: one-dimensional density-based clustering (DBSCAN)
+ * of z0 over the tracks with at least vtx_min_hits hits and pT at least
+ * vtx_pt_min (|q/pT| <= 1/vtx_pt_min compared in single precision), finite
+ * z0 and a positive variance of z0.  Two tracks are neighbours when their
+ * z0 differ by at most vtx_eps (difference of the single-precision values
+ * in double precision); a core has at least vtx_min_pts neighbours, itself
+ * included; connected cores form a cluster; a non-core track with a core
+ * neighbour joins its nearest core's cluster (ties: the lower core), the
+ * rest belong to no vertex.  Per cluster, over its tracks in increasing
+ * (z0, index) order, in double precision: w = 1/var(z0), z = sum(w z0) /
+ * sum(w), z_err = sqrt(1/sum(w)), chi2 = sum(w (z0 - z)^2), rounded to
+ * single precision on output.
+ *
+ * Caller-owned DEVICE buffers.  Event e's vertices are at
+ * [e * max_per_event, e * max_per_event + n_vertices[e]), in increasing z.
+ * track_vertex[k] = the vertex (index within its event) of output track k,
+ * or -1.  An event with more than PXT_VTX_MAX_TRACKS selected tracks or
+ * more than max_per_event vertices gets none: summary->status =
+ * PXT_ERR_CAPACITY with the sizes it needs in max_selected and
+ * required_per_event.  If the tracks themselves failed (pxt_counts.status
+ * not PXT_OK), summary->status carries that status and nothing is written. */
+#define PXT_VTX_MAX_TRACKS 4096
+typedef struct pxt_vertex_summary {
+  int32_t status;
+  uint32_t n_vertices;          /* over all events                     */
+  uint32_t required_per_event;  /* largest vertex count of an event    */
+  uint32_t max_selected;        /* largest selected-track count        */
+} pxt_vertex_summary;
+
+typedef struct pxt_vertices {
+  uint32_t max_per_event;
+  float* z;                     /* [n_events][max_per_event] */
+  float* z_err;
+  float* chi2;
+  uint32_t* n_tracks;           /* tracks in each vertex      */
+  uint32_t* n_vertices;         /* [n_events]                 */
+  int32_t* track_vertex;        /* [track capacity]           */
+  pxt_vertex_summary* summary;  /* [1]                        */
+} pxt_vertices;
+
 typedef struct pxt_tracks {
   uint32_t capacity;
   uint32_t* hit_idx;          /* [capacity][8]  */
@@ -168,6 +233,9 @@ typedef struct pxt_tracks {
   uint8_t* flags;             /* [capacity]     */
   uint32_t* per_event_tracks; /* [n_events]     */
   pxt_counts* counts;         /* [1]            */
+  const pxt_vertices* vertices; /* HOST struct of device buffers, or NULL:
+                                   when set, the call also finds the
+                                   vertices of its tracks               */
 } pxt_tracks;
 
 typedef struct pxt_ctx pxt_ctx;
@@ -229,11 +297,24 @@ int pxt_set_timing(pxt_ctx* ctx, int enable);
  * floats; *n_stages receives the number of stages (PXT_N_STAGES).  Stages
  * skipped by that call (an empty batch) read 0.  Errors:
  * PXT_ERR_INVALID_ARG (no timed call yet, null pointers), PXT_ERR_HIP. */
-#define PXT_N_STAGES 19
+#define PXT_N_STAGES 20
 int pxt_stage_times(pxt_ctx* ctx, float* ms, int cap, int* n_stages);
 
 /* Static name of stage i (0 <= i < PXT_N_STAGES), or NULL. */
 const char* pxt_stage_name(int stage);
+
+/* Vertices of tracks already in device memory (for example the outputs of
+ * an earlier pxt_reconstruct), by the reading given with pxt_vertices; the
+ * same kernels run at the end of pxt_reconstruct when pxt_tracks.vertices
+ * is set.  Uses cfg's vtx_* fields only (validated as by pxt_create).
+ * tracks: DEVICE buffers of the tracks of n_events events, grouped by event
+ * in event order with per_event_tracks[e] tracks each (n_hits, params and
+ * cov are read; tracks->counts may be NULL, else its status must be PXT_OK
+ * or the call only reports it).  Asynchronous on hip_stream; allocates
+ * nothing.  Errors: PXT_ERR_INVALID_ARG, PXT_ERR_HIP (message from
+ * pxt_last_error(NULL)). */
+int pxt_find_vertices(const pxt_config* cfg, uint32_t n_events, const pxt_tracks* tracks,
+                      const pxt_vertices* out, void* hip_stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops and harnesses that forbid hipMalloc): the same

@@ -131,13 +131,16 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def reconstruct(x, y, z, layer, det):
+def reconstruct(x, y, z, layer, det, min_hits=None):
     """Run the whole path on one event.  Returns a dict of numpy arrays:
 
     doublets [Nd,2], links [Nl,3], raw [Nt,8], raw_score [Nt], keep [Nt],
     tracks [Nk,8], params [Nk,5], cov [Nk,15], chi2 [Nk,2], kref [Nk],
     status (0 ok, 1 path longer than 8 hits).  Hit indices are event-local
-    input-order indices; tuples are padded with 0xFFFFFFFF.
+    input-order indices; tuples are padded with 0xFFFFFFFF.  Tracks (and
+    their params, cov, chi2, kref) with fewer than min_hits hits are left
+    out (default: the detector's quality.min_hits, else 3); the cleaning is
+    the same, since a shorter n-tuplet never outranks a longer one.
     """
     L = lib()
     cfg = make_config(det)
@@ -162,9 +165,15 @@ def reconstruct(x, y, z, layer, det):
                 a = np.frombuffer(buf, dtype=dt).copy()
                 a = a.reshape(int(n), w) if w > 1 else a
             out[name] = a
-        return out
     finally:
         L.orc_free(r)
+    if min_hits is None:
+        min_hits = (det.get("quality") or {}).get("min_hits", 3)
+    if min_hits > 3 and out["tracks"].shape[0]:
+        keep = (out["tracks"] != PAD).sum(axis=1) >= min_hits
+        for name in ("tracks", "params", "cov", "chi2", "kref"):
+            out[name] = out[name][keep]
+    return out
 
 
 def fit(X, Y, Z, kind, det):
@@ -266,6 +275,29 @@ def event_vertices(o, det):
     if p.shape[0] == 0:
         return vertices(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), det)
     return vertices(p[:, 4], cv[:, 14], p[:, 2], nh, det)
+
+
+def quality_flags(params, chi2, nhits, det):
+    """Quality bits of fitted tracks (the reading stated with the library's
+    flags): 2 = LOOSE, finite parameters and chi2 per degree of freedom at
+    most the limit in both planes (transverse ndf n-3, at least 1;
+    longitudinal n-2); 4 = STRICT, LOOSE with pT, |d0| and |z0| within their
+    limits.  Decided in single precision on the values rounded to single
+    precision, as the library hands them over."""
+    q = det["quality"]
+    p = np.asarray(params, np.float64).astype(np.float32).reshape(-1, 5)
+    ch = np.asarray(chi2, np.float64).astype(np.float32).reshape(-1, 2)
+    n = np.asarray(nhits, np.int64)
+    ndf_c = np.maximum(n - 3, 1).astype(np.float32)
+    ndf_z = (n - 2).astype(np.float32)
+    lim = np.float32(q["chi2"])
+    fin = np.all(np.isfinite(p), axis=1)
+    with np.errstate(invalid="ignore"):
+        loose = fin & (ch[:, 0] <= lim * ndf_c) & (ch[:, 1] <= lim * ndf_z)
+        strict = (loose & (np.abs(p[:, 2]) <= np.float32(1.0 / float(np.float32(q["pt_min"]))))
+                  & (np.abs(p[:, 1]) <= np.float32(q["d0_max"]))
+                  & (np.abs(p[:, 4]) <= np.float32(q["z0_max"])))
+    return (loose.astype(np.uint8) * 2) | (strict.astype(np.uint8) * 4)
 
 
 def rechits(cl, table, max_per_module):

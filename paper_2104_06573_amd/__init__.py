@@ -33,11 +33,13 @@ EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_de
            "pxt_create", "pxt_destroy", "pxt_reconstruct", "pxt_debug_dump",
            "pxt_set_timing", "pxt_stage_times", "pxt_stage_name",
            "pxt_server_create", "pxt_submit", "pxt_poll", "pxt_server_get_stats",
-           "pxt_server_destroy", "pxt_reconstruct_static")
+           "pxt_server_destroy", "pxt_reconstruct_static", "pxt_find_vertices")
 STATIC_SCRATCH_BYTES = 64 << 20
 STATIC_MAX_EVENTS = 64
-N_STAGES = 19
-ABI_VERSION = 2  # layout of the structs below
+N_STAGES = 20
+ABI_VERSION = 3  # layout of the structs below
+VTX_MAX_TRACKS = 4096
+FLAG_FP64, FLAG_LOOSE, FLAG_STRICT = 1, 2, 4
 
 
 class PxtConfig(ctypes.Structure):
@@ -60,6 +62,11 @@ class PxtConfig(ctypes.Structure):
         ("group_lanes", ctypes.c_int32), ("link_kernel", ctypes.c_int32),
         ("use_graph", ctypes.c_int32), ("doublet_mode", ctypes.c_int32),
         ("pt_fp64", ctypes.c_double),
+        ("min_hits", ctypes.c_int32), ("q_chi2", ctypes.c_float),
+        ("q_pt_min", ctypes.c_float), ("q_d0_max", ctypes.c_float),
+        ("q_z0_max", ctypes.c_float),
+        ("vtx_eps", ctypes.c_double), ("vtx_min_pts", ctypes.c_int32),
+        ("vtx_min_hits", ctypes.c_int32), ("vtx_pt_min", ctypes.c_double),
     ]
 
 
@@ -82,6 +89,20 @@ class PxtCounts(ctypes.Structure):
     ]
 
 
+class PxtVertexSummary(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_vertices", ctypes.c_uint32),
+                ("required_per_event", ctypes.c_uint32), ("max_selected", ctypes.c_uint32)]
+
+
+class PxtVertices(ctypes.Structure):
+    _fields_ = [
+        ("max_per_event", ctypes.c_uint32),
+        ("z", ctypes.c_void_p), ("z_err", ctypes.c_void_p), ("chi2", ctypes.c_void_p),
+        ("n_tracks", ctypes.c_void_p), ("n_vertices", ctypes.c_void_p),
+        ("track_vertex", ctypes.c_void_p), ("summary", ctypes.c_void_p),
+    ]
+
+
 class PxtTracks(ctypes.Structure):
     _fields_ = [
         ("capacity", ctypes.c_uint32),
@@ -89,7 +110,7 @@ class PxtTracks(ctypes.Structure):
         ("event_id", ctypes.c_void_p), ("params", ctypes.c_void_p),
         ("cov", ctypes.c_void_p), ("chi2", ctypes.c_void_p),
         ("flags", ctypes.c_void_p), ("per_event_tracks", ctypes.c_void_p),
-        ("counts", ctypes.c_void_p),
+        ("counts", ctypes.c_void_p), ("vertices", ctypes.c_void_p),
     ]
 
 
@@ -137,6 +158,9 @@ def lib():
         L.pxt_reconstruct_static.argtypes = [ctypes.POINTER(PxtConfig), ctypes.c_int,
                                              ctypes.POINTER(PxtHits), ctypes.POINTER(PxtTracks),
                                              ctypes.c_void_p]
+        L.pxt_find_vertices.argtypes = [ctypes.POINTER(PxtConfig), ctypes.c_uint32,
+                                        ctypes.POINTER(PxtTracks), ctypes.POINTER(PxtVertices),
+                                        ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -147,7 +171,8 @@ def stage_names():
 
 def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
                 max_link_words=None, max_tuples=1 << 19, phi_bins=256, block_size=256,
-                group_lanes=8, link_kernel=0, use_graph=0, doublet_mode=2, pt_fp64=20.0):
+                group_lanes=8, link_kernel=0, use_graph=0, doublet_mode=2, pt_fp64=20.0,
+                min_hits=None):
     """pxt_config from a detector dictionary (eventgen.DETECTOR layout)."""
     c = PxtConfig()
     if lib().pxt_config_defaults(ctypes.byref(c)) != OK:
@@ -178,6 +203,17 @@ def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
     c.use_graph = use_graph
     c.doublet_mode = doublet_mode
     c.pt_fp64 = pt_fp64
+    q = det.get("quality")
+    if q:
+        c.min_hits = q["min_hits"] if min_hits is None else min_hits
+        c.q_chi2, c.q_pt_min, c.q_d0_max, c.q_z0_max = (q["chi2"], q["pt_min"], q["d0_max"],
+                                                        q["z0_max"])
+    elif min_hits is not None:
+        c.min_hits = min_hits
+    v = det.get("vertex")
+    if v:
+        c.vtx_eps, c.vtx_min_pts = v["eps"], v["min_pts"]
+        c.vtx_min_hits, c.vtx_pt_min = v["min_hits"], v["pt_min"]
     return c
 
 
@@ -210,6 +246,58 @@ def counts_dict(words):
                 required=list(c.required))
 
 
+class VertexBuffers:
+    """Device buffers of a pxt_vertices for n_events events and n_tracks
+    tracks, V vertex slots per event."""
+
+    def __init__(self, n_events, n_tracks, V, device):
+        import torch as t
+        self.V = V
+        self.z = t.empty((n_events, V), dtype=t.float32, device=device)
+        self.z_err = t.empty((n_events, V), dtype=t.float32, device=device)
+        self.chi2 = t.empty((n_events, V), dtype=t.float32, device=device)
+        self.n_tracks = t.empty((n_events, V), dtype=t.int32, device=device)
+        self.n_vertices = t.empty(n_events, dtype=t.int32, device=device)
+        self.track_vertex = t.empty(max(n_tracks, 1), dtype=t.int32, device=device)
+        self.summary = t.empty(4, dtype=t.int32, device=device)
+        self.struct = PxtVertices(V, self.z.data_ptr(), self.z_err.data_ptr(),
+                                  self.chi2.data_ptr(), self.n_tracks.data_ptr(),
+                                  self.n_vertices.data_ptr(), self.track_vertex.data_ptr(),
+                                  self.summary.data_ptr())
+
+    def read(self, n_events, n_tracks):
+        """Host copy: summary dict, and per event a dict of z, z_err, chi2,
+        n_tracks arrays; track_vertex of the n_tracks tracks."""
+        sm = self.summary.cpu().numpy()
+        summary = dict(status=int(sm[0]), n_vertices=int(sm[1].view(np.uint32)),
+                       required_per_event=int(sm[2].view(np.uint32)),
+                       max_selected=int(sm[3].view(np.uint32)))
+        nv = self.n_vertices[:n_events].cpu().numpy()
+        z, ze, ch, nt = (a[:n_events].cpu().numpy() for a in (self.z, self.z_err, self.chi2,
+                                                              self.n_tracks))
+        events = [dict(z=z[e, :nv[e]], z_err=ze[e, :nv[e]], chi2=ch[e, :nv[e]],
+                       n_tracks=nt[e, :nv[e]]) for e in range(n_events)]
+        return summary, events, self.track_vertex[:n_tracks].cpu().numpy()
+
+
+def find_vertices(cfg, per_event_tracks, n_hits, params, cov, max_per_event, stream=None):
+    """pxt_find_vertices on device tensors of tracks grouped by event
+    (per_event_tracks int32 [E], n_hits uint8 [T], params float32 [T, 5],
+    cov float32 [T, 15]); returns the VertexBuffers (read() for results)."""
+    import torch as t
+    E = int(per_event_tracks.shape[0])
+    T = int(n_hits.shape[0])
+    vb = VertexBuffers(max(E, 1), T, int(max_per_event), params.device)
+    tr = PxtTracks(T, None, n_hits.data_ptr(), None, params.data_ptr(), cov.data_ptr(), None,
+                   None, per_event_tracks.data_ptr(), None, None)
+    st = stream or t.cuda.current_stream(params.device)
+    rc = lib().pxt_find_vertices(ctypes.byref(cfg), E, ctypes.byref(tr), ctypes.byref(vb.struct),
+                                 ctypes.c_void_p(st.cuda_stream))
+    if rc != OK:
+        raise PxtError(rc, lib().pxt_last_error(None).decode())
+    return vb
+
+
 def upload_events(events, device=0):
     """Concatenate host events (objects with x, y, z, layer arrays) into one
     ragged batch on the device; returns (x, y, z, layer, offsets) with the
@@ -231,7 +319,7 @@ class Reconstructor:
     ABI; owned by this object here).
     """
 
-    def __init__(self, det, device=0, max_tracks=1 << 18, **caps):
+    def __init__(self, det, device=0, max_tracks=1 << 18, max_vertices_per_event=0, **caps):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -257,7 +345,11 @@ class Reconstructor:
         self._tracks = PxtTracks(
             T, self.o_hit_idx.data_ptr(), self.o_n_hits.data_ptr(), self.o_event_id.data_ptr(),
             self.o_params.data_ptr(), self.o_cov.data_ptr(), self.o_chi2.data_ptr(),
-            self.o_flags.data_ptr(), self.o_per_event.data_ptr(), self.o_counts.data_ptr())
+            self.o_flags.data_ptr(), self.o_per_event.data_ptr(), self.o_counts.data_ptr(), None)
+        self.vtx = None
+        if max_vertices_per_event > 0:
+            self.vtx = VertexBuffers(max(E, 1), T, int(max_vertices_per_event), dev)
+            self._tracks.vertices = ctypes.addressof(self.vtx.struct)
 
     def close(self):
         if getattr(self, "h", None):

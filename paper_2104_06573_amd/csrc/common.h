@@ -63,6 +63,15 @@ struct DevCfg {
   uint32_t cap_doublets, cap_words, cap_tuples;
   int link_kernel;                          // 0 thread, 1 lane group, 2 wave
   float th_win, th_far;                     // r-z angle prefilter of the links
+  // output selection and quality flags
+  int min_hits;                             // shorter survivors are not output
+  float q_chi2;                             // LOOSE: chi2 per ndf at most
+  float q_qopt_max;                         // STRICT: |q/pT| at most (1/pT_min)
+  float q_d0_max, q_z0_max;                 // STRICT: |d0|, |z0| at most
+  // vertices
+  double vtx_eps;
+  int vtx_min_pts, vtx_min_hits;
+  float vtx_qopt_max;                       // 1/pT_min in single precision
 };
 
 struct CallDesc;

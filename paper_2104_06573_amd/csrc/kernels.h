@@ -12,6 +12,7 @@
 #include "common.h"
 #include "cuts.h"
 #include "fit.h"
+#include "vertex.h"
 
 namespace pxt {
 
@@ -34,12 +35,14 @@ struct OutPtrs {
 struct CallDesc {
   uint32_t n_events;
   uint32_t n_hits;
-  uint32_t pad[2];
+  uint32_t has_vtx;  // 1: find the vertices of the tracks into vtx
+  uint32_t pad;
   const float* x;
   const float* y;
   const float* z;
   const int16_t* layer;
   OutPtrs out;
+  VtxOut vtx;
 };
 
 // ------------------------------------------------------------------ clear
@@ -1466,8 +1469,10 @@ __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const uint32_t ntup = w.ctr[C_NTUP];
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
-    uint32_t alive = 1;
     const int n = w.tn[t];
+    // shorter n-tuplets than min_hits are not output (they never outrank a
+    // longer one, so the others' fate does not depend on them)
+    uint32_t alive = n >= c.min_hits ? 1u : 0u;
     uint32_t tc[kMaxHits];
     load_row(w.tcell, t, tc);
 #pragma unroll
@@ -1622,6 +1627,22 @@ __global__ __launch_bounds__(256) void k_fitorder(Ws w) {
 
 // ------------------------------------------------------------------ fit --
 
+// Quality bits of a fitted track from its single-precision outputs:
+// LOOSE = finite parameters and chi2 per degree of freedom within q_chi2 in
+// both planes (transverse ndf n-3, at least 1; longitudinal n-2); STRICT =
+// LOOSE and pT, |d0|, |z0| within their limits.
+__device__ __forceinline__ uint32_t quality_flags(const DevCfg& c, int n, const float* p,
+                                                  const float* chi2) {
+  bool fin = true;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) fin = fin && isfinite(p[i]);
+  const float ndf_c = (float)(n - 3 > 1 ? n - 3 : 1), ndf_z = (float)(n - 2);
+  const bool loose = fin && chi2[0] <= c.q_chi2 * ndf_c && chi2[1] <= c.q_chi2 * ndf_z;
+  const bool strict = loose && fabsf(p[2]) <= c.q_qopt_max && fabsf(p[1]) <= c.q_d0_max &&
+                      fabsf(p[4]) <= c.q_z0_max;
+  return (loose ? PXT_FLAG_LOOSE : 0u) | (strict ? PXT_FLAG_STRICT : 0u);
+}
+
 // Fit survivor s; NFIX > 0: the tuple is known to have NFIX hits.
 template <typename T, int NFIX = 0>
 __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_t s,
@@ -1673,7 +1694,7 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   for (int i = 0; i < 15; ++i) o.cov[(size_t)s * 15 + i] = f.cov[i];
   o.chi2[(size_t)s * 2 + 0] = f.chi2[0];
   o.chi2[(size_t)s * 2 + 1] = f.chi2[1];
-  o.flags[s] = fp64 ? 1 : 0;
+  o.flags[s] = (uint8_t)((fp64 ? PXT_FLAG_FP64 : 0u) | quality_flags(c, n, f.params, f.chi2));
 }
 
 // One kernel per tuple length N over that length's range of the fitting
@@ -1726,6 +1747,22 @@ __global__ void k_finish(Ws w) {
   k->required[1] = ctr[C_REQ_W];
   k->required[2] = ctr[C_REQ_T];
   k->required[3] = ctr[C_REQ_K];
+}
+
+// --------------------------------------------------------------- vertices --
+// The vertex step of a pxt_reconstruct call (after k_finish), on the call's
+// own outputs; nothing when the call has no vertex buffers.
+
+__global__ void k_vtx_begin_call(Ws w) {
+  if (w.call->has_vtx) k_vtx_begin_body(w.call->vtx);
+}
+
+__global__ __launch_bounds__(kVtxThreads) void k_vertices_call(Ws w, DevCfg c) {
+  const CallDesc* cd = w.call;
+  if (!cd->has_vtx) return;
+  const VtxIn in{cd->n_events, cd->out.per_event_tracks, cd->out.n_hits, cd->out.params,
+                 cd->out.cov, cd->out.counts};
+  vertices_block(in, cd->vtx, c);
 }
 
 }  // namespace pxt

@@ -195,6 +195,12 @@ int validate_config(const pxt_config* c, std::string& why) {
   if (c->link_kernel < 0 || c->link_kernel > 2) return why = "link_kernel must be 0, 1 or 2", 1;
   if (c->use_graph != 0 && c->use_graph != 1) return why = "use_graph must be 0 or 1", 1;
   if (c->doublet_mode < 0 || c->doublet_mode > 2) return why = "doublet_mode must be 0, 1 or 2", 1;
+  if (c->min_hits < 3 || c->min_hits > PXT_MAX_TUPLE_HITS) return why = "min_hits out of 3..8", 1;
+  if (!(c->q_chi2 > 0 && c->q_pt_min > 0 && c->q_d0_max > 0 && c->q_z0_max > 0))
+    return why = "quality limits must be > 0", 1;
+  if (!(c->vtx_eps > 0 && c->vtx_pt_min > 0) || c->vtx_min_pts < 1 || c->vtx_min_hits < 3 ||
+      c->vtx_min_hits > PXT_MAX_TUPLE_HITS)
+    return why = "vertex constants out of range", 1;
   return 0;
 }
 
@@ -226,6 +232,15 @@ void make_devcfg(const pxt_config& c, DevCfg& d) {
   d.cap_words = c.max_link_words;
   d.cap_tuples = c.max_tuples;
   d.link_kernel = c.link_kernel;
+  d.min_hits = c.min_hits;
+  d.q_chi2 = c.q_chi2;
+  d.q_qopt_max = (float)(1.0 / (double)c.q_pt_min);
+  d.q_d0_max = c.q_d0_max;
+  d.q_z0_max = c.q_z0_max;
+  d.vtx_eps = c.vtx_eps;
+  d.vtx_min_pts = c.vtx_min_pts;
+  d.vtx_min_hits = c.vtx_min_hits;
+  d.vtx_qopt_max = (float)(1.0 / c.vtx_pt_min);
   // L1 holds only if the r-z directions of the two doublets differ by at
   // most asin(arz) or by at least pi - asin(arz).  The FP32 angles carry an
   // error below 1e-6 rad (inputs rounded to FP32: < 1.2e-7; atan2f: a few
@@ -260,7 +275,7 @@ const char* const kStageNames[PXT_N_STAGES] = {
     "clear",       "prep",       "bin_scan",    "fill",       "doublet_count",
     "doublet_scan", "doublet_fill", "mask_clear", "links",    "roots",
     "tuple_count", "tuple_scan", "tuple_fill",  "score",      "best",
-    "survive",     "fit32",      "fit64",       "finish"};
+    "survive",     "fit32",      "fit64",       "finish",     "vertices"};
 
 // Marks the start of stage i when timing is on (c == nullptr: no timing).
 struct StageMarks {
@@ -430,6 +445,12 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
   }
   if (timed) sm.mark(18);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, w);
+  // vertices of the call's tracks (the kernels leave at once when the call
+  // has no vertex buffers)
+  if (timed) sm.mark(19);
+  hipLaunchKernelGGL(k_vtx_begin_call, dim3(1), dim3(64), 0, s, w);
+  hipLaunchKernelGGL(k_vertices_call, dim3(std::max<uint32_t>(1, E)), dim3(kVtxThreads), 0, s,
+                     w, d);
   if (timed) {
     (void)hipEventRecord(c->ev[PXT_N_STAGES], s);
     c->timed_valid = true;
@@ -443,6 +464,19 @@ void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, u
   (void)hipMemcpyAsync(const_cast<CallDesc*>(c->ws.call),
                        c->h_slots + (size_t)slot * c->slot_bytes, copy, hipMemcpyHostToDevice, s);
   enqueue_path(c, c->cfg, c->ws, c->dc, c->n_cu, s, graph_mode, H, E);
+}
+
+int validate_vertices(const pxt_vertices* v, uint32_t E, std::string& why) {
+  if (!v->summary || (E > 0 && !v->n_vertices)) return why = "null vertex summary / counts", 1;
+  if (E > 0 && (!v->track_vertex || (v->max_per_event > 0 &&
+                                     (!v->z || !v->z_err || !v->chi2 || !v->n_tracks))))
+    return why = "null vertex buffer", 1;
+  return 0;
+}
+
+VtxOut make_vtx_out(const pxt_vertices* v) {
+  return VtxOut{v->max_per_event, v->z, v->z_err, v->chi2, v->n_tracks, v->n_vertices,
+                v->track_vertex, v->summary};
 }
 
 // Checks of one call's input and output descriptions against cfg.
@@ -463,6 +497,7 @@ int validate_call(const pxt_config& cfg, const pxt_hits* in, const pxt_tracks* o
   if (out->capacity > 0 && (!out->hit_idx || !out->n_hits || !out->event_id || !out->params ||
                             !out->cov || !out->chi2 || !out->flags))
     return why = "null track buffer", 1;
+  if (out->vertices && validate_vertices(out->vertices, E, why)) return 1;
   return 0;
 }
 
@@ -476,6 +511,8 @@ CallDesc make_desc(const pxt_hits* in, const pxt_tracks* out) {
   desc.layer = in->layer;
   desc.out = OutPtrs{out->capacity, out->hit_idx, out->n_hits, out->event_id, out->params,
                      out->cov, out->chi2, out->flags, out->per_event_tracks, out->counts};
+  desc.has_vtx = out->vertices ? 1u : 0u;
+  if (out->vertices) desc.vtx = make_vtx_out(out->vertices);
   return desc;
 }
 
@@ -552,6 +589,39 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->use_graph = 0;
   cfg->doublet_mode = 2;
   cfg->pt_fp64 = 20.0;
+  cfg->min_hits = 3;
+  cfg->q_chi2 = 5.0f;
+  cfg->q_pt_min = 0.5f;
+  cfg->q_d0_max = 0.05f;
+  cfg->q_z0_max = 15.0f;
+  cfg->vtx_eps = 0.02;
+  cfg->vtx_min_pts = 6;
+  cfg->vtx_min_hits = 4;
+  cfg->vtx_pt_min = 0.5;
+  return PXT_OK;
+}
+
+int pxt_find_vertices(const pxt_config* cfg, uint32_t n_events, const pxt_tracks* tracks,
+                      const pxt_vertices* out, void* stream) {
+  if (!cfg || !tracks || !out) return fail(nullptr, PXT_ERR_INVALID_ARG, "null argument");
+  std::string why;
+  if (validate_config(cfg, why)) return fail(nullptr, PXT_ERR_INVALID_ARG, why);
+  if (n_events > 0 && (!tracks->per_event_tracks || !tracks->n_hits || !tracks->params ||
+                       !tracks->cov))
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "null track buffer");
+  if (validate_vertices(out, n_events, why)) return fail(nullptr, PXT_ERR_INVALID_ARG, why);
+  DevCfg dc;
+  make_devcfg(*cfg, dc);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const VtxOut vo = make_vtx_out(out);
+  const VtxIn vi{n_events, tracks->per_event_tracks, tracks->n_hits, tracks->params, tracks->cov,
+                 tracks->counts};
+  hipLaunchKernelGGL(k_vtx_begin, dim3(1), dim3(64), 0, s, vo);
+  if (n_events > 0)
+    hipLaunchKernelGGL(k_vertices, dim3(n_events), dim3(kVtxThreads), 0, s, vi, vo, dc);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(nullptr, PXT_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
   return PXT_OK;
 }
 

@@ -30,7 +30,7 @@ def test_header_symbols_exported():
 
 def test_version_and_status_strings():
     L = pxt.lib()
-    assert L.pxt_abi_version() == pxt.ABI_VERSION == 2
+    assert L.pxt_abi_version() == pxt.ABI_VERSION == 3
     assert L.pxt_status_str(0) == b"ok"
     assert L.pxt_status_str(2) == b"capacity exceeded"
     assert L.pxt_status_str(99) == b"unknown status"
@@ -77,9 +77,12 @@ def test_struct_sizes_match_header():
 #include <stddef.h>
 #include "pxt.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(pxt_config), offsetof(pxt_config, pt_fp64),
-         offsetof(pxt_config, group_lanes), offsetof(pxt_config, doublet_mode),
-         sizeof(pxt_hits), sizeof(pxt_tracks), sizeof(pxt_counts));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pxt_config),
+         offsetof(pxt_config, pt_fp64), offsetof(pxt_config, group_lanes),
+         offsetof(pxt_config, doublet_mode), offsetof(pxt_config, min_hits),
+         offsetof(pxt_config, q_z0_max), offsetof(pxt_config, vtx_eps),
+         offsetof(pxt_config, vtx_pt_min), sizeof(pxt_hits), sizeof(pxt_tracks),
+         sizeof(pxt_counts), sizeof(pxt_vertices), sizeof(pxt_vertex_summary));
   return 0;
 }
 '''
@@ -89,10 +92,12 @@ int main(void) {
         exe = os.path.join(d, "p")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
         got = list(map(int, subprocess.check_output([exe]).split()))
-    want = [ctypes.sizeof(pxt.PxtConfig), pxt.PxtConfig.pt_fp64.offset,
-            pxt.PxtConfig.group_lanes.offset, pxt.PxtConfig.doublet_mode.offset,
-            ctypes.sizeof(pxt.PxtHits),
-            ctypes.sizeof(pxt.PxtTracks), ctypes.sizeof(pxt.PxtCounts)]
+    C = pxt.PxtConfig
+    want = [ctypes.sizeof(C), C.pt_fp64.offset, C.group_lanes.offset, C.doublet_mode.offset,
+            C.min_hits.offset, C.q_z0_max.offset, C.vtx_eps.offset, C.vtx_pt_min.offset,
+            ctypes.sizeof(pxt.PxtHits), ctypes.sizeof(pxt.PxtTracks),
+            ctypes.sizeof(pxt.PxtCounts), ctypes.sizeof(pxt.PxtVertices),
+            ctypes.sizeof(pxt.PxtVertexSummary)]
     assert got == want
 
 
@@ -140,3 +145,23 @@ def test_static_entry_point_validation():
                                     None) == pxt.ERR_INVALID_ARG
     assert L.pxt_reconstruct_static(None, 0, ctypes.byref(hits), ctypes.byref(out),
                                     None) == pxt.ERR_INVALID_ARG
+
+
+def test_output_policy_and_vertex_config_validation():
+    L = pxt.lib()
+    h = ctypes.c_void_p()
+    for field, bad in (("min_hits", 2), ("min_hits", 9), ("q_chi2", 0.0), ("q_pt_min", -1.0),
+                       ("vtx_eps", 0.0), ("vtx_min_pts", 0), ("vtx_min_hits", 2),
+                       ("vtx_pt_min", 0.0)):
+        c = pxt.make_config(eventgen.DETECTOR)
+        setattr(c, field, bad)
+        assert L.pxt_create(ctypes.byref(c), 0, ctypes.byref(h)) == pxt.ERR_INVALID_ARG, field
+        assert L.pxt_find_vertices(ctypes.byref(c), 0, ctypes.byref(pxt.PxtTracks()),
+                                   ctypes.byref(pxt.PxtVertices()), None) == pxt.ERR_INVALID_ARG
+    good = pxt.make_config(eventgen.DETECTOR)
+    # null buffers are rejected before any device call
+    assert L.pxt_find_vertices(ctypes.byref(good), 2, ctypes.byref(pxt.PxtTracks()),
+                               ctypes.byref(pxt.PxtVertices()), None) == pxt.ERR_INVALID_ARG
+    assert L.pxt_find_vertices(None, 0, None, None, None) == pxt.ERR_INVALID_ARG
+    d = pxt.make_config({**eventgen.DETECTOR, "quality": None}, min_hits=4)
+    assert d.min_hits == 4 and d.q_chi2 == 5.0  # library defaults of the quality limits

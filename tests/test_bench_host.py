@@ -48,7 +48,13 @@ def test_algorithmic_bytes_follow_the_method_formula():
              + 12 * 3.5 * 300 + 120 * 300)
     assert bench.path_bytes(n) == pytest.approx(total)
     # the steps' shares add up to the whole path
-    assert sum(bench.step_bytes(s, n) for s in bench.STEP_STAGES) == pytest.approx(total)
+    assert sum(bench.step_bytes(s, n) or 0 for s in bench.STEP_STAGES) == pytest.approx(total)
+    # with vertices: the tracks' z0 values read and their vertex written, and
+    # the vertices
+    nv = dict(n, Nv=40)
+    assert bench.path_bytes(nv) == pytest.approx(total + 17 * 300 + 16 * 40)
+    assert sum(bench.step_bytes(s, nv) for s in bench.STEP_STAGES) == pytest.approx(
+        bench.path_bytes(nv))
     assert bench.step_bytes("links", n) == 8 * 20000 + 4 * (1000 + 20000) + 4 * 3000
     assert bench.step_bytes("no_such_step", n) is None
 

@@ -374,3 +374,47 @@ def test_path_longer_than_eight_hits(torch):
     ev8 = cs.Ev(ev9.x[keep], ev9.y[keep], ev9.z[keep], ev9.layer[keep])
     res, out, dumps = run_and_dump(rec, [ev8])
     check_events([ev8], res, out, dumps, det=d9)
+
+
+def test_quadruplets_only(torch):
+    # min_hits 4: only quadruplets and longer come out, the same ones as the
+    # oracle's; doublets, links and raw n-tuplets are unchanged
+    det4 = {**DET, "quality": {**DET["quality"], "min_hits": 4}}
+    events = [eventgen.generate("pu50", 100 + s) for s in range(3)]
+    rec = make_rec(det=det4)
+    res, out, dumps = run_and_dump(rec, events)
+    assert out["n_hits"].min() >= 4
+    check_events(events, res, out, dumps, det=det4)
+
+
+def test_quality_flags(torch):
+    # LOOSE / STRICT bits against the oracle's decisions on its own fitted
+    # values; a track whose oracle value lies within the fit tolerance of a
+    # limit may go either way and is left out (counted and printed)
+    events = [eventgen.generate("pu50", 100 + s) for s in range(3)]
+    rec = make_rec()
+    res = rec.run_numpy(events)
+    assert res.counts["status"] == 0
+    out = res.numpy()
+    oref = oracle_events(events, DET)
+    q = DET["quality"]
+    checked = near = 0
+    for e in range(len(events)):
+        gh, gp, gc, gx, gf, oh, op, oc, ox = match_tracks(out, oref[e], e)
+        n = (oh != 0xFFFFFFFF).sum(axis=1)
+        want = oracle.quality_flags(op, ox, n, DET)
+        ndf_c = np.maximum(n - 3, 1)
+        ndf_z = n - 2
+        rel = lambda v, lim, fl: np.abs(np.abs(v) - lim) <= 1e-4 * np.maximum(np.abs(v), fl)
+        close = (rel(op[:, 2], 1.0 / q["pt_min"], 0.001) | rel(op[:, 1], q["d0_max"], 0.01)
+                 | rel(op[:, 4], q["z0_max"], 1.0)
+                 | (np.abs(ox[:, 0] - q["chi2"] * ndf_c) <= 2e-3 * (1 + ox[:, 0]))
+                 | (np.abs(ox[:, 1] - q["chi2"] * ndf_z) <= 2e-3 * (1 + ox[:, 1])))
+        got = gf & 6
+        np.testing.assert_array_equal(got[~close], want[~close])
+        checked += int((~close).sum())
+        near += int(close.sum())
+    frac = lambda b: float(np.mean((out["flags"] & b) != 0))
+    print("flags: %d tracks compared, %d near a limit; loose %.3f strict %.3f fp64 %.4f" %
+          (checked, near, frac(2), frac(4), frac(1)))
+    assert checked > 0.99 * (checked + near)
