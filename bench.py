@@ -63,6 +63,8 @@ def parse(argv=None):
                     help="one-event calls timed on the plain path (cycled over the pool)")
     ap.add_argument("--pu200-steps", type=int, default=100)
     ap.add_argument("--no-pu200", action="store_true")
+    ap.add_argument("--no-rechits", action="store_true")
+    ap.add_argument("--rechits-steps", type=int, default=200)
     ap.add_argument("--no-pcie", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048,
@@ -112,6 +114,62 @@ def batch_caps(kind, n_events, max_hits):
 def _gen_one(a):
     import eventgen
     return eventgen.generate(a[0], a[1])
+
+
+def _gen_clusters(a):
+    import eventgen
+    from eventgen import clusters
+    ev = eventgen.generate(a[0], a[1])
+    c = clusters.make_clusters(ev, a[1])
+    c.pop("hit_of_cluster")
+    return c
+
+
+def gen_clusters(kind, n, seed0, workers=1):
+    """Pixel clusters of events seed0 .. seed0+n-1 (the RecHits input)."""
+    args = [(kind, seed0 + i) for i in range(n)]
+    if workers <= 1:
+        return [_gen_clusters(a) for a in args]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(workers, n),
+                             mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(_gen_clusters, args))
+
+
+def rechits_leg(torch, pxt, clusters, args):
+    """pxt_rechits on one batch of clusters, timed over --rechits-steps
+    calls: events/s, and the step's algorithmic bytes (module id and pixel
+    range per cluster, 6 bytes per pixel read; 20 bytes per hit and the
+    per-module counters and offsets written) against the HBM peak."""
+    from eventgen import clusters as C
+    table = C.module_table()
+    dev, ev = pxt.upload_clusters(clusters)
+    nc = int(ev[-1])
+    E = len(clusters)
+    rh = pxt.RecHits(table, E, nc)
+    limit = 1024
+    for _ in range(5):
+        rh.launch(dev, E, nc, limit)
+    torch.cuda.synchronize()
+    status = rh.read(E)[0]
+    assert status == 0, status
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.rechits_steps):
+        rh.launch(dev, E, nc, limit)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.rechits_steps
+    npix = int(dev["pixel_offsets"][-1].item())
+    nh = int(rh.hit_offsets[E].item())
+    byts = 6 * nc + 6 * npix + 20 * nh + 12 * E * table.shape[0]
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"workload": "pixel clusters of the %d PU~50 events of one batch (%d clusters, "
+                        "%d pixels, %d modules)" % (E, nc, npix, table.shape[0]),
+            "events_per_s": round(E / (ms * 1e-3), 2), "ms_per_step": round(ms, 5),
+            "steps": args.rechits_steps, "hits": nh, "algorithmic_bytes": int(byts),
+            "achieved_gbs": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 5)}
 
 
 def gen_events(kind, n, seed0, workers=1):
@@ -533,6 +591,9 @@ def main(argv=None):
     B = args.batch or batch_default
     flat = gen_events(kind, B * args.pool, 1000, workers=HOST_WORKERS)
     pool = [flat[p * B:(p + 1) * B] for p in range(args.pool)]
+    clusters = None
+    if not args.no_rechits and args.workload == "pu50":
+        clusters = gen_clusters(kind, B, 1000, workers=HOST_WORKERS)
     pu200 = None
     if not args.no_pu200 and args.workload == "pu50":
         f2 = gen_events("pu200", 64, 5000, workers=HOST_WORKERS)
@@ -616,6 +677,7 @@ def main(argv=None):
                 "plain_events_per_s": round(pv2, 2),
                 "batched_over_plain": round(v2 / pv2, 2)}
 
+    rech = rechits_leg(torch, pxt, clusters, args) if clusters is not None else None
     cgbs = copy_peak(torch)
     counts = c0
     out = {
@@ -660,6 +722,8 @@ def main(argv=None):
         out["pu200"] = p200
     if ablations is not None:
         out["ablations"] = ablations
+    if rech is not None:
+        out["rechits"] = rech
     out["roofline"] = roofline(stages, n, ev_per_s / B, HBM_PEAK_GBS, cgbs, args.workload, args)
     if served is not None:
         out["served"] = served

@@ -316,6 +316,67 @@ const char* pxt_stage_name(int stage);
 int pxt_find_vertices(const pxt_config* cfg, uint32_t n_events, const pxt_tracks* tracks,
                       const pxt_vertices* out, void* hip_stream);
 
+/* ------------------------------------------------------------------ */
+/* RecHits: pixel clusters to 3-D hits (the paper's RecHits module,      */
+/* Sec. 2: it estimates the 3-D position of each cluster, forming hits;  */
+/* its Fig. 3 limits each module's cluster count and turns the counts    */
+/* into the modules' first-hit offsets).  The output is the input of     */
+/* pxt_reconstruct.                                                      */
+/*                                                                      */
+/* Reading, per event: c[m] = the clusters of module m, limited to       */
+/* max_per_module; module_start = running sum of c (one array over all  */
+/* events, so the hits of all events are contiguous, in event and module */
+/* order); a cluster's rank among the earlier clusters of its module     */
+/* decides whether it makes a hit (rank < max_per_module) and where      */
+/* (module_start + rank); its local position is the charge-weighted      */
+/* centroid of its pixel centres, u = u0 + pitch_u * (sum q (iu + 1/2) / */
+/* sum q), v likewise (double precision, pixels in order); the 3-D hit:  */
+/* barrel module, the tangent-plane point r n + u t projected radially   */
+/* onto the cylinder of radius r, (r c - u s, r s + u c) r / sqrt(r r +  */
+/* u u), z = z_c + v; disk module, ((r + u) c - v s, (r + u) s + v c,    */
+/* z_disk); rounded to single precision.  A cluster without charge makes */
+/* a hit with layer -1 at the origin (it takes part in nothing).         */
+/*                                                                      */
+/* Module table: DEVICE float64 [n_modules][10] rows (layer id, kind 0   */
+/* barrel / 1 disk, cos phi_c, sin phi_c, r (barrel radius / disk ring   */
+/* centre), z (module centre / disk plane), u0, v0 (local position of    */
+/* pixel (0, 0)'s corner), pitch_u, pitch_v), cm.                        */
+
+typedef struct pxt_clusters {
+  uint32_t n_events;
+  uint32_t n_clusters;
+  const uint32_t* event_offsets; /* DEVICE [n_events + 1] clusters of each event */
+  const uint16_t* module;        /* DEVICE [n_clusters]: within an event,
+                                    non-decreasing (grouped by module)   */
+  const uint32_t* pixel_offsets; /* DEVICE [n_clusters + 1] pixel ranges */
+  const uint16_t* pix_u;         /* DEVICE pixel column, row, charge     */
+  const uint16_t* pix_v;
+  const uint16_t* charge;
+} pxt_clusters;
+
+typedef struct pxt_rechits_out {
+  uint32_t capacity;             /* hits                                  */
+  float* x;                      /* DEVICE [capacity]                     */
+  float* y;
+  float* z;
+  int16_t* layer;
+  uint16_t* module;
+  uint32_t* cluster;             /* the cluster each hit comes from       */
+  uint32_t* module_start;        /* DEVICE [n_events * n_modules + 1]     */
+  uint32_t* hit_offsets;         /* DEVICE [n_events + 1]                 */
+  int32_t* status;               /* DEVICE [1]: PXT_OK, PXT_ERR_CAPACITY
+                                    (more hits than capacity: only the
+                                    offsets are valid), PXT_ERR_INVALID_ARG
+                                    (a module id out of range or clusters
+                                    not grouped by module)               */
+} pxt_rechits_out;
+
+/* Asynchronous on hip_stream; allocates nothing.  Errors returned
+ * directly: PXT_ERR_INVALID_ARG (null pointers, n_modules out of 1..65535,
+ * max_per_module 0), PXT_ERR_HIP (message from pxt_last_error(NULL)). */
+int pxt_rechits(const double* modules, uint32_t n_modules, uint32_t max_per_module,
+                const pxt_clusters* in, const pxt_rechits_out* out, void* hip_stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops and harnesses that forbid hipMalloc): the same
  * computation as pxt_reconstruct on a context created from the same cfg,

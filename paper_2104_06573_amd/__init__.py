@@ -33,7 +33,8 @@ EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_de
            "pxt_create", "pxt_destroy", "pxt_reconstruct", "pxt_debug_dump",
            "pxt_set_timing", "pxt_stage_times", "pxt_stage_name",
            "pxt_server_create", "pxt_submit", "pxt_poll", "pxt_server_get_stats",
-           "pxt_server_destroy", "pxt_reconstruct_static", "pxt_find_vertices")
+           "pxt_server_destroy", "pxt_reconstruct_static", "pxt_find_vertices",
+           "pxt_rechits")
 STATIC_SCRATCH_BYTES = 64 << 20
 STATIC_MAX_EVENTS = 64
 N_STAGES = 20
@@ -114,6 +115,20 @@ class PxtTracks(ctypes.Structure):
     ]
 
 
+class PxtClusters(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_uint32), ("n_clusters", ctypes.c_uint32),
+                ("event_offsets", ctypes.c_void_p), ("module", ctypes.c_void_p),
+                ("pixel_offsets", ctypes.c_void_p), ("pix_u", ctypes.c_void_p),
+                ("pix_v", ctypes.c_void_p), ("charge", ctypes.c_void_p)]
+
+
+class PxtRechitsOut(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_uint32), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("layer", ctypes.c_void_p), ("module", ctypes.c_void_p),
+                ("cluster", ctypes.c_void_p), ("module_start", ctypes.c_void_p),
+                ("hit_offsets", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
 COUNTS_WORDS = ctypes.sizeof(PxtCounts) // 4
 
 _lib = None
@@ -161,6 +176,9 @@ def lib():
         L.pxt_find_vertices.argtypes = [ctypes.POINTER(PxtConfig), ctypes.c_uint32,
                                         ctypes.POINTER(PxtTracks), ctypes.POINTER(PxtVertices),
                                         ctypes.c_void_p]
+        L.pxt_rechits.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.POINTER(PxtClusters), ctypes.POINTER(PxtRechitsOut),
+                                  ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -296,6 +314,90 @@ def find_vertices(cfg, per_event_tracks, n_hits, params, cov, max_per_event, str
     if rc != OK:
         raise PxtError(rc, lib().pxt_last_error(None).decode())
     return vb
+
+
+def upload_clusters(clusters, device=0):
+    """Concatenate per-event cluster dicts (module, pixel_offsets from 0,
+    pix_u, pix_v, charge) into one device batch; returns a dict of device
+    tensors (event_offsets, module, pixel_offsets, pix_u, pix_v, charge)
+    and the host cluster offsets of the events."""
+    import torch as t
+    dev = t.device("cuda", device) if isinstance(device, int) else device
+    nc = [len(c["module"]) for c in clusters]
+    ev = np.zeros(len(clusters) + 1, np.uint32)
+    ev[1:] = np.cumsum(nc)
+    po = [np.zeros(1, np.uint32)]
+    base = 0
+    for c in clusters:
+        po.append(np.asarray(c["pixel_offsets"][1:], np.int64) + base)
+        base += int(c["pixel_offsets"][-1])
+    cat = lambda k, dt: np.ascontiguousarray(
+        np.concatenate([c[k] for c in clusters]) if clusters else np.zeros(0), dt)
+    to = lambda a: t.from_numpy(a).to(dev)
+    # uint16 arrays travel as int16 tensors (same bits)
+    return dict(event_offsets=to(ev.view(np.int32)),
+                module=to(cat("module", np.uint16).view(np.int16)),
+                pixel_offsets=to(np.concatenate(po).astype(np.uint32).view(np.int32)),
+                pix_u=to(cat("pix_u", np.uint16).view(np.int16)),
+                pix_v=to(cat("pix_v", np.uint16).view(np.int16)),
+                charge=to(cat("charge", np.uint16).view(np.int16))), ev
+
+
+class RecHits:
+    """Output buffers of pxt_rechits for up to max_events events of
+    n_modules modules and `capacity` hits, with the module table on the
+    device."""
+
+    def __init__(self, table, max_events, capacity, device=0):
+        import torch as t
+        self.torch = t
+        dev = t.device("cuda", device) if isinstance(device, int) else device
+        self.table = t.from_numpy(np.ascontiguousarray(table, np.float64)).to(dev)
+        self.n_modules = int(table.shape[0])
+        self.capacity = int(capacity)
+        C = max(self.capacity, 1)
+        self.x = t.empty(C, dtype=t.float32, device=dev)
+        self.y = t.empty(C, dtype=t.float32, device=dev)
+        self.z = t.empty(C, dtype=t.float32, device=dev)
+        self.layer = t.empty(C, dtype=t.int16, device=dev)
+        self.module = t.empty(C, dtype=t.int16, device=dev)
+        self.cluster = t.empty(C, dtype=t.int32, device=dev)
+        self.module_start = t.empty(max_events * self.n_modules + 1, dtype=t.int32, device=dev)
+        self.hit_offsets = t.empty(max_events + 1, dtype=t.int32, device=dev)
+        self.status = t.empty(1, dtype=t.int32, device=dev)
+        self.max_events = max_events
+        self._out = PxtRechitsOut(self.capacity, self.x.data_ptr(), self.y.data_ptr(),
+                                  self.z.data_ptr(), self.layer.data_ptr(),
+                                  self.module.data_ptr(), self.cluster.data_ptr(),
+                                  self.module_start.data_ptr(), self.hit_offsets.data_ptr(),
+                                  self.status.data_ptr())
+
+    def launch(self, dev_clusters, n_events, n_clusters, max_per_module, stream=None):
+        if n_events > self.max_events:
+            raise PxtError(ERR_INVALID_ARG, "more events than the buffers hold")
+        d = dev_clusters
+        cl = PxtClusters(n_events, n_clusters, d["event_offsets"].data_ptr(),
+                         d["module"].data_ptr(), d["pixel_offsets"].data_ptr(),
+                         d["pix_u"].data_ptr(), d["pix_v"].data_ptr(), d["charge"].data_ptr())
+        st = stream or self.torch.cuda.current_stream(self.x.device)
+        rc = lib().pxt_rechits(ctypes.c_void_p(self.table.data_ptr()), self.n_modules,
+                               int(max_per_module), ctypes.byref(cl), ctypes.byref(self._out),
+                               ctypes.c_void_p(st.cuda_stream))
+        if rc != OK:
+            raise PxtError(rc, lib().pxt_last_error(None).decode())
+
+    def read(self, n_events):
+        """Host copy: status, hit offsets per event, module_start, and the
+        hits (x, y, z, layer, module, cluster) of all events."""
+        status = int(self.status.cpu().numpy()[0])
+        ho = self.hit_offsets[:n_events + 1].cpu().numpy().view(np.uint32).copy()
+        ms = self.module_start[:n_events * self.n_modules + 1].cpu().numpy().view(np.uint32)
+        n = int(ho[-1]) if status == OK else 0
+        hits = dict(x=self.x[:n].cpu().numpy(), y=self.y[:n].cpu().numpy(),
+                    z=self.z[:n].cpu().numpy(), layer=self.layer[:n].cpu().numpy(),
+                    module=self.module[:n].cpu().numpy().view(np.uint16),
+                    cluster=self.cluster[:n].cpu().numpy().view(np.uint32))
+        return status, ho, ms.copy(), hits
 
 
 def upload_events(events, device=0):

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "rechits.h"
 
 using namespace pxt;
 
@@ -598,6 +599,50 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->vtx_min_pts = 6;
   cfg->vtx_min_hits = 4;
   cfg->vtx_pt_min = 0.5;
+  return PXT_OK;
+}
+
+int pxt_rechits(const double* modules, uint32_t n_modules, uint32_t max_per_module,
+                const pxt_clusters* in, const pxt_rechits_out* out, void* stream) {
+  if (!modules || !in || !out) return fail(nullptr, PXT_ERR_INVALID_ARG, "null argument");
+  if (n_modules < 1 || n_modules > 65535)
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "n_modules out of 1..65535");
+  if (max_per_module < 1) return fail(nullptr, PXT_ERR_INVALID_ARG, "max_per_module must be >= 1");
+  const uint64_t nmod = (uint64_t)in->n_events * n_modules;
+  if (nmod + 1 >= 0xffffffffull)
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "n_events * n_modules too large");
+  if (!out->module_start || !out->hit_offsets || !out->status)
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "null offsets / status buffer");
+  if (in->n_clusters > 0 &&
+      (!in->event_offsets || !in->module || !in->pixel_offsets || !in->pix_u || !in->pix_v ||
+       !in->charge || in->n_events == 0))
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "null cluster array or no events");
+  if (in->n_clusters > 0 && (!out->x || !out->y || !out->z || !out->layer || !out->module ||
+                             !out->cluster))
+    return fail(nullptr, PXT_ERR_INVALID_ARG, "null hit buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RhIn ri{in->n_events, in->n_clusters, in->event_offsets, in->module, in->pixel_offsets,
+                in->pix_u, in->pix_v, in->charge};
+  const RhOut ro{out->capacity, out->x,       out->y,           out->z,
+                 out->layer,    out->module,  out->cluster,     out->module_start,
+                 out->hit_offsets, out->status};
+  const uint32_t n = (uint32_t)nmod;
+  hipLaunchKernelGGL(k_rh_zero, dim3(grid_for((uint64_t)n + 1, 256, 2048)), dim3(256), 0, s, ro,
+                     n);
+  if (in->n_clusters > 0) {
+    const uint32_t g = grid_for(in->n_clusters, 256, 4096);
+    hipLaunchKernelGGL(k_rh_count, dim3(g), dim3(256), 0, s, ri, ro, n_modules);
+    hipLaunchKernelGGL(k_rh_offsets, dim3(1), dim3(kRhScanThreads), 0, s, ro, in->n_events,
+                       n_modules, max_per_module);
+    hipLaunchKernelGGL(k_rh_hits, dim3(g), dim3(256), 0, s, ri, ro, modules, n_modules,
+                       max_per_module);
+  } else {
+    hipLaunchKernelGGL(k_rh_offsets, dim3(1), dim3(kRhScanThreads), 0, s, ro, in->n_events,
+                       n_modules, max_per_module);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(nullptr, PXT_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
   return PXT_OK;
 }
 

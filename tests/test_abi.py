@@ -83,6 +83,7 @@ int main(void) {
          offsetof(pxt_config, q_z0_max), offsetof(pxt_config, vtx_eps),
          offsetof(pxt_config, vtx_pt_min), sizeof(pxt_hits), sizeof(pxt_tracks),
          sizeof(pxt_counts), sizeof(pxt_vertices), sizeof(pxt_vertex_summary));
+  printf("%zu %zu\n", sizeof(pxt_clusters), sizeof(pxt_rechits_out));
   return 0;
 }
 '''
@@ -97,7 +98,8 @@ int main(void) {
             C.min_hits.offset, C.q_z0_max.offset, C.vtx_eps.offset, C.vtx_pt_min.offset,
             ctypes.sizeof(pxt.PxtHits), ctypes.sizeof(pxt.PxtTracks),
             ctypes.sizeof(pxt.PxtCounts), ctypes.sizeof(pxt.PxtVertices),
-            ctypes.sizeof(pxt.PxtVertexSummary)]
+            ctypes.sizeof(pxt.PxtVertexSummary), ctypes.sizeof(pxt.PxtClusters),
+            ctypes.sizeof(pxt.PxtRechitsOut)]
     assert got == want
 
 
@@ -165,3 +167,21 @@ def test_output_policy_and_vertex_config_validation():
     assert L.pxt_find_vertices(None, 0, None, None, None) == pxt.ERR_INVALID_ARG
     d = pxt.make_config({**eventgen.DETECTOR, "quality": None}, min_hits=4)
     assert d.min_hits == 4 and d.q_chi2 == 5.0  # library defaults of the quality limits
+
+
+def test_rechits_validation():
+    L = pxt.lib()
+    ms = (ctypes.c_uint32 * 8)()
+    out = pxt.PxtRechitsOut(0, None, None, None, None, None, None, ctypes.addressof(ms),
+                            ctypes.addressof(ms), ctypes.addressof(ms))
+    cl = pxt.PxtClusters(1, 0, None, None, None, None, None, None)
+    tab = ctypes.c_void_p(1)
+    for nm, lim in ((0, 8), (65536, 8), (10, 0)):
+        assert L.pxt_rechits(tab, nm, lim, ctypes.byref(cl), ctypes.byref(out),
+                             None) == pxt.ERR_INVALID_ARG
+    assert L.pxt_rechits(None, 10, 8, ctypes.byref(cl), ctypes.byref(out), None) == \
+        pxt.ERR_INVALID_ARG
+    cl2 = pxt.PxtClusters(1, 5, None, None, None, None, None, None)
+    assert L.pxt_rechits(tab, 10, 8, ctypes.byref(cl2), ctypes.byref(out), None) == \
+        pxt.ERR_INVALID_ARG
+    assert b"null" in L.pxt_last_error(None)
