@@ -353,32 +353,70 @@ def host_threads():
 
 
 def serving_leg(det, args):
-    """Continuous batching under Poisson arrivals (PU 30..140 mix), then a
-    saturating burst for the sustained rate."""
+    """Continuous batching over the PU 30..140 mix, driven by the library's
+    native replay (arrivals submitted and results released by native
+    threads): three runs of Poisson arrivals at --serve-rate, then a
+    saturating burst of the same events; phase means from the server's
+    counters.  Returns the entry and the pool (for the batched comparison
+    on the same mix)."""
     import eventgen
-    from paper_2104_06573_amd.serve import Server, poisson_run
+    from paper_2104_06573_amd.serve import Server, poisson_schedule, replay
     pool = eventgen.make_batch("serve", args.serve_pool, seed=11)
-    events = [pool[i % len(pool)] for i in range(args.serve_events)]
     srv = Server(det, n_lanes=args.serve_lanes, max_batch_events=64, doublets_per_hit=40,
                  max_events=64, max_hits=1_400_000, max_doublets=36 << 20,
                  max_link_words=160 << 20, max_tuples=6 << 20, phi_bins=args.phi_bins,
                  group_lanes=args.group_lanes, link_kernel=args.link_kernel, use_graph=1,
                  doublet_mode=args.latency_doublet_mode)
-    poisson_run(srv, events[:300], rate_hz=args.serve_rate)          # warm-up
-    rep = poisson_run(srv, events, rate_hz=args.serve_rate)
-    sat = poisson_run(srv, events, rate_hz=1e7)
+    replay(srv, pool, *poisson_schedule(300, args.serve_rate, len(pool)))      # warm-up
+    keep = ("events", "events_per_s", "p50_us", "p99_us", "mean_us", "mean_batch",
+            "max_batch", "failed", "phases_us")
+    rnd = lambda r: {k: round(r[k], 2) if isinstance(r[k], float) else r[k] for k in keep}
+    runs = [rnd(replay(srv, pool, *poisson_schedule(args.serve_events, args.serve_rate,
+                                                     len(pool), seed=k)))
+            for k in range(3)]
+    sat = rnd(replay(srv, pool, *poisson_schedule(args.serve_events, float("inf"), len(pool))))
     st = srv.stats()
     srv.close()
-    keep = ("events", "events_per_s", "p50_us", "p99_us", "mean_us", "mean_batch", "failed")
+    p50 = [r["p50_us"] for r in runs]
+    p99 = [r["p99_us"] for r in runs]
     return {
         "workload": "Poisson arrivals, PU uniform 30..140 (30 tracks per PU unit), pool of %d "
-                    "distinct events cycled" % len(pool),
+                    "distinct events cycled; native replay (submission and release in "
+                    "library threads)" % len(pool),
         "lanes": args.serve_lanes,
         "offered_rate_hz": args.serve_rate,
-        "at_rate": {k: round(rep[k], 2) if isinstance(rep[k], float) else rep[k] for k in keep},
-        "saturated": {k: round(sat[k], 2) if isinstance(sat[k], float) else sat[k] for k in keep},
+        "at_rate": runs,
+        "at_rate_p50_us_range": [min(p50), max(p50)],
+        "at_rate_p99_us_range": [min(p99), max(p99)],
+        "saturated": sat,
         "solo_retries": st["solo_retries"],
-    }
+    }, pool
+
+
+def mix_batched(torch, pxt, det, pool, args):
+    """The batched path (64 events per batch, graph, batches in flight) on
+    the serving mix, for the saturated serving rate to be compared with."""
+    B = 64
+    batches = [[pool[(B * k + j) % len(pool)] for j in range(B)] for k in range(2)]
+    caps = dict(max_events=B, max_hits=max(sum(e.n_hits for e in b) for b in batches) + 1024,
+                max_doublets=36 << 20, max_link_words=160 << 20, max_tuples=6 << 20,
+                max_tracks=6 << 20)
+    bat = Batched.__new__(Batched)
+    bat.torch = torch
+    bat.recs = [pxt.Reconstructor(det, phi_bins=args.phi_bins, group_lanes=args.group_lanes,
+                                  link_kernel=args.link_kernel, use_graph=args.graph,
+                                  doublet_mode=args.doublet_mode, **caps)
+                for _ in range(max(1, args.inflight))]
+    bat.streams = [torch.cuda.Stream() for _ in bat.recs]
+    bat.dev = [bat.recs[0].upload(b) for b in batches]
+    bat.B = B
+    bat.caps = caps
+    torch.cuda.synchronize()
+    bat.check()
+    v, ms, st = bat.timed(200, 5, args.trials)
+    bat.close()
+    return {"events_per_s": round(v, 2), "ms_per_step": round(ms, 4), "trials": st,
+            "events_per_batch": B}
 
 
 def stats(values):
@@ -607,9 +645,9 @@ def main(argv=None):
     det = eventgen.DETECTOR
     # the serving leg runs first, before this process creates any other
     # stream: its lanes' streams then get hardware queues of their own
-    served = None
+    served = serve_pool = None
     if not args.no_serve and args.workload == "pu50":
-        served = serving_leg(det, args)
+        served, serve_pool = serving_leg(det, args)
     if args.calib_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -678,6 +716,11 @@ def main(argv=None):
                 "batched_over_plain": round(v2 / pv2, 2)}
 
     rech = rechits_leg(torch, pxt, clusters, args) if clusters is not None else None
+    if served is not None:
+        mb = mix_batched(torch, pxt, det, serve_pool, args)
+        served["batched_same_mix"] = mb
+        served["saturated_over_batched"] = round(
+            served["saturated"]["events_per_s"] / mb["events_per_s"], 3)
     cgbs = copy_peak(torch)
     counts = c0
     out = {

@@ -449,6 +449,15 @@ typedef struct pxt_server_stats {
   uint64_t submitted, completed, failed, rejected, batches;
   uint64_t events_in_batches;   /* sum of batch sizes                    */
   uint64_t solo_retries;        /* events re-run alone after an overflow */
+  uint64_t delivered;           /* events handed over by pxt_poll        */
+  /* sums over the completed events of the time each spent, in us:
+   * queued (arrival to admission into a batch), staging and launch
+   * (admission to the batch's calls issued), device (to the counts back
+   * on the host), copy-back of the tracks; over the delivered events:
+   * delivery (tracks on the host to pxt_poll's return), and the whole
+   * latency (arrival to pxt_poll's return) */
+  double sum_queue_us, sum_launch_us, sum_device_us, sum_copyback_us;
+  double sum_deliver_us, sum_latency_us;
 } pxt_server_stats;
 
 /* Create a server on HIP device `hip_device`.  cfg gives physics and the
@@ -467,6 +476,11 @@ int pxt_submit(pxt_server* s, const float* x, const float* y, const float* z,
 
 /* Wait up to timeout_ms (negative: forever) for the event's result and copy
  * it into *out; the ticket is released once the result has been delivered.
+ * With out->capacity == 0 and out->hit_idx == NULL the tracks are not
+ * copied: status, n_tracks and the timings are set and the ticket is
+ * released.  A finished event's tracks wait in its lane's pinned result
+ * buffers (two sets per lane) until it is polled: a lane whose two sets
+ * both hold unpolled events takes no new batch.
  * Returns PXT_OK, PXT_ERR_NOT_READY (timeout; the ticket stays valid),
  * PXT_ERR_CAPACITY (out->capacity is below the event's track count, which
  * is written to out->n_tracks; nothing is copied and the ticket stays
@@ -476,10 +490,26 @@ int pxt_submit(pxt_server* s, const float* x, const float* y, const float* z,
  * overflowed the lane's arenas (it has no tracks; the ticket is released). */
 int pxt_poll(pxt_server* s, uint64_t ticket, pxt_event_tracks* out, int timeout_ms);
 
+/* Open-loop replay for measuring the server: arrival i submits event
+ * event_of_arrival[i] of a pool (HOST SoA arrays x, y, z, layer with
+ * pool_offsets[n_pool + 1]) at arrival_us[i] (non-decreasing, us after
+ * the call starts; a full queue is retried, the wait counting as
+ * latency), from the calling thread, while a second native thread polls
+ * the events in arrival order without copying their tracks.  results[i]
+ * (HOST, n entries) receives status, n_tracks, batch_events, queue_us and
+ * latency_us (from the scheduled arrival to the hand-over).  Returns when
+ * every event is done.  Errors: PXT_ERR_INVALID_ARG (null pointers, an
+ * event index or size out of range, decreasing arrival times). */
+int pxt_server_replay(pxt_server* s, uint32_t n, const uint32_t* event_of_arrival,
+                      const double* arrival_us, uint32_t n_pool, const uint32_t* pool_offsets,
+                      const float* x, const float* y, const float* z, const int16_t* layer,
+                      pxt_event_tracks* results);
+
 /* Counters since creation. */
 int pxt_server_get_stats(pxt_server* s, pxt_server_stats* out);
 
-/* Finish the work in flight, stop the dispatcher and free everything. */
+/* Finish the batches in flight, drop the events still queued (their status
+ * becomes PXT_ERR_BUSY), stop the dispatcher and free everything. */
 void pxt_server_destroy(pxt_server* s);
 
 #ifdef __cplusplus

@@ -34,7 +34,7 @@ EXPORTS = ("pxt_abi_version", "pxt_status_str", "pxt_last_error", "pxt_config_de
            "pxt_set_timing", "pxt_stage_times", "pxt_stage_name",
            "pxt_server_create", "pxt_submit", "pxt_poll", "pxt_server_get_stats",
            "pxt_server_destroy", "pxt_reconstruct_static", "pxt_find_vertices",
-           "pxt_rechits")
+           "pxt_rechits", "pxt_server_replay")
 STATIC_SCRATCH_BYTES = 64 << 20
 STATIC_MAX_EVENTS = 64
 N_STAGES = 20

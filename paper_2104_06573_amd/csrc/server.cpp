@@ -4,17 +4,25 @@
 // and output buffers and pinned host staging; lanes run their batches
 // concurrently, so the copy-in, reconstruction and copy-out of one batch
 // overlap with the others on the device.  A dispatcher thread owns every
-// HIP call: it admits pending events into a batch whenever a lane is free
-// (first come, first served, while the batch fits the lane's capacities),
-// and advances each busy lane through two phases -- reconstruction with the
-// copy-back of the counts, then the copy-back of exactly the tracks found.
-// Results are split per event (tracks come out grouped by event, in event
-// order) and handed to pxt_poll.  This is the serving form of the paper's
-// two throughput levers for one GPU: several events in flight at once and
+// HIP call and every lane: it admits pending events into a batch whenever a
+// lane is free (first come, first served, while the batch fits the lane's
+// capacities), and advances each busy lane through two phases --
+// reconstruction with the copy-back of the counts, then the copy-back of
+// exactly the tracks found.  The server lock guards only the queue, the
+// tickets and the counters: staging, HIP calls and result hand-over run
+// outside it.
+//
+// Results are not copied on the host by the server: each lane has two
+// pinned result sets, a finished batch's events point into the set its
+// tracks were copied to, and pxt_poll copies an event's tracks straight
+// from there into the caller's buffers; a set is reused once every event
+// in it has been polled.  This is the serving form of the paper's two
+// throughput levers for one GPU: several events in flight at once and
 // device memory allocated once and reused (Sec. 5).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -32,20 +40,35 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+double us_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::micro>(b - a).count();
+}
+
+// Pinned host copy of one batch's tracks.
+struct ResultSet {
+  uint32_t* hit_idx = nullptr;
+  uint8_t* nh = nullptr;
+  uint8_t* flags = nullptr;
+  float* params = nullptr;
+  float* cov = nullptr;
+  float* chi2 = nullptr;
+  std::atomic<uint32_t> refs{0};  // events of the set not yet polled
+};
+
 struct Request {
   uint64_t ticket = 0;
   std::vector<float> x, y, z;
   std::vector<int16_t> layer;
-  Clock::time_point t_submit, t_start;
+  // arrival (submit, or the scheduled arrival of a replay), admission into
+  // a batch, launch issued, counts back, tracks back
+  Clock::time_point t_arrival, t_start, t_launch, t_device, t_ready;
   bool solo = false;
   bool done = false;
   int status = PXT_OK;
   uint32_t batch_events = 0;
   uint32_t n_tracks = 0;
-  std::vector<uint32_t> hit_idx;
-  std::vector<uint8_t> n_hits, flags;
-  std::vector<float> params, cov, chi2;
-  double latency_us = 0.0, queue_us = 0.0;
+  ResultSet* rs = nullptr;  // where the tracks are (status PXT_OK)
+  uint32_t base = 0;        // first track of the event in rs
 };
 using ReqPtr = std::shared_ptr<Request>;
 
@@ -75,11 +98,11 @@ struct Lane {
   float *hx = nullptr, *hy = nullptr, *hz = nullptr;
   int16_t* hl = nullptr;
   pxt_counts* h_counts = nullptr;
-  uint32_t *h_per_event = nullptr, *h_hit_idx = nullptr;
-  uint8_t *h_nh = nullptr, *h_flags = nullptr;
-  float *h_params = nullptr, *h_cov = nullptr, *h_chi2 = nullptr;
-  // state
+  uint32_t* h_per_event = nullptr;
+  ResultSet res[2];
+  // state (dispatcher thread only)
   int phase = 0;  // 0 idle, 1 reconstruction in flight, 2 track copy-back in flight
+  int cur = 0;    // result set of the batch in flight
   std::vector<ReqPtr> batch;
   std::vector<uint32_t> offsets;
 
@@ -99,11 +122,19 @@ struct Lane {
          dev_alloc(&d_counts, 1);
     ok = ok && host_alloc(&hx, max_hits) && host_alloc(&hy, max_hits) &&
          host_alloc(&hz, max_hits) && host_alloc(&hl, max_hits) && host_alloc(&h_counts, 1) &&
-         host_alloc(&h_per_event, max_events) && host_alloc(&h_hit_idx, 8ull * max_tracks) &&
-         host_alloc(&h_nh, max_tracks) && host_alloc(&h_flags, max_tracks) &&
-         host_alloc(&h_params, 5ull * max_tracks) && host_alloc(&h_cov, 15ull * max_tracks) &&
-         host_alloc(&h_chi2, 2ull * max_tracks);
+         host_alloc(&h_per_event, max_events);
+    for (auto& r : res)
+      ok = ok && host_alloc(&r.hit_idx, 8ull * max_tracks) && host_alloc(&r.nh, max_tracks) &&
+           host_alloc(&r.flags, max_tracks) && host_alloc(&r.params, 5ull * max_tracks) &&
+           host_alloc(&r.cov, 15ull * max_tracks) && host_alloc(&r.chi2, 2ull * max_tracks);
     return ok;
+  }
+
+  // a result set nobody reads any more, or -1
+  int free_set() const {
+    for (int i = 0; i < 2; ++i)
+      if (res[i].refs.load(std::memory_order_acquire) == 0) return i;
+    return -1;
   }
 
   void release() {
@@ -113,9 +144,12 @@ struct Lane {
                     (void*)d_cov, (void*)d_chi2, (void*)d_counts})
       if (p) (void)hipFree(p);
     for (void* p : {(void*)hx, (void*)hy, (void*)hz, (void*)hl, (void*)h_counts,
-                    (void*)h_per_event, (void*)h_hit_idx, (void*)h_nh, (void*)h_flags,
-                    (void*)h_params, (void*)h_cov, (void*)h_chi2})
+                    (void*)h_per_event})
       if (p) (void)hipHostFree(p);
+    for (auto& r : res)
+      for (void* p : {(void*)r.hit_idx, (void*)r.nh, (void*)r.flags, (void*)r.params,
+                      (void*)r.cov, (void*)r.chi2})
+        if (p) (void)hipHostFree(p);
     if (ev) (void)hipEventDestroy(ev);
     if (stream) (void)hipStreamDestroy(stream);
     if (ctx) pxt_destroy(ctx);
@@ -140,26 +174,19 @@ struct pxt_server {
   std::thread worker;
 
   void run();
-  bool launch(Lane& L);
-  void advance(Lane& L);
-  void fail_batch(Lane& L, int status);
-  void deliver(Lane& L);
+  void take_batch(Lane& L);        // lock held
+  void start_batch(Lane& L);       // lock not held
+  void advance(Lane& L);           // lock not held
+  void finish(Lane& L, int status);  // lock not held
+  int submit(const float* x, const float* y, const float* z, const int16_t* layer,
+             uint32_t n_hits, Clock::time_point arrival, uint64_t* ticket);
+  int poll(uint64_t ticket, pxt_event_tracks* out, int timeout_ms, bool release_only);
 };
 
-namespace {
-
-double us_between(Clock::time_point a, Clock::time_point b) {
-  return std::chrono::duration<double, std::micro>(b - a).count();
-}
-
-}  // namespace
-
-// Form a batch from the pending events (lock held by the caller) and start
-// it on lane L.  Returns true if a batch was started.
-bool pxt_server::launch(Lane& L) {
-  if (pending.empty()) return false;
+// Move pending events into lane L's batch (first come, first served, while
+// the batch fits the lane); the server lock is held.
+void pxt_server::take_batch(Lane& L) {
   L.batch.clear();
-  L.offsets.assign(1, 0u);
   uint64_t hits = 0, est_d = 0;
   const uint32_t max_ev = std::min(scfg.max_batch_events, L.max_events);
   while (!pending.empty() && L.batch.size() < max_ev) {
@@ -173,7 +200,14 @@ bool pxt_server::launch(Lane& L) {
     L.batch.push_back(r);
     pending.pop_front();
   }
+  stats.batches++;
+  stats.events_in_batches += L.batch.size();
+}
+
+// Stage the batch's hits and launch it on the lane's stream.
+void pxt_server::start_batch(Lane& L) {
   const auto now = Clock::now();
+  L.offsets.assign(1, 0u);
   uint32_t off = 0;
   for (auto& r : L.batch) {
     r->t_start = now;
@@ -185,8 +219,6 @@ bool pxt_server::launch(Lane& L) {
     off += n;
     L.offsets.push_back(off);
   }
-  stats.batches++;
-  stats.events_in_batches += L.batch.size();
   const size_t H = off;
   bool ok = true;
   if (H) {
@@ -197,136 +229,245 @@ bool pxt_server::launch(Lane& L) {
   }
   pxt_hits in{(uint32_t)L.batch.size(), L.offsets.data(), L.dx, L.dy, L.dz, L.dl, nullptr};
   pxt_tracks out{L.max_tracks, L.d_hit_idx, L.d_nh, L.d_evt, L.d_params, L.d_cov,
-                 L.d_chi2, L.d_flags, L.d_per_event, L.d_counts};
+                 L.d_chi2, L.d_flags, L.d_per_event, L.d_counts, nullptr};
   ok = ok && pxt_reconstruct(L.ctx, &in, &out, L.stream) == PXT_OK;
   ok = ok && hipMemcpyAsync(L.h_counts, L.d_counts, sizeof(pxt_counts), hipMemcpyDeviceToHost,
                             L.stream) == hipSuccess;
   ok = ok && hipMemcpyAsync(L.h_per_event, L.d_per_event, 4ull * L.batch.size(),
                             hipMemcpyDeviceToHost, L.stream) == hipSuccess;
   ok = ok && hipEventRecord(L.ev, L.stream) == hipSuccess;
+  const auto t = Clock::now();
+  for (auto& r : L.batch) r->t_launch = t;
   L.phase = 1;
-  if (!ok) fail_batch(L, PXT_ERR_HIP);
-  return true;
+  if (!ok) finish(L, PXT_ERR_HIP);
 }
 
-void pxt_server::fail_batch(Lane& L, int status) {
+// Hand the batch's events over: status, track counts and where their tracks
+// are (status PXT_OK); then the pollers are woken.
+void pxt_server::finish(Lane& L, int status) {
   const auto now = Clock::now();
-  for (auto& r : L.batch) {
-    r->status = status;
-    r->done = true;
-    r->n_tracks = 0;
-    r->latency_us = us_between(r->t_submit, now);
-    r->queue_us = us_between(r->t_submit, r->t_start);
-    r->batch_events = (uint32_t)L.batch.size();
-    stats.completed++;
-    stats.failed++;
-  }
-  L.batch.clear();
-  L.phase = 0;
-  cv_done.notify_all();
-}
-
-void pxt_server::deliver(Lane& L) {
-  const auto now = Clock::now();
-  uint32_t base = 0;
   const uint32_t nb = (uint32_t)L.batch.size();
+  ResultSet* rs = &L.res[L.cur];
+  if (status == PXT_OK) rs->refs.store(nb, std::memory_order_release);
+  uint32_t base = 0;
   for (uint32_t e = 0; e < nb; ++e) {
     Request& r = *L.batch[e];
-    const uint32_t n = L.h_per_event[e];
-    r.n_tracks = n;
-    r.hit_idx.assign(L.h_hit_idx + 8ull * base, L.h_hit_idx + 8ull * (base + n));
-    r.n_hits.assign(L.h_nh + base, L.h_nh + base + n);
-    r.flags.assign(L.h_flags + base, L.h_flags + base + n);
-    r.params.assign(L.h_params + 5ull * base, L.h_params + 5ull * (base + n));
-    r.cov.assign(L.h_cov + 15ull * base, L.h_cov + 15ull * (base + n));
-    r.chi2.assign(L.h_chi2 + 2ull * base, L.h_chi2 + 2ull * (base + n));
-    r.status = PXT_OK;
+    r.status = status;
     r.batch_events = nb;
-    r.latency_us = us_between(r.t_submit, now);
-    r.queue_us = us_between(r.t_submit, r.t_start);
-    r.done = true;
-    base += n;
-    stats.completed++;
+    r.t_ready = now;
+    if (status == PXT_OK) {
+      r.n_tracks = L.h_per_event[e];
+      r.rs = rs;
+      r.base = base;
+      base += r.n_tracks;
+    } else {
+      r.n_tracks = 0;
+      r.t_device = r.t_device == Clock::time_point{} ? now : r.t_device;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& rp : L.batch) {
+      Request& r = *rp;
+      r.done = true;
+      stats.completed++;
+      if (status != PXT_OK) stats.failed++;
+      stats.sum_queue_us += us_between(r.t_arrival, r.t_start);
+      stats.sum_launch_us += us_between(r.t_start, r.t_launch);
+      stats.sum_device_us += us_between(r.t_launch, r.t_device);
+      stats.sum_copyback_us += us_between(r.t_device, r.t_ready);
+    }
   }
   L.batch.clear();
   L.phase = 0;
   cv_done.notify_all();
 }
 
-// Move lane L on if its device work has finished (lock held).
+// Move lane L on if its device work has finished.
 void pxt_server::advance(Lane& L) {
   if (L.phase == 0) return;
   const hipError_t q = hipEventQuery(L.ev);
   if (q == hipErrorNotReady) return;
   if (q != hipSuccess) {
-    fail_batch(L, PXT_ERR_HIP);
+    finish(L, PXT_ERR_HIP);
     return;
   }
   if (L.phase == 1) {
+    const auto now = Clock::now();
+    for (auto& r : L.batch) r->t_device = now;
     const int st = L.h_counts->status;
     if (st != PXT_OK) {
       if (L.batch.size() > 1) {
         // re-run each event alone, ahead of the queue, in order
-        for (auto it = L.batch.rbegin(); it != L.batch.rend(); ++it) {
-          (*it)->solo = true;
-          pending.push_front(*it);
+        {
+          std::lock_guard<std::mutex> g(mu);
+          for (auto it = L.batch.rbegin(); it != L.batch.rend(); ++it) {
+            (*it)->solo = true;
+            (*it)->t_device = Clock::time_point{};
+            pending.push_front(*it);
+          }
+          stats.solo_retries += L.batch.size();
         }
-        stats.solo_retries += L.batch.size();
         L.batch.clear();
         L.phase = 0;
       } else {
-        fail_batch(L, st);
+        finish(L, st);
       }
       return;
     }
     const size_t n = L.h_counts->n_tracks;
+    ResultSet& R = L.res[L.cur];
     bool ok = true;
     if (n) {
-      ok = hipMemcpyAsync(L.h_hit_idx, L.d_hit_idx, 32 * n, hipMemcpyDeviceToHost, L.stream) ==
+      ok = hipMemcpyAsync(R.hit_idx, L.d_hit_idx, 32 * n, hipMemcpyDeviceToHost, L.stream) ==
                hipSuccess &&
-           hipMemcpyAsync(L.h_nh, L.d_nh, n, hipMemcpyDeviceToHost, L.stream) == hipSuccess &&
-           hipMemcpyAsync(L.h_flags, L.d_flags, n, hipMemcpyDeviceToHost, L.stream) == hipSuccess &&
-           hipMemcpyAsync(L.h_params, L.d_params, 20 * n, hipMemcpyDeviceToHost, L.stream) ==
+           hipMemcpyAsync(R.nh, L.d_nh, n, hipMemcpyDeviceToHost, L.stream) == hipSuccess &&
+           hipMemcpyAsync(R.flags, L.d_flags, n, hipMemcpyDeviceToHost, L.stream) == hipSuccess &&
+           hipMemcpyAsync(R.params, L.d_params, 20 * n, hipMemcpyDeviceToHost, L.stream) ==
                hipSuccess &&
-           hipMemcpyAsync(L.h_cov, L.d_cov, 60 * n, hipMemcpyDeviceToHost, L.stream) ==
+           hipMemcpyAsync(R.cov, L.d_cov, 60 * n, hipMemcpyDeviceToHost, L.stream) ==
                hipSuccess &&
-           hipMemcpyAsync(L.h_chi2, L.d_chi2, 8 * n, hipMemcpyDeviceToHost, L.stream) ==
+           hipMemcpyAsync(R.chi2, L.d_chi2, 8 * n, hipMemcpyDeviceToHost, L.stream) ==
                hipSuccess;
     }
     ok = ok && hipEventRecord(L.ev, L.stream) == hipSuccess;
     if (!ok) {
-      fail_batch(L, PXT_ERR_HIP);
+      finish(L, PXT_ERR_HIP);
       return;
     }
     L.phase = 2;
     return;
   }
-  deliver(L);
+  finish(L, PXT_OK);
 }
 
 void pxt_server::run() {
   (void)hipSetDevice(device);
-  std::unique_lock<std::mutex> lk(mu);
+  uint32_t idle_rounds = 0;
   for (;;) {
-    bool progress = false;
-    bool busy = false;
+    bool progress = false, busy = false;
     for (auto& L : lanes) {
       const int before = L.phase;
       advance(L);
       if (L.phase != before) progress = true;
-      if (L.phase == 0 && !pending.empty()) progress |= launch(L);
-      busy |= L.phase != 0;
-    }
-    if (stop && !busy && pending.empty()) break;
-    if (!progress) {
-      if (busy) {
-        // device work in flight: short wait, woken early by a submission
-        cv_work.wait_for(lk, std::chrono::microseconds(20));
-      } else {
-        cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      if (L.phase != 0) continue;
+      const int set = L.free_set();
+      if (set < 0) continue;
+      {
+        std::lock_guard<std::mutex> g(mu);
+        if (pending.empty() || stop) continue;
+        take_batch(L);
       }
+      L.cur = set;
+      start_batch(L);
+      progress = true;
     }
+    for (auto& L : lanes) busy |= L.phase != 0;
+    std::unique_lock<std::mutex> lk(mu);
+    if (stop) {
+      // queued events are dropped; the batches on the lanes finish
+      for (auto& r : pending) {
+        r->status = PXT_ERR_BUSY;
+        r->done = true;
+        stats.completed++;
+        stats.failed++;
+      }
+      if (!pending.empty()) cv_done.notify_all();
+      pending.clear();
+      if (!busy) break;
+    }
+    if (progress) {
+      idle_rounds = 0;
+      continue;
+    }
+    if (busy && ++idle_rounds < 2000) {
+      // device work in flight: query the lanes again at once (a wait on
+      // the condition variable would add tens of microseconds per phase)
+      lk.unlock();
+      std::this_thread::yield();
+      continue;
+    }
+    idle_rounds = 0;
+    cv_work.wait_for(lk, std::chrono::microseconds(busy ? 50 : 1000),
+                     [&] { return stop || !pending.empty(); });
   }
+}
+
+int pxt_server::submit(const float* x, const float* y, const float* z, const int16_t* layer,
+                       uint32_t n_hits, Clock::time_point arrival, uint64_t* ticket) {
+  auto r = std::make_shared<Request>();
+  r->x.assign(x, x + n_hits);
+  r->y.assign(y, y + n_hits);
+  r->z.assign(z, z + n_hits);
+  r->layer.assign(layer, layer + n_hits);
+  r->t_arrival = arrival;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (stop) return PXT_ERR_BUSY;
+    if (pending.size() >= scfg.queue_depth) {
+      stats.rejected++;
+      return PXT_ERR_BUSY;
+    }
+    r->ticket = next_ticket++;
+    tickets[r->ticket] = r;
+    pending.push_back(r);
+    stats.submitted++;
+    *ticket = r->ticket;
+  }
+  cv_work.notify_one();
+  return PXT_OK;
+}
+
+int pxt_server::poll(uint64_t ticket, pxt_event_tracks* out, int timeout_ms, bool release_only) {
+  ReqPtr r;
+  {
+    std::unique_lock<std::mutex> lk(mu);
+    auto it = tickets.find(ticket);
+    if (it == tickets.end()) return PXT_ERR_INVALID_ARG;
+    r = it->second;
+    auto ready = [&] { return r->done; };
+    if (timeout_ms < 0) {
+      cv_done.wait(lk, ready);
+    } else if (!cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+      return PXT_ERR_NOT_READY;
+    }
+    const uint32_t n = r->n_tracks;
+    out->n_tracks = n;
+    out->status = r->status;
+    out->queue_us = us_between(r->t_arrival, r->t_start);
+    out->batch_events = r->batch_events;
+    if (r->status == PXT_OK && !release_only) {
+      // a buffer too small keeps the ticket: the caller polls again with room
+      // for out->n_tracks tracks
+      if (n > out->capacity) return PXT_ERR_CAPACITY;
+      if (n && (!out->hit_idx || !out->n_hits || !out->params || !out->cov || !out->chi2 ||
+                !out->flags))
+        return PXT_ERR_INVALID_ARG;
+    }
+    tickets.erase(it);
+  }
+  // the event's tracks straight from the lane's pinned result set
+  const uint32_t n = r->n_tracks;
+  if (r->status == PXT_OK && n && !release_only) {
+    const ResultSet& R = *r->rs;
+    const size_t b = r->base;
+    std::memcpy(out->hit_idx, R.hit_idx + 8 * b, 32ull * n);
+    std::memcpy(out->n_hits, R.nh + b, n);
+    std::memcpy(out->flags, R.flags + b, n);
+    std::memcpy(out->params, R.params + 5 * b, 20ull * n);
+    std::memcpy(out->cov, R.cov + 15 * b, 60ull * n);
+    std::memcpy(out->chi2, R.chi2 + 2 * b, 8ull * n);
+  }
+  const auto now = Clock::now();
+  out->latency_us = us_between(r->t_arrival, now);
+  if (r->rs && r->rs->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) cv_work.notify_one();
+  {
+    std::lock_guard<std::mutex> g(mu);
+    stats.sum_deliver_us += us_between(r->t_ready, now);
+    stats.sum_latency_us += out->latency_us;
+    stats.delivered++;
+  }
+  return PXT_OK;
 }
 
 extern "C" {
@@ -343,7 +484,7 @@ int pxt_server_create(const pxt_config* cfg, const pxt_server_config* scfg, int 
   s->cfg = *cfg;
   s->scfg = *scfg;
   s->device = hip_device;
-  s->lanes.resize(scfg->n_lanes);
+  s->lanes = std::vector<Lane>(scfg->n_lanes);
   for (auto& L : s->lanes) {
     if (!L.init(*cfg, hip_device)) {
       for (auto& M : s->lanes) M.release();
@@ -360,64 +501,68 @@ int pxt_submit(pxt_server* s, const float* x, const float* y, const float* z,
                const int16_t* layer, uint32_t n_hits, uint64_t* ticket) {
   if (!s || !ticket || (n_hits && (!x || !y || !z || !layer))) return PXT_ERR_INVALID_ARG;
   if (n_hits > s->cfg.max_hits) return PXT_ERR_INVALID_ARG;
-  auto r = std::make_shared<Request>();
-  r->x.assign(x, x + n_hits);
-  r->y.assign(y, y + n_hits);
-  r->z.assign(z, z + n_hits);
-  r->layer.assign(layer, layer + n_hits);
-  {
-    std::lock_guard<std::mutex> g(s->mu);
-    if (s->stop) return PXT_ERR_BUSY;
-    if (s->pending.size() >= s->scfg.queue_depth) {
-      s->stats.rejected++;
-      return PXT_ERR_BUSY;
-    }
-    r->ticket = s->next_ticket++;
-    r->t_submit = Clock::now();
-    s->tickets[r->ticket] = r;
-    s->pending.push_back(r);
-    s->stats.submitted++;
-    *ticket = r->ticket;
-  }
-  s->cv_work.notify_one();
-  return PXT_OK;
+  return s->submit(x, y, z, layer, n_hits, Clock::now(), ticket);
 }
 
 int pxt_poll(pxt_server* s, uint64_t ticket, pxt_event_tracks* out, int timeout_ms) {
   if (!s || !out) return PXT_ERR_INVALID_ARG;
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->tickets.find(ticket);
-  if (it == s->tickets.end()) return PXT_ERR_INVALID_ARG;
-  ReqPtr r = it->second;
-  auto ready = [&] { return r->done; };
-  if (timeout_ms < 0) {
-    s->cv_done.wait(lk, ready);
-  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
-    return PXT_ERR_NOT_READY;
+  const bool release_only = out->capacity == 0 && out->hit_idx == nullptr;
+  return s->poll(ticket, out, timeout_ms, release_only);
+}
+
+int pxt_server_replay(pxt_server* s, uint32_t n, const uint32_t* event_of_arrival,
+                      const double* arrival_us, uint32_t n_pool, const uint32_t* pool_offsets,
+                      const float* x, const float* y, const float* z, const int16_t* layer,
+                      pxt_event_tracks* results) {
+  if (!s || (n && (!event_of_arrival || !arrival_us || !pool_offsets || !results)) ||
+      (n_pool && (!x || !y || !z || !layer)))
+    return PXT_ERR_INVALID_ARG;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (event_of_arrival[i] >= n_pool) return PXT_ERR_INVALID_ARG;
+    if (i && arrival_us[i] < arrival_us[i - 1]) return PXT_ERR_INVALID_ARG;
+    const uint32_t e = event_of_arrival[i];
+    if (pool_offsets[e + 1] < pool_offsets[e] ||
+        pool_offsets[e + 1] - pool_offsets[e] > s->cfg.max_hits)
+      return PXT_ERR_INVALID_ARG;
   }
-  const uint32_t n = r->n_tracks;
-  out->n_tracks = n;
-  out->status = r->status;
-  out->latency_us = r->latency_us;
-  out->queue_us = r->queue_us;
-  out->batch_events = r->batch_events;
-  if (r->status == PXT_OK) {
-    // a buffer too small keeps the ticket: the caller polls again with room
-    // for out->n_tracks tracks
-    if (n > out->capacity) return PXT_ERR_CAPACITY;
-    if (n) {
-      if (!out->hit_idx || !out->n_hits || !out->params || !out->cov || !out->chi2 || !out->flags)
-        return PXT_ERR_INVALID_ARG;
-      std::memcpy(out->hit_idx, r->hit_idx.data(), 32ull * n);
-      std::memcpy(out->n_hits, r->n_hits.data(), n);
-      std::memcpy(out->flags, r->flags.data(), n);
-      std::memcpy(out->params, r->params.data(), 20ull * n);
-      std::memcpy(out->cov, r->cov.data(), 60ull * n);
-      std::memcpy(out->chi2, r->chi2.data(), 8ull * n);
+  std::vector<uint64_t> tix(n, 0);
+  std::atomic<uint32_t> submitted{0};
+  std::atomic<int> failure{PXT_OK};
+  // collector: releases the events in arrival order as they finish
+  std::thread collector([&] {
+    for (uint32_t i = 0; i < n; ++i) {
+      while (submitted.load(std::memory_order_acquire) <= i) {
+        if (failure.load() != PXT_OK) return;
+        std::this_thread::yield();
+      }
+      pxt_event_tracks& o = results[i];
+      o.capacity = 0;
+      o.hit_idx = nullptr;
+      const int st = s->poll(tix[i], &o, -1, true);
+      if (st != PXT_OK) failure.store(st);
     }
+  });
+  const auto t0 = Clock::now();
+  for (uint32_t i = 0; i < n; ++i) {
+    const auto due = t0 + std::chrono::duration_cast<Clock::duration>(
+                              std::chrono::duration<double, std::micro>(arrival_us[i]));
+    while (Clock::now() < due) {
+      const auto left = due - Clock::now();
+      if (left > std::chrono::microseconds(200))
+        std::this_thread::sleep_for(left - std::chrono::microseconds(100));
+    }
+    const uint32_t e = event_of_arrival[i], a = pool_offsets[e], h = pool_offsets[e + 1] - a;
+    int st;
+    while ((st = s->submit(x + a, y + a, z + a, layer + a, h, due, &tix[i])) == PXT_ERR_BUSY)
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    if (st != PXT_OK) {
+      failure.store(st);
+      break;
+    }
+    submitted.store(i + 1, std::memory_order_release);
   }
-  s->tickets.erase(it);
-  return PXT_OK;
+  collector.join();
+  return failure.load();
 }
 
 int pxt_server_get_stats(pxt_server* s, pxt_server_stats* out) {

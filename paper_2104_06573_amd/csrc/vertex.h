@@ -109,20 +109,44 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
   if (lane_id() == 0 && part) atomicAdd(&s_toff, part);
   __syncthreads();
   const uint32_t toff = s_toff, ntr = in.per_event_tracks[e];
-  // selection: keys appended in any order (the sort fixes the order)
-  for (uint32_t t = tid; t < ntr; t += nthr) {
-    const uint32_t g = toff + t;
-    o.track_vertex[g] = -1;
-    const float q = in.params[(size_t)g * 5 + 2];
-    const float z = in.params[(size_t)g * 5 + 4];
-    const float v = in.cov[(size_t)g * 15 + 14];
-    const bool ok = (int)in.n_hits[g] >= c.vtx_min_hits && fabsf(q) <= c.vtx_qopt_max &&
-                    isfinite(z) && isfinite(v) && v > 0.0f;
-    if (ok && t < (1u << 20)) {
-      const uint32_t slot = atomicAdd(&s_m, 1u);
-      if (slot < (uint32_t)kVtxMax) {
-        s_key[slot] = ((uint64_t)z_key(z) << 32) | ((uint64_t)t << 12) | slot;
-        s_var[slot] = v;
+  // selection: keys appended in any order (the sort fixes the order).  A
+  // thread takes kSel tracks per round and issues their loads back to back
+  // (hit counts first, then the values of the tracks with enough hits), so
+  // the latency of one event's thousands of tracks overlaps.
+  constexpr int kSel = 8;
+  for (uint32_t t0 = tid; t0 < ntr; t0 += nthr * kSel) {
+    uint32_t nh[kSel];
+#pragma unroll
+    for (int u = 0; u < kSel; ++u) {
+      const uint32_t t = t0 + (uint32_t)u * nthr;
+      nh[u] = t < ntr ? (uint32_t)in.n_hits[toff + t] : 0u;
+    }
+    float q[kSel], z[kSel], v[kSel];
+#pragma unroll
+    for (int u = 0; u < kSel; ++u) {
+      const uint32_t t = t0 + (uint32_t)u * nthr;
+      q[u] = z[u] = v[u] = 0.0f;
+      if (t < ntr) {
+        const size_t g = toff + t;
+        o.track_vertex[g] = -1;
+        if ((int)nh[u] >= c.vtx_min_hits) {
+          q[u] = in.params[g * 5 + 2];
+          z[u] = in.params[g * 5 + 4];
+          v[u] = in.cov[g * 15 + 14];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSel; ++u) {
+      const uint32_t t = t0 + (uint32_t)u * nthr;
+      const bool ok = t < ntr && (int)nh[u] >= c.vtx_min_hits && fabsf(q[u]) <= c.vtx_qopt_max &&
+                      isfinite(z[u]) && isfinite(v[u]) && v[u] > 0.0f;
+      if (ok && t < (1u << 20)) {
+        const uint32_t slot = atomicAdd(&s_m, 1u);
+        if (slot < (uint32_t)kVtxMax) {
+          s_key[slot] = ((uint64_t)z_key(z[u]) << 32) | ((uint64_t)t << 12) | slot;
+          s_var[slot] = v[u];
+        }
       }
     }
   }

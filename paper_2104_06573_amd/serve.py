@@ -35,7 +35,10 @@ class EventTracks(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "rejected",
-                                               "batches", "events_in_batches", "solo_retries")]
+                                               "batches", "events_in_batches", "solo_retries",
+                                               "delivered")] + \
+        [(n, ctypes.c_double) for n in ("sum_queue_us", "sum_launch_us", "sum_device_us",
+                                        "sum_copyback_us", "sum_deliver_us", "sum_latency_us")]
 
 
 _bound = False
@@ -53,6 +56,9 @@ def _bind():
     L.pxt_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(EventTracks),
                            ctypes.c_int]
     L.pxt_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ServerStats)]
+    L.pxt_server_replay.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_uint32] + [ctypes.c_void_p] * 5 + \
+        [ctypes.POINTER(EventTracks)]
     L.pxt_server_destroy.argtypes = [ctypes.c_void_p]
     L.pxt_server_destroy.restype = None
     _bound = True
@@ -139,6 +145,65 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def phase_means(before, after):
+    """Mean time per event in each serving phase between two stats()
+    snapshots (us): queued, staging and launch, device, copy-back,
+    delivery, whole latency."""
+    dc = max(after["completed"] - before["completed"], 1)
+    dd = max(after["delivered"] - before["delivered"], 1)
+    out = {k: (after["sum_%s_us" % k] - before["sum_%s_us" % k]) / dc
+           for k in ("queue", "launch", "device", "copyback")}
+    out.update({k: (after["sum_%s_us" % k] - before["sum_%s_us" % k]) / dd
+                for k in ("deliver", "latency")})
+    return {k: round(v, 2) for k, v in out.items()}
+
+
+def replay(srv, pool, event_of_arrival, arrival_us):
+    """Native open-loop replay (pxt_server_replay): arrival i submits
+    pool[event_of_arrival[i]] at arrival_us[i] from a native thread while a
+    second native thread releases the results in arrival order.  Returns
+    latency percentiles (us, from the scheduled arrival), sustained
+    events/s, mean batch size and the mean time per serving phase."""
+    L = _bind()
+    offs = np.zeros(len(pool) + 1, np.uint32)
+    offs[1:] = np.cumsum([e.n_hits for e in pool])
+    cat = lambda f, dt: np.ascontiguousarray(np.concatenate([getattr(e, f) for e in pool]), dt)
+    x, y, z, lay = cat("x", np.float32), cat("y", np.float32), cat("z", np.float32), \
+        cat("layer", np.int16)
+    ev = np.ascontiguousarray(event_of_arrival, np.uint32)
+    at = np.ascontiguousarray(arrival_us, np.float64)
+    n = ev.shape[0]
+    res = (EventTracks * n)()
+    before = srv.stats()
+    t0 = time.perf_counter()
+    st = L.pxt_server_replay(srv.h, n, ev.ctypes.data, at.ctypes.data, len(pool),
+                             offs.ctypes.data, x.ctypes.data, y.ctypes.data, z.ctypes.data,
+                             lay.ctypes.data, res)
+    wall = time.perf_counter() - t0
+    if st != OK:
+        raise PxtError(st, "pxt_server_replay")
+    after = srv.stats()
+    lat = np.array([r.latency_us for r in res])
+    bsz = np.array([r.batch_events for r in res])
+    return dict(events=n, wall_s=wall, events_per_s=n / wall,
+                p50_us=float(np.percentile(lat, 50)), p99_us=float(np.percentile(lat, 99)),
+                mean_us=float(lat.mean()), mean_batch=float(bsz.mean()),
+                max_batch=int(bsz.max()), failed=int(sum(r.status != OK for r in res)),
+                n_tracks=[int(r.n_tracks) for r in res], phases_us=phase_means(before, after))
+
+
+def poisson_schedule(n, rate_hz, n_pool, seed=0):
+    """Arrival times (us) of n Poisson arrivals at rate_hz, cycling over a
+    pool of n_pool events; rate_hz = inf: all at once (a saturating
+    burst)."""
+    rng = np.random.default_rng(seed)
+    if np.isinf(rate_hz):
+        at = np.zeros(n)
+    else:
+        at = np.cumsum(rng.exponential(1e6 / rate_hz, n))
+    return np.arange(n) % n_pool, at
 
 
 def poisson_run(srv, events, rate_hz, seed=0, keep_results=False):

@@ -214,11 +214,12 @@ def test_fit_recovers_exact_helix(det, case):
     pt = np.exp(rng.uniform(np.log(0.5), np.log(50.0)))
     q = 1.0 if case % 2 else -1.0
     k = -q * det["c_kappa"] / pt
-    cot = rng.uniform(-1.5, 1.5)
     z0 = rng.uniform(-5, 5)
+    # cot(theta) within what keeps the outermost hit (arc length below 16.5
+    # cm at these curvatures) inside the barrel's |z| < 26.5 cm
+    cot = rng.uniform(-1.0, 1.0) * (26.0 - abs(z0)) / 16.5
     X, Y, Z = hx.barrel_hits(phi0, d0, k, cot, z0)
-    if not (np.abs(Z) < 26.5).all():
-        pytest.skip("outside the barrel")
+    assert (np.abs(Z) < 26.5).all()
     p, cov, chi2, kref = oracle.fit(X, Y, Z, [0, 0, 0, 0], det)
     truth = np.array([phi0, d0, q / pt, cot, z0])
     err = np.abs(p - truth)

@@ -113,3 +113,46 @@ def test_poll_timeout_and_unknown_ticket(torch):
         r = srv.poll(t, 10)
     assert r["status"] == 0 and r["n_tracks"] == 20
     srv.close()
+
+
+def test_native_replay_and_phases(torch):
+    # the native replay: a burst of 96 events of the serving mix is admitted
+    # into multi-event batches, every event comes back with the track count
+    # it has alone, and the phase means add up to about the latency
+    from paper_2104_06573_amd.serve import Server, poisson_schedule, replay
+    pool = eventgen.make_batch("serve", 12, seed=9)
+    solo = _solo(pool)
+    srv = Server(DET, n_lanes=2, max_batch_events=16, **CAPS)
+    order, at = poisson_schedule(96, float("inf"), len(pool))
+    rep = replay(srv, pool, order, at)
+    assert rep["failed"] == 0 and rep["max_batch"] > 1
+    assert rep["n_tracks"] == [solo[i % len(pool)][0].shape[0] for i in range(96)]
+    ph = rep["phases_us"]
+    parts = ph["queue"] + ph["launch"] + ph["device"] + ph["copyback"] + ph["deliver"]
+    assert abs(parts - ph["latency"]) <= 0.05 * ph["latency"] + 50, ph
+    # at a modest rate as well
+    order, at = poisson_schedule(48, 5000.0, len(pool), seed=1)
+    rep2 = replay(srv, pool, order, at)
+    assert rep2["failed"] == 0
+    assert rep2["n_tracks"] == [solo[i % len(pool)][0].shape[0] for i in range(48)]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == st["delivered"] == 144
+
+
+def test_release_without_copy(torch):
+    import ctypes
+
+    from paper_2104_06573_amd import OK, lib
+    from paper_2104_06573_amd.serve import EventTracks, Server
+    ev = eventgen.generate("pu50", 3, n_tracks=300)
+    solo = _solo([ev])
+    srv = Server(DET, n_lanes=1, **CAPS)
+    t = srv.submit(ev.x, ev.y, ev.z, ev.layer)
+    et = EventTracks(0, None, None, None, None, None, None, 0, 0, 0.0, 0.0, 0)
+    assert lib().pxt_poll(srv.h, t, ctypes.byref(et), -1) == OK
+    assert et.status == OK and et.n_tracks == solo[0][0].shape[0]
+    # the ticket is gone
+    with pytest.raises(Exception):
+        srv.poll(t, 0)
+    srv.close()
