@@ -854,8 +854,8 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
   } else {
     const uint32_t T = c->cfg.max_tuples;
     const uint32_t n = std::min(nt, T);
-    std::vector<uint32_t> th(8ull * T);
-    if (n) HIP_OR_FAIL(c, hipMemcpy(th.data(), w.thit, 4ull * 8 * T, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> th(8ull * n);
+    if (n) HIP_OR_FAIL(c, hipMemcpy(th.data(), w.thit, 4ull * 8 * n, hipMemcpyDeviceToHost));
     rows.reserve(9ull * n);
     for (uint32_t t = 0; t < n; ++t) {
       rows.push_back(bevt[th[(size_t)t * 8]]);
