@@ -60,7 +60,8 @@ def parse(argv=None):
     ap.add_argument("--batch", type=int, default=0, help="events per batch (default per workload)")
     ap.add_argument("--pool", type=int, default=2, help="distinct batches cycled through")
     ap.add_argument("--plain-events", type=int, default=512,
-                    help="one-event calls timed on the plain path (cycled over the pool)")
+                    help="one-event calls timed on the plain path (cycled over the pool); 0 "
+                         "skips the plain legs and the ablations")
     ap.add_argument("--pu200-steps", type=int, default=100)
     ap.add_argument("--no-pu200", action="store_true")
     ap.add_argument("--no-rechits", action="store_true")
@@ -680,10 +681,12 @@ def main(argv=None):
 
     # plain path: one event per call, synchronised per event
     plain_events = [e for b in pool for e in b]
-    plain_ev_s = plain_leg(torch, pxt, det, kind, plain_events, args, args.plain_events)
+    plain_ev_s = None
+    if args.plain_events > 0:
+        plain_ev_s = plain_leg(torch, pxt, det, kind, plain_events, args, args.plain_events)
 
     ablations = None
-    if not args.no_ablations:
+    if not args.no_ablations and args.plain_events > 0:
         ablations = {
             "workload": "plain path (one event per call) over the %d %s events of the pool" %
                         (len(plain_events), args.workload),
@@ -707,13 +710,14 @@ def main(argv=None):
         v2, ms2, st2 = b2.timed(args.pu200_steps, 5, args.trials)
         b2.close()
         del b2
-        pv2 = plain_leg(torch, pxt, det, "pu200", [e for b in pu200 for e in b], args, 128)
+        pv2 = (plain_leg(torch, pxt, det, "pu200", [e for b in pu200 for e in b], args, 128)
+               if args.plain_events > 0 else None)
         p200 = {"workload": WORKLOADS["pu200"][2] + ", 32 events per batch",
                 "hits_per_event": round(float(np.mean([e.n_hits for b in pu200 for e in b])), 1),
                 "batched_events_per_s": round(v2, 2), "ms_per_step": round(ms2, 4),
                 "steps": args.pu200_steps, "trials": st2,
-                "plain_events_per_s": round(pv2, 2),
-                "batched_over_plain": round(v2 / pv2, 2)}
+                "plain_events_per_s": round(pv2, 2) if pv2 else None,
+                "batched_over_plain": round(v2 / pv2, 2) if pv2 else None}
 
     rech = rechits_leg(torch, pxt, clusters, args) if clusters is not None else None
     if served is not None:
@@ -721,7 +725,8 @@ def main(argv=None):
         served["batched_same_mix"] = mb
         served["saturated_over_batched"] = round(
             served["saturated"]["events_per_s"] / mb["events_per_s"], 3)
-    cgbs = copy_peak(torch)
+    # (a counter-calibration run measures its one 512 MiB copy alone)
+    cgbs = None if args.calib_copy else copy_peak(torch)
     counts = c0
     out = {
         "metric": "events/s at PU50/PU200 on 1 MI355X (batched/served vs plain)",
@@ -751,8 +756,8 @@ def main(argv=None):
             "vertices": bool(args.vertices),
         },
         "trials": trials,
-        "plain_events_per_s": round(plain_ev_s, 2),
-        "batched_over_plain": round(ev_per_s / plain_ev_s, 2),
+        "plain_events_per_s": round(plain_ev_s, 2) if plain_ev_s else None,
+        "batched_over_plain": round(ev_per_s / plain_ev_s, 2) if plain_ev_s else None,
         "hits_per_s": round(ev_per_s * hits_per_event, 1),
         "per_batch_counts": dict({k: counts[k] for k in ("n_doublets", "n_links",
                                                          "n_raw_tuples", "n_tracks", "n_fp64")},
