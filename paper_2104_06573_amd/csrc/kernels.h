@@ -870,22 +870,32 @@ __device__ __forceinline__ void outer_range(Ws& w, uint32_t d, uint32_t j, bool 
 // atomicOr.
 
 // Queue entry: qa = (doublet, candidate index, candidate doublet, inner x),
-// qb = (inner y, inner z, outer x, outer y), qz = outer z.
+// qb = (inner y, inner z, outer x, outer y), qz = (outer z, the doublet's
+// number of candidates).
 __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const uint4* qa,
-                                                   const uint4* qb, const float* qz,
+                                                   const uint4* qb, const float2* qz,
                                                    uint32_t n, uint32_t nd, uint32_t& links) {
   const uint32_t lane = lane_id();
   if (lane < n) {
     const uint4 ea = qa[lane], eb = qb[lane];
     const uint32_t d = ea.x, k = ea.y, d2 = ea.z;
     const HitD ha = hit_xyz(__uint_as_float(ea.w), __uint_as_float(eb.x), __uint_as_float(eb.y));
-    const HitD hb = hit_xyz(__uint_as_float(eb.z), __uint_as_float(eb.w), qz[lane]);
+    const HitD hb = hit_xyz(__uint_as_float(eb.z), __uint_as_float(eb.w), qz[lane].x);
     const float4 oc = w.oh[d2];
     const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * nd + d], 1ull << (k & 63u));
       atomicAdd(&w.nout[d], 1u);
       w.has_inner[d2] = 1;
+      // only linked doublets are read by the n-tuplet search (candidate
+      // range) and the cleaning (election slots): every accepted link
+      // writes them for both its doublets, the same values each time
+      w.cb[d] = d2 - k;
+      w.cdeg[d] = __float_as_uint(qz[lane].y);
+      w.bkey[d] = ~0ull;
+      w.best[d] = kPad;
+      w.bkey[d2] = ~0ull;
+      w.best[d2] = kPad;
       ++links;
     }
   }
@@ -894,7 +904,7 @@ __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const
 __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   __shared__ uint4 s_qa[256 / kWave][kQueue];
   __shared__ uint4 s_qb[256 / kWave][kQueue];
-  __shared__ float s_qz[256 / kWave][kQueue];
+  __shared__ float2 s_qz[256 / kWave][kQueue];
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
@@ -903,7 +913,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   const uint64_t below = (1ull << lane) - 1ull;
   uint4* qa = s_qa[wib];
   uint4* qb = s_qb[wib];
-  float* qz = s_qz[wib];
+  float2* qz = s_qz[wib];
   uint32_t links = 0, qn = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
   // every lane of the wavefront runs the same number of rounds, so the
@@ -917,7 +927,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     if (d < nd) {
       const uint2 io = w.cio[d];
       const uint32_t a = io.x;
-      outer_range(w, d, io.y, true, k0, deg);
+      outer_range(w, d, io.y, false, k0, deg);
       ob = w.oh[d];
       const float4 av = w.bh[a];
       ax = av.x;
@@ -985,7 +995,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
           qa[slot] = make_uint4(od, idx - lo, idx, __float_as_uint(oax));
           qb[slot] = make_uint4(__float_as_uint(oay), __float_as_uint(oaz), __float_as_uint(obx),
                                 __float_as_uint(oby));
-          qz[slot] = obz;
+          qz[slot] = make_float2(obz, __uint_as_float(odeg));
         }
         qn += (uint32_t)__popcll(bal);
         if (qn >= (uint32_t)kWave) {
@@ -994,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
           __threadfence_block();
           const uint32_t rest = qn - kWave;
           uint4 ma = make_uint4(0, 0, 0, 0), mb = ma;
-          float mz = 0.f;
+          float2 mz = make_float2(0.f, 0.f);
           if (lane < rest) {
             ma = qa[kWave + lane];
             mb = qb[kWave + lane];

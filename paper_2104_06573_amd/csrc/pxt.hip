@@ -827,10 +827,14 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
         rows.push_back(bidx[cout[k]]);
       }
     } else {
-      std::vector<uint32_t> cell_off(nb + 1), mw(nd);
+      // mask words of the doublets with links (the thread link kernel
+      // stores candidate ranges only for those); their count follows from
+      // the outer hit's range of doublets
+      std::vector<uint32_t> cell_off(nb + 1), mw(nd), nout(nd);
       HIP_OR_FAIL(c, hipMemcpy(cell_off.data(), w.cell_off, 4ull * (nb + 1), hipMemcpyDeviceToHost));
-      if (nd) HIP_OR_FAIL(c, hipMemcpy(mw.data(), w.cdeg, 4ull * nd, hipMemcpyDeviceToHost));
-      for (auto& v : mw) v = (v + 63u) >> 6;
+      if (nd) HIP_OR_FAIL(c, hipMemcpy(nout.data(), w.nout, 4ull * nd, hipMemcpyDeviceToHost));
+      for (uint32_t k = 0; k < nd; ++k)
+        mw[k] = nout[k] ? (cell_off[cout[k] + 1] - cell_off[cout[k]] + 63u) >> 6 : 0u;
       const uint32_t nwords = ctr[C_NWORDS];
       std::vector<uint64_t> masks(nwords);
       if (nwords)
