@@ -870,18 +870,20 @@ __device__ __forceinline__ void outer_range(Ws& w, uint32_t d, uint32_t j, bool 
 // atomicOr.
 
 // Queue entry: qa = (doublet, candidate index, candidate doublet, inner x),
-// qb = (inner y, inner z, outer x, outer y), qz = (outer z, the doublet's
-// number of candidates).
+// qb = (inner y, inner z, the doublet's number of candidates, unused).  The
+// doublet's outer hit is loaded by the flush (for the few survivors only),
+// beside the candidate's.
 __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const uint4* qa,
-                                                   const uint4* qb, const float2* qz,
-                                                   uint32_t n, uint32_t nd, uint32_t& links) {
+                                                   const uint4* qb, uint32_t n, uint32_t nd,
+                                                   uint32_t& links) {
   const uint32_t lane = lane_id();
   if (lane < n) {
     const uint4 ea = qa[lane], eb = qb[lane];
     const uint32_t d = ea.x, k = ea.y, d2 = ea.z;
-    const HitD ha = hit_xyz(__uint_as_float(ea.w), __uint_as_float(eb.x), __uint_as_float(eb.y));
-    const HitD hb = hit_xyz(__uint_as_float(eb.z), __uint_as_float(eb.w), qz[lane].x);
+    const float4 ob = w.oh[d];
     const float4 oc = w.oh[d2];
+    const HitD ha = hit_xyz(__uint_as_float(ea.w), __uint_as_float(eb.x), __uint_as_float(eb.y));
+    const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
     const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * nd + d], 1ull << (k & 63u));
@@ -891,7 +893,7 @@ __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const
       // range) and the cleaning (election slots): every accepted link
       // writes them for both its doublets, the same values each time
       w.cb[d] = d2 - k;
-      w.cdeg[d] = __float_as_uint(qz[lane].y);
+      w.cdeg[d] = eb.z;
       w.bkey[d] = ~0ull;
       w.best[d] = kPad;
       w.bkey[d2] = ~0ull;
@@ -904,7 +906,6 @@ __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const
 __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   __shared__ uint4 s_qa[256 / kWave][kQueue];
   __shared__ uint4 s_qb[256 / kWave][kQueue];
-  __shared__ float2 s_qz[256 / kWave][kQueue];
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
@@ -913,7 +914,6 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   const uint64_t below = (1ull << lane) - 1ull;
   uint4* qa = s_qa[wib];
   uint4* qb = s_qb[wib];
-  float2* qz = s_qz[wib];
   uint32_t links = 0, qn = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
   // every lane of the wavefront runs the same number of rounds, so the
@@ -922,13 +922,13 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   for (uint32_t dw = d0; dw < nd; dw += stride) {
     const uint32_t d = dw + lane;
     uint32_t k0 = 0, deg = 0;
-    float4 ob = make_float4(0.f, 0.f, 0.f, 0.f);
+    float tho = 0.f;  // the doublet's r-z angle
     float ax = 0.f, ay = 0.f, az = 0.f;
     if (d < nd) {
       const uint2 io = w.cio[d];
       const uint32_t a = io.x;
       outer_range(w, d, io.y, false, k0, deg);
-      ob = w.oh[d];
+      tho = w.th[d];
       const float4 av = w.bh[a];
       ax = av.x;
       ay = av.y;
@@ -956,7 +956,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       for (uint32_t step = kWave / 2; step >= 1; step >>= 1)
         if (__shfl(cex, (int)(own + step)) <= q) own += step;
       const uint32_t ok0 = __shfl(k0, (int)own), odeg = __shfl(deg, (int)own);
-      const float ta = __shfl(ob.w, (int)own);
+      const float ta = __shfl(tho, (int)own);
       const uint32_t lo = ok0, hi = ok0 + odeg;
       const uint32_t a0 = (ok0 & ~3u) + 16u * (q - __shfl(cex, (int)own));
       uint32_t pm = 0;  // bit u: candidate a0 + u passes
@@ -981,8 +981,6 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       const uint32_t od = dw + own;
       const float oax = __shfl(ax, (int)own), oay = __shfl(ay, (int)own);
       const float oaz = __shfl(az, (int)own);
-      const float obx = __shfl(ob.x, (int)own), oby = __shfl(ob.y, (int)own);
-      const float obz = __shfl(ob.z, (int)own);
       // append the survivors, one per lane and round
       while (__any(pm != 0u)) {
         const bool has = pm != 0u;
@@ -993,28 +991,23 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
           const uint32_t slot = qn + (uint32_t)__popcll(bal & below);
           const uint32_t idx = a0 + u;
           qa[slot] = make_uint4(od, idx - lo, idx, __float_as_uint(oax));
-          qb[slot] = make_uint4(__float_as_uint(oay), __float_as_uint(oaz), __float_as_uint(obx),
-                                __float_as_uint(oby));
-          qz[slot] = make_float2(obz, __uint_as_float(odeg));
+          qb[slot] = make_uint4(__float_as_uint(oay), __float_as_uint(oaz), odeg, 0u);
         }
         qn += (uint32_t)__popcll(bal);
         if (qn >= (uint32_t)kWave) {
           __threadfence_block();
-          links_thread_flush(w, c, qa, qb, qz, kWave, nd, links);
+          links_thread_flush(w, c, qa, qb, kWave, nd, links);
           __threadfence_block();
           const uint32_t rest = qn - kWave;
           uint4 ma = make_uint4(0, 0, 0, 0), mb = ma;
-          float2 mz = make_float2(0.f, 0.f);
           if (lane < rest) {
             ma = qa[kWave + lane];
             mb = qb[kWave + lane];
-            mz = qz[kWave + lane];
           }
           __threadfence_block();
           if (lane < rest) {
             qa[lane] = ma;
             qb[lane] = mb;
-            qz[lane] = mz;
           }
           __threadfence_block();
           qn = rest;
@@ -1023,7 +1016,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     }
   }
   __threadfence_block();
-  links_thread_flush(w, c, qa, qb, qz, qn, nd, links);
+  links_thread_flush(w, c, qa, qb, qn, nd, links);
   links = wave_sum(links);
   if (lane_id() == 0 && links) atomicAdd(&ctr[C_NLINKS], links);
 }
