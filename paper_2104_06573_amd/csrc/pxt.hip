@@ -629,16 +629,22 @@ int pxt_rechits(const double* modules, uint32_t n_modules, uint32_t max_per_modu
   const uint32_t n = (uint32_t)nmod;
   hipLaunchKernelGGL(k_rh_zero, dim3(grid_for((uint64_t)n + 1, 256, 2048)), dim3(256), 0, s, ro,
                      n);
+  const uint32_t E = in->n_events;
   if (in->n_clusters > 0) {
     const uint32_t g = grid_for(in->n_clusters, 256, 4096);
     hipLaunchKernelGGL(k_rh_count, dim3(g), dim3(256), 0, s, ri, ro, n_modules);
-    hipLaunchKernelGGL(k_rh_offsets, dim3(1), dim3(kRhScanThreads), 0, s, ro, in->n_events,
-                       n_modules, max_per_module);
+  }
+  if (E > 0)
+    hipLaunchKernelGGL(k_rh_event_offsets, dim3(E), dim3(kRhEvThreads), 0, s, ro, E, n_modules,
+                       max_per_module);
+  hipLaunchKernelGGL(k_rh_events, dim3(1), dim3(kRhScanThreads), 0, s, ro, E, n_modules);
+  if (E > 0)
+    hipLaunchKernelGGL(k_rh_absolute, dim3(grid_for((uint64_t)E * n_modules, 256, 2048)),
+                       dim3(256), 0, s, ro, E, n_modules);
+  if (in->n_clusters > 0) {
+    const uint32_t g = grid_for(in->n_clusters, 256, 4096);
     hipLaunchKernelGGL(k_rh_hits, dim3(g), dim3(256), 0, s, ri, ro, modules, n_modules,
                        max_per_module);
-  } else {
-    hipLaunchKernelGGL(k_rh_offsets, dim3(1), dim3(kRhScanThreads), 0, s, ro, in->n_events,
-                       n_modules, max_per_module);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess)

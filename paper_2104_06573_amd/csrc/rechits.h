@@ -4,10 +4,12 @@
 // modules' first-hit offsets).  The reading is stated with pxt_rechits in
 // pxt.h.  Three steps over a ragged batch of events:
 //   count    one thread per cluster adds one to its (event, module) counter;
-//   offsets  one workgroup limits every counter to max_per_module and scans
-//            them into the first-hit offset of each (event, module): the
-//            hits of all events come out contiguous, in event and module
-//            order;
+//   offsets  one workgroup per event limits its modules' counters to
+//            max_per_module and scans them into offsets from the event's
+//            first hit; one workgroup scans the event totals into the
+//            events' first hits; a last pass makes the module offsets
+//            absolute: the hits of all events come out contiguous, in event
+//            and module order;
 //   hits     one thread per cluster finds its rank among its module's
 //            clusters (clusters arrive grouped by module, so the rank is its
 //            distance from the module's first cluster, found by binary
@@ -73,34 +75,75 @@ __global__ __launch_bounds__(256) void k_rh_count(RhIn in, RhOut o, uint32_t n_m
       atomicCAS((unsigned int*)o.status, 0u, (unsigned int)PXT_ERR_INVALID_ARG);
       continue;
     }
-    atomicAdd(&o.module_start[(size_t)e * n_modules + m + 1], 1u);
+    atomicAdd(&o.module_start[(size_t)e * n_modules + m], 1u);
   }
 }
 
-// One workgroup: limit the counters and scan them in place.
-__global__ __launch_bounds__(kRhScanThreads) void k_rh_offsets(RhOut o, uint32_t n_events,
-                                                               uint32_t n_modules,
-                                                               uint32_t max_per_module) {
-  __shared__ uint32_t s_scan[kRhScanThreads / kWave + 1];
-  const uint32_t n = n_events * n_modules;
-  const uint32_t per = (n + kRhScanThreads - 1) / kRhScanThreads;
-  const uint32_t a = min(n, threadIdx.x * per), b = min(n, a + per);
-  uint32_t sum = 0;
-  for (uint32_t j = a; j < b; ++j) sum += min(o.module_start[j + 1], max_per_module);
-  uint32_t tot = 0;
-  uint32_t run = block_excl_scan(sum, s_scan, tot);
-  for (uint32_t j = a; j < b; ++j) {
-    run += min(o.module_start[j + 1], max_per_module);
-    o.module_start[j + 1] = run;
+// One workgroup per event: its modules' counters, limited to
+// max_per_module, become offsets from the event's first hit (in place),
+// and the event's hit total goes to hit_offsets[e + 1].
+constexpr int kRhEvThreads = 256;
+constexpr int kRhEvPer = 8;  // counters per thread per round
+
+__global__ __launch_bounds__(kRhEvThreads) void k_rh_event_offsets(RhOut o, uint32_t n_events,
+                                                                   uint32_t n_modules,
+                                                                   uint32_t max_per_module) {
+  __shared__ uint32_t s_scan[kRhEvThreads / kWave + 1];
+  const uint32_t e = blockIdx.x;
+  if (e >= n_events) return;
+  uint32_t* ms = o.module_start + (size_t)e * n_modules;
+  uint32_t run = 0;
+  for (uint32_t r0 = 0; r0 < n_modules; r0 += kRhEvThreads * kRhEvPer) {
+    const uint32_t a = r0 + threadIdx.x * kRhEvPer;
+    uint32_t v[kRhEvPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kRhEvPer; ++q) {
+      v[q] = a + q < n_modules ? min(ms[a + q], max_per_module) : 0u;
+      sum += v[q];
+    }
+    uint32_t tot = 0;
+    uint32_t x = run + block_excl_scan(sum, s_scan, tot);
+#pragma unroll
+    for (int q = 0; q < kRhEvPer; ++q) {
+      if (a + q < n_modules) ms[a + q] = x;
+      x += v[q];
+    }
+    run += tot;
   }
-  if (threadIdx.x == 0) o.module_start[0] = 0;
+  if (threadIdx.x == 0) o.hit_offsets[e + 1] = run;
+}
+
+// One workgroup: the events' totals become their first-hit offsets; the
+// last offset (all hits) closes module_start; an overflow of the caller's
+// hit buffers is reported.
+__global__ __launch_bounds__(kRhScanThreads) void k_rh_events(RhOut o, uint32_t n_events,
+                                                              uint32_t n_modules) {
+  __shared__ uint32_t s_scan[kRhScanThreads / kWave + 1];
+  uint32_t run = 0;
+  for (uint32_t e0 = 0; e0 < n_events; e0 += kRhScanThreads) {
+    const uint32_t e = e0 + threadIdx.x;
+    const uint32_t v = e < n_events ? o.hit_offsets[e + 1] : 0u;
+    uint32_t tot = 0;
+    const uint32_t x = run + block_excl_scan(v, s_scan, tot);
+    if (e < n_events) o.hit_offsets[e] = x;
+    run += tot;
+  }
   __syncthreads();
-  // event starts: the offsets at each event's first module (read after
-  // every thread has written its part)
-  for (uint32_t e = threadIdx.x; e <= n_events; e += kRhScanThreads)
-    o.hit_offsets[e] = e == n_events ? tot : o.module_start[e * n_modules];
-  if (threadIdx.x == 0 && tot > o.capacity)
-    atomicCAS((unsigned int*)o.status, 0u, (unsigned int)PXT_ERR_CAPACITY);
+  if (threadIdx.x == 0) {
+    o.hit_offsets[n_events] = run;
+    o.module_start[(size_t)n_events * n_modules] = run;
+    if (run > o.capacity) atomicCAS((unsigned int*)o.status, 0u, (unsigned int)PXT_ERR_CAPACITY);
+  }
+}
+
+// Event-relative module offsets to absolute ones.
+__global__ __launch_bounds__(256) void k_rh_absolute(RhOut o, uint32_t n_events,
+                                                     uint32_t n_modules) {
+  const uint32_t n = n_events * n_modules;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    o.module_start[i] += o.hit_offsets[i / n_modules];
 }
 
 __global__ __launch_bounds__(256) void k_rh_hits(RhIn in, RhOut o, const double* __restrict__ table,
