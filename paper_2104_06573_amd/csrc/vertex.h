@@ -4,9 +4,12 @@
 // reading of the paper's Vertices module (Sec. 2, Fig. 1: vertices are
 // formed from the pixel tracks) stated with pxt_vertices in pxt.h.
 //
-// One workgroup of 1024 threads per event, everything in LDS:
+// One workgroup of 1024 threads per event, everything in LDS (112 KB of
+// gfx950's 160 KB):
 //   select   tracks passing the selection append (z0, track) keys;
-//   sort     bitonic sort of the keys by (z0, track index);
+//   sort     bitonic sort of the keys by (z0, track index), four keys per
+//            thread in registers, wavefront shuffles for the short
+//            distances;
 //   cores    each track counts its neighbours within eps by two binary
 //            searches of the sorted z0 (the difference of two single-
 //            precision values taken in double precision is monotone in
@@ -87,9 +90,88 @@ __device__ __forceinline__ uint32_t vtx_excl_sum(uint32_t v, uint32_t* lds, uint
   return r;
 }
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, kWave);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, kWave);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The keeper of element i in a bitonic compare-exchange with element i ^ j
+// of sub-sequence size k: the smaller key when i is the lower of the pair
+// in an ascending run or the upper in a descending one.
+__device__ __forceinline__ uint64_t bitonic_keep(uint64_t a, uint64_t b, uint32_t i, uint32_t j,
+                                                 uint32_t k) {
+  const bool take_min = ((i & j) == 0) == ((i & k) == 0);
+  return take_min ? (a < b ? a : b) : (a < b ? b : a);
+}
+
+// Ascending bitonic sort of s_key[0..M) (M a power of two, at most kVtxMax;
+// s_key[M..kVtxMax) hold padding) by all kVtxThreads threads.  Thread t
+// keeps elements 4t..4t+3 in registers: distances 1 and 2 are exchanged in
+// registers, 4..128 by shuffles within the wavefront, and only 256 and more
+// through LDS (10 of the 78 steps of a 4096-key sort need a barrier).
+__device__ __forceinline__ void vtx_sort(uint64_t* s_key, uint32_t M) {
+  static_assert(kVtxMax == 4 * kVtxThreads, "four keys per thread");
+  const uint32_t t = threadIdx.x;
+  uint64_t v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = s_key[4 * t + r];
+  for (uint32_t k = 2; k <= M; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 4 * kWave) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s_key[4 * t + r] = v[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t i = 4 * t + r;
+          v[r] = bitonic_keep(v[r], s_key[i ^ j], i, j, k);
+        }
+      } else if (j >= 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t i = 4 * t + r;
+          v[r] = bitonic_keep(v[r], shfl_xor_u64(v[r], (int)(j >> 2)), i, j, k);
+        }
+      } else {
+        uint64_t w[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t i = 4 * t + r;
+          w[r] = bitonic_keep(v[r], v[r ^ j], i, j, k);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = w[r];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) s_key[4 * t + r] = v[r];
+  __syncthreads();
+}
+
+// Ascending sort of the m <= kVtxThreads unique keys s_key[0..m) by rank:
+// each thread counts the keys below its own (broadcast LDS reads, two keys
+// per read; s_key[m] must hold padding) and writes its key there.
+__device__ __forceinline__ void vtx_rank_sort(uint64_t* s_key, uint32_t m) {
+  const uint32_t t = threadIdx.x;
+  const uint64_t mine = t < m ? s_key[t] : 0ull;
+  uint32_t rank = 0;
+  const ulonglong2* p2 = reinterpret_cast<const ulonglong2*>(s_key);
+  for (uint32_t j = 0; j < m; j += 2) {
+    const ulonglong2 ab = p2[j >> 1];
+    rank += (ab.x < mine ? 1u : 0u) + (ab.y < mine ? 1u : 0u);
+  }
+  __syncthreads();
+  if (t < m) s_key[rank] = mine;
+  __syncthreads();
+}
+
 __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c, uint32_t e) {
-  __shared__ uint64_t s_key[kVtxMax];   // (z0 key, track << 12 | slot)
-  __shared__ float s_var[kVtxMax];      // var(z0) by selection slot
+  __shared__ __align__(16) uint64_t s_key[kVtxMax];  // (z0 key, track << 12 | slot)
+  __shared__ double s_w[kVtxMax];       // weight 1/var(z0) by selection slot
   __shared__ int32_t s_lab[kVtxMax];    // core flag, then cluster (-1: none)
   __shared__ uint32_t s_rank[kVtxMax];  // cores before each entry; then cluster ends
   __shared__ uint32_t s_core[kVtxMax];  // position of each core; then cluster starts
@@ -113,7 +195,7 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
   // thread takes kSel tracks per round and issues their loads back to back
   // (hit counts first, then the values of the tracks with enough hits), so
   // the latency of one event's thousands of tracks overlaps.
-  constexpr int kSel = 8;
+  constexpr int kSel = 16;
   for (uint32_t t0 = tid; t0 < ntr; t0 += nthr * kSel) {
     uint32_t nh[kSel];
 #pragma unroll
@@ -145,7 +227,9 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
         const uint32_t slot = atomicAdd(&s_m, 1u);
         if (slot < (uint32_t)kVtxMax) {
           s_key[slot] = ((uint64_t)z_key(z[u]) << 32) | ((uint64_t)t << 12) | slot;
-          s_var[slot] = v[u];
+          // the weight of every selected track at once (the clusters' sums
+          // below then only add, in their fixed order)
+          s_w[slot] = 1.0 / (double)v[u];
         }
       }
     }
@@ -162,24 +246,12 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
   }
   uint32_t M = 1;
   while (M < m) M <<= 1;
-  for (uint32_t i = m + tid; i < M; i += nthr) s_key[i] = ~0ull;
+  for (uint32_t i = m + tid; i < (uint32_t)kVtxMax; i += nthr) s_key[i] = ~0ull;
   __syncthreads();
-  // bitonic sort, ascending
-  for (uint32_t k = 2; k <= M; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = tid; i < M; i += nthr) {
-        const uint32_t p = i ^ j;
-        if (p > i) {
-          const uint64_t a = s_key[i], b = s_key[p];
-          if ((a > b) == ((i & k) == 0)) {
-            s_key[i] = b;
-            s_key[p] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  if (m <= (uint32_t)kVtxThreads)
+    vtx_rank_sort(s_key, m);
+  else
+    vtx_sort(s_key, M);
   // cores: the neighbours of entry i are the range [first j with
   // zi - zj <= eps, first j > i with zj - zi > eps)
   for (uint32_t i = tid; i < m; i += nthr) {
@@ -277,29 +349,51 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
     if (i + 1 == m || s_lab[i + 1] != lab) s_rank[lab] = i;
   }
   __syncthreads();
+  // (members read kVs at a time, so that their LDS loads overlap; the sums
+  // still run in sorted order)
+  constexpr uint32_t kVs = 8;
   for (uint32_t v = tid; v < ncl; v += nthr) {
-    const uint32_t a = s_core[v], b = s_rank[v];
+    const uint32_t a = s_core[v], b = s_rank[v] + 1;
     double sw = 0.0, swz = 0.0;
-    for (uint32_t i = a; i <= b; ++i) {
-      const uint64_t k = s_key[i];
-      const double w = 1.0 / (double)s_var[k & 0xfffu];
-      sw += w;
-      swz += w * (double)z_of_key(k);
+    for (uint32_t i0 = a; i0 < b; i0 += kVs) {
+      uint64_t k[kVs];
+      double w[kVs];
+#pragma unroll
+      for (uint32_t q = 0; q < kVs; ++q) k[q] = i0 + q < b ? s_key[i0 + q] : 0ull;
+#pragma unroll
+      for (uint32_t q = 0; q < kVs; ++q) w[q] = i0 + q < b ? s_w[k[q] & 0xfffu] : 0.0;
+#pragma unroll
+      for (uint32_t q = 0; q < kVs; ++q) {
+        if (i0 + q < b) {
+          sw += w[q];
+          swz += w[q] * (double)z_of_key(k[q]);
+        }
+      }
     }
     const double zv = swz / sw;
     double chi2 = 0.0;
-    for (uint32_t i = a; i <= b; ++i) {
-      const uint64_t k = s_key[i];
-      const double w = 1.0 / (double)s_var[k & 0xfffu];
-      const double rz = (double)z_of_key(k) - zv;
-      chi2 += w * rz * rz;
-      o.track_vertex[toff + (uint32_t)((k >> 12) & 0xfffffu)] = (int32_t)v;
+    for (uint32_t i0 = a; i0 < b; i0 += kVs) {
+      uint64_t k[kVs];
+      double w[kVs];
+#pragma unroll
+      for (uint32_t q = 0; q < kVs; ++q) k[q] = i0 + q < b ? s_key[i0 + q] : 0ull;
+#pragma unroll
+      for (uint32_t q = 0; q < kVs; ++q) w[q] = i0 + q < b ? s_w[k[q] & 0xfffu] : 0.0;
+#pragma unroll
+      for (uint32_t q = 0; q < kVs; ++q) {
+        if (i0 + q < b) {
+          const double rz = (double)z_of_key(k[q]) - zv;
+          chi2 += w[q] * rz * rz;
+          o.track_vertex[toff + (uint32_t)((k[q] >> 12) & 0xfffffu)] = (int32_t)v;
+        }
+      }
     }
+    const uint32_t bl = b - 1;
     const size_t slot = (size_t)e * o.max_per_event + v;
     o.z[slot] = (float)zv;
     o.z_err[slot] = (float)sqrt(1.0 / sw);
     o.chi2[slot] = (float)chi2;
-    o.n_tracks[slot] = b - a + 1;
+    o.n_tracks[slot] = bl - a + 1;
   }
   if (tid == 0) {
     o.n_vertices[e] = ncl;
