@@ -762,6 +762,9 @@ def main(argv=None):
         "per_batch_counts": dict({k: counts[k] for k in ("n_doublets", "n_links",
                                                          "n_raw_tuples", "n_tracks", "n_fp64")},
                                  **({"n_vertices": n["Nv"]} if "Nv" in n else {})),
+        # share of the fitted tracks refitted in FP64 (reference pT above
+        # pt_fp64, an ill-conditioned FP32 system or a non-finite result)
+        "fp64_fraction": round(counts["n_fp64"] / max(1, counts["n_tracks"]), 5),
         "stage_ms": stages,
     }
     if pcie is not None:

@@ -18,15 +18,16 @@
 //              or / |cos(theta)| (disk); p from the reference curvature.
 //
 // Precision split for gfx950: the geometry that differences coordinates
-// (reference circle, local frame, residuals, arc lengths, and the final
-// parameters) runs in FP64, where it costs a few dozen operations per hit;
-// the small-matrix work (normal equations, Cholesky, inversion, covariance
-// propagation) runs in FP32 registers, Jacobi-scaled.  Tuples whose
-// reference pT exceeds pt_fp64, whose Cholesky pivot ratio falls below 2^-12,
-// or whose FP32 result is not finite are refitted with the same code in FP64.
-// The covariance Jacobian of (phi0, d0, q/pT) w.r.t. (u0, u1, dk) is exact,
-// by forward-mode dual numbers; that of (cot theta, z0) w.r.t. (w0, w1) is
-// written out.
+// (reference circle, local frame, arc lengths, and the final parameters)
+// runs in FP64, where it costs a few dozen operations per hit; the
+// residuals, hit errors and multiple-scattering widths are kept in FP32
+// registers, and the small-matrix work (normal equations, Cholesky, the
+// covariance block of the parameters at the first hits, covariance
+// propagation) runs in FP32, Jacobi-scaled.  Tuples whose reference pT
+// exceeds pt_fp64, whose Cholesky pivot ratio falls below 2^-12, or whose
+// FP32 result is not finite are refitted with the same code in FP64.
+// The covariance Jacobian of (phi0, d0, q/pT) w.r.t. (u0, u1, dk) and that
+// of (cot theta, z0) w.r.t. (w0, w1) are written out by the chain rule.
 #pragma once
 
 #include "common.h"
@@ -35,13 +36,16 @@ namespace pxt {
 
 // ------------------------------------------------------------ geometry --
 
+// T is the fit's working precision: the residuals, hit errors and
+// multiple-scattering widths enter only its systems and are stored in T.
+template <typename T>
 struct FitGeo {
   int n;
   double x0, y0, z0;
   double tx, ty, nx, ny;
   double kref, tref, sinT, cosT;
-  double m[kMaxHits], s[kMaxHits], mz[kMaxHits], th0[kMaxHits], sz[kMaxHits];
-  double ds[kMaxHits];
+  double s[kMaxHits], ds[kMaxHits];
+  T m[kMaxHits], mz[kMaxHits], sz[kMaxHits], th0[kMaxHits];
 };
 
 // Signed distance of local (a, b) from the circle of curvature k through the
@@ -57,12 +61,19 @@ __device__ __forceinline__ double circ_arc(double a, double b, double k) {
 
 // N is the number of hits, a compile-time constant so that every array index
 // is static and the arrays stay in registers.
-template <int N>
-__device__ inline void fit_geometry(const DevCfg& c, const double (&X)[kMaxHits],
-                                    const double (&Y)[kMaxHits], const double (&Z)[kMaxHits],
-                                    const int (&kind)[kMaxHits], FitGeo& g) {
+template <int N, typename T>
+__device__ inline void fit_geometry(const DevCfg& c, const float (&Xf)[kMaxHits],
+                                    const float (&Yf)[kMaxHits], const float (&Zf)[kMaxHits],
+                                    const int (&kind)[kMaxHits], FitGeo<T>& g) {
   constexpr int m = N / 2;
   g.n = N;
+  double X[N], Y[N], Z[N];  // the hit coordinates are FP32; differences in FP64 are exact
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    X[i] = (double)Xf[i];
+    Y[i] = (double)Yf[i];
+    Z[i] = (double)Zf[i];
+  }
   const double d1x = X[m] - X[0], d1y = Y[m] - Y[0];
   const double d2x = X[N - 1] - X[0], d2y = Y[N - 1] - Y[0];
   const double d3x = X[N - 1] - X[m], d3y = Y[N - 1] - Y[m];
@@ -74,8 +85,8 @@ __device__ inline void fit_geometry(const DevCfg& c, const double (&X)[kMaxHits]
   const double chx = d2x / l2, chy = d2y / l2;
   double sa = k * l2 / 2.0;
   sa = fmin(1.0, fmax(-1.0, sa));
-  const double al = asin(sa);
-  const double ca = cos(al), sn = sin(al);
+  // rotation by asin(sa): cosine sqrt(1 - sa^2) >= 0, sine sa
+  const double ca = sqrt(1.0 - sa * sa), sn = sa;
   g.tx = chx * ca + chy * sn;
   g.ty = -chx * sn + chy * ca;
   g.nx = -g.ty;
@@ -87,7 +98,7 @@ __device__ inline void fit_geometry(const DevCfg& c, const double (&X)[kMaxHits]
     const double ex = X[i] - X[0], ey = Y[i] - Y[0];
     const double a = ex * g.tx + ey * g.ty;
     const double b = ex * g.nx + ey * g.ny;
-    g.m[i] = circ_dist(a, b, k);
+    g.m[i] = (T)circ_dist(a, b, k);
     g.s[i] = circ_arc(a, b, k);
   }
   g.tref = (Z[N - 1] - Z[0]) / (g.s[N - 1] - g.s[0]);
@@ -97,10 +108,10 @@ __device__ inline void fit_geometry(const DevCfg& c, const double (&X)[kMaxHits]
   const double p = c.c_kappa / (kabs * g.sinT);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const double x = c.x_over_x0 / (kind[i] == PXT_LAYER_BARREL ? g.sinT : fabs(g.cosT));
-    g.th0[i] = 0.0136 / p * sqrt(x) * (1.0 + 0.038 * log(x));
-    g.sz[i] = kind[i] == PXT_LAYER_BARREL ? c.sigma_z : c.sigma_r * fabs(g.tref);
-    g.mz[i] = Z[i] - Z[0] - g.tref * (g.s[i] - g.s[0]);
+    const T x = (T)(c.x_over_x0 / (kind[i] == PXT_LAYER_BARREL ? g.sinT : fabs(g.cosT)));
+    g.th0[i] = (T)(0.0136 / p) * sqrt(x) * ((T)1 + (T)0.038 * log(x));
+    g.sz[i] = (T)(kind[i] == PXT_LAYER_BARREL ? c.sigma_z : c.sigma_r * fabs(g.tref));
+    g.mz[i] = (T)(Z[i] - Z[0] - g.tref * (g.s[i] - g.s[0]));
   }
 #pragma unroll
   for (int i = 0; i + 1 < N; ++i) g.ds[i] = g.s[i + 1] - g.s[i];
@@ -108,8 +119,10 @@ __device__ inline void fit_geometry(const DevCfg& c, const double (&X)[kMaxHits]
 
 // ------------------------------------------------------- linear algebra --
 
-// Solve the Jacobi-scaled SPD system As y = b in place of b by Cholesky in T.
-// Returns the pivot ratio min/max (0 if not positive definite).
+// Cholesky factorisation A = L L^T of the Jacobi-scaled SPD matrix in place,
+// in T: the lower triangle receives L, with the reciprocal 1/L_jj stored on
+// the diagonal.  Returns the pivot ratio min/max (0 if not positive
+// definite).
 template <int K, typename T>
 __device__ __forceinline__ T cholesky(T (&A)[K][K]) {
   T pmin = (T)1e30, pmax = (T)0;
@@ -121,8 +134,8 @@ __device__ __forceinline__ T cholesky(T (&A)[K][K]) {
     pmin = s < pmin ? s : pmin;
     pmax = s > pmax ? s : pmax;
     const T d = s > (T)0 ? sqrt(s) : (T)1;
-    A[j][j] = d;
     const T inv = (T)1 / d;
+    A[j][j] = inv;
 #pragma unroll
     for (int i = j + 1; i < K; ++i) {
       T t = A[i][j];
@@ -141,114 +154,163 @@ __device__ __forceinline__ void chol_solve(const T (&L)[K][K], T (&b)[K]) {
     T t = b[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) t -= L[i][k] * b[k];
-    b[i] = t / L[i][i];
+    b[i] = t * L[i][i];
   }
 #pragma unroll
   for (int i = K - 1; i >= 0; --i) {
     T t = b[i];
 #pragma unroll
     for (int k = i + 1; k < K; ++k) t -= L[k][i] * b[k];
-    b[i] = t / L[i][i];
+    b[i] = t * L[i][i];
   }
 }
 
-// ---------------------------------------------------------- dual numbers --
+// ------------------------------------------- point of closest approach --
 
-struct Dual3 {
-  double v, d[3];
-};
-__device__ __forceinline__ Dual3 dconst(double v) { return {v, {0.0, 0.0, 0.0}}; }
-__device__ __forceinline__ Dual3 dvar(double v, int i) {
-  Dual3 r = dconst(v);
-  r.d[i] = 1.0;
-  return r;
-}
-__device__ __forceinline__ Dual3 operator+(Dual3 a, Dual3 b) {
-  return {a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2]}};
-}
-__device__ __forceinline__ Dual3 operator-(Dual3 a, Dual3 b) {
-  return {a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2]}};
-}
-__device__ __forceinline__ Dual3 operator-(Dual3 a) { return {-a.v, {-a.d[0], -a.d[1], -a.d[2]}}; }
-__device__ __forceinline__ Dual3 operator*(Dual3 a, Dual3 b) {
-  return {a.v * b.v,
-          {a.d[0] * b.v + a.v * b.d[0], a.d[1] * b.v + a.v * b.d[1], a.d[2] * b.v + a.v * b.d[2]}};
-}
-__device__ __forceinline__ Dual3 operator*(double s, Dual3 a) {
-  return {s * a.v, {s * a.d[0], s * a.d[1], s * a.d[2]}};
-}
-__device__ __forceinline__ Dual3 operator/(Dual3 a, Dual3 b) {
-  const double iv = 1.0 / b.v;
-  const double q = a.v * iv;
-  return {q, {(a.d[0] - q * b.d[0]) * iv, (a.d[1] - q * b.d[1]) * iv, (a.d[2] - q * b.d[2]) * iv}};
-}
-__device__ __forceinline__ Dual3 dscale(Dual3 a, double s) { return s * a; }
-__device__ __forceinline__ Dual3 dsqrt(Dual3 a) {
-  const double r = sqrt(a.v);
-  const double f = 0.5 / r;
-  return {r, {f * a.d[0], f * a.d[1], f * a.d[2]}};
-}
-__device__ __forceinline__ Dual3 dsin(Dual3 a) {
-  const double c = cos(a.v);
-  return {sin(a.v), {c * a.d[0], c * a.d[1], c * a.d[2]}};
-}
-__device__ __forceinline__ Dual3 dcos(Dual3 a) {
-  const double s = -sin(a.v);
-  return {cos(a.v), {s * a.d[0], s * a.d[1], s * a.d[2]}};
-}
-__device__ __forceinline__ Dual3 datan2(Dual3 y, Dual3 x) {
-  const double r2 = x.v * x.v + y.v * y.v;
-  const double fy = x.v / r2, fx = -y.v / r2;
-  return {atan2(y.v, x.v),
-          {fy * y.d[0] + fx * x.d[0], fy * y.d[1] + fx * x.d[1], fy * y.d[2] + fx * x.d[2]}};
+// sin and cos of an angle that is almost always small (the fitted slope
+// against the reference tangent): Taylor series to the 8th order below 1/32
+// (truncation below 2^-60 relative), the library otherwise.
+__device__ __forceinline__ void small_sincos(double x, double& s, double& c) {
+  if (fabs(x) < 0.03125) {
+    const double x2 = x * x;
+    s = x * (1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0 * (1.0 - x2 / 72.0))));
+    c = 1.0 - x2 / 2.0 * (1.0 - x2 / 12.0 * (1.0 - x2 / 30.0 * (1.0 - x2 / 56.0)));
+  } else {
+    sincos(x, &s, &c);
+  }
 }
 
-// Transverse parameters (phi0, d0, q/pT) at the point of closest approach,
-// with derivatives w.r.t. (u0, u1, dk); spca = arc length to it.
-__device__ inline void pca_transverse(const DevCfg& c, const FitGeo& g, double u0v,
-                                      double u1v, double dkv, Dual3 out[3],
+// atan2 in the precision of the fit: the angles it gives (the direction and
+// turning angle at the point of closest approach) need 1e-7 absolute only.
+template <typename D>
+__device__ __forceinline__ double atan2_in(double y, double x) {
+  if constexpr (sizeof(D) == sizeof(float))
+    return (double)atan2f((float)y, (float)x);
+  else
+    return atan2(y, x);
+}
+
+// Transverse parameters (phi0, d0, q/pT) at the point of closest approach to
+// the beam line, from the fitted offsets u0, u1 of the first two hits and the
+// curvature correction dk, in FP64; their Jacobian J[a][p] with respect to
+// (u0, u1, dk) in D (FP32 for the single-precision fits: it only feeds the
+// covariance, which is output in FP32), written out by the chain rule;
+// spca = arc length from the first hit to that point.
+//
+// The track leaves the first hit P (on the reference circle's normal at u0)
+// in direction c, the reference tangent turned by the fitted slope.  In the
+// frame of P and c the origin sits at (aO, bO); d0 is its signed distance
+// from the circle of curvature kap, and th = kap * spca the angle the track
+// turns through between the two points.
+template <typename D>
+__device__ inline void pca_transverse(const DevCfg& c, const FitGeo<D>& g, double u0, double u1,
+                                      double dk, double (&val)[3], D (&J)[3][3],
                                       double& spca) {
-  const Dual3 u0 = dvar(u0v, 0), u1 = dvar(u1v, 1), dk = dvar(dkv, 2);
-  const Dual3 kap = dconst(g.kref) + dk;
-  const Dual3 Px = dconst(g.x0) + dscale(u0, g.nx);
-  const Dual3 Py = dconst(g.y0) + dscale(u0, g.ny);
-  const Dual3 slope = dscale(u1 - u0, 1.0 / g.ds[0]) - dscale(dk, g.ds[0] / 2.0);
-  const Dual3 phis = dconst(atan2(g.ty, g.tx)) + slope;
-  const Dual3 ctx = dcos(phis), cty = dsin(phis);
-  const Dual3 aO = -(Px * ctx) - Py * cty;
-  const Dual3 bO = Px * cty - Py * ctx;
-  const Dual3 q = aO * aO + bO * bO;
-  const Dual3 d0 = (dscale(bO, 2.0) - kap * q) /
-                   (dconst(1.0) + dsqrt(dconst(1.0) - dscale(kap * bO, 2.0) + kap * kap * q));
-  Dual3 sp;
-  if (kap.v == 0.0) sp = aO;
-  else sp = datan2(kap * aO, dconst(1.0) - kap * bO) / kap;
-  Dual3 phi0 = phis + kap * sp;
-  phi0.v = atan2(sin(phi0.v), cos(phi0.v));
-  out[0] = phi0;
-  out[1] = d0;
-  out[2] = dscale(kap, -1.0 / c.c_kappa);
-  spca = sp.v;
+  const double kap = g.kref + dk;
+  const double Px = g.x0 + u0 * g.nx, Py = g.y0 + u0 * g.ny;
+  const double slope = (u1 - u0) * (1.0 / g.ds[0]) - dk * (g.ds[0] / 2.0);
+  double ss, cs;
+  small_sincos(slope, ss, cs);
+  const double cx = g.tx * cs - g.ty * ss, cy = g.ty * cs + g.tx * ss;
+  const double aO = -(Px * cx) - Py * cy;
+  const double bO = Px * cy - Py * cx;
+  const double q = aO * aO + bO * bO;
+  const double r = sqrt(1.0 - 2.0 * (kap * bO) + kap * kap * q);
+  const double den = 1.0 + r;
+  const double d0 = (2.0 * bO - kap * q) / den;
+  const double Yv = kap * aO, Xv = 1.0 - kap * bO;
+  const double th = atan2_in<D>(Yv, Xv);
+  spca = kap == 0.0 ? aO : th / kap;
+  double phi0 = atan2_in<D>(cy, cx) + th;
+  const double pi = 3.141592653589793;
+  if (phi0 > pi) phi0 -= 2.0 * pi;
+  else if (phi0 <= -pi) phi0 += 2.0 * pi;
+  val[0] = phi0;
+  val[1] = d0;
+  val[2] = -kap / c.c_kappa;
+  // Jacobian: d slope / d(u0, u1, dk), dP / du0 = (nx, ny), dc = (-cy, cx) d slope
+  const D dsl[3] = {(D)(-1.0 / g.ds[0]), (D)(1.0 / g.ds[0]), (D)(-g.ds[0] / 2.0)};
+  const D fa = (D)aO, fb = (D)bO, fcx = (D)cx, fcy = (D)cy, fk = (D)kap, fq = (D)q;
+  const D fd0 = (D)d0, i2r = (D)(0.5 / r), iden = (D)(1.0 / den);
+  const D fX = (D)Xv, fY = (D)Yv, iR2 = (D)(1.0 / (Xv * Xv + Yv * Yv));
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const D dPx = p == 0 ? (D)g.nx : (D)0, dPy = p == 0 ? (D)g.ny : (D)0;
+    const D dkap = p == 2 ? (D)1 : (D)0;
+    const D daO = -(dPx * fcx + dPy * fcy) + fb * dsl[p];
+    const D dbO = (dPx * fcy - dPy * fcx) - fa * dsl[p];
+    const D dq = (D)2 * (fa * daO + fb * dbO);
+    const D dnum = (D)2 * dbO - dkap * fq - fk * dq;
+    const D dr = ((D)-2 * (dkap * fb + fk * dbO) + (D)2 * fk * dkap * fq + fk * fk * dq) * i2r;
+    J[1][p] = (dnum - fd0 * dr) * iden;
+    const D dY = dkap * fa + fk * daO, dX = -(dkap * fb + fk * dbO);
+    J[0][p] = dsl[p] + (fX * dY - fY * dX) * iR2;
+    J[2][p] = p == 2 ? (D)(-1.0 / c.c_kappa) : (D)0;
+  }
 }
 
 __device__ __forceinline__ int tri(int a, int b) { return a * (a + 1) / 2 + b; }
 
+// Results of one fit: the parameters and chi2 are kept (the quality flags
+// are derived from them); the 15 covariance terms go straight to `cov`
+// (lower triangle, row by row) as they are computed.
 struct FitOut {
   float params[5];
-  float cov[15];
+  float* cov;
   float chi2[2];
   bool need64;
 };
 
+// Lower triangle of the trailing M x M block of (L L^T)^-1 for a Cholesky
+// factor L: with L = [[L11, 0], [L21, L22]] that block is (L22 L22^T)^-1 =
+// L22^-T L22^-1, so only the trailing block of L is inverted.
+template <int K, int M, typename T>
+__device__ __forceinline__ void tail_inverse(const T (&L)[K][K], T (&C)[M * (M + 1) / 2]) {
+  constexpr int B = K - M;
+  T Mi[M][M];  // L22^-1, lower triangular
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    Mi[j][j] = L[B + j][B + j];
+#pragma unroll
+    for (int i = j + 1; i < M; ++i) {
+      T t = (T)0;
+#pragma unroll
+      for (int k = j; k < i; ++k) t -= L[B + i][B + k] * Mi[k][j];
+      Mi[i][j] = t * L[B + i][B + i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      T t = (T)0;
+#pragma unroll
+      for (int k = i; k < M; ++k) t += Mi[k][i] * Mi[k][j];
+      C[tri(i, j)] = t;
+    }
+}
+
+// Place of unknown i (0..N-1) in the elimination order of a fit of N hits:
+// the unknowns of the hits from the third on come first, those of the first
+// two hits last (followed only by the curvature correction, place N), so that
+// the covariance of the first two is the trailing block of the inverse.
+template <int N>
+__device__ constexpr int elim_pos(int i) {
+  return i >= 2 ? i - 2 : N - 2 + i;
+}
+
 // Fit with the linear algebra in T for a tuple of exactly N hits.
 //
+// Both systems are solved with the unknowns in elimination order (elim_pos),
+// so that the covariance of the parameters at the first two hits, which the
+// track covariance needs, is the trailing block of the inverse.
 // The normal matrices are built directly in their Jacobi-scaled form
 // As = D A D with D = diag(A)^-1/2 (the scaled diagonal is exactly 1): the
 // diagonal of A is accumulated in FP64 first, then every kink adds its
 // rank-one term, scaled, to the working-precision matrix.  The kink
 // coefficients are recomputed rather than stored, to keep registers low.
 template <int N, typename T>
-__device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
+__device__ inline void fit_linear(const DevCfg& c, const FitGeo<T>& g, FitOut& o) {
   constexpr int K = N + 1;
   // ---- transverse: unknowns u_0..u_{N-1}, dk
   const double wu = 1.0 / (c.sigma_u * c.sigma_u);
@@ -279,13 +341,15 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
 #pragma unroll
     for (int j = 0; j < K; ++j) As[i][j] = (T)0;
     As[i][i] = (T)1;
-    y[i] = i < N ? (T)(wu * g.m[i] * Dg[i]) : (T)0;
   }
+#pragma unroll
+  for (int i = 0; i < N; ++i) y[elim_pos<N>(i)] = (T)(wu * g.m[i] * Dg[i]);
+  y[N] = (T)0;
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
     const double w = g.sinT / g.th0[j];
     const double v = w * w;
-    const int idx[4] = {j - 1, j, j + 1, N};
+    const int idx[4] = {elim_pos<N>(j - 1), elim_pos<N>(j), elim_pos<N>(j + 1), N};
     const double cf[4] = {inv_ds[j - 1] * Dg[j - 1], -(inv_ds[j - 1] + inv_ds[j]) * Dg[j],
                           inv_ds[j] * Dg[j + 1], -(g.ds[j - 1] + g.ds[j]) / 2.0 * Dg[N]};
 #pragma unroll
@@ -298,19 +362,19 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
   chol_solve<K, T>(As, y);
   double x[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) x[i] = (double)y[i] * Dg[i];
-  // inverse-matrix block on (u0, u1, dk)
-  const int vi[3] = {0, 1, N};
-  double C3[3][3];
+  for (int i = 0; i < N; ++i) x[i] = (double)y[elim_pos<N>(i)] * Dg[i];
+  x[N] = (double)y[N] * Dg[N];
+  // (u0, u1, dk) covariance, lower triangle
+  T C3[6];
+  {
+    T Cs[6];
+    tail_inverse<K, 3, T>(As, Cs);
+    const int vi[3] = {0, 1, N};
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    T e[K];
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int i = 0; i < K; ++i) e[i] = (T)0;
-    e[vi[a]] = (T)1;
-    chol_solve<K, T>(As, e);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) C3[b][a] = Dg[vi[b]] * (double)e[vi[b]] * Dg[vi[a]];
+      for (int b = 0; b <= a; ++b)
+        C3[tri(a, b)] = (T)(Dg[vi[a]] * (double)Cs[tri(a, b)] * Dg[vi[b]]);
   }
   // chi2 at the solution (FP64 accumulation)
   double chic = 0.0;
@@ -323,6 +387,35 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
                         x[N] * (g.ds[j - 1] + g.ds[j]) / 2.0;
     chic += w * w * beta * beta;
   }
+  // transverse parameters at the point of closest approach (FP64 values)
+  // and their covariance block J C3 J^T (in T)
+  double tv[3];
+  T J[3][3];
+  double spca;
+  pca_transverse<T>(c, g, x[0], x[1], x[N], tv, J, spca);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T jc[3];  // row a of J C3
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      T s = (T)0;
+#pragma unroll
+      for (int p = 0; p < 3; ++p) s += J[a][p] * C3[p >= q ? tri(p, q) : tri(q, p)];
+      jc[q] = s;
+    }
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      T s = (T)0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) s += jc[q] * J[b][q];
+      o.cov[tri(a, b)] = (float)s;
+    }
+  }
+  o.params[0] = (float)tv[0];
+  o.params[1] = (float)tv[1];
+  o.params[2] = (float)tv[2];
+  o.chi2[0] = (float)chic;
+  bool bad = !((double)pr >= 1.0 / 4096.0);  // pivot ratio below 2^-12
   // ---- longitudinal: unknowns w_0..w_{N-1}
   double Dz[N];
 #pragma unroll
@@ -345,13 +438,13 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
 #pragma unroll
     for (int j = 0; j < N; ++j) Bs[i][j] = (T)0;
     Bs[i][i] = (T)1;
-    yz[i] = (T)(g.mz[i] / (g.sz[i] * g.sz[i]) * Dz[i]);
+    yz[elim_pos<N>(i)] = (T)(g.mz[i] / (g.sz[i] * g.sz[i]) * Dz[i]);
   }
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
     const double w = g.sinT * g.sinT / g.th0[j];
     const double v = w * w;
-    const int idx[3] = {j - 1, j, j + 1};
+    const int idx[3] = {elim_pos<N>(j - 1), elim_pos<N>(j), elim_pos<N>(j + 1)};
     const double cf[3] = {inv_ds[j - 1] * Dz[j - 1], -(inv_ds[j - 1] + inv_ds[j]) * Dz[j],
                           inv_ds[j] * Dz[j + 1]};
 #pragma unroll
@@ -364,17 +457,16 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
   chol_solve<N, T>(Bs, yz);
   double wv[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) wv[i] = (double)yz[i] * Dz[i];
-  double CL[2][2];
+  for (int i = 0; i < N; ++i) wv[i] = (double)yz[elim_pos<N>(i)] * Dz[i];
+  // (w0, w1) covariance, lower triangle
+  T CL[3];
+  {
+    T Cs[3];
+    tail_inverse<N, 2, T>(Bs, Cs);
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    T e[N];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int i = 0; i < N; ++i) e[i] = (T)0;
-    e[a] = (T)1;
-    chol_solve<N, T>(Bs, e);
-#pragma unroll
-    for (int b = 0; b < 2; ++b) CL[b][a] = Dz[b] * (double)e[b] * Dz[a];
+      for (int b = 0; b <= a; ++b) CL[tri(a, b)] = (T)(Dz[a] * (double)Cs[tri(a, b)] * Dz[b]);
   }
   double chiz = 0.0;
 #pragma unroll
@@ -388,55 +480,29 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
     const double gam = (wv[j + 1] - wv[j]) * inv_ds[j] - (wv[j] - wv[j - 1]) * inv_ds[j - 1];
     chiz += w * w * gam * gam;
   }
-  // ---- parameters at the point of closest approach (FP64)
-  Dual3 tp[3];
-  double spca;
-  pca_transverse(c, g, x[0], x[1], x[N], tp, spca);
   const double cot = g.tref + (wv[1] - wv[0]) / g.ds[0];
   const double z0 = g.z0 + wv[0] + cot * spca;
-  // ---- covariance: transverse block J C3 J^T, longitudinal JL CL JL^T
-  double cv[5][5];
+  // longitudinal block JL CL JL^T; the blocks do not correlate
+  const T JL[2][2] = {{(T)(-1.0 / g.ds[0]), (T)(1.0 / g.ds[0])},
+                      {(T)(1.0 - spca / g.ds[0]), (T)(spca / g.ds[0])}};
 #pragma unroll
-  for (int a = 0; a < 5; ++a)
+  for (int a = 0; a < 2; ++a) {
 #pragma unroll
-    for (int b = 0; b < 5; ++b) cv[a][b] = 0.0;
+    for (int b = 0; b < 3; ++b) o.cov[tri(3 + a, b)] = 0.0f;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      double s = 0.0;
-#pragma unroll
-      for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) s += tp[a].d[p] * C3[p][q] * tp[b].d[q];
-      cv[a][b] = s;
-    }
-  const double JL[2][2] = {{-1.0 / g.ds[0], 1.0 / g.ds[0]},
-                           {1.0 - spca / g.ds[0], spca / g.ds[0]}};
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      double s = 0.0;
+    for (int b = 0; b <= a; ++b) {
+      T s = (T)0;
 #pragma unroll
       for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) s += JL[a][p] * CL[p][q] * JL[b][q];
-      cv[3 + a][3 + b] = s;
+        for (int q = 0; q < 2; ++q) s += JL[a][p] * CL[p >= q ? tri(p, q) : tri(q, p)] * JL[b][q];
+      o.cov[tri(3 + a, 3 + b)] = (float)s;
     }
-  o.params[0] = (float)tp[0].v;
-  o.params[1] = (float)tp[1].v;
-  o.params[2] = (float)tp[2].v;
+  }
   o.params[3] = (float)cot;
   o.params[4] = (float)z0;
-#pragma unroll
-  for (int a = 0; a < 5; ++a)
-#pragma unroll
-    for (int b = 0; b <= a; ++b) o.cov[tri(a, b)] = (float)cv[a][b];
-  o.chi2[0] = (float)chic;
   o.chi2[1] = (float)chiz;
-  const double pmin = 1.0 / 4096.0;  // 2^-12
-  bool bad = !((double)pr >= pmin) || !((double)prz >= pmin);
+  bad |= !((double)prz >= 1.0 / 4096.0);
 #pragma unroll
   for (int i = 0; i < 5; ++i) bad |= !isfinite(o.params[i]);
   bad |= fabs(g.kref) < c.c_kappa / c.pt_fp64;
@@ -444,18 +510,18 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo& g, FitOut& o) {
 }
 
 template <int N, typename T>
-__device__ inline void fit_n(const DevCfg& c, const double (&X)[kMaxHits],
-                             const double (&Y)[kMaxHits], const double (&Z)[kMaxHits],
+__device__ inline void fit_n(const DevCfg& c, const float (&X)[kMaxHits],
+                             const float (&Y)[kMaxHits], const float (&Z)[kMaxHits],
                              const int (&kind)[kMaxHits], FitOut& o) {
-  FitGeo g;
-  fit_geometry<N>(c, X, Y, Z, kind, g);
+  FitGeo<T> g;
+  fit_geometry<N, T>(c, X, Y, Z, kind, g);
   fit_linear<N, T>(c, g, o);
 }
 
 // Fit a tuple of n hits (3..8) given in path order.
 template <typename T>
-__device__ inline void fit_tuple(const DevCfg& c, int n, const double (&X)[kMaxHits],
-                                 const double (&Y)[kMaxHits], const double (&Z)[kMaxHits],
+__device__ inline void fit_tuple(const DevCfg& c, int n, const float (&X)[kMaxHits],
+                                 const float (&Y)[kMaxHits], const float (&Z)[kMaxHits],
                                  const int (&kind)[kMaxHits], FitOut& o) {
   switch (n) {
     case 3: fit_n<3, T>(c, X, Y, Z, kind, o); break;

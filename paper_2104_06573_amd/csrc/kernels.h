@@ -1653,7 +1653,7 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   constexpr int NH = NFIX > 0 ? NFIX : kMaxHits;  // hit slots that can be used
   const uint32_t t = w.surv[s];
   const int n = NFIX > 0 ? NFIX : (int)w.tn[t];
-  double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
+  float X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
   int kind[kMaxHits];
   uint32_t row[kMaxHits];
   load_row(w.thit, t, row);
@@ -1673,16 +1673,17 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
     if (j < NH && j < n) {
       const uint32_t h = row[j];
       const float4 v = w.bh[h];
-      X[j] = (double)v.x;
-      Y[j] = (double)v.y;
-      Z[j] = (double)v.z;
+      X[j] = v.x;
+      Y[j] = v.y;
+      Z[j] = v.z;
       kind[j] = c.layer_kind[w.blay[h]];
     } else {
-      X[j] = Y[j] = Z[j] = 0.0;
+      X[j] = Y[j] = Z[j] = 0.0f;
       kind[j] = 0;
     }
   }
   FitOut f;
+  f.cov = o.cov + (size_t)s * 15;
   if constexpr (NFIX > 0)
     fit_n<NFIX, T>(c, X, Y, Z, kind, f);
   else
@@ -1693,8 +1694,6 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) o.params[(size_t)s * 5 + i] = f.params[i];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) o.cov[(size_t)s * 15 + i] = f.cov[i];
   o.chi2[(size_t)s * 2 + 0] = f.chi2[0];
   o.chi2[(size_t)s * 2 + 1] = f.chi2[1];
   o.flags[s] = (uint8_t)((fp64 ? PXT_FLAG_FP64 : 0u) | quality_flags(c, n, f.params, f.chi2));
@@ -1702,9 +1701,13 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
 
 // One kernel per tuple length N over that length's range of the fitting
 // order (N = 0: all lengths from 5 up, rarer, in one kernel); the N = 3
-// instance also reports an output overflow.
+// instance also reports an output overflow.  The grid has a thread for
+// every tuple the context can hold.  The triplet fit, the most frequent,
+// is held to 128 registers (four wavefronts per SIMD), which it meets
+// without spilling.
 template <int N>
-__global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 3 ? 4 : 1)))
+void k_fit32(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const OutPtrs o = w.call->out;
   const uint32_t ns = w.ctr[C_NSURV];
@@ -1719,8 +1722,11 @@ __global__ __launch_bounds__(256) void k_fit32(Ws w, DevCfg c) {
   const uint32_t off = w.ctr[C_FITO0 + K0];
   uint32_t cnt = 0;
   for (int k = K0; k <= (N > 0 ? N : kMaxHits); ++k) cnt += w.ctr[C_FITN0 + k];
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
-    fit_one<float, N>(w, c, o, w.sfit[off + i], false);
+  // one tuple per thread, no grid-stride loop: a loop would keep the values
+  // derived from the configuration live across iterations and double the
+  // register footprint (the grid covers the tuple capacity)
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) fit_one<float, N>(w, c, o, w.sfit[off + i], false);
 }
 
 __global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c) {
