@@ -114,7 +114,12 @@ typedef struct pxt_config {
                                the pairs in device memory, scan, scatter
                                (most throughput on large batches).  All
                                modes give the same results.               */
-  double pt_fp64;           /* fit tuples with pT_ref above this in FP64   */
+  double pt_fp64;           /* fit tuples with pT_ref above this in FP64
+                               (default 1e9 GeV: none; the FP32 transverse
+                               solve is refined once against its FP64
+                               residual, which holds at any pT; ill-
+                               conditioned or non-finite fits are refitted
+                               in FP64 regardless)                        */
   /* --- output selection and track quality (pxt_tracks.flags) ---------- */
   int32_t min_hits;         /* tracks with fewer hits are not output:
                                3 keeps triplets and longer, 4 gives

@@ -189,7 +189,7 @@ def stage_names():
 
 def make_config(det, max_events=1, max_hits=1 << 16, max_doublets=1 << 21,
                 max_link_words=None, max_tuples=1 << 19, phi_bins=256, block_size=256,
-                group_lanes=8, link_kernel=0, use_graph=0, doublet_mode=2, pt_fp64=20.0,
+                group_lanes=8, link_kernel=0, use_graph=0, doublet_mode=2, pt_fp64=1e9,
                 min_hits=None):
     """pxt_config from a detector dictionary (eventgen.DETECTOR layout)."""
     c = PxtConfig()

@@ -20,14 +20,17 @@
 // Precision split for gfx950: the geometry that differences coordinates
 // (reference circle, local frame, arc lengths, and the final parameters)
 // runs in FP64, where it costs a few dozen operations per hit; the
-// residuals, hit errors and multiple-scattering widths are kept in FP32
-// registers, and the small-matrix work (normal equations, Cholesky, the
-// covariance block of the parameters at the first hits, covariance
-// propagation) runs in FP32, Jacobi-scaled.  Tuples whose reference pT
-// exceeds pt_fp64, whose Cholesky pivot ratio falls below 2^-12, or whose
-// FP32 result is not finite are refitted with the same code in FP64.
-// The covariance Jacobian of (phi0, d0, q/pT) w.r.t. (u0, u1, dk) and that
-// of (cot theta, z0) w.r.t. (w0, w1) are written out by the chain rule.
+// residuals, hit errors and multiple-scattering widths are stored in the
+// working precision.  The transverse system (N + 1 unknowns) is factorised
+// and solved in FP32, Jacobi-scaled, and refined once against its residual
+// computed in FP64, which restores FP64-level parameters at any pT for
+// systems that are not ill-conditioned; the small longitudinal system is
+// solved in FP64.  Tuples whose transverse Cholesky pivot ratio falls below
+// 2^-12, whose result is not finite, or whose reference pT exceeds pt_fp64
+// (a configuration option, off by default) are refitted with the same code
+// in FP64 throughout.  The covariance Jacobian of (phi0, d0, q/pT) w.r.t.
+// (u0, u1, dk) and that of (cot theta, z0) w.r.t. (w0, w1) are written out
+// by the chain rule.
 #pragma once
 
 #include "common.h"
@@ -360,10 +363,43 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo<T>& g, FitOut& o
   }
   const T pr = cholesky<K, T>(As);
   chol_solve<K, T>(As, y);
+  double yd[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) yd[i] = (double)y[i];
+  if constexpr (sizeof(T) < sizeof(double)) {
+    // one step of iterative refinement: the residual of the scaled system
+    // in FP64 (its off-diagonal entries recomputed from the kinks, unrounded),
+    // corrected with the FP32 factor
+    double r[K];
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[elim_pos<N>(i)] = wu * (double)g.m[i] * Dg[i];
+    r[N] = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) r[i] -= yd[i];
+#pragma unroll
+    for (int j = 1; j + 1 < N; ++j) {
+      const double w = g.sinT / g.th0[j];
+      const double v = w * w;
+      const int idx[4] = {elim_pos<N>(j - 1), elim_pos<N>(j), elim_pos<N>(j + 1), N};
+      const double cf[4] = {inv_ds[j - 1] * Dg[j - 1], -(inv_ds[j - 1] + inv_ds[j]) * Dg[j],
+                            inv_ds[j] * Dg[j + 1], -(g.ds[j - 1] + g.ds[j]) / 2.0 * Dg[N]};
+      double sk = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sk += cf[q] * yd[idx[q]];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) r[idx[p]] -= v * cf[p] * (sk - cf[p] * yd[idx[p]]);
+    }
+    T rr[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) rr[i] = (T)r[i];
+    chol_solve<K, T>(As, rr);
+#pragma unroll
+    for (int i = 0; i < K; ++i) yd[i] += (double)rr[i];
+  }
   double x[K];
 #pragma unroll
-  for (int i = 0; i < N; ++i) x[i] = (double)y[elim_pos<N>(i)] * Dg[i];
-  x[N] = (double)y[N] * Dg[N];
+  for (int i = 0; i < N; ++i) x[i] = yd[elim_pos<N>(i)] * Dg[i];
+  x[N] = yd[N] * Dg[N];
   // (u0, u1, dk) covariance, lower triangle
   T C3[6];
   {
@@ -431,14 +467,14 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo<T>& g, FitOut& o
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) Dz[i] = 1.0 / sqrt(Dz[i]);
-  T Bs[N][N];
-  T yz[N];
+  double Bs[N][N];  // the longitudinal system is small: FP64
+  double yz[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) Bs[i][j] = (T)0;
-    Bs[i][i] = (T)1;
-    yz[elim_pos<N>(i)] = (T)(g.mz[i] / (g.sz[i] * g.sz[i]) * Dz[i]);
+    for (int j = 0; j < N; ++j) Bs[i][j] = 0.0;
+    Bs[i][i] = 1.0;
+    yz[elim_pos<N>(i)] = (double)g.mz[i] / ((double)g.sz[i] * (double)g.sz[i]) * Dz[i];
   }
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
@@ -451,22 +487,22 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo<T>& g, FitOut& o
     for (int p = 0; p < 3; ++p)
 #pragma unroll
       for (int q = 0; q < 3; ++q)
-        if (p != q) Bs[idx[p]][idx[q]] += (T)(v * cf[p] * cf[q]);
+        if (p != q) Bs[idx[p]][idx[q]] += v * cf[p] * cf[q];
   }
-  const T prz = cholesky<N, T>(Bs);
-  chol_solve<N, T>(Bs, yz);
+  cholesky<N, double>(Bs);
+  chol_solve<N, double>(Bs, yz);
   double wv[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) wv[i] = (double)yz[elim_pos<N>(i)] * Dz[i];
+  for (int i = 0; i < N; ++i) wv[i] = yz[elim_pos<N>(i)] * Dz[i];
   // (w0, w1) covariance, lower triangle
   T CL[3];
   {
-    T Cs[3];
-    tail_inverse<N, 2, T>(Bs, Cs);
+    double Cs[3];
+    tail_inverse<N, 2, double>(Bs, Cs);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b <= a; ++b) CL[tri(a, b)] = (T)(Dz[a] * (double)Cs[tri(a, b)] * Dz[b]);
+      for (int b = 0; b <= a; ++b) CL[tri(a, b)] = (T)(Dz[a] * Cs[tri(a, b)] * Dz[b]);
   }
   double chiz = 0.0;
 #pragma unroll
@@ -502,7 +538,6 @@ __device__ inline void fit_linear(const DevCfg& c, const FitGeo<T>& g, FitOut& o
   o.params[3] = (float)cot;
   o.params[4] = (float)z0;
   o.chi2[1] = (float)chiz;
-  bad |= !((double)prz >= 1.0 / 4096.0);
 #pragma unroll
   for (int i = 0; i < 5; ++i) bad |= !isfinite(o.params[i]);
   bad |= fabs(g.kref) < c.c_kappa / c.pt_fp64;

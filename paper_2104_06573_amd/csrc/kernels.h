@@ -1706,7 +1706,7 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
 // is held to 128 registers (four wavefronts per SIMD), which it meets
 // without spilling.
 template <int N>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 3 ? 4 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 3 ? 4 : (N == 4 ? 3 : 1))))
 void k_fit32(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const OutPtrs o = w.call->out;

@@ -590,7 +590,7 @@ int pxt_config_defaults(pxt_config* cfg) {
   cfg->link_kernel = 0;
   cfg->use_graph = 0;
   cfg->doublet_mode = 2;
-  cfg->pt_fp64 = 20.0;
+  cfg->pt_fp64 = 1e9;  // no refit by pT: the refined FP32 solve holds at any pT
   cfg->min_hits = 3;
   cfg->q_chi2 = 5.0f;
   cfg->q_pt_min = 0.5f;

@@ -132,6 +132,30 @@ def test_pu200_event(torch):
           "fp64 fraction %.4f" % (res.counts["n_fp64"] / max(res.counts["n_tracks"], 1)))
 
 
+def test_fp64_refit_by_pt(torch):
+    """The FP64 refit path at parity: with pt_fp64 = 2 GeV every track above
+    2 GeV of reference pT is refitted in FP64 (FP64 flag set) and all fits
+    still match the oracle; the refitted tracks' parameters also match those
+    of the default configuration (FP32 with one refinement step)."""
+    import paper_2104_06573_amd as pxt
+    events = [eventgen.generate("pu50", 300 + s) for s in range(2)]
+    oref = oracle_events(events, DET)
+    rec = make_rec(pt_fp64=2.0)
+    res, out, dumps = run_and_dump(rec, events)
+    check_events(events, res, out, dumps, oref=oref)
+    n64 = int(np.count_nonzero(out["flags"] & pxt.FLAG_FP64))
+    assert n64 == res.counts["n_fp64"]
+    hi = int(np.count_nonzero(np.abs(out["params"][:, 2]) < 1 / 2.5))
+    assert n64 >= hi > 0, (n64, hi)
+    base = make_rec().run_numpy(events).numpy()
+    for e in range(len(events)):
+        ga = match_tracks(out, oref[e], e)
+        gb = match_tracks(base, oref[e], e)
+        np.testing.assert_array_equal(ga[0], gb[0])
+        assert (fit_errors(ga[1], gb[1].astype(np.float64)) <= FIT_RTOL).all()
+    print("fp64 refits with pt_fp64 = 2 GeV: %d of %d tracks" % (n64, res.counts["n_tracks"]))
+
+
 def _tracks_by_event(out, n):
     rows = []
     for e in range(n):
