@@ -99,8 +99,7 @@ struct Ws {
   uint64_t* masks;        // [W] link masks, C_WSTRIDE words per doublet
   uint8_t* has_inner;     // [D]
   uint32_t* nout;         // [D] outer links per doublet
-  float4* oh;             // [D] outer hit (x, y, z) and r-z angle of each doublet
-  float* th;              // [D] the r-z angle alone (the link prefilter's stream)
+  float* th;              // [D + 16] r-z angle of each doublet (the link prefilter's stream)
   uint32_t* cb;           // [D] first doublet leaving the outer hit
   uint32_t* cdeg;         // [D] number of doublets leaving the outer hit
   uint32_t* roots;        // [D] root doublets, ascending

@@ -513,9 +513,7 @@ __device__ __forceinline__ void store_doublet(Ws& w, const DevCfg& c, uint32_t q
   w.cio[q] = make_uint2(g, j);
   w.has_inner[q] = 0;
   if (c.link_kernel == 1) w.nout[q] = 0;
-  const float th = rz_angle(hi, ho);
-  w.oh[q] = make_float4((float)ho.x, (float)ho.y, (float)ho.z, th);
-  w.th[q] = th;
+  w.th[q] = rz_angle(hi, ho);
 }
 
 // Link-mask words of the largest out-degree: C_WSTRIDE is raised only when
@@ -817,11 +815,12 @@ __global__ __launch_bounds__(256) void k_dscatter(Ws w, DevCfg c) {
 // ---------------------------------------------------------------- links --
 // The candidate outer neighbours of doublet (a,b) are the doublets leaving
 // hit b: the contiguous range cell_off[b] .. cell_off[b+1] (doublets are
-// stored grouped by inner hit).  Each doublet carries its outer hit and its
-// r-z angle in one float4, and the angle again in a compact array: the FP32
-// angle prefilter, which passes only a few percent, streams the compact
-// angles, and the survivors go on to the exact FP64 cuts with the float4.  The accepted candidates form a bit mask over the
-// range, one 64-bit word per 64.
+// stored grouped by inner hit).  The FP32 angle prefilter, which passes
+// only a few percent, streams the doublets' r-z angles (th, 4 bytes each),
+// and the survivors go on to the exact FP64 cuts with their three hits
+// loaded from the binned-hit array (hit-indexed, a few MB per batch), not
+// from per-doublet copies.  The accepted candidates form a bit mask over
+// the range, one 64-bit word per 64.
 
 // The link masks take C_WSTRIDE words per doublet (one word per 64
 // candidates of the largest out-degree of the batch), stored word-major:
@@ -869,22 +868,22 @@ __device__ __forceinline__ void outer_range(Ws& w, uint32_t d, uint32_t j, bool 
 // any of its candidates is queued; accepted links set their bit with
 // atomicOr.
 
-// Queue entry: qa = (doublet, candidate index, candidate doublet, inner x),
-// qb = (inner y, inner z, the doublet's number of candidates, unused).  The
-// doublet's outer hit is loaded by the flush (for the few survivors only),
-// beside the candidate's.
+// Queue entry: qa = (doublet, candidate doublet, inner hit, outer hit),
+// qb = (candidate index, the doublet's number of candidates).  The flush
+// loads the candidate's outer hit index and the three hits.
 __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const uint4* qa,
-                                                   const uint4* qb, uint32_t n, uint32_t nd,
+                                                   const uint2* qb, uint32_t n, uint32_t nd,
                                                    uint32_t& links) {
   const uint32_t lane = lane_id();
   if (lane < n) {
-    const uint4 ea = qa[lane], eb = qb[lane];
-    const uint32_t d = ea.x, k = ea.y, d2 = ea.z;
-    const float4 ob = w.oh[d];
-    const float4 oc = w.oh[d2];
-    const HitD ha = hit_xyz(__uint_as_float(ea.w), __uint_as_float(eb.x), __uint_as_float(eb.y));
-    const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
-    const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
+    const uint4 ea = qa[lane];
+    const uint2 eb = qb[lane];
+    const uint32_t d = ea.x, d2 = ea.y, k = eb.x;
+    const float4 va = w.bh[ea.z], vb = w.bh[ea.w];
+    const float4 vc = w.bh[w.cio[d2].y];
+    const HitD ha = hit_xyz(va.x, va.y, va.z);
+    const HitD hb = hit_xyz(vb.x, vb.y, vb.z);
+    const HitD hc = hit_xyz(vc.x, vc.y, vc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * nd + d], 1ull << (k & 63u));
       atomicAdd(&w.nout[d], 1u);
@@ -893,7 +892,7 @@ __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const
       // range) and the cleaning (election slots): every accepted link
       // writes them for both its doublets, the same values each time
       w.cb[d] = d2 - k;
-      w.cdeg[d] = eb.z;
+      w.cdeg[d] = eb.y;
       w.bkey[d] = ~0ull;
       w.best[d] = kPad;
       w.bkey[d2] = ~0ull;
@@ -905,7 +904,7 @@ __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const
 
 __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   __shared__ uint4 s_qa[256 / kWave][kQueue];
-  __shared__ uint4 s_qb[256 / kWave][kQueue];
+  __shared__ uint2 s_qb[256 / kWave][kQueue];
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t nd = ctr[C_ND];
@@ -913,7 +912,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   const uint32_t lane = lane_id(), wib = threadIdx.x / kWave;
   const uint64_t below = (1ull << lane) - 1ull;
   uint4* qa = s_qa[wib];
-  uint4* qb = s_qb[wib];
+  uint2* qb = s_qb[wib];
   uint32_t links = 0, qn = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
   // every lane of the wavefront runs the same number of rounds, so the
@@ -921,18 +920,14 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   const uint32_t d0 = xcd_block() * blockDim.x + (threadIdx.x & ~(uint32_t)(kWave - 1));
   for (uint32_t dw = d0; dw < nd; dw += stride) {
     const uint32_t d = dw + lane;
-    uint32_t k0 = 0, deg = 0;
+    uint32_t k0 = 0, deg = 0, ha = 0, hb = 0;
     float tho = 0.f;  // the doublet's r-z angle
-    float ax = 0.f, ay = 0.f, az = 0.f;
     if (d < nd) {
       const uint2 io = w.cio[d];
-      const uint32_t a = io.x;
-      outer_range(w, d, io.y, false, k0, deg);
+      ha = io.x;
+      hb = io.y;
+      outer_range(w, d, hb, false, k0, deg);
       tho = w.th[d];
-      const float4 av = w.bh[a];
-      ax = av.x;
-      ay = av.y;
-      az = av.z;
       const uint32_t nwd = (deg + 63u) >> 6;
       for (uint32_t j = 0; j < nwd; ++j) w.masks[(size_t)j * nd + d] = 0;
       w.nout[d] = 0;
@@ -944,7 +939,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     // are numbered by a prefix sum over its doublets, and in each round
     // every lane takes the next chunk, finds its doublet by a binary search
     // of the prefix (shuffles) and reads the 16 angles as four aligned
-    // float4s (one cache line per lane and load)
+    // float4s (one 64-byte line per lane)
     const uint32_t nch = deg ? (k0 + deg - (k0 & ~3u) + 15u) >> 4 : 0u;
     const uint32_t cinc = wave_incl_scan(nch), cex = cinc - nch;
     const uint32_t C = __shfl(cinc, kWave - 1);
@@ -979,8 +974,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       }
       // the owner's hits travel with its survivors
       const uint32_t od = dw + own;
-      const float oax = __shfl(ax, (int)own), oay = __shfl(ay, (int)own);
-      const float oaz = __shfl(az, (int)own);
+      const uint32_t oha = __shfl(ha, (int)own), ohb = __shfl(hb, (int)own);
       // append the survivors, one per lane and round
       while (__any(pm != 0u)) {
         const bool has = pm != 0u;
@@ -990,8 +984,8 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
         if (has) {
           const uint32_t slot = qn + (uint32_t)__popcll(bal & below);
           const uint32_t idx = a0 + u;
-          qa[slot] = make_uint4(od, idx - lo, idx, __float_as_uint(oax));
-          qb[slot] = make_uint4(__float_as_uint(oay), __float_as_uint(oaz), odeg, 0u);
+          qa[slot] = make_uint4(od, idx, oha, ohb);
+          qb[slot] = make_uint2(idx - lo, odeg);
         }
         qn += (uint32_t)__popcll(bal);
         if (qn >= (uint32_t)kWave) {
@@ -999,7 +993,8 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
           links_thread_flush(w, c, qa, qb, kWave, nd, links);
           __threadfence_block();
           const uint32_t rest = qn - kWave;
-          uint4 ma = make_uint4(0, 0, 0, 0), mb = ma;
+          uint4 ma = make_uint4(0, 0, 0, 0);
+          uint2 mb = make_uint2(0, 0);
           if (lane < rest) {
             ma = qa[kWave + lane];
             mb = qb[kWave + lane];
@@ -1037,12 +1032,11 @@ __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint3*
   if (lane < n) {
     const uint3 it = q[lane];
     const uint32_t d = it.x, k = it.y;
-    const HitD ha = load_hit(w, w.cio[d].x);
-    const float4 ob = w.oh[d];
-    const HitD hb = hit_xyz(ob.x, ob.y, ob.z);
+    const uint2 io = w.cio[d];
+    const HitD ha = load_hit(w, io.x);
+    const HitD hb = load_hit(w, io.y);
     const uint32_t d2 = it.z;
-    const float4 oc = w.oh[d2];
-    const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
+    const HitD hc = load_hit(w, w.cio[d2].y);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * w.ctr[C_ND] + d],
                1ull << (k & 63u));
@@ -1144,8 +1138,7 @@ __device__ __forceinline__ void wave_links_flush(Ws& w, const DevCfg& c, const W
     const HitD ha = load_hit(w, ao);
     const HitD hb = hit_xyz(bx, by, bz);
     const uint32_t d2 = kbo + kk;
-    const float4 oc = w.oh[d2];
-    const HitD hc = hit_xyz(oc.x, oc.y, oc.z);
+    const HitD hc = load_hit(w, w.cio[d2].y);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       const unsigned long long bit = 1ull << (kk & 63u);
       // LDS at workgroup scope, device memory at agent scope: two distinct
@@ -1186,7 +1179,8 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
       const uint2 io = w.cio[d];
       a = io.x;
       outer_range(w, d, io.y, true, kb, deg);
-      ob = w.oh[d];
+      ob = w.bh[io.y];  // the outer hit, with the doublet's r-z angle in .w
+      ob.w = w.th[d];
       mo = d;
     }
     const uint32_t nwd = (deg + 63u) >> 6;

@@ -127,7 +127,6 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.nout = cv.take<uint32_t>(D);
-  w.oh = cv.take<float4>(D);
   w.th = cv.take<float>(D + 16);  // aligned float4 reads may pass the end by 3
   w.cb = cv.take<uint32_t>(D);
   w.cdeg = cv.take<uint32_t>(D);
@@ -327,6 +326,34 @@ void launch_doublets(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, c
     }                                                                            \
   } while (0)
 
+// Blocks of a kernel that all compute units hold at once (from its register
+// and LDS footprint), as a multiple of 8 (an equal share per XCD): the grid
+// of a grid-stride kernel whose blocks get equal shares of the work, so that
+// no second, partial round of blocks trails the first.  Cached per kernel and
+// block size in a fixed table (no allocation on this path).
+uint32_t resident_grid(const void* kernel, int bs, int n_cu) {
+  struct Entry {
+    const void* kernel;
+    int bs, nb;
+  };
+  static std::mutex mu;
+  static Entry cache[32];
+  static int used = 0;
+  int nb = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < used; ++i)
+      if (cache[i].kernel == kernel && cache[i].bs == bs) nb = cache[i].nb;
+    if (nb == 0) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, bs, 0) != hipSuccess ||
+          nb < 1)
+        nb = 1;
+      if (used < 32) cache[used++] = Entry{kernel, bs, nb};
+    }
+  }
+  return std::max<uint32_t>(8, (uint32_t)nb * (uint32_t)n_cu / 8u * 8u);
+}
+
 void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, const DevCfg& d) {
   if (d.link_kernel == 0) {
     hipLaunchKernelGGL(k_links_thread, grid, block, 0, s, w, d);
@@ -403,9 +430,15 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
     const uint32_t gd = grid_for(cfg.max_doublets, bs, persist);
     if (cfg.link_kernel == 1) hipLaunchKernelGGL(k_zero_words, dim3(gd), dim3(256), 0, s, w, d);
     if (timed) sm.mark(8);
-    launch_links(G, dim3(cfg.link_kernel == 1 ? grid_chunked((uint64_t)H * 16, bs, G, persist)
-                                               : std::max<uint32_t>(8, gd / 8 * 8)),
-                 dim3(bs), s, w, d);
+    uint32_t gl;
+    if (cfg.link_kernel == 1)
+      gl = grid_chunked((uint64_t)H * 16, bs, G, persist);
+    else
+      gl = std::min(std::max<uint32_t>(8, gd / 8 * 8),
+                    resident_grid(cfg.link_kernel == 0 ? (const void*)k_links_thread
+                                                       : (const void*)k_links_wave,
+                                  bs, n_cu));
+    launch_links(G, dim3(gl), dim3(bs), s, w, d);
     if (timed) sm.mark(9);
     hipLaunchKernelGGL(k_roots, dim3(scan_grid(cfg.max_doublets)), dim3(kScanThreads1), 0, s, w,
                        6u);
