@@ -404,7 +404,21 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
     hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
                        dim3(256), 0, s, w, d);
     const int G = cfg.group_lanes;
-    const uint32_t gh = grid_chunked(H, bs, G, std::min<uint32_t>(persist, kCompactBlocksMax));
+    uint32_t gh = grid_chunked(H, bs, G, std::min<uint32_t>(persist, kCompactBlocksMax));
+    if (cfg.doublet_mode == 2) {
+      // the staging pair shares one grid (the scatter reads the stage's
+      // per-wavefront regions): the smaller of their resident grids
+      const void* ks = nullptr;
+      const void* kc = nullptr;
+      switch (G) {
+        case 4: ks = (const void*)k_dstage<4>; kc = (const void*)k_dscatter<4>; break;
+        case 8: ks = (const void*)k_dstage<8>; kc = (const void*)k_dscatter<8>; break;
+        case 16: ks = (const void*)k_dstage<16>; kc = (const void*)k_dscatter<16>; break;
+        case 64: ks = (const void*)k_dstage<64>; kc = (const void*)k_dscatter<64>; break;
+        default: ks = (const void*)k_dstage<32>; kc = (const void*)k_dscatter<32>; break;
+      }
+      gh = std::min({gh, resident_grid(ks, bs, n_cu), resident_grid(kc, bs, n_cu)});
+    }
     if (cfg.doublet_mode == 1) {
       // one pass (its time shows under doublet_fill)
       const uint32_t gpb = (uint32_t)(bs / G);
@@ -443,18 +457,25 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
     hipLaunchKernelGGL(k_roots, dim3(scan_grid(cfg.max_doublets)), dim3(kScanThreads1), 0, s, w,
                        6u);
     if (timed) sm.mark(10);
-    hipLaunchKernelGGL(k_tuples<false>, dim3(gd), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_tuples<false>,
+                       dim3(std::min(gd, resident_grid((const void*)k_tuples<false>, bs, n_cu))),
+                       dim3(bs), 0, s, w, d);
     if (timed) sm.mark(11);
     launch_scan1(w, w.rcnt, w.roff, w.ctr + C_NROOT, w.ctr + C_NTUP, cfg.max_doublets, 3, s);
     if (timed) sm.mark(12);
-    hipLaunchKernelGGL(k_tuples<true>, dim3(gd), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_tuples<true>,
+                       dim3(std::min(gd, resident_grid((const void*)k_tuples<true>, bs, n_cu))),
+                       dim3(bs), 0, s, w, d);
     const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
     if (timed) sm.mark(13);
-    hipLaunchKernelGGL(k_score, dim3(gt), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_score, dim3(std::min(gt, resident_grid((const void*)k_score, bs, n_cu))),
+                       dim3(bs), 0, s, w, d);
     if (timed) sm.mark(14);
-    hipLaunchKernelGGL(k_best, dim3(gt), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_best, dim3(std::min(gt, resident_grid((const void*)k_best, bs, n_cu))),
+                       dim3(bs), 0, s, w, d);
     if (timed) sm.mark(15);
-    hipLaunchKernelGGL(k_alive, dim3(gt), dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_alive, dim3(std::min(gt, resident_grid((const void*)k_alive, bs, n_cu))),
+                       dim3(bs), 0, s, w, d);
     launch_scan1(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, cfg.max_tuples, 5, s);
     {
       // survivors, then the fitting order grouped by length (the same grid
