@@ -98,10 +98,8 @@ struct Ws {
   uint2* cio;             // [D] (inner, outer) binned hits: one store, one load
   uint64_t* masks;        // [W] link masks, C_WSTRIDE words per doublet
   uint8_t* has_inner;     // [D]
-  uint32_t* nout;         // [D] outer links per doublet
+  uint8_t* has_out;       // [D] the doublet has an outer link
   float* th;              // [D + 16] r-z angle of each doublet (the link prefilter's stream)
-  uint32_t* cb;           // [D] first doublet leaving the outer hit
-  uint32_t* cdeg;         // [D] number of doublets leaving the outer hit
   uint32_t* roots;        // [D] root doublets, ascending
   uint32_t* rcnt;         // [D + 1] n-tuplets per root doublet
   uint32_t* roff;         // [D + 1]
@@ -116,8 +114,8 @@ struct Ws {
   uint8_t* tn;            // [T] hits
   double* tscore;         // [T]
   // cleaning
-  uint64_t* bkey;         // [D] smallest order key of the tuples through it
-  uint32_t* best;         // [D] best tuple through each doublet
+  uint64_t* bkey;         // [D] smallest order key of the tuples through it (call-tagged)
+  uint64_t* best;         // [D] best tuple through each doublet: call epoch << 32 | tuple
   uint32_t* talive;       // [T + 1] survives the cleaning
   uint32_t* toff;         // [T + 1]
   uint32_t* surv;         // [T]

@@ -60,6 +60,19 @@ __global__ void k_clear(Ws w, DevCfg c) {
   if (tid == 0) w.epoch[0] += 1u;
 }
 
+// The cleaning's per-doublet election slots are tagged with the call (see
+// order_key) instead of being cleared for every doublet of every call; they
+// are reset in full on the first call and every 256th after it, when the
+// tag byte wraps.
+__global__ __launch_bounds__(256) void k_slots_clear(Ws w, DevCfg c) {
+  if (((w.epoch[0] - 1u) & 0xffu) != 0u) return;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < c.cap_doublets; i += stride) {
+    w.bkey[i] = ~0ull;
+    w.best[i] = 0ull;
+  }
+}
+
 // Fills n 64-bit words with v (used where device memory must be reset
 // without a memset node in a stream that may be captured).
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
@@ -310,21 +323,21 @@ __global__ __launch_bounds__(kScanThreads1) void k_roots(Ws w, uint32_t scan_id)
   const uint32_t base = tile * kTile + threadIdx.x * kTileItems;
   uint32_t flags = 0;
   if (base + kTileItems <= n) {
-    // 16 flags as one 16-byte load, 16 counts as four
+    // 16 flags of each kind as one 16-byte load
     const uint4 hv = *reinterpret_cast<const uint4*>(w.has_inner + base);
+    const uint4 ov = *reinterpret_cast<const uint4*>(w.has_out + base);
     const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
+    const uint32_t ow[4] = {ov.x, ov.y, ov.z, ov.w};
 #pragma unroll
-    for (int q = 0; q < kTileItems / 4; ++q) {
-      const uint4 nv = reinterpret_cast<const uint4*>(w.nout + base)[q];
-      const uint32_t nn[4] = {nv.x, nv.y, nv.z, nv.w};
+    for (int q = 0; q < kTileItems / 4; ++q)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        if (((hw[q] >> (8 * b)) & 0xffu) == 0u && nn[b] != 0u) flags |= 1u << (4 * q + b);
-    }
+        if (((hw[q] >> (8 * b)) & 0xffu) == 0u && ((ow[q] >> (8 * b)) & 0xffu) != 0u)
+          flags |= 1u << (4 * q + b);
   } else {
 #pragma unroll
     for (int i = 0; i < kTileItems; ++i)
-      if (base + i < n && !w.has_inner[base + i] && w.nout[base + i] != 0u) flags |= 1u << i;
+      if (base + i < n && !w.has_inner[base + i] && w.has_out[base + i]) flags |= 1u << i;
   }
   uint32_t agg;
   const uint32_t texcl = block_excl_scan((uint32_t)__popc(flags), lds, agg);
@@ -506,13 +519,12 @@ __device__ __forceinline__ uint32_t visit_doublets(const Ws& w, const DevCfg& c,
   return cnt;
 }
 
-// The per-doublet arrays written when doublet q = (g, j) is stored; the
-// outer hit's own doublet range (cb, cdeg) is filled by the link kernels.
+// The per-doublet arrays written when doublet q = (g, j) is stored.
 __device__ __forceinline__ void store_doublet(Ws& w, const DevCfg& c, uint32_t q, uint32_t g,
                                               uint32_t j, const HitD& hi, const HitD& ho) {
   w.cio[q] = make_uint2(g, j);
   w.has_inner[q] = 0;
-  if (c.link_kernel == 1) w.nout[q] = 0;
+  if (c.link_kernel == 1) w.has_out[q] = 0;
   w.th[q] = rz_angle(hi, ho);
 }
 
@@ -840,21 +852,12 @@ __device__ __forceinline__ bool links_capacity(Ws& w, const DevCfg& c) {
   return ok;
 }
 
-// Candidate range of doublet d (outer hit j): the doublets leaving j, from
-// the per-hit offsets; stored in cb/cdeg (by one lane when `store`) for the
-// n-tuplet search, with the cleaning's election slots of d cleared.
-__device__ __forceinline__ void outer_range(Ws& w, uint32_t d, uint32_t j, bool store,
-                                            uint32_t& kb, uint32_t& deg) {
+// Candidate range of a doublet with outer hit j: the doublets leaving j,
+// from the per-hit offsets (the n-tuplet search finds it the same way).
+__device__ __forceinline__ void outer_range(const Ws& w, uint32_t j, uint32_t& kb,
+                                            uint32_t& deg) {
   kb = w.cell_off[j];
   deg = w.cell_off[j + 1] - kb;
-  if (store) {
-    w.cb[d] = kb;
-    w.cdeg[d] = deg;
-    // the cleaning's per-doublet election starts from "no tuple" (cleared
-    // here, coalesced, for every doublet)
-    w.bkey[d] = ~0ull;
-    w.best[d] = kPad;
-  }
 }
 
 // One thread per doublet (a,b) for its set-up (mask words and link count
@@ -886,17 +889,8 @@ __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const
     const HitD hc = hit_xyz(vc.x, vc.y, vc.z);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * nd + d], 1ull << (k & 63u));
-      atomicAdd(&w.nout[d], 1u);
+      w.has_out[d] = 1;
       w.has_inner[d2] = 1;
-      // only linked doublets are read by the n-tuplet search (candidate
-      // range) and the cleaning (election slots): every accepted link
-      // writes them for both its doublets, the same values each time
-      w.cb[d] = d2 - k;
-      w.cdeg[d] = eb.y;
-      w.bkey[d] = ~0ull;
-      w.best[d] = kPad;
-      w.bkey[d2] = ~0ull;
-      w.best[d2] = kPad;
       ++links;
     }
   }
@@ -926,11 +920,11 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       const uint2 io = w.cio[d];
       ha = io.x;
       hb = io.y;
-      outer_range(w, d, hb, false, k0, deg);
+      outer_range(w, hb, k0, deg);
       tho = w.th[d];
       const uint32_t nwd = (deg + 63u) >> 6;
       for (uint32_t j = 0; j < nwd; ++j) w.masks[(size_t)j * nd + d] = 0;
-      w.nout[d] = 0;
+      w.has_out[d] = 0;
     }
     __threadfence_block();
     // the prefilter in chunks of 16 candidates spread evenly over the lanes:
@@ -1023,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
 // tests (divisions, square roots) would run with almost all lanes idle --
 // but pushed to a per-wavefront queue in LDS; whenever 64 are queued they
 // are tested with all lanes busy.  Accepted links set their bit in the
-// (pre-cleared) mask word with atomicOr and count into nout.
+// (pre-cleared) mask word with atomicOr and flag has_out.
 
 
 __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint3* q, uint32_t n,
@@ -1040,7 +1034,7 @@ __device__ __forceinline__ void links_flush(Ws& w, const DevCfg& c, const uint3*
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * w.ctr[C_ND] + d],
                1ull << (k & 63u));
-      atomicAdd(&w.nout[d], 1u);
+      w.has_out[d] = 1;
       w.has_inner[d2] = 1;
       ++links;
     }
@@ -1066,7 +1060,7 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
     float ta = 0.0f;
     if (d < nd) {
       ta = w.th[d];
-      outer_range(w, d, w.cio[d].y, sub == 0, kb, deg);
+      outer_range(w, w.cio[d].y, kb, deg);
     }
     const uint32_t maxw = wave_max((deg + 63u) / 64u);
     for (uint32_t wd = 0; wd < maxw; ++wd) {
@@ -1178,7 +1172,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
     if (d < nd) {
       const uint2 io = w.cio[d];
       a = io.x;
-      outer_range(w, d, io.y, true, kb, deg);
+      outer_range(w, io.y, kb, deg);
       ob = w.bh[io.y];  // the outer hit, with the doublet's r-z angle in .w
       ob.w = w.th[d];
       mo = d;
@@ -1229,7 +1223,7 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
     if (d < nd) {
       if (staged)
         for (uint32_t j = 0; j < nwd; ++j) w.masks[(size_t)j * nd + mo] = L.sm[wex + j];
-      w.nout[d] = L.cnt[lane];
+      w.has_out[d] = L.cnt[lane] != 0u;
     }
     __threadfence_block();
   }
@@ -1289,8 +1283,9 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       phit[1] = rio.y;
     }
     {
-      kbase[0] = w.cb[r];
-      nwd[0] = (w.cdeg[r] + 63u) >> 6;
+      uint32_t deg;
+      outer_range(w, rio.y, kbase[0], deg);
+      nwd[0] = (deg + 63u) >> 6;
       word[0] = 0;
       bits[0] = nwd[0] ? w.masks[r] : 0ull;
     }
@@ -1312,10 +1307,10 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
         break;
       }
       path[depth + 1] = child;
-      // the child's outer hit is loaded with its link count (no extra
-      // round trip at a leaf)
-      const uint32_t nchild = w.nout[child];
-      const uint32_t hchild = FILL ? w.cio[child].y : 0u;
+      // the child's outer hit is loaded with its link flag (no extra round
+      // trip at a leaf); its candidate range follows from that hit
+      const uint8_t nchild = w.has_out[child];
+      const uint32_t hchild = w.cio[child].y;
       if (nchild == 0) {
         if (FILL) {
           const uint32_t t = base + cnt;
@@ -1341,8 +1336,9 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       }
       ++depth;
       if (FILL) phit[depth + 1] = hchild;
-      kbase[depth] = w.cb[child];
-      nwd[depth] = (w.cdeg[child] + 63u) >> 6;
+      uint32_t deg;
+      outer_range(w, hchild, kbase[depth], deg);
+      nwd[depth] = (deg + 63u) >> 6;
       word[depth] = 0;
       bits[depth] = nwd[depth] ? w.masks[child] : 0ull;
     }
@@ -1359,16 +1355,23 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
 //
 // The per-doublet election runs in two rounds of atomics instead of a
 // per-doublet list.  The order key packs (8 - hits) above the score's bits
-// with their lowest three dropped: it never decreases along the order, so
+// with their lowest eleven dropped: it never decreases along the order, so
 // the best tuple of a doublet holds the smallest key there (k_score takes
 // the atomicMin).  The tuples holding that key -- almost always just one --
 // then settle the exact order by compare-and-swap on the doublet's best
 // tuple (k_best): a swap only ever installs a better tuple, so the loop
 // ends, and the result does not depend on the order the threads run in.
+//
+// The slots are not cleared per call.  The key's top byte is a call tag
+// that falls by one per call (255 on the first call after a full reset,
+// k_slots_clear), so a key left by an earlier call is larger than any key
+// of this call; the best slot carries the call's epoch in its upper half,
+// and a slot with another epoch counts as empty.
 
-__device__ __forceinline__ uint64_t order_key(int n, double s) {
+__device__ __forceinline__ uint64_t order_key(int n, double s, uint32_t epoch) {
   const uint64_t m = s != s ? 0x7fffffffffffffffull : (uint64_t)__double_as_longlong(s);
-  return ((uint64_t)(kMaxHits - n) << 60) | (m >> 3);
+  const uint64_t tag = 0xffu - ((epoch - 1u) & 0xffu);
+  return (tag << 56) | ((uint64_t)(kMaxHits - n) << 52) | (m >> 11);
 }
 
 // The eight slots of an n-tuplet row (rows are 32 bytes, 32-byte aligned)
@@ -1399,6 +1402,7 @@ __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
   uint32_t* ctr = w.ctr;
   if (ctr[C_STATUS]) return;
   const uint32_t ntup = ctr[C_NTUP];
+  const uint32_t epoch = w.epoch[0];
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     const int n = w.tn[t];
     uint32_t th[kMaxHits], tc[kMaxHits];
@@ -1414,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
       h1 = h2;
     }
     w.tscore[t] = s;
-    const uint64_t key = order_key(n, s);
+    const uint64_t key = order_key(n, s, epoch);
 #pragma unroll
     for (int j = 0; j < kMaxCells; ++j)
       if (j + 1 < n) atomicMin((unsigned long long*)&w.bkey[tc[j]], (unsigned long long)key);
@@ -1442,9 +1446,11 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const uint32_t ntup = w.ctr[C_NTUP];
   const uint32_t T = c.cap_tuples;
+  const uint32_t epoch = w.epoch[0];
+  const uint64_t tag = (uint64_t)epoch << 32;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     const int n = w.tn[t];
-    const uint64_t key = order_key(n, w.tscore[t]);
+    const uint64_t key = order_key(n, w.tscore[t], epoch);
     uint32_t tc[kMaxHits];
     load_row(w.tcell, t, tc);
 #pragma unroll
@@ -1452,9 +1458,11 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
       if (j + 1 >= n) continue;
       const uint32_t d = tc[j];
       if (w.bkey[d] != key) continue;
-      uint32_t cur = w.best[d];
-      while (cur == kPad || ranks_before(w, T, t, cur)) {
-        const uint32_t prev = atomicCAS(&w.best[d], cur, t);
+      // a slot holding another call's tag holds no tuple of this call
+      unsigned long long cur = w.best[d];
+      while ((cur >> 32) != epoch || ranks_before(w, T, t, (uint32_t)cur)) {
+        const unsigned long long prev =
+            atomicCAS((unsigned long long*)&w.best[d], cur, (unsigned long long)(tag | t));
         if (prev == cur) break;
         cur = prev;
       }
@@ -1465,6 +1473,7 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
 __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
   if (w.ctr[C_STATUS]) return;
   const uint32_t ntup = w.ctr[C_NTUP];
+  const uint64_t tag = (uint64_t)w.epoch[0] << 32;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
     const int n = w.tn[t];
     // shorter n-tuplets than min_hits are not output (they never outrank a
@@ -1474,7 +1483,7 @@ __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
     load_row(w.tcell, t, tc);
 #pragma unroll
     for (int j = 0; j < kMaxCells; ++j)
-      if (j + 1 < n && w.best[tc[j]] != t) alive = 0;
+      if (j + 1 < n && w.best[tc[j]] != (tag | t)) alive = 0;
     w.talive[t] = alive;
   }
 }

@@ -126,10 +126,12 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.cio = cv.take<uint2>(D);
   w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
-  w.nout = cv.take<uint32_t>(D);
+  w.has_out = cv.take<uint8_t>(D + 16);  // read 16 flags at a time
   w.th = cv.take<float>(D + 16);  // aligned float4 reads may pass the end by 3
-  w.cb = cv.take<uint32_t>(D);
-  w.cdeg = cv.take<uint32_t>(D);
+  // the election slots keep their contents from call to call (tagged with
+  // the call), so they lie outside the doublet staging span below
+  w.bkey = cv.take<uint64_t>(D);
+  w.best = cv.take<uint64_t>(D);
   w.roots = cv.take<uint32_t>(D);
   w.rcnt = cv.take<uint32_t>(D + 1);
   w.roff = cv.take<uint32_t>(D + 1);
@@ -137,8 +139,6 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.tcell = cv.take<uint32_t>(8 * T);
   w.tn = cv.take<uint8_t>(T);
   w.tscore = cv.take<double>(T);
-  w.bkey = cv.take<uint64_t>(D);
-  w.best = cv.take<uint32_t>(D);
   w.talive = cv.take<uint32_t>(T + 1);
   w.toff = cv.take<uint32_t>(T + 1);
   w.surv = cv.take<uint32_t>(T);
@@ -393,6 +393,8 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
   if (timed) sm.mark(0);
   hipLaunchKernelGGL(k_clear, dim3(grid_for(std::max<uint64_t>(nbins + 1, C_NCTR), 256, persist)),
                      dim3(256), 0, s, w, d);
+  hipLaunchKernelGGL(k_slots_clear, dim3(grid_for(cfg.max_doublets, 256, persist)), dim3(256), 0,
+                     s, w, d);
   if (H > 0) {
     const uint32_t gh1 = grid_for(H, 256, persist);
     if (timed) sm.mark(1);
@@ -888,14 +890,15 @@ int pxt_debug_dump(pxt_ctx* c, int what, uint32_t* dst, uint64_t cap, uint64_t* 
         rows.push_back(bidx[cout[k]]);
       }
     } else {
-      // mask words of the doublets with links (the thread link kernel
-      // stores candidate ranges only for those); their count follows from
-      // the outer hit's range of doublets
-      std::vector<uint32_t> cell_off(nb + 1), mw(nd), nout(nd);
+      // mask words of the doublets with links (the only ones the link
+      // kernels are bound to leave defined); their count follows from the
+      // outer hit's range of doublets
+      std::vector<uint32_t> cell_off(nb + 1), mw(nd);
+      std::vector<uint8_t> has_out(nd);
       HIP_OR_FAIL(c, hipMemcpy(cell_off.data(), w.cell_off, 4ull * (nb + 1), hipMemcpyDeviceToHost));
-      if (nd) HIP_OR_FAIL(c, hipMemcpy(nout.data(), w.nout, 4ull * nd, hipMemcpyDeviceToHost));
+      if (nd) HIP_OR_FAIL(c, hipMemcpy(has_out.data(), w.has_out, nd, hipMemcpyDeviceToHost));
       for (uint32_t k = 0; k < nd; ++k)
-        mw[k] = nout[k] ? (cell_off[cout[k] + 1] - cell_off[cout[k]] + 63u) >> 6 : 0u;
+        mw[k] = has_out[k] ? (cell_off[cout[k] + 1] - cell_off[cout[k]] + 63u) >> 6 : 0u;
       const uint32_t nwords = ctr[C_NWORDS];
       std::vector<uint64_t> masks(nwords);
       if (nwords)

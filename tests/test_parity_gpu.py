@@ -362,6 +362,33 @@ def test_graph_replays_match_direct(torch):
     assert small.run_numpy([eventgen.generate("tiny", 5)]).counts["status"] == 0
 
 
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_election_slots_across_calls(torch, use_graph):
+    """The cleaning's per-doublet slots are tagged with the call rather than
+    cleared: 300 calls alternating two different batches on one context
+    (across the tag's wrap after 256 calls and its full reset) give every
+    time the tracks of the first call of that batch, which match the
+    oracle."""
+    a = [eventgen.generate("pu50", 400 + s) for s in range(2)]
+    b = [eventgen.generate("pu50", 410 + s) for s in range(3)]
+    rec = make_rec(use_graph=use_graph)
+    up = [rec.upload(a), rec.upload(b)]
+    ref = []
+    for i, evs in enumerate((a, b)):
+        r = rec.run(*up[i])
+        check_events(evs, r, r.numpy(), None, check_cov=False)
+        ref.append((r.counts, _tracks_by_event(r.numpy(), len(evs))))
+    for call in range(2, 300):
+        i = call % 2
+        r = rec.run(*up[i])
+        counts, tracks = ref[i]
+        assert r.counts == counts, (call, r.counts, counts)
+        if call % 16 == 0 or call > 250:
+            for x, y in zip(tracks, _tracks_by_event(r.numpy(), len(up[i][4]) - 1)):
+                np.testing.assert_array_equal(x[0], y[0])
+                np.testing.assert_array_equal(x[1], y[1])
+
+
 def test_constructed_cleaning_cases(torch):
     # hand-built events whose winner is fixed by geometry (tests/constructed):
     # the score's closed form, the impact term deciding, the length rule
