@@ -124,7 +124,6 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.dcnt = cv.take<uint32_t>(H + 1);
   w.cell_off = cv.take<uint32_t>(H + 1);
   w.cio = cv.take<uint2>(D);
-  w.masks = cv.take<uint64_t>(Wd);
   w.has_inner = cv.take<uint8_t>(D);
   w.has_out = cv.take<uint8_t>(D + 16);  // read 16 flags at a time
   w.th = cv.take<float>(D + 16);  // aligned float4 reads may pass the end by 3
@@ -132,6 +131,9 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   // the call), so they lie outside the doublet staging span below
   w.bkey = cv.take<uint64_t>(D);
   w.best = cv.take<uint64_t>(D);
+  // the link masks come first in the staging span: the link kernels write
+  // them only after the doublet scatter has read the staged records
+  w.masks = cv.take<uint64_t>(Wd);
   w.roots = cv.take<uint32_t>(D);
   w.rcnt = cv.take<uint32_t>(D + 1);
   w.roff = cv.take<uint32_t>(D + 1);
@@ -146,11 +148,11 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.bcnt = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
   w.bbase = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
   w.fp64_list = cv.take<uint32_t>(T);
-  // the staging buffer of the doublets spans roots .. fp64_list
-  w.stage = w.roots;
+  // the staging buffer of the doublets spans masks .. fp64_list
+  w.stage = reinterpret_cast<uint32_t*>(w.masks);
   w.stage_words = cv.base ? (uint32_t)std::min<size_t>(
                                  (size_t)(reinterpret_cast<char*>(w.fp64_list + T) -
-                                          reinterpret_cast<char*>(w.roots)) /
+                                          reinterpret_cast<char*>(w.masks)) /
                                      sizeof(uint32_t),
                                  0xfffffffeu)
                            : 0u;
