@@ -408,21 +408,9 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
     hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
                        dim3(256), 0, s, w, d);
     const int G = cfg.group_lanes;
-    uint32_t gh = grid_chunked(H, bs, G, std::min<uint32_t>(persist, kCompactBlocksMax));
-    if (cfg.doublet_mode == 2) {
-      // the staging pair shares one grid (the scatter reads the stage's
-      // per-wavefront regions): the smaller of their resident grids
-      const void* ks = nullptr;
-      const void* kc = nullptr;
-      switch (G) {
-        case 4: ks = (const void*)k_dstage<4>; kc = (const void*)k_dscatter<4>; break;
-        case 8: ks = (const void*)k_dstage<8>; kc = (const void*)k_dscatter<8>; break;
-        case 16: ks = (const void*)k_dstage<16>; kc = (const void*)k_dscatter<16>; break;
-        case 64: ks = (const void*)k_dstage<64>; kc = (const void*)k_dscatter<64>; break;
-        default: ks = (const void*)k_dstage<32>; kc = (const void*)k_dscatter<32>; break;
-      }
-      gh = std::min({gh, resident_grid(ks, bs, n_cu), resident_grid(kc, bs, n_cu)});
-    }
+    // (the staging pair keeps the full persistent grid: measured faster for
+    // the scatter than the resident-block grid)
+    const uint32_t gh = grid_chunked(H, bs, G, std::min<uint32_t>(persist, kCompactBlocksMax));
     if (cfg.doublet_mode == 1) {
       // one pass (its time shows under doublet_fill)
       const uint32_t gpb = (uint32_t)(bs / G);
