@@ -607,6 +607,45 @@ def copy_peak(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def atomic_rates(torch, pxt, rec, n, stages):
+    """Atomic throughput: a ruler (random-address 32-bit integer adds by
+    torch's index_add_, over a 64 MiB array and over 64k counters, the size
+    of the bin histogram of a 64-event batch) and the rates the path's
+    atomic-heavy kernels reach: the binning counts (one add per hit), the
+    election keys (one 64-bit min per raw n-tuplet doublet) and the link
+    bits (one 64-bit or per link), each over its stage time."""
+    dev = "cuda"
+    out = {}
+    g = torch.Generator(device="cpu").manual_seed(7)
+    for name, size in (("ruler_uncontended_gops", 16 << 20), ("ruler_64k_counters_gops", 1 << 16)):
+        n_ops = 1 << 25
+        idx = torch.randint(0, size, (n_ops,), generator=g).to(dev)
+        src = torch.ones(n_ops, dtype=torch.int32, device=dev)
+        dst = torch.zeros(size, dtype=torch.int32, device=dev)
+        dst.index_add_(0, idx, src)  # warm-up
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        a.record()
+        for _ in range(reps):
+            dst.index_add_(0, idx, src)
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = round(n_ops * reps / (a.elapsed_time(b) * 1e-3) / 1e9, 2)
+        del idx, src, dst
+    raw = rec.dump(pxt.DUMP_RAW)
+    cells = int(((raw[:, 1:] != 0xFFFFFFFF).sum(axis=1) - 1).sum()) if raw.shape[0] else 0
+    kern = {}
+    for stage, ops, what in (("prep", n["Nh"], "bin counter adds (one per hit)"),
+                             ("score", cells, "64-bit key mins (one per raw n-tuplet doublet)"),
+                             ("links", n["Nl"], "64-bit mask ors (one per link)")):
+        ms = stages.get(stage, 0.0)
+        kern[stage] = {"atomics": int(ops), "what": what, "ms": round(ms, 4),
+                       "gops": round(ops / (ms * 1e-3) / 1e9, 2) if ms > 0 else None}
+    out["kernels"] = kern
+    return out
+
+
 def path_counts(rec, counts, n_hits, n_events):
     nk = counts["n_tracks"]
     nh = rec.o_n_hits[:nk].cpu().numpy()
@@ -671,6 +710,7 @@ def main(argv=None):
     tb = trec.upload(pool[0])
     stages = trec.stage_times(tb, repeats=5)
     n = path_counts(trec, trec.read_counts(), int(tb[4][-1]), B)
+    atomics = atomic_rates(torch, pxt, trec, n, stages)
     trec.close()
 
     pcie = None
@@ -776,6 +816,7 @@ def main(argv=None):
     if rech is not None:
         out["rechits"] = rech
     out["roofline"] = roofline(stages, n, ev_per_s / B, HBM_PEAK_GBS, cgbs, args.workload, args)
+    out["atomics"] = atomics
     if served is not None:
         out["served"] = served
     if not args.no_cpu:
