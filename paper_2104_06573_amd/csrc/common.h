@@ -22,7 +22,7 @@ constexpr uint32_t kPad = PXT_PAD;
 constexpr int kWave = 64;
 constexpr float kPiF = 3.14159265358979f;
 constexpr int kQueue = 128;                    // LDS queue entries per wavefront
-constexpr uint32_t kCompactBlocksMax = 4096;   // grid cap of k_compact / k_fitorder
+constexpr uint32_t kCompactBlocksMax = 4096;   // grid cap of k_compact and the doublet stage
 
 // Counters kept in device memory for one call (zeroed by k_clear).
 enum Ctr : int {
@@ -41,9 +41,8 @@ enum Ctr : int {
   C_REQ_W,
   C_REQ_T,
   C_REQ_K,
-  C_FITN0,           // survivors with n hits at C_FITN0 + n (n <= 8)
-  C_FITO0 = C_FITN0 + kMaxHits + 1,    // start of their range in sfit
-  C_TICKET0 = C_FITO0 + kMaxHits + 1,  // tile tickets of the single-pass scans
+  C_FITN0,           // survivors of length class k (3, 4, 5+ hits) at C_FITN0 + 3 + k
+  C_TICKET0 = C_FITN0 + kMaxHits + 1,  // tile tickets of the single-pass scans
   C_TICKET_END = C_TICKET0 + 8,
   C_NCTR = C_TICKET_END
 };
@@ -119,9 +118,7 @@ struct Ws {
   uint32_t* talive;       // [T + 1] survives the cleaning
   uint32_t* toff;         // [T + 1]
   uint32_t* surv;         // [T]
-  uint32_t* sfit;         // [T] survivor indices in fitting order
-  uint32_t* bcnt;         // [blocks][9] survivors per length met by each block
-  uint32_t* bbase;        // [blocks][9] each block's places per length
+  uint32_t* sfit;         // [3][T] survivor indices per length class (the fitting order)
   uint32_t* fp64_list;    // [T]
   // scan scratch
   uint64_t* scan_status;  // [max tiles] status words of the single-pass scan

@@ -1492,43 +1492,86 @@ __global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
 // per-event track counts from the event boundaries, which the binned hits,
 // doublets, n-tuplets and survivors all respect in that order.
 //
-// Also the first step of the fitting order.  The fit is compiled once per
-// tuple length, and one kernel per length keeps each body's register
-// budget its own and its wavefronts uniform; for that the survivors are
-// grouped by length, without atomics: each block counts the lengths of the
-// survivors it meets (bcnt), k_fitbase turns the counts into per-block
-// places, and k_fitorder, walking the same tuples in the same order,
-// writes the survivors there.  Every result still goes to its survivor's
-// slot, so only the work assignment changes.
-constexpr int kFitKeys = kMaxHits + 1;  // length keys 0..8 (3..8 used)
+// Also the fitting order.  The fit is compiled once per tuple length class
+// (3 hits, 4 hits, 5 to 8 hits), and one kernel per class keeps each body's
+// register budget its own and its wavefronts uniform; for that each class
+// gets a list of its survivors (region c of sfit, c = class).  A block owns
+// a contiguous chunk of the tuples: it counts the chunk's survivors per
+// class, takes a range of each class's list with one atomic per class, and
+// walks the chunk again writing its survivors there (ballot ranks within a
+// wavefront, the wavefronts' counts in LDS).  The order within a list
+// depends on the order the blocks take their ranges; every result still goes
+// to its survivor's slot, so only the work assignment changes.
+__device__ __forceinline__ uint32_t fit_class(uint32_t n) { return n >= 5u ? 2u : n - 3u; }
 
 __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
-  __shared__ uint32_t s_cnt[kFitKeys];
+  constexpr uint32_t NW = 256 / kWave;
+  __shared__ uint32_t s_cnt[NW][3];  // per wavefront and class
+  __shared__ uint32_t s_run[3];      // the block's next place per class
   if (w.ctr[C_STATUS]) return;
   const uint32_t n_events = w.call->n_events;
   uint32_t* per_event_tracks = w.call->out.per_event_tracks;
   const uint32_t ntup = w.ctr[C_NTUP];
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (threadIdx.x < kFitKeys) s_cnt[threadIdx.x] = 0;
-  __syncthreads();
-  // every lane of a wavefront runs the same number of rounds (ballots)
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t t0 = tid - lane_id(); t0 < ntup; t0 += stride) {
-    const uint32_t t = t0 + lane_id();
-    const bool alive = t < ntup && w.talive[t];
-    uint32_t key = 0;
-    if (alive) {
-      w.surv[w.toff[t]] = t;
-      key = w.tn[t];
-    }
+  const uint32_t T = c.cap_tuples;
+  const uint32_t lane = lane_id(), wib = threadIdx.x / kWave;
+  const uint64_t below = (1ull << lane) - 1ull;
+  // the block's chunk: whole 256-tuple rounds, every thread of the block
+  // runs the same number of rounds (barriers)
+  const uint32_t rounds = (ntup + 255u) / 256u;
+  const uint32_t per = (rounds + gridDim.x - 1u) / gridDim.x;
+  const uint32_t t_begin = min(ntup, blockIdx.x * per * 256u);
+  const uint32_t t_end = min(ntup, (blockIdx.x + 1u) * per * 256u);
+  // pass 1: the chunk's survivors per class
+  uint32_t cnt[3] = {0u, 0u, 0u};
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 256u) {
+    const uint32_t t = t0 + threadIdx.x;
+    const bool alive = t < t_end && w.talive[t];
+    const uint32_t cls = alive ? fit_class(w.tn[t]) : 3u;
 #pragma unroll
-    for (int k = 3; k < kFitKeys; ++k) {
-      const uint64_t m = __ballot(alive && key == (uint32_t)k);
-      if (lane_id() == 0 && m) atomicAdd(&s_cnt[k], (uint32_t)__popcll(m));
-    }
+    for (uint32_t k = 0; k < 3; ++k) cnt[k] += (uint32_t)__popcll(__ballot(cls == k));
+  }
+  if (lane == 0)
+    for (uint32_t k = 0; k < 3; ++k) s_cnt[wib][k] = cnt[k];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const uint32_t k = threadIdx.x;
+    uint32_t tot = 0;
+    for (uint32_t i = 0; i < NW; ++i) tot += s_cnt[i][k];
+    s_run[k] = tot ? atomicAdd(&w.ctr[C_FITN0 + 3 + k], tot) : 0u;
   }
   __syncthreads();
-  if (threadIdx.x < kFitKeys) w.bcnt[(size_t)blockIdx.x * kFitKeys + threadIdx.x] = s_cnt[threadIdx.x];
+  // pass 2: survivors, and their places in the class lists
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 256u) {
+    const uint32_t t = t0 + threadIdx.x;
+    const bool alive = t < t_end && w.talive[t];
+    uint32_t s = 0, cls = 3, rank = 0;
+    if (alive) {
+      s = w.toff[t];
+      w.surv[s] = t;
+      cls = fit_class(w.tn[t]);
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 3; ++k) {
+      const uint64_t m = __ballot(cls == k);
+      if (cls == k) rank = (uint32_t)__popcll(m & below);
+      if (lane == 0) s_cnt[wib][k] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint32_t base = 0;
+    if (alive) {
+      base = s_run[cls];
+      for (uint32_t i = 0; i < wib; ++i) base += s_cnt[i][cls];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      uint32_t add = 0;
+      for (uint32_t i = 0; i < NW; ++i) add += s_cnt[i][threadIdx.x];
+      s_run[threadIdx.x] += add;
+    }
+    if (alive) w.sfit[(size_t)cls * T + base + rank] = s;
+    __syncthreads();
+  }
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t per_ev = (uint32_t)c.n_layers * (uint32_t)c.nphi;
   const uint32_t nr = w.ctr[C_NROOT];
   for (uint32_t e = tid; e < n_events; e += gridDim.x * blockDim.x) {
@@ -1536,98 +1579,6 @@ __global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
     const uint32_t ra = lower_bound_u32(w.roots, nr, w.cell_off[w.bin_off[e * per_ev]]);
     const uint32_t rb = lower_bound_u32(w.roots, nr, w.cell_off[w.bin_off[(e + 1) * per_ev]]);
     per_event_tracks[e] = w.toff[w.roff[rb]] - w.toff[w.roff[ra]];
-  }
-}
-
-// Per-block places of every length in the fitting order: length k takes
-// the range after all shorter lengths, and within it the blocks follow in
-// block order.  One block of kFitBaseThreads: each thread sums the counts
-// of a few consecutive blocks, a scan per length over the threads (within
-// wavefronts, then over the wavefront totals) gives their places.
-constexpr int kFitBaseThreads = 1024;
-
-__global__ __launch_bounds__(kFitBaseThreads) void k_fitbase(Ws w, uint32_t nblocks) {
-  constexpr uint32_t NW = kFitBaseThreads / kWave;
-  __shared__ uint32_t s_wsum[kFitKeys][NW];
-  __shared__ uint32_t s_tot[kFitKeys];
-  if (w.ctr[C_STATUS]) return;
-  const uint32_t tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-  const uint32_t per = (nblocks + kFitBaseThreads - 1) / kFitBaseThreads;
-  const uint32_t b0 = min(nblocks, tid * per), b1 = min(nblocks, b0 + per);
-  uint32_t excl[kFitKeys];  // the thread's place within its wavefront, per length
-#pragma unroll
-  for (int k = 3; k < kFitKeys; ++k) {
-    uint32_t v = 0;
-    for (uint32_t b = b0; b < b1; ++b) v += w.bcnt[(size_t)b * kFitKeys + k];
-    const uint32_t inc = wave_incl_scan(v);
-    excl[k] = inc - v;
-    if (lane == kWave - 1) s_wsum[k][wid] = inc;
-  }
-  __syncthreads();
-  if (tid >= 3 && tid < kFitKeys) {
-    uint32_t run = 0;
-    for (uint32_t i = 0; i < NW; ++i) {
-      const uint32_t t = s_wsum[tid][i];
-      s_wsum[tid][i] = run;
-      run += t;
-    }
-    s_tot[tid] = run;
-  }
-  __syncthreads();
-  uint32_t off = 0;  // lengths below k come first
-#pragma unroll
-  for (int k = 3; k < kFitKeys; ++k) {
-    uint32_t run = off + s_wsum[k][wid] + excl[k];
-    for (uint32_t b = b0; b < b1; ++b) {
-      w.bbase[(size_t)b * kFitKeys + k] = run;
-      run += w.bcnt[(size_t)b * kFitKeys + k];
-    }
-    if (tid == 0) {
-      w.ctr[C_FITN0 + k] = s_tot[k];
-      w.ctr[C_FITO0 + k] = off;
-    }
-    off += s_tot[k];
-  }
-}
-
-// Writes each block's survivors to its places, length by length, visiting
-// the tuples in the order k_compact counted them (same grid and stride).
-__global__ __launch_bounds__(256) void k_fitorder(Ws w) {
-  constexpr int NW = 256 / kWave;
-  __shared__ uint32_t s_w[NW][kFitKeys];  // per wavefront and length
-  __shared__ uint32_t s_run[kFitKeys];    // the block's next place per length
-  if (w.ctr[C_STATUS]) return;
-  const uint32_t ntup = w.ctr[C_NTUP];
-  const uint32_t lane = lane_id(), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  const uint64_t below = (1ull << lane) - 1ull;
-  if (threadIdx.x < kFitKeys) s_run[threadIdx.x] = w.bbase[(size_t)blockIdx.x * kFitKeys + threadIdx.x];
-  __syncthreads();
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < ntup; b0 += stride) {
-    const uint32_t t = b0 + threadIdx.x;
-    const bool alive = t < ntup && w.talive[t];
-    const uint32_t key = alive ? (uint32_t)w.tn[t] : 0u;
-    uint32_t rank = 0;  // among this wavefront's survivors of the same length
-#pragma unroll
-    for (int k = 3; k < kFitKeys; ++k) {
-      const uint64_t m = __ballot(alive && key == (uint32_t)k);
-      if (key == (uint32_t)k) rank = (uint32_t)__popcll(m & below);
-      if (lane == 0) s_w[wid][k] = (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    if (threadIdx.x >= 3 && threadIdx.x < kFitKeys) {
-      const uint32_t k = threadIdx.x;
-      uint32_t run = s_run[k];
-      for (uint32_t i = 0; i < nw; ++i) {
-        const uint32_t v = s_w[i][k];
-        s_w[i][k] = run;
-        run += v;
-      }
-      s_run[k] = run;
-    }
-    __syncthreads();
-    if (alive) w.sfit[s_w[wid][key] + rank] = w.toff[t];
-    __syncthreads();
   }
 }
 
@@ -1706,8 +1657,8 @@ __device__ inline void fit_one(Ws& w, const DevCfg& c, const OutPtrs& o, uint32_
 // order (N = 0: all lengths from 5 up, rarer, in one kernel); the N = 3
 // instance also reports an output overflow.  The grid has a thread for
 // every tuple the context can hold.  The triplet fit, the most frequent,
-// is held to 128 registers (four wavefronts per SIMD), which it meets
-// without spilling.
+// is held to 128 registers (four wavefronts per SIMD) and the 4-hit fit to
+// 168 (three), which they meet without spilling.
 template <int N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 3 ? 4 : (N == 4 ? 3 : 1))))
 void k_fit32(Ws w, DevCfg c) {
@@ -1721,10 +1672,9 @@ void k_fit32(Ws w, DevCfg c) {
     }
     return;
   }
-  constexpr int K0 = N > 0 ? N : 5;
-  const uint32_t off = w.ctr[C_FITO0 + K0];
-  uint32_t cnt = 0;
-  for (int k = K0; k <= (N > 0 ? N : kMaxHits); ++k) cnt += w.ctr[C_FITN0 + k];
+  constexpr uint32_t CLS = N > 0 ? (uint32_t)N - 3u : 2u;  // the length class
+  const size_t off = (size_t)CLS * c.cap_tuples;
+  const uint32_t cnt = w.ctr[C_FITN0 + 3 + CLS];
   // one tuple per thread, no grid-stride loop: a loop would keep the values
   // derived from the configuration live across iterations and double the
   // register footprint (the grid covers the tuple capacity)
@@ -1759,15 +1709,14 @@ __global__ void k_finish(Ws w) {
   k->required[1] = ctr[C_REQ_W];
   k->required[2] = ctr[C_REQ_T];
   k->required[3] = ctr[C_REQ_K];
+  // the vertex step's summary starts empty (the vertex kernel follows)
+  if (w.call->has_vtx) k_vtx_begin_body(w.call->vtx);
 }
 
 // --------------------------------------------------------------- vertices --
-// The vertex step of a pxt_reconstruct call (after k_finish), on the call's
-// own outputs; nothing when the call has no vertex buffers.
-
-__global__ void k_vtx_begin_call(Ws w) {
-  if (w.call->has_vtx) k_vtx_begin_body(w.call->vtx);
-}
+// The vertex step of a pxt_reconstruct call (after k_finish, which resets
+// its summary), on the call's own outputs; nothing when the call has no
+// vertex buffers.
 
 __global__ __launch_bounds__(kVtxThreads) void k_vertices_call(Ws w, DevCfg c) {
   const CallDesc* cd = w.call;

@@ -144,9 +144,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.talive = cv.take<uint32_t>(T + 1);
   w.toff = cv.take<uint32_t>(T + 1);
   w.surv = cv.take<uint32_t>(T);
-  w.sfit = cv.take<uint32_t>(T);
-  w.bcnt = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
-  w.bbase = cv.take<uint32_t>((size_t)kCompactBlocksMax * (kMaxHits + 1));
+  w.sfit = cv.take<uint32_t>(3 * T);
   w.fp64_list = cv.take<uint32_t>(T);
   // the staging buffer of the doublets spans masks .. fp64_list
   w.stage = reinterpret_cast<uint32_t*>(w.masks);
@@ -469,15 +467,11 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
     hipLaunchKernelGGL(k_alive, dim3(std::min(gt, resident_grid((const void*)k_alive, bs, n_cu))),
                        dim3(bs), 0, s, w, d);
     launch_scan1(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, cfg.max_tuples, 5, s);
-    {
-      // survivors, then the fitting order grouped by length (the same grid
-      // for k_compact and k_fitorder: each block meets the same tuples)
-      const uint32_t gc = std::min<uint32_t>(grid_for(cfg.max_tuples, 256, persist),
-                                             kCompactBlocksMax);
-      hipLaunchKernelGGL(k_compact, dim3(gc), dim3(256), 0, s, w, d);
-      hipLaunchKernelGGL(k_fitbase, dim3(1), dim3(kFitBaseThreads), 0, s, w, gc);
-      hipLaunchKernelGGL(k_fitorder, dim3(gc), dim3(256), 0, s, w);
-    }
+    // survivors and the fitting order (one list per length class)
+    hipLaunchKernelGGL(k_compact,
+                       dim3(std::min<uint32_t>(grid_for(cfg.max_tuples, 256, persist),
+                                               kCompactBlocksMax)),
+                       dim3(256), 0, s, w, d);
     if (timed) sm.mark(16);
     {
       // fits of 3 and of 4 hits, then the rarer longer ones together (one
@@ -496,7 +490,6 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
   // vertices of the call's tracks (the kernels leave at once when the call
   // has no vertex buffers)
   if (timed) sm.mark(19);
-  hipLaunchKernelGGL(k_vtx_begin_call, dim3(1), dim3(64), 0, s, w);
   hipLaunchKernelGGL(k_vertices_call, dim3(std::max<uint32_t>(1, E)), dim3(kVtxThreads), 0, s,
                      w, d);
   if (timed) {
