@@ -22,6 +22,7 @@ constexpr uint32_t kPad = PXT_PAD;
 constexpr int kWave = 64;
 constexpr float kPiF = 3.14159265358979f;
 constexpr int kQueue = 128;                    // LDS queue entries per wavefront
+constexpr uint32_t kSmallFit = 8192;           // calls with at most this many tracks: one fit launch
 constexpr uint32_t kCompactBlocksMax = 4096;   // grid cap of k_compact and the doublet stage
 
 // Counters kept in device memory for one call (zeroed by k_clear).

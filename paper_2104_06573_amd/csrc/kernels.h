@@ -1672,6 +1672,7 @@ void k_fit32(Ws w, DevCfg c) {
     }
     return;
   }
+  if (N > 0 && ns <= kSmallFit) return;  // k_fit_small fits them
   constexpr uint32_t CLS = N > 0 ? (uint32_t)N - 3u : 2u;  // the length class
   const size_t off = (size_t)CLS * c.cap_tuples;
   const uint32_t cnt = w.ctr[C_FITN0 + 3 + CLS];
@@ -1680,6 +1681,29 @@ void k_fit32(Ws w, DevCfg c) {
   // register footprint (the grid covers the tuple capacity)
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) fit_one<float, N>(w, c, o, w.sfit[off + i], false);
+}
+
+// Calls with few tracks (one or two events: the plain and served paths)
+// fit the 3-hit and 4-hit classes in one launch instead of two: block b
+// takes the 3-hit list for b < ceil(n3 / 256), then the 4-hit list.  With
+// so few wavefronts each kernel's time is the latency of one fit, so one
+// kernel at the larger class's register budget beats two at their own; the
+// per-class kernels of those classes leave at once (the 5-to-8-hit kernel
+// always runs: together with it this kernel would spill).
+__global__ __launch_bounds__(256) void k_fit_small(Ws w, DevCfg c) {
+  if (w.ctr[C_STATUS]) return;
+  const OutPtrs o = w.call->out;
+  const uint32_t ns = w.ctr[C_NSURV];
+  if (ns > kSmallFit || ns > o.capacity) return;  // the per-class kernels run (or report)
+  const uint32_t n3 = w.ctr[C_FITN0 + 3], n4 = w.ctr[C_FITN0 + 4];
+  const uint32_t b3 = (n3 + 255u) / 256u;
+  if (blockIdx.x < b3) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n3) fit_one<float, 3>(w, c, o, w.sfit[i], false);
+  } else {
+    const uint32_t i = (blockIdx.x - b3) * 256u + threadIdx.x;
+    if (i < n4) fit_one<float, 4>(w, c, o, w.sfit[(size_t)c.cap_tuples + i], false);
+  }
 }
 
 __global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c) {

@@ -477,6 +477,7 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
       // fits of 3 and of 4 hits, then the rarer longer ones together (one
       // thread per tuple of the capacity)
       const uint32_t gf = grid_for(cfg.max_tuples, 256, 0xffffffffu);
+      hipLaunchKernelGGL(k_fit_small, dim3(kSmallFit / 256 + 2), dim3(256), 0, s, w, d);
       hipLaunchKernelGGL(k_fit32<3>, dim3(gf), dim3(256), 0, s, w, d);
       hipLaunchKernelGGL(k_fit32<4>, dim3(gf), dim3(256), 0, s, w, d);
       hipLaunchKernelGGL(k_fit32<0>, dim3(gf), dim3(256), 0, s, w, d);
