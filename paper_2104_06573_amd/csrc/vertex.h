@@ -384,7 +384,6 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
         if (i0 + q < b) {
           const double rz = (double)z_of_key(k[q]) - zv;
           chi2 += w[q] * rz * rz;
-          o.track_vertex[toff + (uint32_t)((k[q] >> 12) & 0xfffffu)] = (int32_t)v;
         }
       }
     }
@@ -394,6 +393,12 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
     o.z_err[slot] = (float)sqrt(1.0 / sw);
     o.chi2[slot] = (float)chi2;
     o.n_tracks[slot] = bl - a + 1;
+  }
+  // every member's vertex, by all threads (the sums above run one thread
+  // per cluster)
+  for (uint32_t i = tid; i < m; i += nthr) {
+    const int32_t lab = s_lab[i];
+    if (lab >= 0) o.track_vertex[toff + (uint32_t)((s_key[i] >> 12) & 0xfffffu)] = lab;
   }
   if (tid == 0) {
     o.n_vertices[e] = ncl;
