@@ -204,6 +204,19 @@ __device__ __forceinline__ bool link_xy_pass(const DevCfg& c, const HitD& a, con
       return false;
   }
   const double D = 2.0 * cr;
+  // L3 first in a form without divisions: with N = D * (centre - a) =
+  // (vy ab2 - uy ac2, ux ac2 - vx ab2), the defining expression below is
+  // d0 = |aa D + 2 a.N| / (|a D + N| + |N|) (also for D = 0, where it is the
+  // distance from the origin to the line), compared with d0max; outside the
+  // relative band its answer is that of the defining expression
+  {
+    const double Nx = vy * ab2 - uy * ac2, Ny = ux * ac2 - vx * ab2;
+    const double px = a.x * D + Nx, py = a.y * D + Ny;
+    const double num = fabs((a.x * a.x + a.y * a.y) * D + 2.0 * (a.x * Nx + a.y * Ny));
+    const double den = c.d0max * (sqrt(px * px + py * py) + sqrt(Nx * Nx + Ny * Ny));
+    if (num > den * kBandHi) return false;
+    if (num < den * kBandLo) return true;
+  }
   double d0;
   if (D == 0.0) {
     d0 = fabs(a.x * vy - a.y * vx) / sqrt(ac2);

@@ -865,11 +865,10 @@ __device__ __forceinline__ void outer_range(const Ws& w, uint32_t j, uint32_t& k
 // evenly over the wavefront's lanes (below).  The few survivors are not tested
 // in place -- their exact FP64 tests would run with most lanes idle -- but
 // appended to a per-wavefront queue in LDS (ballot compaction) together
-// with the doublet's two hits, so that whenever 64 are queued they are
-// tested with all lanes busy and only the candidate's hit is loaded.  A
-// doublet's mask words and link count are cleared by its own thread before
-// any of its candidates is queued; accepted links set their bit with
-// atomicOr.
+// with the doublet's hits, so that whenever 64 are queued they are tested
+// with all lanes busy.  A doublet's mask words and has-outer flag are
+// cleared by its own thread before any of its candidates is queued;
+// accepted links set their bit with atomicOr.
 
 // Queue entry: qa = (doublet, candidate doublet, inner hit, outer hit),
 // qb = (candidate index, the doublet's number of candidates).  The flush
@@ -882,11 +881,10 @@ __device__ __forceinline__ void links_thread_flush(Ws& w, const DevCfg& c, const
     const uint4 ea = qa[lane];
     const uint2 eb = qb[lane];
     const uint32_t d = ea.x, d2 = ea.y, k = eb.x;
-    const float4 va = w.bh[ea.z], vb = w.bh[ea.w];
-    const float4 vc = w.bh[w.cio[d2].y];
-    const HitD ha = hit_xyz(va.x, va.y, va.z);
-    const HitD hb = hit_xyz(vb.x, vb.y, vb.z);
-    const HitD hc = hit_xyz(vc.x, vc.y, vc.z);
+    // the FP64 radii are loaded with the coordinates (an FP64 square root
+    // per hit costs more than the load)
+    const HitD ha = load_hit(w, ea.z), hb = load_hit(w, ea.w);
+    const HitD hc = load_hit(w, w.cio[d2].y);
     if (link_rz_pass(c, ha, hb, hc.r, hc.z) && link_xy_pass(c, ha, hb, hc)) {
       atomicOr((unsigned long long*)&w.masks[(size_t)(k >> 6) * nd + d], 1ull << (k & 63u));
       w.has_out[d] = 1;
