@@ -860,8 +860,8 @@ __device__ __forceinline__ void outer_range(const Ws& w, uint32_t j, uint32_t& k
   deg = w.cell_off[j + 1] - kb;
 }
 
-// One thread per doublet (a,b) for its set-up (mask words and link count
-// cleared, hits fetched); the angle prefilter over the candidates is spread
+// One thread per doublet (a,b) for its set-up (mask words and has-outer
+// flag cleared, hit indices fetched); the angle prefilter over the candidates is spread
 // evenly over the wavefront's lanes (below).  The few survivors are not tested
 // in place -- their exact FP64 tests would run with most lanes idle -- but
 // appended to a per-wavefront queue in LDS (ballot compaction) together
