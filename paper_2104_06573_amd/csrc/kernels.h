@@ -958,11 +958,22 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
           tc[4 * v + 2] = f.z;
           tc[4 * v + 3] = f.w;
         }
+        // the angle window first (one compare per candidate), the
+        // anti-parallel window only where it can hold: doublets point outward
+        // (r grows), so their FP32 r-z angles lie in [-pi/2, pi/2] (pi/2
+        // rounded up) and two of them differ by th_far or more only if
+        // |ta| >= th_far - pi/2 (1.5708 covers the roundings)
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const uint32_t idx = a0 + u;
-          if (idx >= lo && idx < hi && rz_prefilter(c, ta, tc[u])) pm |= 1u << u;
+        for (int u = 0; u < 16; ++u)
+          if (fabsf(tc[u] - ta) <= c.th_win) pm |= 1u << u;
+        if (__any(q < C && fabsf(ta) >= c.th_far - 1.5708f)) {
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (fabsf(tc[u] - ta) >= c.th_far) pm |= 1u << u;
         }
+        // the owner's candidates within the chunk: a0 + u in [lo, hi)
+        const uint32_t ub = lo > a0 ? lo - a0 : 0u, ue = min(16u, hi - a0);
+        pm &= (ue >= 16u ? 0xffffu : (1u << ue) - 1u) & ~((1u << ub) - 1u);
       }
       // the owner's hits travel with its survivors
       const uint32_t od = dw + own;
