@@ -214,8 +214,7 @@ def path_bytes(n):
 def step_bytes(step, n):
     Nh, Nd, Nl, Nt, Nk, nbar = n["Nh"], n["Nd"], n["Nl"], n["Nt"], n["Nk"], n["nbar"]
     table = {
-        "prep": 14 * Nh,                                    # hits read
-        "binning": 24 * Nh,                                 # binned hits written
+        "binning": 14 * Nh + 24 * Nh,                       # hits read, binned hits written
         "doublets": 24 * Nh + 8 * Nd + 4 * (Nh + Nd),       # binned read, doublets + CSR written
         "links": 8 * Nd + 4 * (Nh + Nd) + 4 * Nl,           # doublets + CSR read, links written
         "ntuplets": 4 * Nl + 33 * Nt,                       # links read, raw n-tuplets written
@@ -229,8 +228,9 @@ def step_bytes(step, n):
 
 # library stages (pxt_stage_name) of each step of the path
 STEP_STAGES = {
-    "prep": ("clear", "prep"),
-    "binning": ("bin_scan", "fill"),
+    # (ingest and binning are one kernel, one block per event, unless the
+    # histogram of an event exceeds LDS: then k_prep, the scan and k_fill)
+    "binning": ("clear", "prep", "bin_scan", "fill"),
     "doublets": ("doublet_count", "doublet_scan", "doublet_fill"),
     "links": ("mask_clear", "links"),
     "ntuplets": ("roots", "tuple_count", "tuple_scan", "tuple_fill"),
@@ -611,8 +611,8 @@ def atomic_rates(torch, pxt, rec, n, stages):
     """Atomic throughput: a ruler (random-address 32-bit integer adds by
     torch's index_add_, over a 64 MiB array and over 64k counters, the size
     of the bin histogram of a 64-event batch) and the rates the path's
-    atomic-heavy kernels reach: the binning counts (one add per hit), the
-    election keys (one 64-bit min per raw n-tuplet doublet) and the link
+    atomic-heavy kernels reach: the binning counts (two LDS adds per hit),
+    the election keys (one 64-bit min per raw n-tuplet doublet) and the link
     bits (one 64-bit or per link), each over its stage time."""
     dev = "cuda"
     out = {}
@@ -636,7 +636,8 @@ def atomic_rates(torch, pxt, rec, n, stages):
     raw = rec.dump(pxt.DUMP_RAW)
     cells = int(((raw[:, 1:] != 0xFFFFFFFF).sum(axis=1) - 1).sum()) if raw.shape[0] else 0
     kern = {}
-    for stage, ops, what in (("prep", n["Nh"], "bin counter adds (one per hit)"),
+    for stage, ops, what in (("prep", 2 * n["Nh"],
+                              "bin counter adds, in LDS (two per hit: count, fill cursor)"),
                              ("score", cells, "64-bit key mins (one per raw n-tuplet doublet)"),
                              ("links", n["Nl"], "64-bit mask ors (one per link)")):
         ms = stages.get(stage, 0.0)

@@ -62,6 +62,7 @@ struct DevCfg {
   double c_kappa, sigma_u, sigma_z, sigma_r, x_over_x0, pt_max, pt_fp64;
   uint32_t cap_doublets, cap_words, cap_tuples;
   int link_kernel;                          // 0 thread, 1 lane group, 2 wave
+  int bin_lds;                              // binning by one block per event
   float th_win, th_far;                     // r-z angle prefilter of the links
   // output selection and quality flags
   int min_hits;                             // shorter survivors are not output

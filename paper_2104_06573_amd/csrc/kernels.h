@@ -36,7 +36,7 @@ struct CallDesc {
   uint32_t n_events;
   uint32_t n_hits;
   uint32_t has_vtx;  // 1: find the vertices of the tracks into vtx
-  uint32_t pad;
+  uint32_t bin_lds;  // 1: binning by k_bin_events, 0: by k_prep .. k_rmax
   const float* x;
   const float* y;
   const float* z;
@@ -54,9 +54,11 @@ __global__ void k_clear(Ws w, DevCfg c) {
   uint32_t* per_event_tracks = cd->out.per_event_tracks;
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = tid; i < nbins + 1; i += stride) w.bin_cnt[i] = 0;
+  const bool glob = !cd->bin_lds;
+  if (glob)
+    for (uint32_t i = tid; i < nbins + 1; i += stride) w.bin_cnt[i] = 0;
   for (uint32_t i = tid; i < E; i += stride) per_event_tracks[i] = 0;
-  if (tid < C_NCTR) w.ctr[tid] = tid == C_NBINS ? nbins : 0u;
+  if (tid < C_NCTR) w.ctr[tid] = tid == C_NBINS && glob ? nbins : 0u;
   if (tid == 0) w.epoch[0] += 1u;
 }
 
@@ -83,8 +85,14 @@ __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, uint64_t n, uint6
 
 // ------------------------------------------------------- binning (prep) --
 
+__device__ __forceinline__ uint32_t phi_bin(const DevCfg& c, float phi) {
+  const int b = (int)((phi + kPiF) * c.phi_scale);
+  return (uint32_t)(b < 0 ? 0 : (b >= c.nphi ? c.nphi - 1 : b));
+}
+
 __global__ __launch_bounds__(256) void k_prep(Ws w, DevCfg c) {
   const CallDesc* cd = w.call;
+  if (cd->bin_lds) return;
   const uint32_t H = cd->n_hits, E = cd->n_events;
   const float* __restrict__ x = cd->x;
   const float* __restrict__ y = cd->y;
@@ -97,10 +105,8 @@ __global__ __launch_bounds__(256) void k_prep(Ws w, DevCfg c) {
       continue;
     }
     const float xf = x[g], yf = y[g];
-    const float phi = atan2f(yf, xf);
-    int b = (int)((phi + kPiF) * c.phi_scale);
-    b = b < 0 ? 0 : (b >= c.nphi ? c.nphi - 1 : b);
-    const uint32_t key = (e * (uint32_t)c.n_layers + (uint32_t)l) * (uint32_t)c.nphi + (uint32_t)b;
+    const uint32_t b = phi_bin(c, atan2f(yf, xf));
+    const uint32_t key = (e * (uint32_t)c.n_layers + (uint32_t)l) * (uint32_t)c.nphi + b;
     w.keys[g] = key;
     atomicAdd(&w.bin_cnt[key], 1u);
   }
@@ -108,6 +114,7 @@ __global__ __launch_bounds__(256) void k_prep(Ws w, DevCfg c) {
 
 __global__ __launch_bounds__(256) void k_fill(Ws w) {
   const CallDesc* cd = w.call;
+  if (cd->bin_lds) return;
   const uint32_t H = cd->n_hits, E = cd->n_events;
   const float* __restrict__ x = cd->x;
   const float* __restrict__ y = cd->y;
@@ -133,7 +140,14 @@ __global__ __launch_bounds__(256) void k_fill(Ws w) {
 // asin(kmax r / 2) of a curvature-kmax circle through the origin out to
 // that radius (slightly enlarged), the outer term of the doublet phi
 // window; infinity where the window is the whole layer.
+__device__ __forceinline__ void store_rmax(Ws& w, const DevCfg& c, uint32_t sg, float m) {
+  w.rmax[sg] = __float_as_uint(m);
+  const float ao = 0.5f * c.kmax_f * (m * 1.000001f);
+  w.rasin[sg] = ao >= 0.70710678f ? __builtin_huge_valf() : asinf(ao);
+}
+
 __global__ __launch_bounds__(256) void k_rmax(Ws w, DevCfg c) {
+  if (w.call->bin_lds) return;
   const uint32_t n_layers = (uint32_t)c.n_layers, nphi = (uint32_t)c.nphi;
   const uint32_t nseg = w.call->n_events * n_layers;
   const uint32_t wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -144,11 +158,7 @@ __global__ __launch_bounds__(256) void k_rmax(Ws w, DevCfg c) {
     for (uint32_t i = b0 + lane_id(); i < b1; i += kWave) m = fmaxf(m, (float)w.br[i]);
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, kWave));
-    if (lane_id() == 0) {
-      w.rmax[sg] = __float_as_uint(m);
-      const float ao = 0.5f * c.kmax_f * (m * 1.000001f);
-      w.rasin[sg] = ao >= 0.70710678f ? __builtin_huge_valf() : asinf(ao);
-    }
+    if (lane_id() == 0) store_rmax(w, c, sg, m);
   }
 }
 
@@ -353,6 +363,123 @@ __global__ __launch_bounds__(kScanThreads1) void k_roots(Ws w, uint32_t scan_id)
     w.roots[run++] = base + (uint32_t)i;
   }
   if (tile == ntiles - 1 && threadIdx.x == 0) w.ctr[C_NROOT] = s_prefix + agg;
+}
+
+// Binning with one block per event (an event's hits are contiguous in the
+// input, a few thousand to a few tens of thousands of them): the event's
+// (layer, phi bin) histogram, its exclusive scan, the fill cursors and each
+// layer's largest radius all live in LDS, so no global atomics are made;
+// only the event's place in the binned array comes from a decoupled
+// look-back over the events before it (one tile per event, tiles taken in
+// order from the ticket).  Used when the histogram (n_layers x phi bins
+// counters) fits kBinLdsBins and the call has many events or only small
+// ones: one block of one CU cannot bin a single large event as fast as the
+// whole device does.  The layout it writes is the one k_prep, the scan,
+// k_fill and k_rmax write (the order within a bin is arbitrary in both).
+// The call's descriptor names the set that runs (a graph holds one set);
+// the kernels of the other leave at once.
+constexpr int kBinThreads = 1024;
+constexpr uint32_t kBinLdsBins = 12288;  // 48 KB of counters
+constexpr uint32_t kBinScan = 2;         // scan id of the event offsets (the global
+                                         // binning's scan is id 0)
+constexpr int kBinUnroll = 8;
+constexpr uint32_t kBinLdsEvents = 8;     // calls of at least this many events,
+constexpr uint32_t kBinLdsHits = 8192;    // or whose events are all this small
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_events(Ws w, DevCfg c) {
+  extern __shared__ uint32_t s_hist[];  // [n_layers * nphi]
+  __shared__ uint32_t s_lds[kBinThreads / kWave + 1];
+  __shared__ uint32_t s_rmax[kMaxLayers];
+  __shared__ uint32_t s_base;
+  const CallDesc* cd = w.call;
+  const uint32_t E = cd->n_events;
+  if (!cd->bin_lds) return;
+  if (E == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.bin_off[0] = 0u;
+    return;
+  }
+  uint32_t e;
+  if (!take_tile(w, kBinScan, E, e)) return;
+  const float* __restrict__ x = cd->x;
+  const float* __restrict__ y = cd->y;
+  const float* __restrict__ z = cd->z;
+  const int16_t* __restrict__ layer = cd->layer;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t L = (uint32_t)c.n_layers, nphi = (uint32_t)c.nphi, per_ev = L * nphi;
+  const uint32_t h0 = w.evt_off[e], h1 = w.evt_off[e + 1];
+  for (uint32_t k = tid; k < per_ev; k += kBinThreads) s_hist[k] = 0u;
+  if (tid < L) s_rmax[tid] = 0u;
+  __syncthreads();
+  // (each thread loads kBinUnroll hits before using any: the loads of a
+  // round are in flight together)
+  for (uint32_t g0 = h0 + tid; g0 < h1; g0 += kBinUnroll * kBinThreads) {
+    int l[kBinUnroll];
+    float xf[kBinUnroll], yf[kBinUnroll];
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u) {
+      const uint32_t g = g0 + (uint32_t)u * kBinThreads;
+      l[u] = g < h1 ? layer[g] : -1;
+      xf[u] = g < h1 ? x[g] : 0.0f;
+      yf[u] = g < h1 ? y[g] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u)
+      if (l[u] >= 0 && l[u] < (int)L)
+        atomicAdd(&s_hist[(uint32_t)l[u] * nphi + phi_bin(c, atan2f(yf[u], xf[u]))], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the histogram in place: thread t sums its run of
+  // consecutive counters, the block scans the sums
+  const uint32_t per = (per_ev + kBinThreads - 1) / kBinThreads;
+  const uint32_t k0 = min(per_ev, tid * per), k1 = min(per_ev, k0 + per);
+  uint32_t tsum = 0;
+  for (uint32_t k = k0; k < k1; ++k) tsum += s_hist[k];
+  uint32_t agg;
+  uint32_t run = block_excl_scan(tsum, s_lds, agg);
+  if (tid < kWave) {
+    const uint32_t pf = tile_lookback(w, e, w.epoch[0] * 8u + kBinScan, agg);
+    if (tid == 0) s_base = pf;
+  }
+  for (uint32_t k = k0; k < k1; ++k) {
+    const uint32_t n = s_hist[k];
+    s_hist[k] = run;
+    run += n;
+  }
+  __syncthreads();
+  const uint32_t base = s_base;
+  for (uint32_t k = tid; k < per_ev; k += kBinThreads) w.bin_off[e * per_ev + k] = base + s_hist[k];
+  if (e == E - 1 && tid == 0) {
+    w.bin_off[E * per_ev] = base + agg;
+    w.ctr[C_NBINNED] = base + agg;
+  }
+  for (uint32_t g0 = h0 + tid; g0 < h1; g0 += kBinUnroll * kBinThreads) {
+    int l[kBinUnroll];
+    float xf[kBinUnroll], yf[kBinUnroll], zf[kBinUnroll];
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u) {
+      const uint32_t g = g0 + (uint32_t)u * kBinThreads;
+      l[u] = g < h1 ? layer[g] : -1;
+      xf[u] = g < h1 ? x[g] : 0.0f;
+      yf[u] = g < h1 ? y[g] : 0.0f;
+      zf[u] = g < h1 ? z[g] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u) {
+      if (!(l[u] >= 0 && l[u] < (int)L)) continue;
+      const float phi = atan2f(yf[u], xf[u]);
+      const uint32_t pos =
+          base + atomicAdd(&s_hist[(uint32_t)l[u] * nphi + phi_bin(c, phi)], 1u);
+      const double r = hit_xyz(xf[u], yf[u], 0.0f).r;
+      w.bh[pos] = make_float4(xf[u], yf[u], zf[u], phi);
+      w.br[pos] = r;
+      w.bidx[pos] = g0 + (uint32_t)u * kBinThreads - h0;
+      w.bevt[pos] = e;
+      w.blay[pos] = (uint8_t)l[u];
+      atomicMax(&s_rmax[l[u]], __float_as_uint((float)r));
+    }
+  }
+  __syncthreads();
+  if (tid < L) store_rmax(w, c, e * L + tid, __uint_as_float(s_rmax[tid]));
 }
 
 // ------------------------------------------------------------- doublets --

@@ -35,10 +35,11 @@ struct pxt_ctx {
   hipEvent_t slot_free[kSlots] = {};
   bool slot_pending[kSlots] = {};
   int next_slot = 0;
-  // HIP graphs of the launch sequence, one per slot (graph mode)
+  // HIP graphs of the launch sequence, one per slot and binning kernel set
+  // (graph mode), captured at their first use
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph[kSlots] = {};
-  hipGraphExec_t gexec[kSlots] = {};
+  hipGraph_t graph[kSlots][2] = {};
+  hipGraphExec_t gexec[kSlots][2] = {};
   int n_cu = 256;
   // calls made on this context: the scan status words carry a 30-bit tag of
   // (call, scan), which repeats after 2^27 calls, so they are reset every
@@ -98,9 +99,11 @@ size_t scan_tiles(const pxt_config& c) {
   const size_t nbins = (size_t)c.max_events * (size_t)c.n_layers * (size_t)c.phi_bins;
   const size_t n = std::max({nbins, (size_t)c.max_hits, (size_t)c.max_doublets,
                              (size_t)c.max_tuples});
+  // (the per-event binning takes one tile per event)
   // single-pass doublets: one tile per blockDim/group_lanes binned hits
   const size_t gpb = (size_t)std::max(1, c.block_size / std::max(1, c.group_lanes));
-  return std::max((n + kTile - 1) / kTile + 1, (size_t)c.max_hits / gpb + 2);
+  return std::max({(n + kTile - 1) / kTile + 1, (size_t)c.max_hits / gpb + 2,
+                   (size_t)c.max_events + 1});
 }
 
 void carve(Carver& cv, const pxt_config& c, Ws& w) {
@@ -232,6 +235,7 @@ void make_devcfg(const pxt_config& c, DevCfg& d) {
   d.cap_words = c.max_link_words;
   d.cap_tuples = c.max_tuples;
   d.link_kernel = c.link_kernel;
+  d.bin_lds = (uint32_t)c.n_layers * (uint32_t)c.phi_bins <= kBinLdsBins;
   d.min_hits = c.min_hits;
   d.q_chi2 = c.q_chi2;
   d.q_qopt_max = (float)(1.0 / (double)c.q_pt_min);
@@ -378,7 +382,7 @@ void launch_links(int G, dim3 grid, dim3 block, hipStream_t s, const Ws& w, cons
 // the descriptor; in direct mode the grids are sized from this call's hits
 // (H) and events (E).  c supplies the stage timing (nullptr: none).
 void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& d, int n_cu,
-                  hipStream_t s, bool graph_mode, uint32_t H, uint32_t E) {
+                  hipStream_t s, bool graph_mode, uint32_t H, uint32_t E, bool bin_lds) {
   const int bs = cfg.block_size;
   const uint32_t persist = (uint32_t)n_cu * 8u;
   if (graph_mode) {
@@ -391,20 +395,29 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
   if (timed)
     for (int i = 0; i < PXT_N_STAGES; ++i) c->stage_run[i] = false;
   if (timed) sm.mark(0);
-  hipLaunchKernelGGL(k_clear, dim3(grid_for(std::max<uint64_t>(nbins + 1, C_NCTR), 256, persist)),
-                     dim3(256), 0, s, w, d);
+  const bool bin_glob = !bin_lds, bin_ev = bin_lds;  // the call's binning kernels
+  const uint64_t nclear = std::max<uint64_t>(bin_glob ? nbins + 1 : E, C_NCTR);
+  hipLaunchKernelGGL(k_clear, dim3(grid_for(nclear, 256, persist)), dim3(256), 0, s, w, d);
   hipLaunchKernelGGL(k_slots_clear, dim3(grid_for(cfg.max_doublets, 256, persist)), dim3(256), 0,
                      s, w, d);
   if (H > 0) {
-    const uint32_t gh1 = grid_for(H, 256, persist);
     if (timed) sm.mark(1);
-    hipLaunchKernelGGL(k_prep, dim3(gh1), dim3(256), 0, s, w, d);
-    if (timed) sm.mark(2);
-    launch_scan1(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, nbins, 0, s);
-    if (timed) sm.mark(3);
-    hipLaunchKernelGGL(k_fill, dim3(gh1), dim3(256), 0, s, w);
-    hipLaunchKernelGGL(k_rmax, dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
-                       dim3(256), 0, s, w, d);
+    if (bin_glob) {
+      const uint32_t gh1 = grid_for(H, 256, persist);
+      hipLaunchKernelGGL(k_prep, dim3(gh1), dim3(256), 0, s, w, d);
+      if (timed) sm.mark(2);
+      launch_scan1(w, w.bin_cnt, w.bin_off, w.ctr + C_NBINS, w.ctr + C_NBINNED, nbins, 0, s);
+      if (timed) sm.mark(3);
+      hipLaunchKernelGGL(k_fill, dim3(gh1), dim3(256), 0, s, w);
+      hipLaunchKernelGGL(k_rmax,
+                         dim3(grid_for((uint64_t)E * cfg.n_layers * kWave, 256, persist)),
+                         dim3(256), 0, s, w, d);
+    }
+    if (bin_ev) {
+      // one block per event (in direct mode its time shows under prep)
+      hipLaunchKernelGGL(k_bin_events, dim3(std::max<uint32_t>(1, E)), dim3(kBinThreads),
+                         sizeof(uint32_t) * (size_t)cfg.n_layers * (size_t)cfg.phi_bins, s, w, d);
+    }
     const int G = cfg.group_lanes;
     // (the staging pair keeps the full persistent grid: measured faster for
     // the scatter than the resident-block grid)
@@ -503,9 +516,10 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
 // slot, then the kernels.
 void enqueue(pxt_ctx* c, hipStream_t s, int slot, bool graph_mode, uint32_t H, uint32_t E) {
   const size_t copy = graph_mode ? c->slot_bytes : desc_bytes() + sizeof(uint32_t) * (E + 1);
-  (void)hipMemcpyAsync(const_cast<CallDesc*>(c->ws.call),
-                       c->h_slots + (size_t)slot * c->slot_bytes, copy, hipMemcpyHostToDevice, s);
-  enqueue_path(c, c->cfg, c->ws, c->dc, c->n_cu, s, graph_mode, H, E);
+  const char* hs = c->h_slots + (size_t)slot * c->slot_bytes;
+  (void)hipMemcpyAsync(const_cast<CallDesc*>(c->ws.call), hs, copy, hipMemcpyHostToDevice, s);
+  const bool bin_lds = reinterpret_cast<const CallDesc*>(hs)->bin_lds != 0;
+  enqueue_path(c, c->cfg, c->ws, c->dc, c->n_cu, s, graph_mode, H, E, bin_lds);
 }
 
 int validate_vertices(const pxt_vertices* v, uint32_t E, std::string& why) {
@@ -543,8 +557,12 @@ int validate_call(const pxt_config& cfg, const pxt_hits* in, const pxt_tracks* o
   return 0;
 }
 
-CallDesc make_desc(const pxt_hits* in, const pxt_tracks* out) {
+CallDesc make_desc(const pxt_hits* in, const pxt_tracks* out, const DevCfg& d) {
   CallDesc desc{};
+  uint32_t largest = 0;
+  for (uint32_t e = 0; e < in->n_events; ++e)
+    largest = std::max(largest, in->event_offsets[e + 1] - in->event_offsets[e]);
+  desc.bin_lds = d.bin_lds && (in->n_events >= kBinLdsEvents || largest <= kBinLdsHits);
   desc.n_events = in->n_events;
   desc.n_hits = in->event_offsets[in->n_events];
   desc.x = in->x;
@@ -773,8 +791,10 @@ void pxt_destroy(pxt_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (int i = 0; i < pxt_ctx::kSlots; ++i) {
-    if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
-    if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+    for (int v = 0; v < 2; ++v) {
+      if (c->gexec[i][v]) (void)hipGraphExecDestroy(c->gexec[i][v]);
+      if (c->graph[i][v]) (void)hipGraphDestroy(c->graph[i][v]);
+    }
     if (c->slot_free[i]) (void)hipEventDestroy(c->slot_free[i]);
   }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -800,7 +820,7 @@ int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* strea
   c->next_slot = (slot + 1) % pxt_ctx::kSlots;
   if (c->slot_pending[slot]) HIP_OR_FAIL(c, hipEventSynchronize(c->slot_free[slot]));
   char* hs = c->h_slots + (size_t)slot * c->slot_bytes;
-  const CallDesc desc = make_desc(in, out);
+  const CallDesc desc = make_desc(in, out, c->dc);
   std::memcpy(hs, &desc, sizeof(desc));
   std::memcpy(hs + desc_bytes(), in->event_offsets, sizeof(uint32_t) * (E + 1));
 
@@ -811,17 +831,18 @@ int pxt_reconstruct(pxt_ctx* c, const pxt_hits* in, pxt_tracks* out, void* strea
   }
   c->calls++;
   if (cfg.use_graph) {
-    if (!c->gexec[slot]) {
+    const int v = desc.bin_lds ? 1 : 0;
+    if (!c->gexec[slot][v]) {
       HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
       enqueue(c, c->cap_stream, slot, true, 0, 0);
       hipGraph_t g = nullptr;
       const hipError_t e1 = hipStreamEndCapture(c->cap_stream, &g);
       if (e1 != hipSuccess || !g)
         return fail(c, PXT_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e1));
-      c->graph[slot] = g;
-      HIP_OR_FAIL(c, hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0));
+      c->graph[slot][v] = g;
+      HIP_OR_FAIL(c, hipGraphInstantiate(&c->gexec[slot][v], g, nullptr, nullptr, 0));
     }
-    HIP_OR_FAIL(c, hipGraphLaunch(c->gexec[slot], s));
+    HIP_OR_FAIL(c, hipGraphLaunch(c->gexec[slot][v], s));
     c->timed_valid = false;
   } else {
     enqueue(c, s, slot, false, H, E);
@@ -1007,11 +1028,12 @@ int pxt_reconstruct_static(const pxt_config* cfg, int hip_device, const pxt_hits
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(ntiles, 256, 1024)), dim3(256), 0, s,
                      w.scan_status, ntiles, 0ull);
   StaticCall sc{};
-  sc.desc = make_desc(in, out);
+  sc.desc = make_desc(in, out, dc);
   std::memcpy(sc.offsets, in->event_offsets, sizeof(uint32_t) * (E + 1));
   hipLaunchKernelGGL(k_set_call, dim3(1), dim3(64), 0, s, const_cast<CallDesc*>(w.call),
                      w.evt_off, sc, E + 1, w.epoch);
-  enqueue_path(nullptr, *cfg, w, dc, sd.n_cu, s, false, in->event_offsets[E], E);
+  enqueue_path(nullptr, *cfg, w, dc, sd.n_cu, s, false, in->event_offsets[E], E,
+               sc.desc.bin_lds != 0);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return fail(nullptr, PXT_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));

@@ -204,7 +204,10 @@ class _Ev:
         self.layer = np.asarray(layer, np.int16)
 
 
-def test_edge_cases(torch):
+# 256 phi bins: binning by one block per event; 4096: the histogram of an
+# event exceeds LDS and the binning takes the global-atomic kernels
+@pytest.mark.parametrize("phi_bins", [256, 4096])
+def test_edge_cases(torch, phi_bins):
     tiny = eventgen.generate("tiny", 1)
     empty = _Ev([], [], [], [])
     one_layer = _Ev(tiny.x[tiny.layer == 0], tiny.y[tiny.layer == 0], tiny.z[tiny.layer == 0],
@@ -215,7 +218,7 @@ def test_edge_cases(torch):
     dup = _Ev(np.concatenate([tiny.x, tiny.x[:10]]), np.concatenate([tiny.y, tiny.y[:10]]),
               np.concatenate([tiny.z, tiny.z[:10]]), np.concatenate([tiny.layer, tiny.layer[:10]]))
     events = [empty, tiny, one_layer, empty, bad_layers, dup, empty]
-    rec = make_rec()
+    rec = make_rec(phi_bins=phi_bins)
     res, out, dumps = run_and_dump(rec, events)
     check_events(events, res, out, dumps)
     # an empty batch
@@ -339,6 +342,13 @@ def test_graph_replays_match_direct(torch):
     # eager work and synchronisations sit between the replays
     batches = [eventgen.make_batch("batch", n, seed=20 + n) for n in (3, 1, 5, 2, 4, 1, 3)]
     batches.append([eventgen.generate("tiny", 4)])
+    # the binning of each call by one block per event (eight events or
+    # more, or only small ones) or by the global kernels (a few large
+    # events), in turn on the same context (a graph per slot and kernel set)
+    batches += [eventgen.make_batch("batch", 9, seed=40), [eventgen.generate("pu200", 41)],
+                [eventgen.generate("pu50", 42 + s) for s in range(2)],
+                [eventgen.generate("pu200", 43), eventgen.generate("tiny", 44)],
+                eventgen.make_batch("batch", 8, seed=45)]
     direct = make_rec()
     graph = make_rec(use_graph=1)
     for i, evs in enumerate(batches):
