@@ -1510,6 +1510,12 @@ __device__ __forceinline__ uint64_t order_key(int n, double s, uint32_t epoch) {
   return (tag << 56) | ((uint64_t)(kMaxHits - n) << 52) | (m >> 11);
 }
 
+// Best slot of a doublet on which two tuples of the call tied for the key
+// (no tuple index: tuples are below the capacity, under 2^32 - 1).
+__device__ __forceinline__ uint64_t tie_mark(uint32_t epoch) {
+  return ((uint64_t)epoch << 32) | 0xffffffffull;
+}
+
 // The eight slots of an n-tuplet row (rows are 32 bytes, 32-byte aligned)
 // as two 16-byte loads, and a slot picked by a run-time index without
 // spilling the row to scratch.
@@ -1555,9 +1561,15 @@ __global__ __launch_bounds__(256) void k_score(Ws w, DevCfg c) {
     }
     w.tscore[t] = s;
     const uint64_t key = order_key(n, s, epoch);
+    // a tuple that finds its own key already there ties with another one:
+    // the doublet's best slot is marked, so that k_best settles it by
+    // compare-and-swap (a tie at the minimum is always seen this way: the
+    // second of two equal keys finds the first one still in place)
 #pragma unroll
     for (int j = 0; j < kMaxCells; ++j)
-      if (j + 1 < n) atomicMin((unsigned long long*)&w.bkey[tc[j]], (unsigned long long)key);
+      if (j + 1 < n &&
+          atomicMin((unsigned long long*)&w.bkey[tc[j]], (unsigned long long)key) == key)
+        w.best[tc[j]] = tie_mark(epoch);
   }
 }
 
@@ -1594,9 +1606,17 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
       if (j + 1 >= n) continue;
       const uint32_t d = tc[j];
       if (w.bkey[d] != key) continue;
-      // a slot holding another call's tag holds no tuple of this call
       unsigned long long cur = w.best[d];
-      while ((cur >> 32) != epoch || ranks_before(w, T, t, (uint32_t)cur)) {
+      // a slot untouched by this call (another call's tag): no tie was
+      // marked, so this tuple alone holds the doublet's minimum key
+      if ((cur >> 32) != epoch) {
+        w.best[d] = tag | t;
+        continue;
+      }
+      // a tie (the slot holds the mark, or a tied tuple put there by the
+      // loop): the exact order decides; the mark holds no tuple
+      while (cur == tie_mark(epoch) || (cur >> 32) != epoch ||
+             ranks_before(w, T, t, (uint32_t)cur)) {
         const unsigned long long prev =
             atomicCAS((unsigned long long*)&w.best[d], cur, (unsigned long long)(tag | t));
         if (prev == cur) break;
