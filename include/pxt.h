@@ -184,7 +184,8 @@ typedef struct pxt_counts {
  * direction of motion.  cov = packed lower triangle of the 5x5 covariance
  * (row-major: (0,0),(1,0),(1,1),(2,0),...).  chi2 = (transverse, long.).
  * flags: PXT_FLAG_* bits.  per_event_tracks[e] receives the number of
- * tracks of event e.  counts receives the summary. */
+ * tracks of event e (zero for every event when the call fails).  counts
+ * receives the summary. */
 /* Vertices of a call's tracks (the Vertices module that follows the Tracks
  * module in the paper's chain, Sec. 2 and Fig. 1; the paper gives no
  * algorithm).  Reading: one-dimensional density-based clustering (DBSCAN)

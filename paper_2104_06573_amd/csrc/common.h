@@ -23,7 +23,7 @@ constexpr int kWave = 64;
 constexpr float kPiF = 3.14159265358979f;
 constexpr int kQueue = 128;                    // LDS queue entries per wavefront
 constexpr uint32_t kSmallFit = 8192;           // calls with at most this many tracks: one fit launch
-constexpr uint32_t kCompactBlocksMax = 4096;   // grid cap of k_compact and the doublet stage
+constexpr uint32_t kCompactBlocksMax = 4096;   // grid cap of the doublet stage
 
 // Counters kept in device memory for one call (zeroed by k_clear).
 enum Ctr : int {
@@ -117,8 +117,7 @@ struct Ws {
   // cleaning
   uint64_t* bkey;         // [D] smallest order key of the tuples through it (call-tagged)
   uint64_t* best;         // [D] best tuple through each doublet: call epoch << 32 | tuple
-  uint32_t* talive;       // [T + 1] survives the cleaning
-  uint32_t* toff;         // [T + 1]
+  uint32_t* evt_surv;     // [E + 1] first survivor of each event
   uint32_t* surv;         // [T]
   uint32_t* sfit;         // [3][T] survivor indices per length class (the fitting order)
   uint32_t* fp64_list;    // [T]

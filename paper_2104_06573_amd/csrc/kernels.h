@@ -1626,116 +1626,108 @@ __global__ __launch_bounds__(256) void k_best(Ws w, DevCfg c) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_alive(Ws w, DevCfg c) {
-  if (w.ctr[C_STATUS]) return;
-  const uint32_t ntup = w.ctr[C_NTUP];
-  const uint64_t tag = (uint64_t)w.epoch[0] << 32;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntup; t += gridDim.x * blockDim.x) {
-    const int n = w.tn[t];
-    // shorter n-tuplets than min_hits are not output (they never outrank a
-    // longer one, so the others' fate does not depend on them)
-    uint32_t alive = n >= c.min_hits ? 1u : 0u;
-    uint32_t tc[kMaxHits];
-    load_row(w.tcell, t, tc);
-#pragma unroll
-    for (int j = 0; j < kMaxCells; ++j)
-      if (j + 1 < n && w.best[tc[j]] != (tag | t)) alive = 0;
-    w.talive[t] = alive;
-  }
-}
-
-// Survivors in n-tuplet order (offsets from the scan of the alive flags);
-// per-event track counts from the event boundaries, which the binned hits,
-// doublets, n-tuplets and survivors all respect in that order.
+// Survivors of the cleaning, in n-tuplet order, in one pass: a 1024-tuple
+// tile per block (tiles taken by ticket), a tuple surviving when it is the
+// elected best of every one of its doublets (and long enough for output);
+// the block scans its survivor flags and takes its tile's offset by
+// decoupled look-back, like the scans.  Each survivor's index goes to the
+// survivor list.
 //
 // Also the fitting order.  The fit is compiled once per tuple length class
 // (3 hits, 4 hits, 5 to 8 hits), and one kernel per class keeps each body's
 // register budget its own and its wavefronts uniform; for that each class
-// gets a list of its survivors (region c of sfit, c = class).  A block owns
-// a contiguous chunk of the tuples: it counts the chunk's survivors per
-// class, takes a range of each class's list with one atomic per class, and
-// walks the chunk again writing its survivors there (ballot ranks within a
-// wavefront, the wavefronts' counts in LDS).  The order within a list
-// depends on the order the blocks take their ranges; every result still goes
-// to its survivor's slot, so only the work assignment changes.
+// gets a list of its survivors (region c of sfit, c = class): the block
+// takes a range of each class's list with one atomic per class and writes
+// its survivors there (ballot ranks within a wavefront, the wavefronts'
+// counts in LDS).  The order within a list depends on the order the blocks
+// take their ranges; every result still goes to its survivor's slot, so
+// only the work assignment changes.
+//
+// And the first survivor of each event: n-tuplets follow the events in
+// order (as the binned hits, doublets and roots do), so a tuple whose event
+// differs from its predecessor's records its survivor offset for the events
+// from the predecessor's (exclusive) to its own; k_finish turns these into
+// per-event track counts.
+constexpr int kSurvThreads = 1024;
+constexpr uint32_t kSurvScan = 5;  // scan id of the survivor offsets
+
 __device__ __forceinline__ uint32_t fit_class(uint32_t n) { return n >= 5u ? 2u : n - 3u; }
 
-__global__ __launch_bounds__(256) void k_compact(Ws w, DevCfg c) {
-  constexpr uint32_t NW = 256 / kWave;
+__device__ __forceinline__ uint32_t tuple_event(const Ws& w, uint32_t t) {
+  return w.bevt[w.thit[(size_t)t * kMaxHits]];
+}
+
+__global__ __launch_bounds__(kSurvThreads) void k_survive(Ws w, DevCfg c) {
+  constexpr uint32_t NW = kSurvThreads / kWave;
+  __shared__ uint32_t s_lds[NW + 1];
   __shared__ uint32_t s_cnt[NW][3];  // per wavefront and class
-  __shared__ uint32_t s_run[3];      // the block's next place per class
-  if (w.ctr[C_STATUS]) return;
-  const uint32_t n_events = w.call->n_events;
-  uint32_t* per_event_tracks = w.call->out.per_event_tracks;
-  const uint32_t ntup = w.ctr[C_NTUP];
+  __shared__ uint32_t s_base[3];     // the block's range of each class list
+  __shared__ uint32_t s_prefix;
+  uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t ntup = ctr[C_NTUP];
+  const uint32_t E = w.call->n_events;
+  const uint32_t ntiles = ntup ? (ntup + kSurvThreads - 1u) / kSurvThreads : 1u;
+  uint32_t tile;
+  if (!take_tile(w, kSurvScan, ntiles, tile)) return;
   const uint32_t T = c.cap_tuples;
   const uint32_t lane = lane_id(), wib = threadIdx.x / kWave;
-  const uint64_t below = (1ull << lane) - 1ull;
-  // the block's chunk: whole 256-tuple rounds, every thread of the block
-  // runs the same number of rounds (barriers)
-  const uint32_t rounds = (ntup + 255u) / 256u;
-  const uint32_t per = (rounds + gridDim.x - 1u) / gridDim.x;
-  const uint32_t t_begin = min(ntup, blockIdx.x * per * 256u);
-  const uint32_t t_end = min(ntup, (blockIdx.x + 1u) * per * 256u);
-  // pass 1: the chunk's survivors per class
-  uint32_t cnt[3] = {0u, 0u, 0u};
-  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 256u) {
-    const uint32_t t = t0 + threadIdx.x;
-    const bool alive = t < t_end && w.talive[t];
-    const uint32_t cls = alive ? fit_class(w.tn[t]) : 3u;
+  const uint64_t tag = (uint64_t)w.epoch[0] << 32;
+  const uint32_t t = tile * kSurvThreads + threadIdx.x;
+  bool alive = false;
+  uint32_t n = 0;
+  if (t < ntup) {
+    n = w.tn[t];
+    // shorter n-tuplets than min_hits are not output (they never outrank a
+    // longer one, so the others' fate does not depend on them)
+    alive = n >= (uint32_t)c.min_hits;
+    uint32_t tc[kMaxHits];
+    load_row(w.tcell, t, tc);
 #pragma unroll
-    for (uint32_t k = 0; k < 3; ++k) cnt[k] += (uint32_t)__popcll(__ballot(cls == k));
+    for (int j = 0; j < kMaxCells; ++j)
+      if (j + 1 < (int)n && w.best[tc[j]] != (tag | t)) alive = false;
   }
-  if (lane == 0)
-    for (uint32_t k = 0; k < 3; ++k) s_cnt[wib][k] = cnt[k];
+  uint32_t agg;
+  const uint32_t excl = block_excl_scan(alive ? 1u : 0u, s_lds, agg);
+  if (threadIdx.x < kWave) {
+    const uint32_t pf = tile_lookback(w, tile, w.epoch[0] * 8u + kSurvScan, agg);
+    if (threadIdx.x == 0) s_prefix = pf;
+  }
+  const uint32_t cls = alive ? fit_class(n) : 3u;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t rank = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 3; ++k) {
+    const uint64_t m = __ballot(cls == k);
+    if (cls == k) rank = (uint32_t)__popcll(m & below);
+    if (lane == 0) s_cnt[wib][k] = (uint32_t)__popcll(m);
+  }
   __syncthreads();
   if (threadIdx.x < 3) {
     const uint32_t k = threadIdx.x;
     uint32_t tot = 0;
     for (uint32_t i = 0; i < NW; ++i) tot += s_cnt[i][k];
-    s_run[k] = tot ? atomicAdd(&w.ctr[C_FITN0 + 3 + k], tot) : 0u;
+    s_base[k] = tot ? atomicAdd(&ctr[C_FITN0 + 3 + k], tot) : 0u;
   }
   __syncthreads();
-  // pass 2: survivors, and their places in the class lists
-  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 256u) {
-    const uint32_t t = t0 + threadIdx.x;
-    const bool alive = t < t_end && w.talive[t];
-    uint32_t s = 0, cls = 3, rank = 0;
-    if (alive) {
-      s = w.toff[t];
-      w.surv[s] = t;
-      cls = fit_class(w.tn[t]);
-    }
-#pragma unroll
-    for (uint32_t k = 0; k < 3; ++k) {
-      const uint64_t m = __ballot(cls == k);
-      if (cls == k) rank = (uint32_t)__popcll(m & below);
-      if (lane == 0) s_cnt[wib][k] = (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    uint32_t base = 0;
-    if (alive) {
-      base = s_run[cls];
-      for (uint32_t i = 0; i < wib; ++i) base += s_cnt[i][cls];
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      uint32_t add = 0;
-      for (uint32_t i = 0; i < NW; ++i) add += s_cnt[i][threadIdx.x];
-      s_run[threadIdx.x] += add;
-    }
-    if (alive) w.sfit[(size_t)cls * T + base + rank] = s;
-    __syncthreads();
+  const uint32_t s = s_prefix + excl;  // survivors before tuple t
+  if (alive) {
+    uint32_t base = s_base[cls];
+    for (uint32_t i = 0; i < wib; ++i) base += s_cnt[i][cls];
+    w.surv[s] = t;
+    w.sfit[(size_t)cls * T + base + rank] = s;
   }
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t per_ev = (uint32_t)c.n_layers * (uint32_t)c.nphi;
-  const uint32_t nr = w.ctr[C_NROOT];
-  for (uint32_t e = tid; e < n_events; e += gridDim.x * blockDim.x) {
-    // first root doublet at or after the event's first doublet
-    const uint32_t ra = lower_bound_u32(w.roots, nr, w.cell_off[w.bin_off[e * per_ev]]);
-    const uint32_t rb = lower_bound_u32(w.roots, nr, w.cell_off[w.bin_off[(e + 1) * per_ev]]);
-    per_event_tracks[e] = w.toff[w.roff[rb]] - w.toff[w.roff[ra]];
+  // first survivor of each event
+  if (t < ntup) {
+    const uint32_t ev = tuple_event(w, t);
+    const uint32_t from = t == 0 ? 0u : tuple_event(w, t - 1u) + 1u;
+    for (uint32_t e = from; e <= ev; ++e) w.evt_surv[e] = s;
+    if (t == ntup - 1u)
+      for (uint32_t e = ev + 1u; e <= E; ++e) w.evt_surv[e] = s + (alive ? 1u : 0u);
+  } else if (ntup == 0 && threadIdx.x == 0) {
+    for (uint32_t e = 0; e <= E; ++e) w.evt_surv[e] = 0u;
   }
+  if (tile == ntiles - 1u && threadIdx.x == 0) ctr[C_NSURV] = s_prefix + agg;
 }
 
 // ------------------------------------------------------------------ fit --
@@ -1873,10 +1865,16 @@ __global__ __launch_bounds__(64) void k_fit64(Ws w, DevCfg c) {
 // --------------------------------------------------------------- finish --
 
 __global__ void k_finish(Ws w) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const uint32_t* ctr = w.ctr;
-  pxt_counts* k = w.call->out.counts;
   const int st = (int)ctr[C_STATUS];
+  // per-event track counts from the events' first survivors (left at zero
+  // when the call failed)
+  const CallDesc* cd = w.call;
+  if (st == 0 && ctr[C_NTUP] > 0)
+    for (uint32_t e = threadIdx.x; e < cd->n_events; e += blockDim.x)
+      cd->out.per_event_tracks[e] = w.evt_surv[e + 1] - w.evt_surv[e];
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  pxt_counts* k = cd->out.counts;
   k->status = st;
   k->n_tracks = st ? 0u : ctr[C_NSURV];
   k->n_doublets = ctr[C_ND];

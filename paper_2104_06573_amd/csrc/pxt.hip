@@ -144,8 +144,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.tcell = cv.take<uint32_t>(8 * T);
   w.tn = cv.take<uint8_t>(T);
   w.tscore = cv.take<double>(T);
-  w.talive = cv.take<uint32_t>(T + 1);
-  w.toff = cv.take<uint32_t>(T + 1);
+  w.evt_surv = cv.take<uint32_t>(E + 1);
   w.surv = cv.take<uint32_t>(T);
   w.sfit = cv.take<uint32_t>(3 * T);
   w.fp64_list = cv.take<uint32_t>(T);
@@ -477,14 +476,11 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
     hipLaunchKernelGGL(k_best, dim3(std::min(gt, resident_grid((const void*)k_best, bs, n_cu))),
                        dim3(bs), 0, s, w, d);
     if (timed) sm.mark(15);
-    hipLaunchKernelGGL(k_alive, dim3(std::min(gt, resident_grid((const void*)k_alive, bs, n_cu))),
-                       dim3(bs), 0, s, w, d);
-    launch_scan1(w, w.talive, w.toff, w.ctr + C_NTUP, w.ctr + C_NSURV, cfg.max_tuples, 5, s);
-    // survivors and the fitting order (one list per length class)
-    hipLaunchKernelGGL(k_compact,
-                       dim3(std::min<uint32_t>(grid_for(cfg.max_tuples, 256, persist),
-                                               kCompactBlocksMax)),
-                       dim3(256), 0, s, w, d);
+    // survivors, the fitting order (one list per length class) and each
+    // event's first survivor
+    hipLaunchKernelGGL(k_survive,
+                       dim3((uint32_t)(((uint64_t)cfg.max_tuples + kSurvThreads - 1) / kSurvThreads)),
+                       dim3(kSurvThreads), 0, s, w, d);
     if (timed) sm.mark(16);
     {
       // fits of 3 and of 4 hits, then the rarer longer ones together (one
