@@ -6,11 +6,15 @@
 // overlap with the others on the device.  A dispatcher thread owns every
 // HIP call and every lane: it admits pending events into a batch whenever a
 // lane is free (first come, first served, while the batch fits the lane's
-// capacities), and advances each busy lane through two phases --
+// capacities), and advances each batch through two phases --
 // reconstruction with the copy-back of the counts, then the copy-back of
-// exactly the tracks found.  The server lock guards only the queue, the
-// tickets and the counters: staging, HIP calls and result hand-over run
-// outside it.
+// exactly the tracks found.  A lane holds up to two batches: once one
+// batch's track copy-back is queued, the next batch is staged and launched
+// behind it on the same stream, so the lane's device work does not wait for
+// the copy-back to be seen done (stream order keeps the shared device
+// buffers safe: the next batch's copy-in and kernels run after the copy-back
+// has read them).  The server lock guards only the queue, the tickets and
+// the counters: staging, HIP calls and result hand-over run outside it.
 //
 // Results are not copied on the host by the server: each lane has two
 // pinned result sets, a finished batch's events point into the set its
@@ -82,10 +86,18 @@ bool host_alloc(T** p, size_t n) {
          hipSuccess;
 }
 
+// One batch on a lane.
+struct Flight {
+  std::vector<ReqPtr> batch;
+  int phase = 0;             // 0 none, 1 reconstruction in flight, 2 track copy-back in flight
+  int set = 0;               // the result set its tracks go to
+  hipEvent_t ev = nullptr;   // end of its current phase on the lane's stream
+  std::vector<uint32_t> per_event;  // track counts, read when the reconstruction ends
+};
+
 struct Lane {
   pxt_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t ev = nullptr;
   uint32_t max_hits = 0, max_events = 0, max_tracks = 0;
   // device buffers
   float *dx = nullptr, *dy = nullptr, *dz = nullptr;
@@ -100,19 +112,28 @@ struct Lane {
   pxt_counts* h_counts = nullptr;
   uint32_t* h_per_event = nullptr;
   ResultSet res[2];
-  // state (dispatcher thread only)
-  int phase = 0;  // 0 idle, 1 reconstruction in flight, 2 track copy-back in flight
-  int cur = 0;    // result set of the batch in flight
-  std::vector<ReqPtr> batch;
+  // state (dispatcher thread only): up to two batches, fl[head] the older
+  Flight fl[2];
+  int head = 0, nfl = 0;
   std::vector<uint32_t> offsets;
+
+  Flight& oldest() { return fl[head]; }
+  Flight& next_free() { return fl[(head + nfl) & 1]; }
+  void pop_oldest() {
+    head = (head + 1) & 1;
+    --nfl;
+  }
+  // a new batch may start: the lane is idle, or its one batch is in copy-back
+  bool can_start() const { return nfl == 0 || (nfl == 1 && fl[head].phase == 2); }
 
   bool init(const pxt_config& cfg, int dev) {
     max_hits = cfg.max_hits;
     max_events = cfg.max_events;
     max_tracks = cfg.max_tuples;
     if (pxt_create(&cfg, dev, &ctx) != PXT_OK) return false;
-    bool ok = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+    for (auto& f : fl)
+      ok = ok && hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) == hipSuccess;
     ok = ok && dev_alloc(&dx, max_hits) && dev_alloc(&dy, max_hits) && dev_alloc(&dz, max_hits) &&
          dev_alloc(&dl, max_hits);
     ok = ok && dev_alloc(&d_hit_idx, 8ull * max_tracks) && dev_alloc(&d_evt, max_tracks) &&
@@ -130,10 +151,13 @@ struct Lane {
     return ok;
   }
 
-  // a result set nobody reads any more, or -1
+  // a result set nobody reads any more and no batch in flight writes, or -1
   int free_set() const {
-    for (int i = 0; i < 2; ++i)
-      if (res[i].refs.load(std::memory_order_acquire) == 0) return i;
+    for (int i = 0; i < 2; ++i) {
+      bool used = false;
+      for (int k = 0; k < nfl; ++k) used |= fl[(head + k) & 1].set == i;
+      if (!used && res[i].refs.load(std::memory_order_acquire) == 0) return i;
+    }
     return -1;
   }
 
@@ -150,7 +174,8 @@ struct Lane {
       for (void* p : {(void*)r.hit_idx, (void*)r.nh, (void*)r.flags, (void*)r.params,
                       (void*)r.cov, (void*)r.chi2})
         if (p) (void)hipHostFree(p);
-    if (ev) (void)hipEventDestroy(ev);
+    for (auto& f : fl)
+      if (f.ev) (void)hipEventDestroy(f.ev);
     if (stream) (void)hipStreamDestroy(stream);
     if (ctx) pxt_destroy(ctx);
   }
@@ -174,42 +199,44 @@ struct pxt_server {
   std::thread worker;
 
   void run();
-  void take_batch(Lane& L);        // lock held
-  void start_batch(Lane& L);       // lock not held
-  void advance(Lane& L);           // lock not held
-  void finish(Lane& L, int status);  // lock not held
+  void take_batch(Lane& L, Flight& F);            // lock held
+  void start_batch(Lane& L, Flight& F);           // lock not held
+  bool advance(Lane& L);                          // lock not held
+  void finish(Lane& L, Flight& F, int status);    // lock not held
   int submit(const float* x, const float* y, const float* z, const int16_t* layer,
              uint32_t n_hits, Clock::time_point arrival, uint64_t* ticket);
   int poll(uint64_t ticket, pxt_event_tracks* out, int timeout_ms, bool release_only);
 };
 
-// Move pending events into lane L's batch (first come, first served, while
-// the batch fits the lane); the server lock is held.
-void pxt_server::take_batch(Lane& L) {
-  L.batch.clear();
+// Move pending events into a new batch F of lane L (first come, first
+// served, while the batch fits the lane); the server lock is held.
+void pxt_server::take_batch(Lane& L, Flight& F) {
+  std::vector<ReqPtr>& batch = F.batch;
+  batch.clear();
   uint64_t hits = 0, est_d = 0;
   const uint32_t max_ev = std::min(scfg.max_batch_events, L.max_events);
-  while (!pending.empty() && L.batch.size() < max_ev) {
+  while (!pending.empty() && batch.size() < max_ev) {
     const ReqPtr& r = pending.front();
     const uint64_t h = r->x.size();
     const uint64_t d = h * scfg.doublets_per_hit;
-    if (!L.batch.empty() && (r->solo || L.batch.front()->solo)) break;
-    if (!L.batch.empty() && (hits + h > L.max_hits || est_d + d > cfg.max_doublets)) break;
+    if (!batch.empty() && (r->solo || batch.front()->solo)) break;
+    if (!batch.empty() && (hits + h > L.max_hits || est_d + d > cfg.max_doublets)) break;
     hits += h;
     est_d += d;
-    L.batch.push_back(r);
+    batch.push_back(r);
     pending.pop_front();
   }
   stats.batches++;
-  stats.events_in_batches += L.batch.size();
+  stats.events_in_batches += batch.size();
 }
 
-// Stage the batch's hits and launch it on the lane's stream.
-void pxt_server::start_batch(Lane& L) {
+// Stage batch F's hits and launch it on the lane's stream (behind the
+// copy-back of the lane's other batch, if any).
+void pxt_server::start_batch(Lane& L, Flight& F) {
   const auto now = Clock::now();
   L.offsets.assign(1, 0u);
   uint32_t off = 0;
-  for (auto& r : L.batch) {
+  for (auto& r : F.batch) {
     r->t_start = now;
     const uint32_t n = (uint32_t)r->x.size();
     std::memcpy(L.hx + off, r->x.data(), 4ull * n);
@@ -227,36 +254,43 @@ void pxt_server::start_batch(Lane& L) {
          hipMemcpyAsync(L.dz, L.hz, 4 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
          hipMemcpyAsync(L.dl, L.hl, 2 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess;
   }
-  pxt_hits in{(uint32_t)L.batch.size(), L.offsets.data(), L.dx, L.dy, L.dz, L.dl, nullptr};
+  pxt_hits in{(uint32_t)F.batch.size(), L.offsets.data(), L.dx, L.dy, L.dz, L.dl, nullptr};
   pxt_tracks out{L.max_tracks, L.d_hit_idx, L.d_nh, L.d_evt, L.d_params, L.d_cov,
                  L.d_chi2, L.d_flags, L.d_per_event, L.d_counts, nullptr};
   ok = ok && pxt_reconstruct(L.ctx, &in, &out, L.stream) == PXT_OK;
   ok = ok && hipMemcpyAsync(L.h_counts, L.d_counts, sizeof(pxt_counts), hipMemcpyDeviceToHost,
                             L.stream) == hipSuccess;
-  ok = ok && hipMemcpyAsync(L.h_per_event, L.d_per_event, 4ull * L.batch.size(),
+  ok = ok && hipMemcpyAsync(L.h_per_event, L.d_per_event, 4ull * F.batch.size(),
                             hipMemcpyDeviceToHost, L.stream) == hipSuccess;
-  ok = ok && hipEventRecord(L.ev, L.stream) == hipSuccess;
+  ok = ok && hipEventRecord(F.ev, L.stream) == hipSuccess;
   const auto t = Clock::now();
-  for (auto& r : L.batch) r->t_launch = t;
-  L.phase = 1;
-  if (!ok) finish(L, PXT_ERR_HIP);
+  for (auto& r : F.batch) r->t_launch = t;
+  F.phase = 1;
+  ++L.nfl;
+  if (!ok) {
+    // a failed launch leaves the stream's earlier work in place: wait for
+    // it, so that the lane's batches still end in order
+    (void)hipStreamSynchronize(L.stream);
+    finish(L, F, PXT_ERR_HIP);
+    --L.nfl;
+  }
 }
 
-// Hand the batch's events over: status, track counts and where their tracks
-// are (status PXT_OK); then the pollers are woken.
-void pxt_server::finish(Lane& L, int status) {
+// Hand batch F's events over: status, track counts and where their tracks
+// are (status PXT_OK); then the pollers are woken.  F leaves the lane.
+void pxt_server::finish(Lane& L, Flight& F, int status) {
   const auto now = Clock::now();
-  const uint32_t nb = (uint32_t)L.batch.size();
-  ResultSet* rs = &L.res[L.cur];
+  const uint32_t nb = (uint32_t)F.batch.size();
+  ResultSet* rs = &L.res[F.set];
   if (status == PXT_OK) rs->refs.store(nb, std::memory_order_release);
   uint32_t base = 0;
   for (uint32_t e = 0; e < nb; ++e) {
-    Request& r = *L.batch[e];
+    Request& r = *F.batch[e];
     r.status = status;
     r.batch_events = nb;
     r.t_ready = now;
     if (status == PXT_OK) {
-      r.n_tracks = L.h_per_event[e];
+      r.n_tracks = F.per_event[e];
       r.rs = rs;
       r.base = base;
       base += r.n_tracks;
@@ -267,7 +301,7 @@ void pxt_server::finish(Lane& L, int status) {
   }
   {
     std::lock_guard<std::mutex> g(mu);
-    for (auto& rp : L.batch) {
+    for (auto& rp : F.batch) {
       Request& r = *rp;
       r.done = true;
       stats.completed++;
@@ -278,45 +312,58 @@ void pxt_server::finish(Lane& L, int status) {
       stats.sum_copyback_us += us_between(r.t_device, r.t_ready);
     }
   }
-  L.batch.clear();
-  L.phase = 0;
+  F.batch.clear();
+  F.phase = 0;
   cv_done.notify_all();
 }
 
-// Move lane L on if its device work has finished.
-void pxt_server::advance(Lane& L) {
-  if (L.phase == 0) return;
-  const hipError_t q = hipEventQuery(L.ev);
-  if (q == hipErrorNotReady) return;
-  if (q != hipSuccess) {
-    finish(L, PXT_ERR_HIP);
-    return;
-  }
-  if (L.phase == 1) {
+// Move lane L's batches on as their device work finishes (in stream order:
+// the older batch first); true if anything moved.
+bool pxt_server::advance(Lane& L) {
+  bool moved = false;
+  while (L.nfl > 0) {
+    Flight& F = L.oldest();
+    const hipError_t q = hipEventQuery(F.ev);
+    if (q == hipErrorNotReady) return moved;
+    moved = true;
+    if (q != hipSuccess) {
+      finish(L, F, PXT_ERR_HIP);
+      L.pop_oldest();
+      continue;
+    }
+    if (F.phase == 2) {
+      finish(L, F, PXT_OK);
+      L.pop_oldest();
+      continue;
+    }
+    // the reconstruction has ended (no batch runs behind it yet)
     const auto now = Clock::now();
-    for (auto& r : L.batch) r->t_device = now;
+    for (auto& r : F.batch) r->t_device = now;
     const int st = L.h_counts->status;
     if (st != PXT_OK) {
-      if (L.batch.size() > 1) {
+      if (F.batch.size() > 1) {
         // re-run each event alone, ahead of the queue, in order
         {
           std::lock_guard<std::mutex> g(mu);
-          for (auto it = L.batch.rbegin(); it != L.batch.rend(); ++it) {
+          for (auto it = F.batch.rbegin(); it != F.batch.rend(); ++it) {
             (*it)->solo = true;
             (*it)->t_device = Clock::time_point{};
             pending.push_front(*it);
           }
-          stats.solo_retries += L.batch.size();
+          stats.solo_retries += F.batch.size();
         }
-        L.batch.clear();
-        L.phase = 0;
+        F.batch.clear();
+        F.phase = 0;
       } else {
-        finish(L, st);
+        finish(L, F, st);
       }
-      return;
+      L.pop_oldest();
+      return moved;
     }
+    // the counts now, before a next batch's copy-back overwrites them
+    F.per_event.assign(L.h_per_event, L.h_per_event + F.batch.size());
     const size_t n = L.h_counts->n_tracks;
-    ResultSet& R = L.res[L.cur];
+    ResultSet& R = L.res[F.set];
     bool ok = true;
     if (n) {
       ok = hipMemcpyAsync(R.hit_idx, L.d_hit_idx, 32 * n, hipMemcpyDeviceToHost, L.stream) ==
@@ -330,15 +377,17 @@ void pxt_server::advance(Lane& L) {
            hipMemcpyAsync(R.chi2, L.d_chi2, 8 * n, hipMemcpyDeviceToHost, L.stream) ==
                hipSuccess;
     }
-    ok = ok && hipEventRecord(L.ev, L.stream) == hipSuccess;
+    ok = ok && hipEventRecord(F.ev, L.stream) == hipSuccess;
     if (!ok) {
-      finish(L, PXT_ERR_HIP);
-      return;
+      (void)hipStreamSynchronize(L.stream);
+      finish(L, F, PXT_ERR_HIP);
+      L.pop_oldest();
+      return moved;
     }
-    L.phase = 2;
-    return;
+    F.phase = 2;
+    return moved;
   }
-  finish(L, PXT_OK);
+  return moved;
 }
 
 void pxt_server::run() {
@@ -347,22 +396,21 @@ void pxt_server::run() {
   for (;;) {
     bool progress = false, busy = false;
     for (auto& L : lanes) {
-      const int before = L.phase;
-      advance(L);
-      if (L.phase != before) progress = true;
-      if (L.phase != 0) continue;
+      if (advance(L)) progress = true;
+      if (!L.can_start()) continue;
       const int set = L.free_set();
       if (set < 0) continue;
+      Flight& F = L.next_free();
       {
         std::lock_guard<std::mutex> g(mu);
         if (pending.empty() || stop) continue;
-        take_batch(L);
+        take_batch(L, F);
       }
-      L.cur = set;
-      start_batch(L);
+      F.set = set;
+      start_batch(L, F);
       progress = true;
     }
-    for (auto& L : lanes) busy |= L.phase != 0;
+    for (auto& L : lanes) busy |= L.nfl != 0;
     std::unique_lock<std::mutex> lk(mu);
     if (stop) {
       // queued events are dropped; the batches on the lanes finish
