@@ -4,7 +4,7 @@
 // reading of the paper's Vertices module (Sec. 2, Fig. 1: vertices are
 // formed from the pixel tracks) stated with pxt_vertices in pxt.h.
 //
-// One workgroup of 1024 threads per event, everything in LDS (112 KB of
+// One workgroup of 1024 threads per event, everything in LDS (144 KB of
 // gfx950's 160 KB):
 //   select   tracks passing the selection append (z0, track) keys;
 //   sort     bitonic sort of the keys by (z0, track index), four keys per
@@ -172,6 +172,7 @@ __device__ __forceinline__ void vtx_rank_sort(uint64_t* s_key, uint32_t m) {
 __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c, uint32_t e) {
   __shared__ __align__(16) uint64_t s_key[kVtxMax];  // (z0 key, track << 12 | slot)
   __shared__ double s_w[kVtxMax];       // weight 1/var(z0) by selection slot
+  __shared__ double s_ws[kVtxMax];      // the same in sorted order
   __shared__ int32_t s_lab[kVtxMax];    // core flag, then cluster (-1: none)
   __shared__ uint32_t s_rank[kVtxMax];  // cores before each entry; then cluster ends
   __shared__ uint32_t s_core[kVtxMax];  // position of each core; then cluster starts
@@ -341,16 +342,18 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
     }
     return;
   }
-  // cluster ranges (contiguous): starts over s_core, ends over s_rank
+  // cluster ranges (contiguous): starts over s_core, ends over s_rank; and
+  // the weights in sorted order, so that the sums below stream them
   for (uint32_t i = tid; i < m; i += nthr) {
+    s_ws[i] = s_w[s_key[i] & 0xfffu];
     const int32_t lab = s_lab[i];
     if (lab < 0) continue;
     if (i == 0 || s_lab[i - 1] != lab) s_core[lab] = i;
     if (i + 1 == m || s_lab[i + 1] != lab) s_rank[lab] = i;
   }
   __syncthreads();
-  // (members read kVs at a time, so that their LDS loads overlap; the sums
-  // still run in sorted order)
+  // (members read kVs at a time, key and weight independently, so that
+  // their LDS loads overlap; the sums still run in sorted order)
   constexpr uint32_t kVs = 8;
   for (uint32_t v = tid; v < ncl; v += nthr) {
     const uint32_t a = s_core[v], b = s_rank[v] + 1;
@@ -359,9 +362,10 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
       uint64_t k[kVs];
       double w[kVs];
 #pragma unroll
-      for (uint32_t q = 0; q < kVs; ++q) k[q] = i0 + q < b ? s_key[i0 + q] : 0ull;
-#pragma unroll
-      for (uint32_t q = 0; q < kVs; ++q) w[q] = i0 + q < b ? s_w[k[q] & 0xfffu] : 0.0;
+      for (uint32_t q = 0; q < kVs; ++q) {
+        k[q] = i0 + q < b ? s_key[i0 + q] : 0ull;
+        w[q] = i0 + q < b ? s_ws[i0 + q] : 0.0;
+      }
 #pragma unroll
       for (uint32_t q = 0; q < kVs; ++q) {
         if (i0 + q < b) {
@@ -376,9 +380,10 @@ __device__ void vertices_event(const VtxIn& in, const VtxOut& o, const DevCfg& c
       uint64_t k[kVs];
       double w[kVs];
 #pragma unroll
-      for (uint32_t q = 0; q < kVs; ++q) k[q] = i0 + q < b ? s_key[i0 + q] : 0ull;
-#pragma unroll
-      for (uint32_t q = 0; q < kVs; ++q) w[q] = i0 + q < b ? s_w[k[q] & 0xfffu] : 0.0;
+      for (uint32_t q = 0; q < kVs; ++q) {
+        k[q] = i0 + q < b ? s_key[i0 + q] : 0ull;
+        w[q] = i0 + q < b ? s_ws[i0 + q] : 0.0;
+      }
 #pragma unroll
       for (uint32_t q = 0; q < kVs; ++q) {
         if (i0 + q < b) {
