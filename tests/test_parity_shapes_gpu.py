@@ -84,7 +84,10 @@ def test_pu50_batch64_graph_two_contexts(torch):
 
 
 def test_pu200_batch_graph(torch):
-    events = bench.gen_events("pu200", 4, 1000)
+    # eight events: the call bins by one block per event (as the benchmark's
+    # 32-event batches do), where a single PU~200 event takes the global
+    # kernels (test_pu200_event)
+    events = bench.gen_events("pu200", 8, 1000)
     oref = oracle_events(events, DET)
     rec = _rec("pu200", events)
     d = rec.upload(events)
@@ -92,7 +95,7 @@ def test_pu200_batch_graph(torch):
         rec.launch(*d)
         torch.cuda.synchronize()
         res = _check(rec, events, oref)
-    print("pu200 x4 graph: %d tracks, fp64 fraction %.4f" %
+    print("pu200 x8 graph: %d tracks, fp64 fraction %.4f" %
           (res.counts["n_tracks"], res.counts["n_fp64"] / max(res.counts["n_tracks"], 1)))
 
 
