@@ -111,13 +111,16 @@ struct Ws {
   // which hold nothing until the links are done
   uint32_t* stage;
   uint32_t stage_words;
-  uint32_t* dwn;          // [blocks * 4] records per wavefront region
+  uint32_t* dwn;          // [blocks * 4] records per wavefront region (the doublet
+                          // staging, then the n-tuplet walk)
   uint8_t* tn;            // [T] hits
   double* tscore;         // [T]
   // cleaning
   uint64_t* bkey;         // [D] smallest order key of the tuples through it (call-tagged)
   uint64_t* best;         // [D] best tuple through each doublet: call epoch << 32 | tuple
   uint32_t* evt_surv;     // [E + 1] first survivor of each event
+  uint4* trow;            // [T][4] staged n-tuplet rows (hits, doublets)
+  uint2* tmeta;           // [T] staged row: root, index among its paths | hits << 28
   uint32_t* surv;         // [T]
   uint32_t* sfit;         // [3][T] survivor indices per length class (the fitting order)
   uint32_t* fp64_list;    // [T]

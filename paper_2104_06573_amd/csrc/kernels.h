@@ -1380,25 +1380,30 @@ __global__ __launch_bounds__(256) void k_zero_words(Ws w, DevCfg c) {
 // One thread per root doublet (no inner neighbour, at least one outer;
 // listed by k_roots, so no lane idles on the other doublets):
 // iterative depth-first search over the outer-neighbour masks; every path
-// that ends at a doublet without outer neighbours is an n-tuplet.  Two
-// passes: the first counts each root's paths, an exclusive scan turns the
-// counts into offsets, the second writes the paths there.  No atomics, and
-// the n-tuplets come out ordered by root doublet (hence by event).
+// that ends at a doublet without outer neighbours is an n-tuplet.  One
+// walk: k_tuples<false> counts each root's paths and writes every path's
+// row to its wavefront's region of a staging array, with the path's root
+// and its index among the root's paths (slots from an LDS cursor per
+// wavefront); an exclusive scan turns the counts into offsets; k_tuples<true>
+// (same grid) moves each staged row to its root's offset + index.  A
+// wavefront whose rows did not fit its region walks its roots again in
+// k_tuples<true> and writes the rows in place.  No global atomics, and the
+// n-tuplets come out ordered by root doublet (hence by event) and, within a
+// root, in the walk's order.
 
-template <bool FILL>
-__global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
+constexpr uint32_t kRowIdxBits = 28;  // staged row: index among the root's paths
+
+__device__ __forceinline__ uint32_t tuple_wave(uint32_t& nwaves) {
+  nwaves = gridDim.x * (blockDim.x / kWave);
+  return blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+}
+
+// The walk of the roots of this thread; STAGE: count and stage (sets
+// *over when the wavefront's region is full), else write the rows in place.
+template <bool STAGE>
+__device__ __forceinline__ void tuple_walk(Ws& w, uint32_t nr, uint32_t nd, uint32_t* s_cur,
+                                           uint32_t cap, size_t rbase, bool& over) {
   uint32_t* ctr = w.ctr;
-  if (ctr[C_STATUS]) return;
-  const uint32_t nr = ctr[C_NROOT];
-  const uint32_t T = c.cap_tuples;
-  const uint32_t nd = ctr[C_ND];
-  if (FILL && w.roff[nr] > T) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      set_status(ctr, PXT_ERR_CAPACITY);
-      ctr[C_REQ_T] = w.roff[nr];
-    }
-    return;
-  }
   for (uint32_t ri = blockIdx.x * blockDim.x + threadIdx.x; ri < nr;
        ri += gridDim.x * blockDim.x) {
     const uint32_t r = w.roots[ri];
@@ -1407,17 +1412,14 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
     uint64_t bits[kMaxCells];   // its remaining bits
     uint32_t nwd[kMaxCells];    // mask words per depth
     uint32_t kbase[kMaxCells];  // first candidate doublet per depth
-    uint32_t phit[kMaxHits];    // fill pass: the path's hits (doublet d spans d, d + 1)
+    uint32_t phit[kMaxHits];    // the path's hits (doublet d spans d, d + 1)
     uint32_t cnt = 0;
-    const uint32_t base = FILL ? w.roff[ri] : 0u;
+    const uint32_t base = STAGE ? 0u : w.roff[ri];
     const uint2 rio = w.cio[r];
-    const uint32_t h0 = rio.x;
     int depth = 0;
     path[0] = r;
-    if (FILL) {
-      phit[0] = h0;
-      phit[1] = rio.y;
-    }
+    phit[0] = rio.x;
+    phit[1] = rio.y;
     {
       uint32_t deg;
       outer_range(w, rio.y, kbase[0], deg);
@@ -1448,16 +1450,31 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       const uint8_t nchild = w.has_out[child];
       const uint32_t hchild = w.cio[child].y;
       if (nchild == 0) {
-        if (FILL) {
+        const int last = depth + 1;
+        uint32_t hh[kMaxHits], cc[kMaxHits];
+#pragma unroll
+        for (int j = 0; j < kMaxHits; ++j)
+          hh[j] = j <= last ? phit[j] : (j == last + 1 ? hchild : kPad);
+#pragma unroll
+        for (int j = 0; j < kMaxCells; ++j) cc[j] = j <= last ? path[j] : kPad;
+        cc[kMaxCells] = kPad;
+        uint4* row = nullptr;
+        if (STAGE) {
+          const uint32_t slot = atomicAdd(s_cur, 1u);
+          if (slot < cap && cnt < (1u << kRowIdxBits)) {
+            row = w.trow + (rbase + slot) * 4u;
+            w.tmeta[rbase + slot] = make_uint2(ri, cnt | ((uint32_t)(last + 2) << kRowIdxBits));
+          } else {
+            over = true;
+          }
+          if (row) {
+            row[0] = make_uint4(hh[0], hh[1], hh[2], hh[3]);
+            row[1] = make_uint4(hh[4], hh[5], hh[6], hh[7]);
+            row[2] = make_uint4(cc[0], cc[1], cc[2], cc[3]);
+            row[3] = make_uint4(cc[4], cc[5], cc[6], cc[7]);
+          }
+        } else {
           const uint32_t t = base + cnt;
-          const int last = depth + 1;
-          uint32_t hh[kMaxHits], cc[kMaxHits];
-#pragma unroll
-          for (int j = 0; j < kMaxHits; ++j)
-            hh[j] = j <= last ? phit[j] : (j == last + 1 ? hchild : kPad);
-#pragma unroll
-          for (int j = 0; j < kMaxCells; ++j) cc[j] = j <= last ? path[j] : kPad;
-          cc[kMaxCells] = kPad;
           // one n-tuplet row: two 16-byte stores per array
           uint4* th4 = reinterpret_cast<uint4*>(w.thit + (size_t)t * kMaxHits);
           uint4* tc4 = reinterpret_cast<uint4*>(w.tcell + (size_t)t * kMaxHits);
@@ -1471,7 +1488,7 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
         continue;
       }
       ++depth;
-      if (FILL) phit[depth + 1] = hchild;
+      phit[depth + 1] = hchild;
       uint32_t deg;
       outer_range(w, hchild, kbase[depth], deg);
       nwd[depth] = (deg + 63u) >> 6;
@@ -1479,7 +1496,63 @@ __global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
       bits[depth] = nwd[depth] ? w.masks[child] : 0ull;
     }
     if (overflow) set_status(ctr, PXT_ERR_PATH);
-    if (!FILL) w.rcnt[ri] = cnt;
+    if (STAGE) w.rcnt[ri] = cnt;
+  }
+}
+
+// staged rows per wavefront region: the whole staging array split evenly
+__device__ __forceinline__ uint32_t tuple_region(const DevCfg& c, uint32_t nwaves) {
+  return c.cap_tuples / nwaves;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_tuples(Ws w, DevCfg c) {
+  __shared__ uint32_t s_cur[256 / kWave];
+  uint32_t* ctr = w.ctr;
+  if (ctr[C_STATUS]) return;
+  const uint32_t nr = ctr[C_NROOT];
+  const uint32_t T = c.cap_tuples;
+  const uint32_t nd = ctr[C_ND];
+  const uint32_t lane = lane_id(), wib = threadIdx.x / kWave;
+  uint32_t nwaves;
+  const uint32_t wid = tuple_wave(nwaves);
+  const uint32_t cap = tuple_region(c, nwaves);
+  const size_t rbase = (size_t)wid * cap;
+  bool over = false;
+  if (!FILL) {
+    if (lane == 0) s_cur[wib] = 0u;
+    __threadfence_block();
+    tuple_walk<true>(w, nr, nd, &s_cur[wib], cap, rbase, over);
+    __threadfence_block();
+    const bool wover = __any(over);
+    if (lane == 0) w.dwn[wid] = wover ? kRecOver : s_cur[wib];
+    return;
+  }
+  if (w.roff[nr] > T) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      set_status(ctr, PXT_ERR_CAPACITY);
+      ctr[C_REQ_T] = w.roff[nr];
+    }
+    return;
+  }
+  const uint32_t n = w.dwn[wid];
+  if (n == kRecOver) {
+    // rows incomplete: this wavefront's roots are walked again
+    tuple_walk<false>(w, nr, nd, nullptr, 0u, 0u, over);
+    return;
+  }
+  for (uint32_t i = lane; i < n; i += kWave) {
+    const uint2 m = w.tmeta[rbase + i];
+    const uint4* row = w.trow + (rbase + i) * 4u;
+    const uint4 a = row[0], b = row[1], e = row[2], f = row[3];
+    const uint32_t t = w.roff[m.x] + (m.y & ((1u << kRowIdxBits) - 1u));
+    uint4* th4 = reinterpret_cast<uint4*>(w.thit + (size_t)t * kMaxHits);
+    uint4* tc4 = reinterpret_cast<uint4*>(w.tcell + (size_t)t * kMaxHits);
+    th4[0] = a;
+    th4[1] = b;
+    tc4[0] = e;
+    tc4[1] = f;
+    w.tn[t] = (uint8_t)(m.y >> kRowIdxBits);
   }
 }
 

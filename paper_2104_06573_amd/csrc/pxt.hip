@@ -145,6 +145,8 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.tn = cv.take<uint8_t>(T);
   w.tscore = cv.take<double>(T);
   w.evt_surv = cv.take<uint32_t>(E + 1);
+  w.trow = cv.take<uint4>(4 * T);
+  w.tmeta = cv.take<uint2>(T);
   w.surv = cv.take<uint32_t>(T);
   w.sfit = cv.take<uint32_t>(3 * T);
   w.fp64_list = cv.take<uint32_t>(T);
@@ -459,15 +461,15 @@ void enqueue_path(pxt_ctx* c, const pxt_config& cfg, const Ws& w, const DevCfg& 
     hipLaunchKernelGGL(k_roots, dim3(scan_grid(cfg.max_doublets)), dim3(kScanThreads1), 0, s, w,
                        6u);
     if (timed) sm.mark(10);
-    hipLaunchKernelGGL(k_tuples<false>,
-                       dim3(std::min(gd, resident_grid((const void*)k_tuples<false>, bs, n_cu))),
-                       dim3(bs), 0, s, w, d);
+    // (the walk and the move share one grid: a wavefront's staging region
+    // and roots are the same in both)
+    const uint32_t gtu = std::min({gd, resident_grid((const void*)k_tuples<false>, bs, n_cu),
+                                   kCompactBlocksMax * (256u / kWave) / (uint32_t)(bs / kWave)});
+    hipLaunchKernelGGL(k_tuples<false>, dim3(gtu), dim3(bs), 0, s, w, d);
     if (timed) sm.mark(11);
     launch_scan1(w, w.rcnt, w.roff, w.ctr + C_NROOT, w.ctr + C_NTUP, cfg.max_doublets, 3, s);
     if (timed) sm.mark(12);
-    hipLaunchKernelGGL(k_tuples<true>,
-                       dim3(std::min(gd, resident_grid((const void*)k_tuples<true>, bs, n_cu))),
-                       dim3(bs), 0, s, w, d);
+    hipLaunchKernelGGL(k_tuples<true>, dim3(gtu), dim3(bs), 0, s, w, d);
     const uint32_t gt = grid_for(cfg.max_tuples, bs, persist);
     if (timed) sm.mark(13);
     hipLaunchKernelGGL(k_score, dim3(std::min(gt, resident_grid((const void*)k_score, bs, n_cu))),
