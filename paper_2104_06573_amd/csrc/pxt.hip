@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "host_copy.h"
 #include "rechits.h"
 
 using namespace pxt;
@@ -609,6 +610,60 @@ constexpr int kStaticDevicesMax = 64;
 StaticDevice g_static[kStaticDevicesMax];
 
 }  // namespace
+
+namespace pxt {
+
+// ------------------------------------------------ results to host memory --
+// (server lanes; see host_copy.h)
+
+// n 32-bit words, as 16-byte vectors where both sides allow it
+__device__ __forceinline__ void copy_words(uint32_t* __restrict__ d, const uint32_t* __restrict__ s,
+                                           size_t n, size_t tid, size_t stride) {
+  const bool vec = ((reinterpret_cast<uintptr_t>(d) | reinterpret_cast<uintptr_t>(s)) & 15u) == 0;
+  size_t head = 0;
+  if (vec) {
+    const size_t n4 = n / 4;
+    for (size_t i = tid; i < n4; i += stride)
+      reinterpret_cast<uint4*>(d)[i] = reinterpret_cast<const uint4*>(s)[i];
+    head = n4 * 4;
+  }
+  for (size_t i = head + tid; i < n; i += stride) d[i] = s[i];
+}
+
+__global__ __launch_bounds__(256) void k_copy_out(pxt_tracks dev, uint32_t n_events,
+                                                  HostTracks host) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const pxt_counts* kc = dev.counts;
+  const uint32_t n = kc->status == 0 ? min(kc->n_tracks, dev.capacity) : 0u;
+  static_assert(sizeof(pxt_counts) % 4 == 0, "counts as words");
+  copy_words(reinterpret_cast<uint32_t*>(host.counts), reinterpret_cast<const uint32_t*>(kc),
+             sizeof(pxt_counts) / 4, tid, stride);
+  copy_words(host.per_event_tracks, dev.per_event_tracks, n_events, tid, stride);
+  copy_words(host.hit_idx, dev.hit_idx, 8ull * n, tid, stride);
+  copy_words(reinterpret_cast<uint32_t*>(host.params),
+             reinterpret_cast<const uint32_t*>(dev.params), 5ull * n, tid, stride);
+  copy_words(reinterpret_cast<uint32_t*>(host.cov), reinterpret_cast<const uint32_t*>(dev.cov),
+             15ull * n, tid, stride);
+  copy_words(reinterpret_cast<uint32_t*>(host.chi2), reinterpret_cast<const uint32_t*>(dev.chi2),
+             2ull * n, tid, stride);
+  for (size_t i = tid; i < n; i += stride) {
+    host.n_hits[i] = dev.n_hits[i];
+    host.flags[i] = dev.flags[i];
+  }
+}
+
+hipError_t launch_copy_out(const pxt_tracks& dev, uint32_t n_events, const HostTracks& host,
+                           hipStream_t s) {
+  // enough threads for a full batch's tracks in a few rounds; the kernel
+  // reads the actual count
+  const uint32_t blocks = std::max<uint32_t>(
+      1u, std::min<uint32_t>(1024u, (uint32_t)(((uint64_t)dev.capacity * 2u + 255u) / 256u)));
+  hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(256), 0, s, dev, n_events, host);
+  return hipGetLastError();
+}
+
+}  // namespace pxt
 
 extern "C" {
 

@@ -6,21 +6,26 @@
 // overlap with the others on the device.  A dispatcher thread owns every
 // HIP call and every lane: it admits pending events into a batch whenever a
 // lane is free (first come, first served, while the batch fits the lane's
-// capacities), and advances each batch through two phases --
-// reconstruction with the copy-back of the counts, then the copy-back of
-// exactly the tracks found.  A lane holds up to two batches: once one
-// batch's track copy-back is queued, the next batch is staged and launched
-// behind it on the same stream, so the lane's device work does not wait for
-// the copy-back to be seen done (stream order keeps the shared device
-// buffers safe: the next batch's copy-in and kernels run after the copy-back
-// has read them).  The server lock guards only the queue, the tickets and
-// the counters: staging, HIP calls and result hand-over run outside it.
+// capacities).  A small batch (at most kDirectHits hits: the one or few
+// events of a lightly loaded server) is one pass on the lane's stream:
+// copy-in of its hits, the reconstruction, and one kernel that copies the
+// counts and exactly the tracks found (it reads their number on the device)
+// into pinned host memory -- no host round trip before the copy-back.  A
+// larger batch takes two phases, as a kernel's writes to host memory are
+// slower than the copy engines for many megabytes: the reconstruction with
+// the copy-back of the counts, then the copy-back of exactly the tracks
+// found.  A lane holds up to two batches on its stream, each with its own
+// pinned staging and result set: a new one is queued behind a one-pass
+// batch at once, behind a two-phase batch once its track copy-back is
+// queued (stream order keeps the lane's shared device buffers safe: a
+// batch's copy-in and kernels run after the previous batch's copy-back has
+// read them).  The server lock guards only the queue, the tickets and the
+// counters: staging, HIP calls and result hand-over run outside it.
 //
-// Results are not copied on the host by the server: each lane has two
-// pinned result sets, a finished batch's events point into the set its
-// tracks were copied to, and pxt_poll copies an event's tracks straight
-// from there into the caller's buffers; a set is reused once every event
-// in it has been polled.  This is the serving form of the paper's two
+// Results are not copied on the host by the server: a finished batch's
+// events point into its result set, and pxt_poll copies an event's tracks
+// straight from there into the caller's buffers; a set (with its staging)
+// is reused once every event in it has been polled.  This is the serving form of the paper's two
 // throughput levers for one GPU: several events in flight at once and
 // device memory allocated once and reused (Sec. 5).
 #include <hip/hip_runtime.h>
@@ -38,6 +43,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "host_copy.h"
 #include "pxt.h"
 
 namespace {
@@ -48,8 +54,13 @@ double us_between(Clock::time_point a, Clock::time_point b) {
   return std::chrono::duration<double, std::micro>(b - a).count();
 }
 
-// Pinned host copy of one batch's tracks.
+// Pinned host memory of one batch: its hits' staging, and its counts and
+// tracks as copied back.
 struct ResultSet {
+  float *hx = nullptr, *hy = nullptr, *hz = nullptr;
+  int16_t* hl = nullptr;
+  pxt_counts* counts = nullptr;
+  uint32_t* per_event = nullptr;
   uint32_t* hit_idx = nullptr;
   uint8_t* nh = nullptr;
   uint8_t* flags = nullptr;
@@ -86,13 +97,15 @@ bool host_alloc(T** p, size_t n) {
          hipSuccess;
 }
 
+constexpr size_t kDirectHits = 32768;  // batches copied back by one kernel
+
 // One batch on a lane.
 struct Flight {
   std::vector<ReqPtr> batch;
-  int phase = 0;             // 0 none, 1 reconstruction in flight, 2 track copy-back in flight
-  int set = 0;               // the result set its tracks go to
+  int phase = 0;             // 1 reconstruction in flight, 2 track copy-back in flight
+  bool direct = false;       // one pass (tracks copied back by a kernel)
+  int set = 0;               // its staging and result set
   hipEvent_t ev = nullptr;   // end of its current phase on the lane's stream
-  std::vector<uint32_t> per_event;  // track counts, read when the reconstruction ends
 };
 
 struct Lane {
@@ -106,11 +119,6 @@ struct Lane {
   uint8_t *d_nh = nullptr, *d_flags = nullptr;
   float *d_params = nullptr, *d_cov = nullptr, *d_chi2 = nullptr;
   pxt_counts* d_counts = nullptr;
-  // pinned host staging
-  float *hx = nullptr, *hy = nullptr, *hz = nullptr;
-  int16_t* hl = nullptr;
-  pxt_counts* h_counts = nullptr;
-  uint32_t* h_per_event = nullptr;
   ResultSet res[2];
   // state (dispatcher thread only): up to two batches, fl[head] the older
   Flight fl[2];
@@ -123,8 +131,11 @@ struct Lane {
     head = (head + 1) & 1;
     --nfl;
   }
-  // a new batch may start: the lane is idle, or its one batch is in copy-back
-  bool can_start() const { return nfl == 0 || (nfl == 1 && fl[head].phase == 2); }
+  // a new batch may start: the lane is idle, or its one batch is a one-pass
+  // batch or in copy-back
+  bool can_start() const {
+    return nfl == 0 || (nfl == 1 && (fl[head].direct || fl[head].phase == 2));
+  }
 
   bool init(const pxt_config& cfg, int dev) {
     max_hits = cfg.max_hits;
@@ -141,11 +152,11 @@ struct Lane {
          dev_alloc(&d_flags, max_tracks) && dev_alloc(&d_params, 5ull * max_tracks) &&
          dev_alloc(&d_cov, 15ull * max_tracks) && dev_alloc(&d_chi2, 2ull * max_tracks) &&
          dev_alloc(&d_counts, 1);
-    ok = ok && host_alloc(&hx, max_hits) && host_alloc(&hy, max_hits) &&
-         host_alloc(&hz, max_hits) && host_alloc(&hl, max_hits) && host_alloc(&h_counts, 1) &&
-         host_alloc(&h_per_event, max_events);
     for (auto& r : res)
-      ok = ok && host_alloc(&r.hit_idx, 8ull * max_tracks) && host_alloc(&r.nh, max_tracks) &&
+      ok = ok && host_alloc(&r.hx, max_hits) && host_alloc(&r.hy, max_hits) &&
+           host_alloc(&r.hz, max_hits) && host_alloc(&r.hl, max_hits) &&
+           host_alloc(&r.counts, 1) && host_alloc(&r.per_event, max_events) &&
+           host_alloc(&r.hit_idx, 8ull * max_tracks) && host_alloc(&r.nh, max_tracks) &&
            host_alloc(&r.flags, max_tracks) && host_alloc(&r.params, 5ull * max_tracks) &&
            host_alloc(&r.cov, 15ull * max_tracks) && host_alloc(&r.chi2, 2ull * max_tracks);
     return ok;
@@ -167,12 +178,10 @@ struct Lane {
                     (void*)d_per_event, (void*)d_nh, (void*)d_flags, (void*)d_params,
                     (void*)d_cov, (void*)d_chi2, (void*)d_counts})
       if (p) (void)hipFree(p);
-    for (void* p : {(void*)hx, (void*)hy, (void*)hz, (void*)hl, (void*)h_counts,
-                    (void*)h_per_event})
-      if (p) (void)hipHostFree(p);
     for (auto& r : res)
-      for (void* p : {(void*)r.hit_idx, (void*)r.nh, (void*)r.flags, (void*)r.params,
-                      (void*)r.cov, (void*)r.chi2})
+      for (void* p : {(void*)r.hx, (void*)r.hy, (void*)r.hz, (void*)r.hl, (void*)r.counts,
+                      (void*)r.per_event, (void*)r.hit_idx, (void*)r.nh, (void*)r.flags,
+                      (void*)r.params, (void*)r.cov, (void*)r.chi2})
         if (p) (void)hipHostFree(p);
     for (auto& f : fl)
       if (f.ev) (void)hipEventDestroy(f.ev);
@@ -230,42 +239,51 @@ void pxt_server::take_batch(Lane& L, Flight& F) {
   stats.events_in_batches += batch.size();
 }
 
-// Stage batch F's hits and launch it on the lane's stream (behind the
-// copy-back of the lane's other batch, if any).
+// Stage batch F's hits and queue its pass on the lane's stream (behind the
+// lane's other batch, if any).
 void pxt_server::start_batch(Lane& L, Flight& F) {
   const auto now = Clock::now();
+  ResultSet& R = L.res[F.set];
   L.offsets.assign(1, 0u);
   uint32_t off = 0;
   for (auto& r : F.batch) {
     r->t_start = now;
     const uint32_t n = (uint32_t)r->x.size();
-    std::memcpy(L.hx + off, r->x.data(), 4ull * n);
-    std::memcpy(L.hy + off, r->y.data(), 4ull * n);
-    std::memcpy(L.hz + off, r->z.data(), 4ull * n);
-    std::memcpy(L.hl + off, r->layer.data(), 2ull * n);
+    std::memcpy(R.hx + off, r->x.data(), 4ull * n);
+    std::memcpy(R.hy + off, r->y.data(), 4ull * n);
+    std::memcpy(R.hz + off, r->z.data(), 4ull * n);
+    std::memcpy(R.hl + off, r->layer.data(), 2ull * n);
     off += n;
     L.offsets.push_back(off);
   }
   const size_t H = off;
   bool ok = true;
   if (H) {
-    ok = hipMemcpyAsync(L.dx, L.hx, 4 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
-         hipMemcpyAsync(L.dy, L.hy, 4 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
-         hipMemcpyAsync(L.dz, L.hz, 4 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
-         hipMemcpyAsync(L.dl, L.hl, 2 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess;
+    ok = hipMemcpyAsync(L.dx, R.hx, 4 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
+         hipMemcpyAsync(L.dy, R.hy, 4 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
+         hipMemcpyAsync(L.dz, R.hz, 4 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess &&
+         hipMemcpyAsync(L.dl, R.hl, 2 * H, hipMemcpyHostToDevice, L.stream) == hipSuccess;
   }
-  pxt_hits in{(uint32_t)F.batch.size(), L.offsets.data(), L.dx, L.dy, L.dz, L.dl, nullptr};
+  const uint32_t nb = (uint32_t)F.batch.size();
+  pxt_hits in{nb, L.offsets.data(), L.dx, L.dy, L.dz, L.dl, nullptr};
   pxt_tracks out{L.max_tracks, L.d_hit_idx, L.d_nh, L.d_evt, L.d_params, L.d_cov,
                  L.d_chi2, L.d_flags, L.d_per_event, L.d_counts, nullptr};
   ok = ok && pxt_reconstruct(L.ctx, &in, &out, L.stream) == PXT_OK;
-  ok = ok && hipMemcpyAsync(L.h_counts, L.d_counts, sizeof(pxt_counts), hipMemcpyDeviceToHost,
-                            L.stream) == hipSuccess;
-  ok = ok && hipMemcpyAsync(L.h_per_event, L.d_per_event, 4ull * F.batch.size(),
-                            hipMemcpyDeviceToHost, L.stream) == hipSuccess;
+  F.direct = H <= kDirectHits;
+  if (F.direct) {
+    const pxt::HostTracks host{R.hit_idx, R.nh,    R.params,    R.cov,
+                               R.chi2,    R.flags, R.per_event, R.counts};
+    ok = ok && pxt::launch_copy_out(out, nb, host, L.stream) == hipSuccess;
+  } else {
+    ok = ok && hipMemcpyAsync(R.counts, L.d_counts, sizeof(pxt_counts), hipMemcpyDeviceToHost,
+                              L.stream) == hipSuccess;
+    ok = ok && hipMemcpyAsync(R.per_event, L.d_per_event, 4ull * nb, hipMemcpyDeviceToHost,
+                              L.stream) == hipSuccess;
+  }
   ok = ok && hipEventRecord(F.ev, L.stream) == hipSuccess;
+  F.phase = 1;
   const auto t = Clock::now();
   for (auto& r : F.batch) r->t_launch = t;
-  F.phase = 1;
   ++L.nfl;
   if (!ok) {
     // a failed launch leaves the stream's earlier work in place: wait for
@@ -290,7 +308,7 @@ void pxt_server::finish(Lane& L, Flight& F, int status) {
     r.batch_events = nb;
     r.t_ready = now;
     if (status == PXT_OK) {
-      r.n_tracks = F.per_event[e];
+      r.n_tracks = rs->per_event[e];
       r.rs = rs;
       r.base = base;
       base += r.n_tracks;
@@ -336,34 +354,36 @@ bool pxt_server::advance(Lane& L) {
       L.pop_oldest();
       continue;
     }
-    // the reconstruction has ended (no batch runs behind it yet)
+    // the reconstruction has ended
     const auto now = Clock::now();
     for (auto& r : F.batch) r->t_device = now;
-    const int st = L.h_counts->status;
+    ResultSet& R = L.res[F.set];
+    const int st = R.counts->status;
     if (st != PXT_OK) {
       if (F.batch.size() > 1) {
         // re-run each event alone, ahead of the queue, in order
-        {
-          std::lock_guard<std::mutex> g(mu);
-          for (auto it = F.batch.rbegin(); it != F.batch.rend(); ++it) {
-            (*it)->solo = true;
-            (*it)->t_device = Clock::time_point{};
-            pending.push_front(*it);
-          }
-          stats.solo_retries += F.batch.size();
+        std::lock_guard<std::mutex> g(mu);
+        for (auto it = F.batch.rbegin(); it != F.batch.rend(); ++it) {
+          (*it)->solo = true;
+          (*it)->t_device = Clock::time_point{};
+          pending.push_front(*it);
         }
+        stats.solo_retries += F.batch.size();
         F.batch.clear();
-        F.phase = 0;
       } else {
         finish(L, F, st);
       }
       L.pop_oldest();
-      return moved;
+      continue;
     }
-    // the counts now, before a next batch's copy-back overwrites them
-    F.per_event.assign(L.h_per_event, L.h_per_event + F.batch.size());
-    const size_t n = L.h_counts->n_tracks;
-    ResultSet& R = L.res[F.set];
+    if (F.direct) {
+      finish(L, F, PXT_OK);
+      L.pop_oldest();
+      continue;
+    }
+    // two phases: the tracks' copy-back, sized by the counts (no batch runs
+    // behind this one yet)
+    const size_t n = R.counts->n_tracks;
     bool ok = true;
     if (n) {
       ok = hipMemcpyAsync(R.hit_idx, L.d_hit_idx, 32 * n, hipMemcpyDeviceToHost, L.stream) ==
@@ -382,7 +402,7 @@ bool pxt_server::advance(Lane& L) {
       (void)hipStreamSynchronize(L.stream);
       finish(L, F, PXT_ERR_HIP);
       L.pop_oldest();
-      return moved;
+      continue;
     }
     F.phase = 2;
     return moved;
