@@ -92,6 +92,8 @@ def parse(argv=None):
     ap.add_argument("--serve-pool", type=int, default=96, help="distinct events cycled through")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--served-child", action="store_true",
+                    help="(internal) run only the serving leg and print its JSON entry")
     ap.add_argument("--vertices", type=int, default=1,
                     help="find the vertices of the tracks in every step (the serving leg "
                          "returns tracks only)")
@@ -394,6 +396,28 @@ def serving_leg(det, args):
     }, pool
 
 
+def served_in_child(args):
+    """The serving leg in a process of its own that uses only the library,
+    as a serving process would: where torch has already taken the device,
+    the lanes share hardware queues with it (measured 28–30k instead of 35k
+    events/s saturated).  Returns the entry and the pool."""
+    import subprocess
+    import eventgen
+    cmd = [sys.executable, os.path.abspath(__file__), "--served-child",
+           "--serve-rate", str(args.serve_rate), "--serve-events", str(args.serve_events),
+           "--serve-pool", str(args.serve_pool), "--serve-lanes", str(args.serve_lanes),
+           "--phi-bins", str(args.phi_bins), "--group-lanes", str(args.group_lanes),
+           "--link-kernel", str(args.link_kernel),
+           "--latency-doublet-mode", str(args.latency_doublet_mode)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode != 0 or not lines:
+        raise RuntimeError("serving leg failed (rc %d): %s" % (r.returncode, r.stderr[-2000:]))
+    entry = json.loads(lines[-1])
+    entry["process"] = "own (library only; the other legs run in the parent)"
+    return entry, eventgen.make_batch("serve", args.serve_pool, seed=11)
+
+
 def mix_batched(torch, pxt, det, pool, args):
     """The batched path (64 events per batch, graph, batches in flight) on
     the serving mix, for the saturated serving rate to be compared with."""
@@ -665,6 +689,11 @@ def main(argv=None):
         print("bench.py: this build runs on one GPU only (events are independent; a multi-GPU "
               "deployment is one process per GPU). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.served_child:
+        import eventgen
+        entry, _ = serving_leg(eventgen.DETECTOR, args)
+        print(json.dumps(entry), flush=True)
+        return
     # every input is generated before the GPU is touched (worker processes)
     kind, batch_default, desc = WORKLOADS[args.workload]
     B = args.batch or batch_default
@@ -684,11 +713,11 @@ def main(argv=None):
     import paper_2104_06573_amd as pxt
 
     det = eventgen.DETECTOR
-    # the serving leg runs first, before this process creates any other
-    # stream: its lanes' streams then get hardware queues of their own
+    # the serving leg first, in a child process, before this one touches
+    # the device
     served = serve_pool = None
     if not args.no_serve and args.workload == "pu50":
-        served, serve_pool = serving_leg(det, args)
+        served, serve_pool = served_in_child(args)
     if args.calib_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
