@@ -459,9 +459,11 @@ typedef struct pxt_server_stats {
   /* sums over the completed events of the time each spent, in us:
    * queued (arrival to admission into a batch), staging and launch
    * (admission to the batch's calls issued), device (to the counts back
-   * on the host), copy-back of the tracks; over the delivered events:
-   * delivery (tracks on the host to pxt_poll's return), and the whole
-   * latency (arrival to pxt_poll's return) */
+   * on the host; for a batch of at most 32768 hits, copied back by one
+   * kernel, the tracks too), copy-back of the tracks (larger batches);
+   * over the delivered events: delivery (tracks on the host to
+   * pxt_poll's return), and the whole latency (arrival to pxt_poll's
+   * return) */
   double sum_queue_us, sum_launch_us, sum_device_us, sum_copyback_us;
   double sum_deliver_us, sum_latency_us;
 } pxt_server_stats;
