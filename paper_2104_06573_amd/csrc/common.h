@@ -63,7 +63,9 @@ struct DevCfg {
   uint32_t cap_doublets, cap_words, cap_tuples;
   int link_kernel;                          // 0 thread, 1 lane group, 2 wave
   int bin_lds;                              // binning by one block per event
-  float th_win, th_far;                     // r-z angle prefilter of the links
+  int q_win, q_far, q_far_min;              // r-z angle prefilter of the links (angle
+                                            // units): window, anti-parallel window, and
+                                            // the |angle| below which the latter cannot hold
   // output selection and quality flags
   int min_hits;                             // shorter survivors are not output
   float q_chi2;                             // LOOSE: chi2 per ndf at most
@@ -100,7 +102,8 @@ struct Ws {
   uint64_t* masks;        // [W] link masks, C_WSTRIDE words per doublet
   uint8_t* has_inner;     // [D]
   uint8_t* has_out;       // [D] the doublet has an outer link
-  float* th;              // [D + 16] r-z angle of each doublet (the link prefilter's stream)
+  int16_t* th;            // [D + 16] r-z angle of each doublet in angle units (the link
+                          // prefilter's stream)
   uint32_t* roots;        // [D] root doublets, ascending
   uint32_t* rcnt;         // [D + 1] n-tuplets per root doublet
   uint32_t* roff;         // [D + 1]

@@ -237,16 +237,28 @@ __device__ __forceinline__ bool link_xy_pass(const DevCfg& c, const HitD& a, con
 // (r_o - r_i, z_o - z_i).  For two doublets (a,b), (b,c) the r-z cross
 // product of L1 is l_ab l_bc sin(angle_bc - angle_ab), so L1 can hold only
 // where the angles differ by at most asin(arz), or by at least
-// pi - asin(arz); rz_prefilter tests that with a margin (th_win, th_far)
-// that covers the FP32 error of both angles.  Candidates it rejects fail
-// L1; the ones it keeps go on to the exact cuts.
+// pi - asin(arz); rz_prefilter tests that on the angles stored in 16-bit
+// units, with windows (q_win, q_far) widened to cover the FP32 error and
+// the rounding to units of both angles.  Candidates it rejects fail L1;
+// the ones it keeps go on to the exact cuts.
 __device__ __forceinline__ float rz_angle(const HitD& i, const HitD& o) {
   return atan2f((float)(o.z - i.z), (float)(o.r - i.r));
 }
 
-__device__ __forceinline__ bool rz_prefilter(const DevCfg& c, float ta, float tc) {
-  const float dd = fabsf(tc - ta);
-  return dd <= c.th_win || dd >= c.th_far;
+// The r-z angle of a doublet in angle units of (pi/2) / 32767 rad, rounded
+// to nearest: doublets point outward (r grows), so the FP32 angle lies in
+// [-pi/2, pi/2] (pi/2 rounded up, hence the clamp), and the stored value is
+// within one unit of it (half a unit from the rounding, ~0.005 from the
+// FP32 product and scale).
+constexpr float kAngleUnits = 32767.0f / 1.57079632679f;
+__device__ __forceinline__ int16_t angle_units(float th) {
+  const float q = rintf(th * kAngleUnits);
+  return (int16_t)fminf(32767.0f, fmaxf(-32767.0f, q));
+}
+
+__device__ __forceinline__ bool rz_prefilter(const DevCfg& c, int ta, int tc) {
+  const int dd = abs(tc - ta);
+  return dd <= c.q_win || dd >= c.q_far;
 }
 
 // Cleaning score of one consecutive hit triple.

@@ -652,7 +652,7 @@ __device__ __forceinline__ void store_doublet(Ws& w, const DevCfg& c, uint32_t q
   w.cio[q] = make_uint2(g, j);
   w.has_inner[q] = 0;
   if (c.link_kernel == 1) w.has_out[q] = 0;
-  w.th[q] = rz_angle(hi, ho);
+  w.th[q] = angle_units(rz_angle(hi, ho));
 }
 
 // Link-mask words of the largest out-degree: C_WSTRIDE is raised only when
@@ -954,8 +954,8 @@ __global__ __launch_bounds__(256) void k_dscatter(Ws w, DevCfg c) {
 // ---------------------------------------------------------------- links --
 // The candidate outer neighbours of doublet (a,b) are the doublets leaving
 // hit b: the contiguous range cell_off[b] .. cell_off[b+1] (doublets are
-// stored grouped by inner hit).  The FP32 angle prefilter, which passes
-// only a few percent, streams the doublets' r-z angles (th, 4 bytes each),
+// stored grouped by inner hit).  The angle prefilter, which passes only a
+// few percent, streams the doublets' r-z angles (th, 16-bit units),
 // and the survivors go on to the exact FP64 cuts with their three hits
 // loaded from the binned-hit array (hit-indexed, a few MB per batch), not
 // from per-doublet copies.  The accepted candidates form a bit mask over
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
   for (uint32_t dw = d0; dw < nd; dw += stride) {
     const uint32_t d = dw + lane;
     uint32_t k0 = 0, deg = 0, ha = 0, hb = 0;
-    float tho = 0.f;  // the doublet's r-z angle
+    int tho = 0;  // the doublet's r-z angle (units)
     if (d < nd) {
       const uint2 io = w.cio[d];
       ha = io.x;
@@ -1054,12 +1054,12 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
     __threadfence_block();
     // the prefilter in chunks of 16 candidates spread evenly over the lanes:
     // a doublet's candidates (absolute indices k0 .. k0+deg-1) form the
-    // 4-aligned chunks starting at (k0 & ~3) + 16 i; the wavefront's chunks
+    // 8-aligned chunks starting at (k0 & ~7) + 16 i; the wavefront's chunks
     // are numbered by a prefix sum over its doublets, and in each round
     // every lane takes the next chunk, finds its doublet by a binary search
-    // of the prefix (shuffles) and reads the 16 angles as four aligned
-    // float4s (one 64-byte line per lane)
-    const uint32_t nch = deg ? (k0 + deg - (k0 & ~3u) + 15u) >> 4 : 0u;
+    // of the prefix (shuffles) and reads the 16 16-bit angles as two aligned
+    // 16-byte vectors
+    const uint32_t nch = deg ? (k0 + deg - (k0 & ~7u) + 15u) >> 4 : 0u;
     const uint32_t cinc = wave_incl_scan(nch), cex = cinc - nch;
     const uint32_t C = __shfl(cinc, kWave - 1);
     for (uint32_t r0 = 0; r0 < C; r0 += kWave) {
@@ -1070,33 +1070,34 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
       for (uint32_t step = kWave / 2; step >= 1; step >>= 1)
         if (__shfl(cex, (int)(own + step)) <= q) own += step;
       const uint32_t ok0 = __shfl(k0, (int)own), odeg = __shfl(deg, (int)own);
-      const float ta = __shfl(tho, (int)own);
+      const int ta = __shfl(tho, (int)own);
       const uint32_t lo = ok0, hi = ok0 + odeg;
-      const uint32_t a0 = (ok0 & ~3u) + 16u * (q - __shfl(cex, (int)own));
+      const uint32_t a0 = (ok0 & ~7u) + 16u * (q - __shfl(cex, (int)own));
       uint32_t pm = 0;  // bit u: candidate a0 + u passes
       if (q < C) {
-        float tc[16];
+        int tc[16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (a0 + 4u * v < hi) f = reinterpret_cast<const float4*>(w.th)[a0 / 4u + v];
-          tc[4 * v] = f.x;
-          tc[4 * v + 1] = f.y;
-          tc[4 * v + 2] = f.z;
-          tc[4 * v + 3] = f.w;
+        for (int v = 0; v < 2; ++v) {
+          uint4 f = make_uint4(0u, 0u, 0u, 0u);
+          if (a0 + 8u * v < hi) f = reinterpret_cast<const uint4*>(w.th)[a0 / 8u + v];
+          const uint32_t fw[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            tc[8 * v + 2 * i] = (int)(int16_t)(fw[i] & 0xffffu);
+            tc[8 * v + 2 * i + 1] = (int)(int16_t)(fw[i] >> 16);
+          }
         }
         // the angle window first (one compare per candidate), the
-        // anti-parallel window only where it can hold: doublets point outward
-        // (r grows), so their FP32 r-z angles lie in [-pi/2, pi/2] (pi/2
-        // rounded up) and two of them differ by th_far or more only if
-        // |ta| >= th_far - pi/2 (1.5708 covers the roundings)
+        // anti-parallel window only where it can hold: angles lie within
+        // +-32767 units, so two of them differ by q_far or more only if
+        // |ta| >= q_far - 32767
 #pragma unroll
         for (int u = 0; u < 16; ++u)
-          if (fabsf(tc[u] - ta) <= c.th_win) pm |= 1u << u;
-        if (__any(q < C && fabsf(ta) >= c.th_far - 1.5708f)) {
+          if (abs(tc[u] - ta) <= c.q_win) pm |= 1u << u;
+        if (__any(q < C && abs(ta) >= c.q_far_min)) {
 #pragma unroll
           for (int u = 0; u < 16; ++u)
-            if (fabsf(tc[u] - ta) >= c.th_far) pm |= 1u << u;
+            if (abs(tc[u] - ta) >= c.q_far) pm |= 1u << u;
         }
         // the owner's candidates within the chunk: a0 + u in [lo, hi)
         const uint32_t ub = lo > a0 ? lo - a0 : 0u, ue = min(16u, hi - a0);
@@ -1193,18 +1194,18 @@ __global__ __launch_bounds__(256) void k_links(Ws w, DevCfg c) {
   for (TileWalk tw = tile_walk((nd + gpb - 1) / gpb); tw.t < tw.end; tw.t += tw.step) {
     const uint32_t d = tw.t * gpb + gib;
     uint32_t kb = 0, deg = 0;
-    float ta = 0.0f;
+    int ta = 0;
     if (d < nd) {
       ta = w.th[d];
       outer_range(w, w.cio[d].y, kb, deg);
     }
     const uint32_t maxw = wave_max((deg + 63u) / 64u);
     for (uint32_t wd = 0; wd < maxw; ++wd) {
-      float tc[U];
+      int tc[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t k = wd * 64u + (uint32_t)(u * G) + sub;
-        tc[u] = k < deg ? w.th[kb + k] : 0.0f;
+        tc[u] = k < deg ? (int)w.th[kb + k] : 0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -1309,8 +1310,8 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
       const uint2 io = w.cio[d];
       a = io.x;
       outer_range(w, io.y, kb, deg);
-      ob = w.bh[io.y];  // the outer hit, with the doublet's r-z angle in .w
-      ob.w = w.th[d];
+      ob = w.bh[io.y];  // the outer hit, with the doublet's r-z angle (units) in .w
+      ob.w = __int_as_float((int)w.th[d]);
       mo = d;
     }
     const uint32_t nwd = (deg + 63u) >> 6;
@@ -1336,8 +1337,8 @@ __global__ __launch_bounds__(256) void k_links_wave(Ws w, DevCfg c) {
         if (__shfl(cex, (int)(own + step)) <= k) own += step;
       const uint32_t kk = k - __shfl(cex, (int)own);
       const uint32_t kbo = __shfl(kb, (int)own);
-      const float tao = __shfl(ob.w, (int)own);
-      const bool pass = k < C && rz_prefilter(c, tao, w.th[kbo + kk]);
+      const int tao = __float_as_int(__shfl(ob.w, (int)own));
+      const bool pass = k < C && rz_prefilter(c, tao, (int)w.th[kbo + kk]);
       const uint64_t bal = __ballot(pass);
       if (pass) L.q[qn + (uint32_t)__popcll(bal & below)] = make_uint2(own, kk);
       qn += (uint32_t)__popcll(bal);

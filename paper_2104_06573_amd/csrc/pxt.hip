@@ -130,7 +130,7 @@ void carve(Carver& cv, const pxt_config& c, Ws& w) {
   w.cio = cv.take<uint2>(D);
   w.has_inner = cv.take<uint8_t>(D);
   w.has_out = cv.take<uint8_t>(D + 16);  // read 16 flags at a time
-  w.th = cv.take<float>(D + 16);  // aligned float4 reads may pass the end by 3
+  w.th = cv.take<int16_t>(D + 16);  // aligned 16-byte reads may pass the end by 7
   // the election slots keep their contents from call to call (tagged with
   // the call), so they lie outside the doublet staging span below
   w.bkey = cv.take<uint64_t>(D);
@@ -250,16 +250,21 @@ void make_devcfg(const pxt_config& c, DevCfg& d) {
   // L1 holds only if the r-z directions of the two doublets differ by at
   // most asin(arz) or by at least pi - asin(arz).  The FP32 angles carry an
   // error below 1e-6 rad (inputs rounded to FP32: < 1.2e-7; atan2f: a few
-  // ulp), so a margin of 1e-5 rad keeps the prefilter a strict superset of
-  // the FP64 decision.  arz >= 1 leaves it open.
+  // ulp), so a margin of 1e-5 rad keeps a prefilter on them a strict
+  // superset of the FP64 decision.  The stored angles are those rounded to
+  // units of (pi/2) / 32767 rad (within one unit each), so the windows in
+  // units widen by two: |ta - tc| <= w rad gives at most floor(w / unit) + 2
+  // units, >= f rad at least ceil(f / unit) - 2.  arz >= 1 leaves it open.
+  const double unit = (M_PI / 2.0) / 32767.0;
   if (c.arz < 1.0) {
     const double a = std::asin(c.arz) + 1e-5;
-    d.th_win = (float)a;
-    d.th_far = (float)(M_PI - a);
+    d.q_win = (int)std::floor(a / unit) + 2;
+    d.q_far = (int)std::ceil((M_PI - a) / unit) - 2;
   } else {
-    d.th_win = 8.0f;
-    d.th_far = 0.0f;
+    d.q_win = 65536;
+    d.q_far = 0;
   }
+  d.q_far_min = d.q_far - 32767;
 }
 
 // Blocks of a single-pass scan over at most max_n entries.
