@@ -1091,9 +1091,12 @@ __global__ __launch_bounds__(256) void k_links_thread(Ws w, DevCfg c) {
         // anti-parallel window only where it can hold: angles lie within
         // +-32767 units, so two of them differ by q_far or more only if
         // |ta| >= q_far - 32767
+        // (|tc - ta| <= W as one unsigned compare: tc + (W - ta) in [0, 2W])
+        const int wa = c.q_win - ta;
+        const uint32_t w2 = 2u * (uint32_t)c.q_win;
 #pragma unroll
         for (int u = 0; u < 16; ++u)
-          if (abs(tc[u] - ta) <= c.q_win) pm |= 1u << u;
+          if ((uint32_t)(tc[u] + wa) <= w2) pm |= 1u << u;
         if (__any(q < C && abs(ta) >= c.q_far_min)) {
 #pragma unroll
           for (int u = 0; u < 16; ++u)
