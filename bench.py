@@ -73,7 +73,9 @@ def parse(argv=None):
     ap.add_argument("--cpu-sample-1t", type=int, default=64,
                     help="events for the one-thread CPU figure")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--phi-bins", type=int, default=256)
+    ap.add_argument("--phi-bins", type=int, default=1024,
+                    help="phi bins per layer (1024: fewer doublet candidates than 256 or "
+                         "512, and still held in LDS by the per-event binning at 10 layers)")
     ap.add_argument("--group-lanes", type=int, default=8)
     ap.add_argument("--link-kernel", type=int, default=0,
                     help="0 thread per doublet (the fastest with batches in flight at PU~50 "

@@ -39,7 +39,7 @@ def _rec(kind, events, n_events=None, **tuning):
     else:
         caps = bench.batch_caps(kind, n_events, max(e.n_hits for e in events) * n_events)
     caps.update({k: tuning.pop(k) for k in list(tuning) if k.startswith("max_")})
-    kw = dict(phi_bins=256, group_lanes=8, link_kernel=0, use_graph=1, doublet_mode=2)
+    kw = dict(phi_bins=1024, group_lanes=8, link_kernel=0, use_graph=1, doublet_mode=2)
     kw.update(tuning)
     return pxt.Reconstructor(DET, **caps, **kw)
 
