@@ -22,7 +22,7 @@ import time
 import numpy as np
 
 DEFAULT_SPACE = {
-    "phi_bins": (64, 128, 256, 512),
+    "phi_bins": (64, 128, 256, 512, 1024),
     "group_lanes": (4, 8, 16),
     "link_kernel": (0, 2),
     "doublet_mode": (1, 2),
