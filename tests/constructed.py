@@ -197,3 +197,40 @@ def tie_across_roots(det):
     b = (6.8, 0.0, 1.2)
     c = (10.9, 0.0, 2.1)
     return event([p, pm, b, c], [0, 1, 2, 3]), tie_detector(det), (0, 2, 3)
+
+
+def rz_threshold_triplet(det, inside, rel=1e-5):
+    """Three hits on barrel layers 0..2 on a straight transverse line
+    through the origin (no curvature, no impact), whose r-z segments turn
+    by an angle with sine arz (1 - rel) (inside: the link holds) or
+    arz (1 + rel) (outside: it does not), set for the float32 coordinates
+    the event carries: the turn is about 1e-7 rad from the cut, far inside the
+    link prefilter's margin, so the prefilter must keep the candidate and
+    the exact cut decide it.  Returns (event, sine)."""
+    arz = det["cuts"]["arz"]
+    phi = 0.7
+    radii = (2.9, 6.8, 10.9)
+    alpha = 0.3
+    target = np.arcsin(arz * (1.0 - rel if inside else 1.0 + rel))
+    za, zb = 1.0, 1.0 + (radii[1] - radii[0]) * np.tan(alpha)
+    pts = [(r * np.cos(phi), r * np.sin(phi), 0.0) for r in radii]
+
+    def build(zc):
+        return event([(pts[0][0], pts[0][1], za), (pts[1][0], pts[1][1], zb),
+                      (pts[2][0], pts[2][1], zc)], [0, 1, 2])
+
+    # the third z from the float32 a, b (their rounding moves the first
+    # segment's angle), then nudged by float32 ulps onto the intended side
+    ev = build(zb + (radii[2] - radii[1]) * np.tan(alpha + target))
+    a, b = _hit(ev, 0), _hit(ev, 1)
+    rb = np.hypot(b[0], b[1])
+    t1 = np.arctan2(b[2] - a[2], rb - np.hypot(a[0], a[1]))
+    c = _hit(ev, 2)
+    zc = np.float32(b[2] + (np.hypot(c[0], c[1]) - rb) * np.tan(t1 + target))
+    for _ in range(64):
+        ev = build(float(zc))
+        s = rz_sine(_hit(ev, 0), _hit(ev, 1), _hit(ev, 2))
+        if (s < arz) == inside and abs(s / arz - 1.0) > 1e-7:
+            return ev, s
+        zc = np.nextafter(zc, np.float32(-np.inf) if inside else np.float32(np.inf))
+    raise RuntimeError("no float32 z on the intended side of the cut")

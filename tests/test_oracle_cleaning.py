@@ -113,3 +113,18 @@ def test_exact_tie_across_roots(det):
     assert rows[0] == (1, 2, 3)
     assert _score_of(r, (0, 2, 3)) == _score_of(r, (1, 2, 3))
     assert [_row(t) for t in r["tracks"]] == [winner]
+
+
+@pytest.mark.parametrize("inside", [True, False])
+def test_rz_cut_at_its_threshold(det, inside):
+    # a straight transverse line through the origin whose r-z segments turn
+    # by an angle with sine within 1e-5 of arz (set on the float32
+    # coordinates, checked by the arctan2 route): the link exists exactly
+    # when the sine is below arz
+    ev, s = cs.rz_threshold_triplet(det, inside)
+    arz = det["cuts"]["arz"]
+    assert (s < arz) == inside and abs(s / arz - 1.0) < 2e-5
+    o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
+    assert len(o["doublets"]) == 2
+    assert len(o["links"]) == (1 if inside else 0)
+    assert len(o["tracks"]) == (1 if inside else 0)

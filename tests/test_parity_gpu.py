@@ -423,6 +423,18 @@ def test_constructed_cleaning_cases(torch):
             rec.close()
 
 
+@pytest.mark.parametrize("lk", [0, 1, 2])
+def test_rz_cut_at_its_threshold(torch, lk):
+    # r-z turns within 1e-5 (relative) of the cut on either side: the link
+    # prefilter (16-bit angles, widened windows) must keep both candidates
+    # and the exact cut decide them as the oracle does
+    events = [cs.rz_threshold_triplet(DET, inside)[0] for inside in (True, False)]
+    rec = make_rec(link_kernel=lk)
+    res, out, dumps = run_and_dump(rec, events)
+    check_events(events, res, out, dumps)
+    assert res.counts["n_links"] == 1
+
+
 def test_path_longer_than_eight_hits(torch):
     import paper_2104_06573_amd as pxt
     d9 = cs.chain_detector(DET, 9)
