@@ -94,7 +94,12 @@ typedef struct pxt_config {
                                1-2 per doublet at PU~50, up to ~8 at PU~200 */
   uint32_t max_tuples;      /* raw n-tuplets before cleaning               */
   /* --- tuning ------------------------------------------------------------ */
-  int32_t phi_bins;         /* phi bins per layer, 16..4096                */
+  int32_t phi_bins;         /* phi bins per layer, 16..4096.  Up to 12288
+                               bins over all layers, a call of 8 events or
+                               more (or of events of at most 8192 hits)
+                               is binned by one block per event in LDS;
+                               otherwise by device-wide kernels (same
+                               result either way)                          */
   int32_t block_size;       /* threads per block of the per-item kernels   */
   int32_t group_lanes;      /* lanes per item in doublet/link kernels:
                                4, 8, 16, 32 or 64                          */
