@@ -234,3 +234,62 @@ def rz_threshold_triplet(det, inside, rel=1e-5):
             return ev, s
         zc = np.nextafter(zc, np.float32(-np.inf) if inside else np.float32(np.inf))
     raise RuntimeError("no float32 z on the intended side of the cut")
+
+
+def _dec(x):
+    return Decimal(float(x))
+
+
+def doublet_curvature_ratio(pa, pb, kmax):
+    """2 |xi yo - yi xo| / (kmax ri ro |ab|) of a doublet in 50-digit
+    arithmetic from the float32 coordinates: the doublet's curvature cut
+    holds when it is at most 1."""
+    getcontext().prec = 50
+    xi, yi, xo, yo = (_dec(v) for v in (pa[0], pa[1], pb[0], pb[1]))
+    cr = abs(xi * yo - yi * xo)
+    ri = (xi * xi + yi * yi).sqrt()
+    ro = (xo * xo + yo * yo).sqrt()
+    ab = ((xo - xi) ** 2 + (yo - yi) ** 2).sqrt()
+    return 2 * cr / (_dec(kmax) * ri * ro * ab)
+
+
+def curvature_threshold_doublet(det, inside, lo=1e-12, hi=1e-9):
+    """A layer-0 / layer-1 doublet whose transverse curvature sits within
+    [lo, hi] (relative) of kmax, below it (inside: the doublet exists) or
+    above: inside the 1e-9 band of the fast squared form, where the
+    defining expression decides.  The outer hit's float32 x and y are
+    stepped by ulps from the real-valued threshold; the ratio is nearly
+    linear in the steps, so for each x step the y step that brings it
+    closest to 1 is tried.  Returns (event, ratio - 1)."""
+    kmax = det["cuts"]["kmax"]
+    phi, ri, ro = 0.4, 2.9, 6.8
+    # sin(dphi) = kmax |ab| / 2 with |ab|^2 = ri^2 + ro^2 - 2 ri ro cos(dphi)
+    dphi = 0.05
+    for _ in range(60):
+        ab = np.sqrt(ri * ri + ro * ro - 2 * ri * ro * np.cos(dphi))
+        dphi = np.arcsin(kmax * ab / 2.0)
+    a = (np.float32(ri * np.cos(phi)), np.float32(ri * np.sin(phi)), np.float32(1.0))
+    bx0 = np.float32(ro * np.cos(phi + dphi))
+    by0 = np.float32(ro * np.sin(phi + dphi))
+    bz = np.float32(1.0 + (ro - ri) * 0.3)
+    ux, uy = np.spacing(bx0), np.spacing(by0)
+
+    def ratio(i, j):
+        b = (bx0 + np.float32(i) * ux, by0 + np.float32(j) * uy)
+        return b, float(doublet_curvature_ratio(a, b, kmax) - 1)
+
+    _, q0 = ratio(0, 0)
+    alpha = ratio(1, 0)[1] - q0
+    beta = ratio(0, 1)[1] - q0
+    best = None
+    for i in range(-3000, 3001):
+        j0 = int(round(-(q0 + alpha * i) / beta))
+        for j in (j0 - 1, j0, j0 + 1):
+            b, q = ratio(i, j)
+            if (q < 0) == inside and lo <= abs(q) <= hi:
+                if best is None or abs(q) < abs(best[1]):
+                    best = (b, q)
+    if best is None:
+        raise RuntimeError("no float32 outer hit within the band")
+    (bx, by), q = best
+    return event([a, (bx, by, bz)], [0, 1]), q

@@ -128,3 +128,14 @@ def test_rz_cut_at_its_threshold(det, inside):
     assert len(o["doublets"]) == 2
     assert len(o["links"]) == (1 if inside else 0)
     assert len(o["tracks"]) == (1 if inside else 0)
+
+
+@pytest.mark.parametrize("inside", [True, False])
+def test_doublet_curvature_cut_in_its_band(det, inside):
+    # a doublet whose curvature is within 1e-9 of kmax (from 50-digit
+    # arithmetic on its float32 coordinates): the oracle keeps it exactly
+    # when it is below
+    ev, q = cs.curvature_threshold_doublet(det, inside)
+    assert (q < 0) == inside and 1e-12 <= abs(q) <= 1e-9
+    o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
+    assert len(o["doublets"]) == (1 if inside else 0)

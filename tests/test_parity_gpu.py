@@ -435,6 +435,18 @@ def test_rz_cut_at_its_threshold(torch, lk):
     assert res.counts["n_links"] == 1
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_doublet_curvature_cut_in_its_band(torch, mode):
+    # doublets within 1e-9 of the curvature cut on either side: inside the
+    # fast squared form's band, the defining expression decides, in every
+    # doublet kernel as in the oracle
+    events = [cs.curvature_threshold_doublet(DET, inside)[0] for inside in (True, False)]
+    rec = make_rec(doublet_mode=mode)
+    res, out, dumps = run_and_dump(rec, events)
+    check_events(events, res, out, dumps)
+    assert res.counts["n_doublets"] == 1
+
+
 def test_path_longer_than_eight_hits(torch):
     import paper_2104_06573_amd as pxt
     d9 = cs.chain_detector(DET, 9)
