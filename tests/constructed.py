@@ -293,3 +293,65 @@ def curvature_threshold_doublet(det, inside, lo=1e-12, hi=1e-9):
         raise RuntimeError("no float32 outer hit within the band")
     (bx, by), q = best
     return event([a, (bx, by, bz)], [0, 1]), q
+
+
+def impact_exact_dec(pa, pb, pc):
+    """impact_exact to 50 digits (a Decimal)."""
+    getcontext().prec = 50
+    P = [(Fraction(float(p[0])), Fraction(float(p[1]))) for p in (pa, pb, pc)]
+    (x1, y1), (x2, y2), (x3, y3) = P
+    # the circle x^2 + y^2 + D x + E y + F = 0 through the three points
+    a11, a12, b1 = x2 - x1, y2 - y1, -((x2 * x2 + y2 * y2) - (x1 * x1 + y1 * y1))
+    a21, a22, b2 = x3 - x1, y3 - y1, -((x3 * x3 + y3 * y3) - (x1 * x1 + y1 * y1))
+    det = a11 * a22 - a12 * a21
+    D = (b1 * a22 - a12 * b2) / det
+    E = (a11 * b2 - b1 * a21) / det
+    F = -(x1 * x1 + y1 * y1) - D * x1 - E * y1
+    c2 = (D * D + E * E) / 4
+    dec = lambda q: Decimal(q.numerator) / Decimal(q.denominator)
+    return abs(dec(F)) / (dec(c2).sqrt() + dec(c2 - F).sqrt())
+
+
+def impact_threshold_triplet(det, inside, lo=1e-12, hi=1e-9):
+    """Three hits on barrel layers 0..2 of a helix of pT about 2 GeV (the
+    curvature cut holds with room) on a straight r-z line (the r-z cut holds
+    exactly), whose transverse impact sits within [lo, hi] (relative) of
+    d0max, below it (inside: the link holds) or above: inside the 1e-9 band
+    of the impact cut's division-free form, where the defining expression
+    decides.  The third hit's float32 x and y are stepped by ulps; the
+    impact is nearly linear in the steps, so for each x step the y step
+    that brings it closest to d0max is tried.  Returns (event, d0 / d0max
+    - 1)."""
+    d0max = det["cuts"]["d0max"]
+    k = det["c_kappa"] / 2.0
+    phi0 = 0.3
+    radii = (2.9, 6.8, 10.9)
+    xy = [hx.point(phi0, d0max, k, 0.0, 0.0, hx.arc_at_radius(phi0, d0max, k, r))[:2]
+          for r in radii]
+    z = [1.0 + 0.5 * (r - radii[0]) for r in radii]
+    a = (np.float32(xy[0][0]), np.float32(xy[0][1]))
+    b = (np.float32(xy[1][0]), np.float32(xy[1][1]))
+    cx0, cy0 = np.float32(xy[2][0]), np.float32(xy[2][1])
+    ux, uy = np.spacing(cx0), np.spacing(cy0)
+    ref = Decimal(float(d0max))
+
+    def rel(i, j):
+        c = (cx0 + np.float32(i) * ux, cy0 + np.float32(j) * uy)
+        return c, float(impact_exact_dec(a, b, c) / ref - 1)
+
+    _, q0 = rel(0, 0)
+    alpha = rel(1, 0)[1] - q0
+    beta = rel(0, 1)[1] - q0
+    best = None
+    for i in range(-4000, 4001):
+        j0 = int(round(-(q0 + alpha * i) / beta))
+        for j in (j0 - 1, j0, j0 + 1):
+            c, q = rel(i, j)
+            if (q < 0) == inside and lo <= abs(q) <= hi:
+                if best is None or abs(q) < abs(best[1]):
+                    best = (c, q)
+    if best is None:
+        raise RuntimeError("no float32 third hit within the band")
+    c, q = best
+    pts = [(a[0], a[1], z[0]), (b[0], b[1], z[1]), (c[0], c[1], z[2])]
+    return event(pts, [0, 1, 2]), q

@@ -139,3 +139,15 @@ def test_doublet_curvature_cut_in_its_band(det, inside):
     assert (q < 0) == inside and 1e-12 <= abs(q) <= 1e-9
     o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
     assert len(o["doublets"]) == (1 if inside else 0)
+
+
+@pytest.mark.parametrize("inside", [True, False])
+def test_link_impact_cut_in_its_band(det, inside):
+    # a triplet whose transverse impact is within 1e-9 of d0max (from exact
+    # rational arithmetic on its float32 coordinates), the other cuts
+    # holding with room: the oracle links it exactly when it is below
+    ev, q = cs.impact_threshold_triplet(det, inside)
+    assert (q < 0) == inside and 1e-12 <= abs(q) <= 1e-9
+    o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
+    assert len(o["doublets"]) == 2
+    assert len(o["links"]) == (1 if inside else 0)

@@ -447,6 +447,19 @@ def test_doublet_curvature_cut_in_its_band(torch, mode):
     assert res.counts["n_doublets"] == 1
 
 
+def test_link_impact_cut_in_its_band(torch):
+    # triplets within 1e-9 of the impact cut on either side: inside the
+    # division-free form's band, the defining expression decides, in every
+    # link kernel as in the oracle
+    events = [cs.impact_threshold_triplet(DET, inside)[0] for inside in (True, False)]
+    for lk in (0, 1, 2):
+        rec = make_rec(link_kernel=lk)
+        res, out, dumps = run_and_dump(rec, events)
+        check_events(events, res, out, dumps)
+        assert res.counts["n_links"] == 1
+        rec.close()
+
+
 def test_path_longer_than_eight_hits(torch):
     import paper_2104_06573_amd as pxt
     d9 = cs.chain_detector(DET, 9)
