@@ -355,3 +355,52 @@ def impact_threshold_triplet(det, inside, lo=1e-12, hi=1e-9):
     c, q = best
     pts = [(a[0], a[1], z[0]), (b[0], b[1], z[1]), (c[0], c[1], z[2])]
     return event(pts, [0, 1, 2]), q
+
+
+def rz_ratio_exact(pa, pb, pc, arz):
+    """|sin| of the r-z turn a -> b -> c over arz, to 50 digits from the
+    float32 coordinates (the cross product of the r-z segments over their
+    lengths): the link's r-z cut holds when it is at most 1."""
+    getcontext().prec = 50
+    r = [(_dec(p[0]) ** 2 + _dec(p[1]) ** 2).sqrt() for p in (pa, pb, pc)]
+    z = [_dec(p[2]) for p in (pa, pb, pc)]
+    dra, dza = r[1] - r[0], z[1] - z[0]
+    drb, dzb = r[2] - r[1], z[2] - z[1]
+    t0 = abs(dra * dzb - dza * drb)
+    return t0 / ((dra * dra + dza * dza).sqrt() * (drb * drb + dzb * dzb).sqrt() * _dec(arz))
+
+
+def rz_band_triplet(det, inside, lo=1e-12, hi=1e-9):
+    """rz_threshold_triplet with the turn's sine within [lo, hi] (relative)
+    of arz: inside the 1e-9 band of the r-z cut's squared form, where the
+    defining expression decides.  The float32 z of the middle and outer hits
+    are stepped by ulps (the ratio is nearly linear in the steps; for each
+    middle step the outer step closest to the cut is tried).  Returns
+    (event, ratio - 1)."""
+    arz = det["cuts"]["arz"]
+    ev0, _ = rz_threshold_triplet(det, inside)
+    a, b, c = _hit(ev0, 0), _hit(ev0, 1), _hit(ev0, 2)
+    zb0, zc0 = np.float32(b[2]), np.float32(c[2])
+    ub, uc = np.spacing(zb0), np.spacing(zc0)
+
+    def rel(i, j):
+        zb = zb0 + np.float32(i) * ub
+        zc = zc0 + np.float32(j) * uc
+        q = float(rz_ratio_exact(a, (b[0], b[1], zb), (c[0], c[1], zc), arz) - 1)
+        return (zb, zc), q
+
+    _, q0 = rel(0, 0)
+    alpha = rel(1, 0)[1] - q0
+    beta = rel(0, 1)[1] - q0
+    best = None
+    for i in range(-3000, 3001):
+        j0 = int(round(-(q0 + alpha * i) / beta))
+        for j in (j0 - 1, j0, j0 + 1):
+            zz, q = rel(i, j)
+            if (q < 0) == inside and lo <= abs(q) <= hi:
+                if best is None or abs(q) < abs(best[1]):
+                    best = (zz, q)
+    if best is None:
+        raise RuntimeError("no float32 z pair within the band")
+    (zb, zc), q = best
+    return event([a, (b[0], b[1], zb), (c[0], c[1], zc)], [0, 1, 2]), q

@@ -151,3 +151,14 @@ def test_link_impact_cut_in_its_band(det, inside):
     o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
     assert len(o["doublets"]) == 2
     assert len(o["links"]) == (1 if inside else 0)
+
+
+@pytest.mark.parametrize("inside", [True, False])
+def test_link_rz_cut_in_its_band(det, inside):
+    # a triplet whose r-z turn has a sine within 1e-9 of arz (50-digit
+    # arithmetic on its float32 coordinates): linked exactly when below
+    ev, q = cs.rz_band_triplet(det, inside)
+    assert (q < 0) == inside and 1e-12 <= abs(q) <= 1e-9
+    o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
+    assert len(o["doublets"]) == 2
+    assert len(o["links"]) == (1 if inside else 0)

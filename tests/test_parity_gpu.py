@@ -450,13 +450,15 @@ def test_doublet_curvature_cut_in_its_band(torch, mode):
 def test_link_impact_cut_in_its_band(torch):
     # triplets within 1e-9 of the impact cut on either side: inside the
     # division-free form's band, the defining expression decides, in every
-    # link kernel as in the oracle
+    # link kernel as in the oracle (one event per triplet)
     events = [cs.impact_threshold_triplet(DET, inside)[0] for inside in (True, False)]
+    # and the same for the r-z cut's squared form
+    events += [cs.rz_band_triplet(DET, inside)[0] for inside in (True, False)]
     for lk in (0, 1, 2):
         rec = make_rec(link_kernel=lk)
         res, out, dumps = run_and_dump(rec, events)
         check_events(events, res, out, dumps)
-        assert res.counts["n_links"] == 1
+        assert res.counts["n_links"] == 2
         rec.close()
 
 
