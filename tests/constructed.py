@@ -404,3 +404,59 @@ def rz_band_triplet(det, inside, lo=1e-12, hi=1e-9):
         raise RuntimeError("no float32 z pair within the band")
     (zb, zc), q = best
     return event([a, (b[0], b[1], zb), (c[0], c[1], zc)], [0, 1, 2]), q
+
+
+def link_curvature_ratio(pa, pb, pc, kmax):
+    """Curvature of the transverse circle through three hits over kmax,
+    2 |(b - a) x (c - a)| / (|ab| |bc| |ac| kmax), to 50 digits from the
+    float32 coordinates: the link's curvature cut holds when it is at most
+    1."""
+    getcontext().prec = 50
+    A, B, C = ([_dec(p[0]), _dec(p[1])] for p in (pa, pb, pc))
+    cr = abs((B[0] - A[0]) * (C[1] - A[1]) - (B[1] - A[1]) * (C[0] - A[0]))
+    ab = ((B[0] - A[0]) ** 2 + (B[1] - A[1]) ** 2).sqrt()
+    bc = ((C[0] - B[0]) ** 2 + (C[1] - B[1]) ** 2).sqrt()
+    ac = ((C[0] - A[0]) ** 2 + (C[1] - A[1]) ** 2).sqrt()
+    return 2 * cr / (ab * bc * ac * _dec(kmax))
+
+
+def curvature_band_triplet(det, inside, lo=1e-12, hi=1e-9):
+    """Three hits on barrel layers 0..2 of a circle of curvature kmax that
+    passes 0.05 cm from the origin (so the doublets' circles through the
+    origin are 3-11 % below kmax and the impact cut holds with room), on a
+    straight r-z line, whose circle's curvature sits within [lo, hi]
+    (relative) of kmax, below (inside: the link holds) or above: inside the
+    1e-9 band of the curvature cut's squared form.  The third hit's float32
+    x and y are stepped by ulps as in impact_threshold_triplet.  Returns
+    (event, ratio - 1)."""
+    kmax = det["cuts"]["kmax"]
+    phi0, d0 = 0.3, -0.05
+    radii = (2.9, 6.8, 10.9)
+    xy = [hx.point(phi0, d0, kmax, 0.0, 0.0, hx.arc_at_radius(phi0, d0, kmax, r))[:2]
+          for r in radii]
+    z = [1.0 + 0.5 * (r - radii[0]) for r in radii]
+    a = (np.float32(xy[0][0]), np.float32(xy[0][1]))
+    b = (np.float32(xy[1][0]), np.float32(xy[1][1]))
+    cx0, cy0 = np.float32(xy[2][0]), np.float32(xy[2][1])
+    ux, uy = np.spacing(cx0), np.spacing(cy0)
+
+    def rel(i, j):
+        c = (cx0 + np.float32(i) * ux, cy0 + np.float32(j) * uy)
+        return c, float(link_curvature_ratio(a, b, c, kmax) - 1)
+
+    _, q0 = rel(0, 0)
+    alpha = rel(1, 0)[1] - q0
+    beta = rel(0, 1)[1] - q0
+    best = None
+    for i in range(-3000, 3001):
+        j0 = int(round(-(q0 + alpha * i) / beta))
+        for j in (j0 - 1, j0, j0 + 1):
+            c, q = rel(i, j)
+            if (q < 0) == inside and lo <= abs(q) <= hi:
+                if best is None or abs(q) < abs(best[1]):
+                    best = (c, q)
+    if best is None:
+        raise RuntimeError("no float32 third hit within the band")
+    c, q = best
+    pts = [(a[0], a[1], z[0]), (b[0], b[1], z[1]), (c[0], c[1], z[2])]
+    return event(pts, [0, 1, 2]), q

@@ -162,3 +162,15 @@ def test_link_rz_cut_in_its_band(det, inside):
     o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
     assert len(o["doublets"]) == 2
     assert len(o["links"]) == (1 if inside else 0)
+
+
+@pytest.mark.parametrize("inside", [True, False])
+def test_link_curvature_cut_in_its_band(det, inside):
+    # a triplet whose circle's curvature is within 1e-9 of kmax (50-digit
+    # arithmetic on its float32 coordinates), the doublet and impact cuts
+    # holding with room: linked exactly when below
+    ev, q = cs.curvature_band_triplet(det, inside)
+    assert (q < 0) == inside and 1e-12 <= abs(q) <= 1e-9
+    o = oracle.reconstruct(ev.x, ev.y, ev.z, ev.layer, det)
+    assert len(o["doublets"]) == 2
+    assert len(o["links"]) == (1 if inside else 0)

@@ -452,13 +452,14 @@ def test_link_impact_cut_in_its_band(torch):
     # division-free form's band, the defining expression decides, in every
     # link kernel as in the oracle (one event per triplet)
     events = [cs.impact_threshold_triplet(DET, inside)[0] for inside in (True, False)]
-    # and the same for the r-z cut's squared form
+    # and the same for the r-z and curvature cuts' squared forms
     events += [cs.rz_band_triplet(DET, inside)[0] for inside in (True, False)]
+    events += [cs.curvature_band_triplet(DET, inside)[0] for inside in (True, False)]
     for lk in (0, 1, 2):
         rec = make_rec(link_kernel=lk)
         res, out, dumps = run_and_dump(rec, events)
         check_events(events, res, out, dumps)
-        assert res.counts["n_links"] == 2
+        assert res.counts["n_links"] == 3
         rec.close()
 
 
